@@ -1,0 +1,177 @@
+/*
+ * pisco.h -- C ABI of the MI355X pixel-space polarised beam convolver.
+ *
+ * The operation (Fluxa, Brewer & Dunner, "Pixel space convolution for cosmic
+ * microwave background experiments", Sec. 4.2, the pixelated convolution
+ * equation) turns a pointing stream into a time-ordered data (TOD) stream:
+ *
+ *   d(theta0, phi0, psi0) = N * sum_k  D(chi_k) Lambda(chi_k) B_k Lambda(-chi_k) S_k
+ *
+ * over the HEALPix sky pixels k whose centres lie within rho_max of the
+ * boresight.  Because D(chi) Lambda(chi) = D(0) (Sec. 4.1, the detector row
+ * vector and the rotation matrix), the detector row can be folded into the
+ * beamsor once per detector; the library therefore takes three effective
+ * beam channels plus the normalising channel:
+ *
+ *   bI = (s/2)[(1+eps) B_TT + (1-eps) B_TQ]      (D(0) B, column T)
+ *   bQ = (s/2)[(1+eps) B_QT + (1-eps) B_QQ]      (D(0) B, column Q)
+ *   bU = (s/2)[(1+eps) B_UT + (1-eps) B_UQ]      (D(0) B, column U)
+ *   bT = B_TT                                    (normalisation, Sec. 3)
+ *
+ * and per pair computes bI I + bQ (cos2chi Q + sin2chi U) + bU (-sin2chi Q + cos2chi U).
+ * The sky's V is taken as zero (the CMB carries no circular polarisation).
+ *
+ * Geometry: theta = colatitude, phi = longitude, psi = position angle of the
+ * antenna basis (Sec. 2, antenna basis vectors); zeta = detector angle from
+ * theta'_0 (Sec. 3, PSB polarisation vectors); chi is the angle from the
+ * pixel's theta_hat to the co-polar direction (Sec. 2 and Appendix A, Ludwig's
+ * third definition).  The beam is a tangent-plane (gnomonic) grid of the
+ * antenna frame: u = tan(rho) cos(sigma), v = tan(rho) sin(sigma).
+ *
+ * Conventions shared by every call:
+ *   - All functions return PISCO_OK or an error code; no exception crosses
+ *     the ABI.  After an error, pisco_last_error(ctx) holds a message; the
+ *     context stays usable and its previous state is unchanged.
+ *   - `mem` says where a caller pointer lives: PISCO_HOST (pageable or pinned
+ *     host memory; the library copies synchronously) or PISCO_DEVICE (memory
+ *     on the context's device).
+ *   - Pointers are borrowed only for the duration of the call unless stated.
+ *   - A context is bound to one device and is not thread-safe; use one
+ *     context per host thread.
+ */
+#ifndef PISCO_H
+#define PISCO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pisco_ctx pisco_ctx;
+
+typedef enum {
+    PISCO_OK = 0,
+    PISCO_EINVAL = 1,      /* invalid argument (size, range, non-finite value, dtype mismatch) */
+    PISCO_ENOMEM = 2,      /* device or host allocation failed */
+    PISCO_EDEVICE = 3,     /* a HIP runtime call failed */
+    PISCO_ESTATE = 4,      /* call out of order (e.g. convolve before set_sky) */
+    PISCO_EUNSUPPORTED = 5 /* device is not gfx950 or feature not built */
+} pisco_status;
+
+enum { PISCO_F32 = 0, PISCO_F64 = 1 };
+enum { PISCO_HOST = 0, PISCO_DEVICE = 1 };
+enum { PISCO_NORM_FIXED = 0, PISCO_NORM_PER_SAMPLE = 1 };
+enum { PISCO_OUT_TOD = 0, PISCO_OUT_STOKES = 1 };
+
+#define PISCO_MAX_DETECTORS 4096
+#define PISCO_MAX_NSIDE 8192
+
+/* ABI version of this header (major * 100 + minor). */
+int pisco_abi_version(void);
+
+/* Create a context on HIP device `device`.  Fails with EUNSUPPORTED unless the
+ * device is gfx950.  *out receives the context (owned by the caller; release
+ * with pisco_destroy). */
+pisco_status pisco_create(int device, pisco_ctx **out);
+
+/* Release every device buffer the context owns.  NULL is accepted. */
+void pisco_destroy(pisco_ctx *ctx);
+
+/* Message of the most recent failed call (empty if none); owned by ctx, valid
+ * until the next call on ctx. */
+const char *pisco_last_error(const pisco_ctx *ctx);
+
+/*
+ * Sky maps (Sec. 5.1: Stokes I, Q, U as HEALPix maps; RING order, Gorski et
+ * al. 2005).  Each map holds 12 * nside^2 elements of `dtype`.  nside must be
+ * a power of two in [1, PISCO_MAX_NSIDE].  The library copies the maps into its
+ * own interleaved device layout (one 16-byte (F32) or 32-byte (F64) record
+ * per pixel); the caller's buffers are not retained.  The sky's dtype fixes
+ * the precision of every later convolve: F64 runs the double-precision
+ * kernel, F32 the mixed-precision one.
+ */
+pisco_status pisco_set_sky(pisco_ctx *ctx, int64_t nside, const void *I, const void *Q, const void *U,
+                           int dtype, int mem);
+
+/*
+ * Effective beam of detector `det` (0 <= det < PISCO_MAX_DETECTORS): an n x n
+ * grid (n odd, 3..8191) of nodes at u, v in [-T, T] (T = half_span_tan > 0),
+ * node (iu, iv) at (-T + iu h, -T + iv h) with h = 2T/(n-1), row-major [iv][iu].
+ * bI, bQ, bU, bT are the channels described above, n*n elements of `dtype`
+ * each, which must equal the sky's dtype at convolve time.  Between nodes the
+ * beam is bilinear; outside the grid it is zero.  Copied into one 16/32-byte
+ * record per node.
+ */
+pisco_status pisco_set_beam(pisco_ctx *ctx, int32_t det, int32_t n, double half_span_tan,
+                            const void *bI, const void *bQ, const void *bU, const void *bT,
+                            int dtype, int mem);
+
+/* Let detector `det` use the beam of detector `src` (no copy; e.g. one shared
+ * far-sidelobe grid).  `src` must already have a beam. */
+pisco_status pisco_share_beam(pisco_ctx *ctx, int32_t det, int32_t src);
+
+/*
+ * Detector parameters: zeta (rad, Sec. 3); pixels with rho_min < rho <= rho_max
+ * take part (rho_min = 0 selects the whole disc, inclusive of rho = 0;
+ * 0 <= rho_min < rho_max < pi/2).  Normalisation N: FIXED -> N = norm_scale;
+ * PER_SAMPLE -> N = norm_scale / sum_k bT(k) over the same pixels (0 when the
+ * sum is 0).
+ */
+pisco_status pisco_set_detector(pisco_ctx *ctx, int32_t det, double zeta, double rho_min, double rho_max,
+                                int norm_mode, double norm_scale);
+
+/*
+ * Pointing stream of detector `det`: n samples of colatitude theta in [0, pi],
+ * longitude phi and position angle psi (radians, float64, structure of arrays).
+ * mem = HOST: copied to the device (after validation).  mem = DEVICE: the
+ * arrays are borrowed and must stay valid, unchanged, until the last convolve
+ * that uses them has completed on its stream; they are validated once here.
+ * Non-finite values or theta outside [0, pi] give EINVAL.  n may be 0.
+ */
+pisco_status pisco_set_pointing(pisco_ctx *ctx, int32_t det, int64_t n, const double *theta,
+                                const double *phi, const double *psi, int mem);
+
+/*
+ * Convolve.  det >= 0: that detector's stream; det = -1: every configured
+ * detector in one persistent launch (replayed from a captured HIP graph when
+ * the configuration and output buffer are unchanged), outputs concatenated in
+ * ascending detector order.  out_mode TOD writes one value per sample;
+ * STOKES writes three per sample ([t][3]: N sum bT Lambda(-chi) S restricted
+ * to I, Q, U, the detector-frame Stokes pickup of the scalar beam bT).
+ * `out` holds elements of the sky's dtype; mem = DEVICE: written
+ * asynchronously on `stream` (a hipStream_t, NULL = default stream);
+ * mem = HOST: the call synchronises and copies.
+ */
+pisco_status pisco_convolve(pisco_ctx *ctx, int32_t det, int out_mode, void *out, int mem, void *stream);
+
+/* Number of output samples convolve(det) writes (det = -1: all detectors). */
+int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
+
+/*
+ * Launch shape of the convolution kernel.  samples_per_tile: consecutive
+ * samples one wavefront processes before taking new work (1..65536);
+ * waves_per_group: wavefronts per workgroup (1, 2, 4 or 8); groups_per_cu:
+ * resident workgroups launched per compute unit (1..16); xcd_queues: 1 = one
+ * shared work queue, 8 = one queue per accelerator die so neighbouring tiles
+ * share its L2.  Zero keeps the current value.
+ */
+pisco_status pisco_set_launch(pisco_ctx *ctx, int32_t samples_per_tile, int32_t waves_per_group,
+                              int32_t groups_per_cu, int32_t xcd_queues);
+pisco_status pisco_get_launch(const pisco_ctx *ctx, int32_t *samples_per_tile, int32_t *waves_per_group,
+                              int32_t *groups_per_cu, int32_t *xcd_queues);
+
+/*
+ * Kernel timing: when enabled, every convolve brackets its kernel launches
+ * with HIP events on the launch stream; pisco_kernel_time reads (and
+ * synchronises on) them.  total_ms = summed kernel time of the convolve calls
+ * since the last reset, launches = their count.
+ */
+pisco_status pisco_set_timing(pisco_ctx *ctx, int on);
+pisco_status pisco_kernel_time(pisco_ctx *ctx, double *total_ms, int64_t *launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PISCO_H */
