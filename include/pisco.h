@@ -37,7 +37,9 @@
  *     on the context's device).
  *   - Pointers are borrowed only for the duration of the call unless stated.
  *   - A context is bound to one device and is not thread-safe; use one
- *     context per host thread.
+ *     context per host thread.  Single-detector launches share one work
+ *     counter, and batched launches another: two launches of the same kind
+ *     must not overlap in time on different streams.
  */
 #ifndef PISCO_H
 #define PISCO_H

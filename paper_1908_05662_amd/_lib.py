@@ -1,0 +1,61 @@
+"""ctypes view of the C ABI in include/pisco.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpisco.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = range(6)
+F32, F64 = 0, 1
+HOST, DEVICE = 0, 1
+NORM_FIXED, NORM_PER_SAMPLE = 0, 1
+OUT_TOD, OUT_STOKES = 0, 1
+
+_STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",
+           EUNSUPPORTED: "EUNSUPPORTED"}
+
+# (name, restype, argtypes) for every exported symbol of include/pisco.h
+_vp, _i32, _i64, _dbl, _cp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_char_p
+_ip = ctypes.POINTER(ctypes.c_int32)
+SIGNATURES = [
+    ("pisco_abi_version", ctypes.c_int, []),
+    ("pisco_create", ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    ("pisco_destroy", None, [_vp]),
+    ("pisco_last_error", _cp, [_vp]),
+    ("pisco_set_sky", ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
+    ("pisco_set_beam", ctypes.c_int, [_vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
+    ("pisco_share_beam", ctypes.c_int, [_vp, _i32, _i32]),
+    ("pisco_set_detector", ctypes.c_int, [_vp, _i32, _dbl, _dbl, _dbl, ctypes.c_int, _dbl]),
+    ("pisco_set_pointing", ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, ctypes.c_int]),
+    ("pisco_convolve", ctypes.c_int, [_vp, _i32, ctypes.c_int, _vp, ctypes.c_int, _vp]),
+    ("pisco_output_samples", _i64, [_vp, _i32]),
+    ("pisco_set_launch", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32]),
+    ("pisco_get_launch", ctypes.c_int, [_vp, _ip, _ip, _ip, _ip]),
+    ("pisco_set_timing", ctypes.c_int, [_vp, ctypes.c_int]),
+    ("pisco_kernel_time", ctypes.c_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64), ctypes.c_int]),
+]
+
+_lib = None
+
+
+class PiscoError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load():
+    """Load libpisco.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib

@@ -1,0 +1,155 @@
+"""Python binding of the C ABI: torch tensors in, torch tensors out.
+
+PyTorch only provides device memory and streams here; every step of the
+convolution runs in the HIP kernels of libpisco.so.  Names follow the C ABI
+(include/pisco.h) without the ``pisco_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+from .beamsor import fold_detector
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+class Convolver:
+    """One context on one GPU (``pisco_create``)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = L.load()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the convolver has no CPU path")
+        self.device = int(device)
+        self.torch_device = torch.device("cuda", self.device)
+        h = ctypes.c_void_p()
+        st = self._lib.pisco_create(self.device, ctypes.byref(h))
+        if st != L.OK:
+            raise L.PiscoError(st, "pisco_create failed (device must be gfx950)")
+        self._h = h
+        self._keep = {}      # borrowed device tensors, per detector
+        self.dtype = None    # torch dtype of the sky
+        self._sizes = {}
+
+    # -- plumbing ---------------------------------------------------------
+    def _check(self, st: int):
+        if st != L.OK:
+            raise L.PiscoError(st, self._lib.pisco_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pisco_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _as_tensor(self, x, dtype):
+        torch = _torch()
+        if isinstance(x, np.ndarray):
+            x = torch.from_numpy(np.ascontiguousarray(x))
+        return x.to(dtype=dtype).contiguous()
+
+    def _mem(self, t):
+        return L.DEVICE if t.is_cuda else L.HOST
+
+    @staticmethod
+    def _code(dtype):
+        torch = _torch()
+        return L.F64 if dtype == torch.float64 else L.F32
+
+    # -- C ABI ------------------------------------------------------------
+    def set_sky(self, nside: int, I, Q, U, dtype=None):
+        torch = _torch()
+        dtype = dtype or torch.float32
+        ts = [self._as_tensor(m, dtype) for m in (I, Q, U)]
+        mems = {self._mem(t) for t in ts}
+        if len(mems) != 1:
+            raise ValueError("I, Q, U must all live on the host or all on the device")
+        self._check(self._lib.pisco_set_sky(self._h, int(nside), *(t.data_ptr() for t in ts), self._code(dtype),
+                                            mems.pop()))
+        self.dtype = dtype
+        self.nside = int(nside)
+
+    def set_beam(self, det: int, n: int, half_span_tan: float, bI, bQ, bU, bT, dtype=None):
+        dtype = dtype or self.dtype or _torch().float32
+        ts = [self._as_tensor(b, dtype).reshape(-1) for b in (bI, bQ, bU, bT)]
+        mems = {self._mem(t) for t in ts}
+        if len(mems) != 1:
+            raise ValueError("beam channels must all live on the host or all on the device")
+        self._check(self._lib.pisco_set_beam(self._h, int(det), int(n), float(half_span_tan),
+                                             *(t.data_ptr() for t in ts), self._code(dtype), mems.pop()))
+
+    def set_beamsor(self, det: int, mueller: np.ndarray, half_span_tan: float, eps: float, s: float, dtype=None):
+        """Fold a (n, n, 4, 4) Mueller field with the detector row and upload it."""
+        bI, bQ, bU, bT = fold_detector(mueller, eps, s)
+        self.set_beam(det, bI.shape[0], half_span_tan, bI, bQ, bU, bT, dtype)
+
+    def share_beam(self, det: int, src: int):
+        self._check(self._lib.pisco_share_beam(self._h, int(det), int(src)))
+
+    def set_detector(self, det: int, zeta: float, rho_min: float, rho_max: float, norm_mode: int,
+                     norm_scale: float = 1.0):
+        self._check(self._lib.pisco_set_detector(self._h, int(det), float(zeta), float(rho_min), float(rho_max),
+                                                 int(norm_mode), float(norm_scale)))
+
+    def set_pointing(self, det: int, theta, phi, psi):
+        torch = _torch()
+        ts = [self._as_tensor(x, torch.float64).reshape(-1) for x in (theta, phi, psi)]
+        n = ts[0].numel()
+        if any(t.numel() != n for t in ts):
+            raise ValueError("theta, phi, psi must have equal length")
+        mems = {self._mem(t) for t in ts}
+        if len(mems) != 1:
+            raise ValueError("pointing arrays must all live on the host or all on the device")
+        mem = mems.pop()
+        self._check(self._lib.pisco_set_pointing(self._h, int(det), n, *(t.data_ptr() for t in ts), mem))
+        if mem == L.DEVICE:
+            self._keep[det] = ts       # borrowed by the library
+        else:
+            self._keep.pop(det, None)
+
+    def output_samples(self, det: int = -1) -> int:
+        return int(self._lib.pisco_output_samples(self._h, int(det)))
+
+    def convolve(self, det: int = -1, out_mode: int = L.OUT_TOD, out=None, stream=None):
+        """Run on the current (or given) torch stream; returns the device output tensor."""
+        torch = _torch()
+        n = self.output_samples(det)
+        shape = (n, 3) if out_mode == L.OUT_STOKES else (n,)
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.torch_device)
+        if tuple(out.shape) != shape or out.dtype != self.dtype or not out.is_cuda or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {self.dtype} device tensor of shape {shape}")
+        s = stream if stream is not None else torch.cuda.current_stream(self.torch_device)
+        self._check(self._lib.pisco_convolve(self._h, int(det), int(out_mode), out.data_ptr(), L.DEVICE,
+                                             ctypes.c_void_p(s.cuda_stream)))
+        return out
+
+    def set_launch(self, samples_per_tile=0, waves_per_group=0, groups_per_cu=0, xcd_queues=0):
+        self._check(self._lib.pisco_set_launch(self._h, samples_per_tile, waves_per_group, groups_per_cu, xcd_queues))
+
+    def get_launch(self):
+        v = [ctypes.c_int32() for _ in range(4)]
+        self._check(self._lib.pisco_get_launch(self._h, *(ctypes.byref(x) for x in v)))
+        return tuple(x.value for x in v)
+
+    def set_timing(self, on: bool = True):
+        self._check(self._lib.pisco_set_timing(self._h, int(bool(on))))
+
+    def kernel_time(self, reset: bool = False):
+        ms, k = ctypes.c_double(), ctypes.c_int64()
+        self._check(self._lib.pisco_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(k), int(reset)))
+        return ms.value, k.value

@@ -1,0 +1,52 @@
+"""Host-side preparation of a detector's beam for the convolution kernels.
+
+The kernels take the detector row already folded into the beamsor
+(Sec. 4.1: D(chi) Lambda(chi) = D(0), so D(0) B is constant over the sky).
+With the Mueller field stored as M[..., out, in] over (T, Q, U, V) -- the
+paper's element B_XY (input X, output Y) at M[Y, X] -- and
+D(0) = (s/2) [1 + eps, 1 - eps, 0, 0]:
+
+    bI = (s/2)[(1+eps) M[T,T] + (1-eps) M[Q,T]]
+    bQ = (s/2)[(1+eps) M[T,Q] + (1-eps) M[Q,Q]]
+    bU = (s/2)[(1+eps) M[T,U] + (1-eps) M[Q,U]]
+    bT = M[T,T]                        (the normalising scalar beam, Sec. 3)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def fold_detector(M: np.ndarray, eps: float, s: float):
+    """M: (n, n, 4, 4) Mueller field -> (bI, bQ, bU, bT), each (n, n) float64."""
+    M = np.asarray(M, dtype=np.float64)
+    if M.ndim != 4 or M.shape[2:] != (4, 4) or M.shape[0] != M.shape[1]:
+        raise ValueError("Mueller field must be (n, n, 4, 4)")
+    a, b = 0.5 * s * (1.0 + eps), 0.5 * s * (1.0 - eps)
+    bI = a * M[:, :, 0, 0] + b * M[:, :, 1, 0]
+    bQ = a * M[:, :, 0, 1] + b * M[:, :, 1, 1]
+    bU = a * M[:, :, 0, 2] + b * M[:, :, 1, 2]
+    return bI, bQ, bU, M[:, :, 0, 0].copy()
+
+
+def fold_elements(elements: dict, n: int, eps: float, s: float):
+    """Same as fold_detector for a sparse {(out, in): (n, n)} Mueller field."""
+    z = np.zeros((n, n))
+    g = lambda o, i: np.asarray(elements.get((o, i), z), dtype=np.float64)  # noqa: E731
+    a, b = 0.5 * s * (1.0 + eps), 0.5 * s * (1.0 - eps)
+    return (a * g(0, 0) + b * g(1, 0), a * g(0, 1) + b * g(1, 1), a * g(0, 2) + b * g(1, 2), g(0, 0).copy())
+
+
+def grid_solid_angle(bT: np.ndarray, half_span_tan: float, rho_max: float | None = None) -> float:
+    """Omega~ = integral of B_TT over the sphere, by the node rule on the tangent
+    grid with the gnomonic Jacobian (1 + u^2 + v^2)^(-3/2); optionally only
+    nodes within rho_max of the centre."""
+    n = bT.shape[0]
+    T = float(half_span_tan)
+    ax = -T + np.arange(n) * (2.0 * T / (n - 1))
+    v, u = np.meshgrid(ax, ax, indexing="ij")
+    r2 = u * u + v * v
+    w = (1.0 + r2) ** -1.5
+    if rho_max is not None:
+        w = w * (np.arctan(np.sqrt(r2)) <= rho_max)
+    h = 2.0 * T / (n - 1)
+    return float(np.sum(bT * w) * h * h)

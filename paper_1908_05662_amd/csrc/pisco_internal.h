@@ -1,0 +1,59 @@
+// Internal types shared by the runtime and the convolution kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pisco {
+
+// Per-detector description, read by the kernel from device memory.
+struct DetDesc {
+    const void *beam;      // n*n records (float4 or double4): bI, bQ, bU, bT
+    const double *theta;   // pointing, SoA
+    const double *phi;
+    const double *psi;
+    int64_t n_samples;
+    int64_t out_offset;    // first output sample of this detector
+    double zeta;
+    double cos_rho_max;    // pixels with cos(rho) >= cos_rho_max ...
+    double cos_rho_min;    // ... and (rho_min == 0 or cos(rho) < cos_rho_min)
+    double rho_max;
+    double norm_scale;
+    double half_span_tan;  // T
+    double inv_h;          // (n - 1) / (2T)
+    int32_t n;             // grid nodes per side
+    int32_t norm_mode;     // 0 fixed, 1 per sample
+    int32_t has_inner;     // rho_min > 0
+    int32_t pad;
+};
+
+// A tile: `count` consecutive samples of detector `det` starting at `begin`.
+struct Tile {
+    int32_t det;
+    int32_t count;
+    int64_t begin;
+};
+
+struct ConvArgs {
+    const void *sky;         // 12 nside^2 records (float4 / double4): I, Q, U, 0
+    const DetDesc *dets;
+    const Tile *tiles;       // tiles[q * tiles_per_queue + i] for queue q
+    int32_t *counters;       // one work counter per queue (zeroed before launch)
+    void *out;               // float or double
+    int64_t nside;
+    int32_t n_queues;        // 1 or 8
+    int32_t tiles_per_queue; // padded queue length
+    const int32_t *queue_len;
+    int32_t out_mode;        // 0 TOD, 1 STOKES
+    int32_t pad;
+};
+
+// Launch helpers (conv_kernel.hip).  Return the launch error.
+hipError_t launch_zero_counters(int32_t *counters, int n, hipStream_t s);
+hipError_t launch_conv(const ConvArgs &a, bool f64, int waves_per_group, int groups, hipStream_t s);
+hipError_t launch_repack4(const void *a, const void *b, const void *c, const void *d, void *out, int64_t n,
+                          bool f64, hipStream_t s);
+hipError_t launch_check_pointing(const double *theta, const double *phi, const double *psi, int64_t n,
+                                 int32_t *bad, hipStream_t s);
+
+}  // namespace pisco

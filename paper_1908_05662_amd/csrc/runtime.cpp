@@ -1,0 +1,654 @@
+// Host runtime behind the C ABI declared in include/pisco.h: device buffers,
+// validation, the tile plan and work queues, HIP-graph replay of the batched
+// launch, and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pisco.h"
+#include "pisco_internal.h"
+
+using pisco::ConvArgs;
+using pisco::DetDesc;
+using pisco::Tile;
+
+namespace {
+
+struct DetState {
+    bool has_beam = false, has_params = false, has_pointing = false;
+    void *beam = nullptr;   // device records
+    bool beam_owned = false;
+    int32_t n = 0;
+    double T = 0.0;
+    int beam_dtype = -1;
+    double zeta = 0.0, rho_min = 0.0, rho_max = 0.0, norm_scale = 1.0;
+    int norm_mode = 0;
+    int64_t nsamp = 0;
+    const double *th = nullptr, *ph = nullptr, *ps = nullptr;
+    double *owned_pointing = nullptr;  // one allocation holding th, ph, ps when copied
+};
+
+struct TimedLaunch {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+// A device-side launch plan: detector descriptors, tile queues, work counters
+// and (for the batched plan) the captured graph.  The context keeps one plan
+// for single-detector launches and one for the batched launch so that eager
+// single-detector calls never invalidate the captured batched graph.
+struct Plan {
+    DetDesc *d_dets = nullptr;
+    size_t d_dets_cap = 0;
+    Tile *d_tiles = nullptr;
+    size_t d_tiles_cap = 0;
+    int32_t *d_ctrl = nullptr;  // [0..8) counters, [8..16) queue lengths
+    uint64_t gen = 0;
+    int32_t det = -2;
+    int32_t spt = 0, xq = 0;
+    int32_t tiles_per_queue = 0, queues = 1;
+    int64_t out_samples = 0;
+    // captured launch
+    hipGraphExec_t gexec = nullptr;
+    uint64_t g_gen = 0;
+    void *g_out = nullptr;
+    hipStream_t g_stream = nullptr;
+    int g_mode = -1;
+    int32_t g_wpg = 0, g_gpc = 0;
+};
+
+struct pisco_ctx {
+    int device = 0;
+    int num_cu = 256;
+    std::string err;
+    int64_t nside = 0;
+    int sky_dtype = -1;
+    void *sky = nullptr;
+    std::vector<DetState> dets;
+    uint64_t generation = 1;  // bumped whenever anything a launch reads changes
+
+    // launch shape
+    int32_t spt = 64, wpg = 4, gpc = 2, xq = 8;
+
+    Plan plans[2];            // [0] batched (det = -1), [1] single detector
+    int32_t *d_flag = nullptr;
+
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    double total_ms = 0.0;
+    int64_t launches = 0;
+};
+
+namespace {
+
+pisco_status fail(pisco_ctx *c, pisco_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+#define HIP_TRY(ctx, call)                                                                              \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess)                                                                           \
+            return fail((ctx), PISCO_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));          \
+    } while (0)
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+size_t rec_bytes(int dtype) { return dtype == PISCO_F64 ? 32 : 16; }
+size_t el_bytes(int dtype) { return dtype == PISCO_F64 ? 8 : 4; }
+
+DetState *det_slot(pisco_ctx *c, int32_t det) {
+    if (det < 0 || det >= PISCO_MAX_DETECTORS) return nullptr;
+    if ((size_t)det >= c->dets.size()) c->dets.resize(det + 1);
+    return &c->dets[det];
+}
+
+bool det_ready(const DetState &d) { return d.has_beam && d.has_params && d.has_pointing; }
+
+void release_beam(pisco_ctx *c, int32_t det) {
+    DetState &d = c->dets[det];
+    if (d.beam_owned && d.beam) {
+        // detectors sharing this buffer lose their beam
+        for (size_t k = 0; k < c->dets.size(); ++k)
+            if ((int32_t)k != det && c->dets[k].beam == d.beam && !c->dets[k].beam_owned) {
+                c->dets[k].beam = nullptr;
+                c->dets[k].has_beam = false;
+            }
+        (void)hipFree(d.beam);
+    }
+    d.beam = nullptr;
+    d.beam_owned = false;
+    d.has_beam = false;
+}
+
+void release_pointing(DetState &d) {
+    if (d.owned_pointing) (void)hipFree(d.owned_pointing);
+    d.owned_pointing = nullptr;
+    d.th = d.ph = d.ps = nullptr;
+    d.nsamp = 0;
+    d.has_pointing = false;
+}
+
+void drop_graph(Plan &p) {
+    if (p.gexec) (void)hipGraphExecDestroy(p.gexec);
+    p.gexec = nullptr;
+}
+
+void free_plan(Plan &p) {
+    drop_graph(p);
+    if (p.d_dets) (void)hipFree(p.d_dets);
+    if (p.d_tiles) (void)hipFree(p.d_tiles);
+    if (p.d_ctrl) (void)hipFree(p.d_ctrl);
+    p = Plan();
+}
+
+// Copy a host or device array to a fresh device buffer of `bytes`.
+pisco_status to_device(pisco_ctx *c, const void *src, size_t bytes, int mem, void **out) {
+    void *p = nullptr;
+    if (bytes == 0) {
+        *out = nullptr;
+        return PISCO_OK;
+    }
+    if (hipMalloc(&p, bytes) != hipSuccess) return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    const hipError_t e = hipMemcpy(p, src, bytes, mem == PISCO_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return fail(c, PISCO_EDEVICE, "copy to device failed: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return PISCO_OK;
+}
+
+// Interleave four n-element channels into n 16/32-byte records on the device.
+pisco_status interleave(pisco_ctx *c, const void *a, const void *b, const void *cc, const void *d, int64_t n,
+                        int dtype, int mem, void **out) {
+    const size_t eb = el_bytes(dtype);
+    void *rec = nullptr;
+    if (hipMalloc(&rec, rec_bytes(dtype) * (size_t)n) != hipSuccess)
+        return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * (size_t)n);
+    const void *src[4] = {a, b, cc, d};
+    void *tmp[4] = {nullptr, nullptr, nullptr, nullptr};
+    pisco_status st = PISCO_OK;
+    for (int k = 0; k < 4 && st == PISCO_OK; ++k) {
+        if (!src[k]) continue;
+        if (mem == PISCO_DEVICE) {
+            tmp[k] = const_cast<void *>(src[k]);
+        } else {
+            st = to_device(c, src[k], eb * (size_t)n, PISCO_HOST, &tmp[k]);
+        }
+    }
+    if (st == PISCO_OK) {
+        hipError_t e = pisco::launch_repack4(tmp[0], tmp[1], tmp[2], tmp[3], rec, n, dtype == PISCO_F64, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = fail(c, PISCO_EDEVICE, "repack failed: %s", hipGetErrorString(e));
+    }
+    if (mem == PISCO_HOST)
+        for (int k = 0; k < 4; ++k)
+            if (tmp[k]) (void)hipFree(tmp[k]);
+    if (st != PISCO_OK) {
+        (void)hipFree(rec);
+        return st;
+    }
+    *out = rec;
+    return PISCO_OK;
+}
+
+template <typename T>
+bool grow(pisco_ctx *c, T **p, size_t *cap, size_t need) {
+    if (*cap >= need) return true;
+    size_t nc = std::max(need, *cap * 2 + 16);
+    void *q = nullptr;
+    if (hipMalloc(&q, nc * sizeof(T)) != hipSuccess) return false;
+    if (*p) (void)hipFree(*p);
+    *p = static_cast<T *>(q);
+    *cap = nc;
+    (void)c;
+    return true;
+}
+
+// Build and upload the tile plan for `det` (-1 = all ready detectors).
+pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
+    if (p.gen == c->generation && p.det == det && p.spt == c->spt && p.xq == c->xq) return PISCO_OK;
+    std::vector<DetDesc> descs;
+    int64_t out_off = 0;
+    const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
+    for (int32_t k = lo; k <= hi; ++k) {
+        const DetState &d = c->dets[k];
+        if (!det_ready(d)) continue;
+        DetDesc x{};
+        x.beam = d.beam;
+        x.theta = d.th;
+        x.phi = d.ph;
+        x.psi = d.ps;
+        x.n_samples = d.nsamp;
+        x.out_offset = out_off;
+        x.zeta = d.zeta;
+        x.cos_rho_max = std::cos(d.rho_max);
+        x.cos_rho_min = std::cos(d.rho_min);
+        x.rho_max = d.rho_max;
+        x.norm_scale = d.norm_scale;
+        x.half_span_tan = d.T;
+        x.inv_h = (double)(d.n - 1) / (2.0 * d.T);
+        x.n = d.n;
+        x.norm_mode = d.norm_mode;
+        x.has_inner = d.rho_min > 0.0 ? 1 : 0;
+        descs.push_back(x);
+        out_off += d.nsamp;
+    }
+    // tiles in (detector, time) order, then split into contiguous queue blocks
+    std::vector<Tile> tiles;
+    for (size_t i = 0; i < descs.size(); ++i)
+        for (int64_t b = 0; b < descs[i].n_samples; b += c->spt) {
+            Tile t;
+            t.det = (int32_t)i;
+            t.begin = b;
+            t.count = (int32_t)std::min<int64_t>(c->spt, descs[i].n_samples - b);
+            tiles.push_back(t);
+        }
+    const int nq = std::max<int32_t>(1, std::min<int32_t>(c->xq, 8));
+    const size_t ntile = tiles.size();
+    const int32_t per = std::max<int32_t>(1, (int32_t)((ntile + nq - 1) / nq));
+    std::vector<Tile> qt((size_t)per * nq);
+    int32_t ctrl[16] = {0};
+    for (int q = 0; q < nq; ++q) {
+        const size_t b = std::min(ntile, (size_t)q * per), e = std::min(ntile, b + per);
+        for (size_t i = b; i < e; ++i) qt[(size_t)q * per + (i - b)] = tiles[i];
+        ctrl[8 + q] = (int32_t)(e - b);
+    }
+    hipError_t e = hipDeviceSynchronize();  // no launch may still read the old plan
+    if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "synchronise failed: %s", hipGetErrorString(e));
+    if (!p.d_ctrl && hipMalloc(&p.d_ctrl, 16 * sizeof(int32_t)) != hipSuccess)
+        return fail(c, PISCO_ENOMEM, "plan allocation failed");
+    if (!grow(c, &p.d_dets, &p.d_dets_cap, std::max<size_t>(descs.size(), 1)) ||
+        !grow(c, &p.d_tiles, &p.d_tiles_cap, qt.size()))
+        return fail(c, PISCO_ENOMEM, "plan allocation failed");
+    if (!descs.empty()) HIP_TRY(c, hipMemcpy(p.d_dets, descs.data(), descs.size() * sizeof(DetDesc), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(p.d_tiles, qt.data(), qt.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(p.d_ctrl, ctrl, sizeof(ctrl), hipMemcpyHostToDevice));
+    p.gen = c->generation;
+    p.det = det;
+    p.spt = c->spt;
+    p.xq = c->xq;
+    p.tiles_per_queue = per;
+    p.queues = nq;
+    p.out_samples = out_off;
+    drop_graph(p);
+    return PISCO_OK;
+}
+
+ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode) {
+    ConvArgs a{};
+    a.sky = c->sky;
+    a.dets = p.d_dets;
+    a.tiles = p.d_tiles;
+    a.counters = p.d_ctrl;
+    a.queue_len = p.d_ctrl + 8;
+    a.out = out;
+    a.nside = c->nside;
+    a.n_queues = p.queues;
+    a.tiles_per_queue = p.tiles_per_queue;
+    a.out_mode = out_mode;
+    return a;
+}
+
+hipError_t enqueue(pisco_ctx *c, const Plan &p, const ConvArgs &a, hipStream_t s) {
+    hipError_t e = pisco::launch_zero_counters(p.d_ctrl, 8, s);
+    if (e != hipSuccess) return e;
+    return pisco::launch_conv(a, c->sky_dtype == PISCO_F64, c->wpg, c->gpc * c->num_cu, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pisco_abi_version(void) { return 100; }
+
+pisco_status pisco_create(int device, pisco_ctx **out) {
+    if (!out) return PISCO_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PISCO_EINVAL;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return PISCO_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return PISCO_EUNSUPPORTED;
+    if (hipSetDevice(device) != hipSuccess) return PISCO_EDEVICE;
+    pisco_ctx *c = new pisco_ctx();
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->d_flag, sizeof(int32_t)) != hipSuccess) {
+        delete c;
+        return PISCO_ENOMEM;
+    }
+    *out = c;
+    return PISCO_OK;
+}
+
+void pisco_destroy(pisco_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &p : c->plans) free_plan(p);
+    for (auto &t : c->pending) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (size_t k = 0; k < c->dets.size(); ++k) {
+        release_beam(c, (int32_t)k);
+        release_pointing(c->dets[k]);
+    }
+    if (c->sky) (void)hipFree(c->sky);
+    if (c->d_flag) (void)hipFree(c->d_flag);
+    delete c;
+}
+
+const char *pisco_last_error(const pisco_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+pisco_status pisco_set_sky(pisco_ctx *c, int64_t nside, const void *I, const void *Q, const void *U, int dtype,
+                           int mem) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (!is_pow2(nside) || nside > PISCO_MAX_NSIDE) return fail(c, PISCO_EINVAL, "nside %lld is not a power of two in [1, %d]", (long long)nside, PISCO_MAX_NSIDE);
+    if (dtype != PISCO_F32 && dtype != PISCO_F64) return fail(c, PISCO_EINVAL, "bad dtype %d", dtype);
+    if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
+    if (!I || !Q || !U) return fail(c, PISCO_EINVAL, "null map");
+    HIP_TRY(c, hipSetDevice(c->device));
+    void *rec = nullptr;
+    const pisco_status st = interleave(c, I, Q, U, nullptr, 12 * nside * nside, dtype, mem, &rec);
+    if (st != PISCO_OK) return st;
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (c->sky) (void)hipFree(c->sky);
+    c->sky = rec;
+    c->nside = nside;
+    c->sky_dtype = dtype;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_beam(pisco_ctx *c, int32_t det, int32_t n, double T, const void *bI, const void *bQ,
+                            const void *bU, const void *bT, int dtype, int mem) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    DetState *d = det_slot(c, det);
+    if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    if (n < 3 || n > 8191 || (n % 2) == 0) return fail(c, PISCO_EINVAL, "grid size %d must be odd in [3, 8191]", n);
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(c, PISCO_EINVAL, "half_span_tan must be finite and > 0");
+    if (dtype != PISCO_F32 && dtype != PISCO_F64) return fail(c, PISCO_EINVAL, "bad dtype %d", dtype);
+    if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
+    if (!bI || !bQ || !bU || !bT) return fail(c, PISCO_EINVAL, "null beam channel");
+    HIP_TRY(c, hipSetDevice(c->device));
+    void *rec = nullptr;
+    const pisco_status st = interleave(c, bI, bQ, bU, bT, (int64_t)n * n, dtype, mem, &rec);
+    if (st != PISCO_OK) return st;
+    HIP_TRY(c, hipDeviceSynchronize());
+    release_beam(c, det);
+    d = &c->dets[det];
+    d->beam = rec;
+    d->beam_owned = true;
+    d->n = n;
+    d->T = T;
+    d->beam_dtype = dtype;
+    d->has_beam = true;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_share_beam(pisco_ctx *c, int32_t det, int32_t src) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (src < 0 || (size_t)src >= c->dets.size() || !c->dets[src].has_beam || !c->dets[src].beam_owned)
+        return fail(c, PISCO_EINVAL, "detector %d has no beam of its own to share", src);
+    if (det == src) return PISCO_OK;
+    DetState *d = det_slot(c, det);
+    if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    HIP_TRY(c, hipDeviceSynchronize());
+    release_beam(c, det);
+    d = &c->dets[det];
+    const DetState &s = c->dets[src];
+    d->beam = s.beam;
+    d->beam_owned = false;
+    d->n = s.n;
+    d->T = s.T;
+    d->beam_dtype = s.beam_dtype;
+    d->has_beam = true;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_detector(pisco_ctx *c, int32_t det, double zeta, double rho_min, double rho_max,
+                                int norm_mode, double norm_scale) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    DetState *d = det_slot(c, det);
+    if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    if (!std::isfinite(zeta) || !std::isfinite(norm_scale)) return fail(c, PISCO_EINVAL, "non-finite parameter");
+    if (!(rho_min >= 0.0) || !(rho_max > rho_min) || !(rho_max < 0.5 * M_PI))
+        return fail(c, PISCO_EINVAL, "need 0 <= rho_min < rho_max < pi/2 (got %g, %g)", rho_min, rho_max);
+    if (norm_mode != PISCO_NORM_FIXED && norm_mode != PISCO_NORM_PER_SAMPLE)
+        return fail(c, PISCO_EINVAL, "bad norm_mode %d", norm_mode);
+    d->zeta = zeta;
+    d->rho_min = rho_min;
+    d->rho_max = rho_max;
+    d->norm_mode = norm_mode;
+    d->norm_scale = norm_scale;
+    d->has_params = true;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_pointing(pisco_ctx *c, int32_t det, int64_t n, const double *theta, const double *phi,
+                                const double *psi, int mem) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    DetState *d = det_slot(c, det);
+    if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(c, PISCO_EINVAL, "bad sample count");
+    if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
+    if (n > 0 && (!theta || !phi || !psi)) return fail(c, PISCO_EINVAL, "null pointing array");
+    HIP_TRY(c, hipSetDevice(c->device));
+    if (mem == PISCO_HOST) {
+        for (int64_t i = 0; i < n; ++i) {
+            const double t = theta[i];
+            if (!std::isfinite(t) || t < 0.0 || t > M_PI || !std::isfinite(phi[i]) || !std::isfinite(psi[i]))
+                return fail(c, PISCO_EINVAL, "pointing sample %lld is non-finite or has theta outside [0, pi]", (long long)i);
+        }
+        double *buf = nullptr;
+        if (n > 0) {
+            if (hipMalloc(&buf, 3 * sizeof(double) * (size_t)n) != hipSuccess)
+                return fail(c, PISCO_ENOMEM, "pointing allocation failed");
+            const size_t b = sizeof(double) * (size_t)n;
+            hipError_t e = hipMemcpy(buf, theta, b, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(buf + n, phi, b, hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(buf + 2 * n, psi, b, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipFree(buf);
+                return fail(c, PISCO_EDEVICE, "pointing copy failed: %s", hipGetErrorString(e));
+            }
+        }
+        HIP_TRY(c, hipDeviceSynchronize());
+        release_pointing(*d);
+        d->owned_pointing = buf;
+        d->th = buf;
+        d->ph = buf ? buf + n : nullptr;
+        d->ps = buf ? buf + 2 * n : nullptr;
+    } else {
+        if (n > 0) {
+            HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int32_t)));
+            HIP_TRY(c, pisco::launch_check_pointing(theta, phi, psi, n, c->d_flag, nullptr));
+            int32_t bad = 0;
+            HIP_TRY(c, hipMemcpy(&bad, c->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+            if (bad) return fail(c, PISCO_EINVAL, "pointing holds non-finite values or theta outside [0, pi]");
+        }
+        HIP_TRY(c, hipDeviceSynchronize());
+        release_pointing(*d);
+        d->th = theta;
+        d->ph = phi;
+        d->ps = psi;
+    }
+    d->nsamp = n;
+    d->has_pointing = true;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+int64_t pisco_output_samples(const pisco_ctx *c, int32_t det) {
+    if (!c) return -1;
+    if (det >= 0) return ((size_t)det < c->dets.size() && det_ready(c->dets[det])) ? c->dets[det].nsamp : 0;
+    int64_t s = 0;
+    for (const auto &d : c->dets)
+        if (det_ready(d)) s += d.nsamp;
+    return s;
+}
+
+pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, int mem, void *stream) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (!c->sky) return fail(c, PISCO_ESTATE, "no sky set");
+    if (out_mode != PISCO_OUT_TOD && out_mode != PISCO_OUT_STOKES) return fail(c, PISCO_EINVAL, "bad out_mode %d", out_mode);
+    if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
+    if (det < -1) return fail(c, PISCO_EINVAL, "bad detector %d", det);
+    if (det >= 0) {
+        if ((size_t)det >= c->dets.size() || !det_ready(c->dets[det]))
+            return fail(c, PISCO_ESTATE, "detector %d lacks a beam, parameters or pointing", det);
+    }
+    bool any = false;
+    const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
+    for (int32_t k = lo; k <= hi; ++k) {
+        const DetState &d = c->dets[k];
+        if (!det_ready(d)) continue;
+        any = true;
+        if (d.beam_dtype != c->sky_dtype)
+            return fail(c, PISCO_EINVAL, "detector %d beam dtype differs from the sky dtype", k);
+    }
+    if (!any) return fail(c, PISCO_ESTATE, "no detector is ready");
+    HIP_TRY(c, hipSetDevice(c->device));
+    Plan &p = c->plans[det < 0 ? 0 : 1];
+    pisco_status st = prepare_plan(c, p, det);
+    if (st != PISCO_OK) return st;
+    const int64_t nout = p.out_samples * (out_mode == PISCO_OUT_STOKES ? 3 : 1);
+    if (nout == 0) return PISCO_OK;
+    if (!out) return fail(c, PISCO_EINVAL, "null output");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    void *dout = out;
+    if (mem == PISCO_HOST) {
+        s = nullptr;
+        if (hipMalloc(&dout, el_bytes(c->sky_dtype) * (size_t)nout) != hipSuccess)
+            return fail(c, PISCO_ENOMEM, "output staging allocation failed");
+    }
+    const ConvArgs a = make_args(c, p, dout, out_mode);
+    TimedLaunch tl{};
+    if (c->timing) {
+        HIP_TRY(c, hipEventCreate(&tl.a));
+        HIP_TRY(c, hipEventCreate(&tl.b));
+        HIP_TRY(c, hipEventRecord(tl.a, s));
+    }
+    hipError_t e = hipSuccess;
+    const bool use_graph = (det < 0) && (s != nullptr);
+    if (use_graph) {
+        if (!p.gexec || p.g_gen != p.gen || p.g_out != dout || p.g_stream != s || p.g_mode != out_mode ||
+            p.g_wpg != c->wpg || p.g_gpc != c->gpc) {
+            drop_graph(p);
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t e1 = enqueue(c, p, a, s);
+                e = hipStreamEndCapture(s, &g);
+                if (e1 != hipSuccess) e = e1;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&p.gexec, g, nullptr, nullptr, 0);
+            if (g) (void)hipGraphDestroy(g);
+            if (e == hipSuccess) {
+                p.g_gen = p.gen;
+                p.g_out = dout;
+                p.g_stream = s;
+                p.g_mode = out_mode;
+                p.g_wpg = c->wpg;
+                p.g_gpc = c->gpc;
+            } else {
+                p.gexec = nullptr;
+            }
+        }
+        if (e == hipSuccess) e = hipGraphLaunch(p.gexec, s);
+    } else {
+        e = enqueue(c, p, a, s);
+    }
+    if (e != hipSuccess) {
+        if (mem == PISCO_HOST) (void)hipFree(dout);
+        return fail(c, PISCO_EDEVICE, "convolution launch failed: %s", hipGetErrorString(e));
+    }
+    if (c->timing) {
+        HIP_TRY(c, hipEventRecord(tl.b, s));
+        c->pending.push_back(tl);
+    }
+    if (mem == PISCO_HOST) {
+        e = hipMemcpy(out, dout, el_bytes(c->sky_dtype) * (size_t)nout, hipMemcpyDeviceToHost);
+        (void)hipFree(dout);
+        if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "output copy failed: %s", hipGetErrorString(e));
+    }
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_launch(pisco_ctx *c, int32_t spt, int32_t wpg, int32_t gpc, int32_t xq) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (spt < 0 || spt > 65536) return fail(c, PISCO_EINVAL, "samples_per_tile out of range");
+    if (wpg != 0 && wpg != 1 && wpg != 2 && wpg != 4 && wpg != 8) return fail(c, PISCO_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+    if (gpc < 0 || gpc > 16) return fail(c, PISCO_EINVAL, "groups_per_cu out of range");
+    if (xq != 0 && xq != 1 && xq != 8) return fail(c, PISCO_EINVAL, "xcd_queues must be 1 or 8");
+    if (spt) c->spt = spt;
+    if (wpg) c->wpg = wpg;
+    if (gpc) c->gpc = gpc;
+    if (xq) c->xq = xq;
+    return PISCO_OK;
+}
+
+pisco_status pisco_get_launch(const pisco_ctx *c, int32_t *spt, int32_t *wpg, int32_t *gpc, int32_t *xq) {
+    if (!c) return PISCO_EINVAL;
+    if (spt) *spt = c->spt;
+    if (wpg) *wpg = c->wpg;
+    if (gpc) *gpc = c->gpc;
+    if (xq) *xq = c->xq;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_timing(pisco_ctx *c, int on) {
+    if (!c) return PISCO_EINVAL;
+    c->timing = on != 0;
+    return PISCO_OK;
+}
+
+pisco_status pisco_kernel_time(pisco_ctx *c, double *total_ms, int64_t *launches, int reset) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    for (auto &t : c->pending) {
+        HIP_TRY(c, hipEventSynchronize(t.b));
+        float ms = 0.0f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, t.a, t.b));
+        c->total_ms += ms;
+        c->launches += 1;
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    c->pending.clear();
+    if (total_ms) *total_ms = c->total_ms;
+    if (launches) *launches = c->launches;
+    if (reset) {
+        c->total_ms = 0.0;
+        c->launches = 0;
+    }
+    return PISCO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,237 @@
+"""GPU parity of the HIP convolution against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import beams as B
+from synth import scans as S
+from synth import workloads as W
+from synth.workloads import Detector, Workload
+
+from gpu_helpers import load_workload, oracle_detector, rel_err, say
+
+pytestmark = pytest.mark.gpu
+D2R = np.pi / 180
+F64_TOL = 1e-12
+F32_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    return t
+
+
+@pytest.fixture()
+def conv(torch):
+    from paper_1908_05662_amd.api import Convolver
+
+    c = Convolver(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def test_c1_fp64_full_stream(conv, torch):
+    """configs[0] at full size: 1e5 samples, FP64 kernel, every sample vs the oracle."""
+    say("case: c1 fp64 1e5 samples")
+    w = W.c1()
+    load_workload(conv, w, np.float64)
+    got = conv.convolve(0).cpu().numpy()
+    want = oracle_detector(w, 0, slice(None), np.float64)
+    e = rel_err(got, want)
+    say(f"c1 fp64 max rel err {e:.3e}")
+    assert e <= F64_TOL
+
+
+def test_c1_fp32_mixed(conv, torch):
+    say("case: c1 fp32 2e4 samples")
+    w = W.c1(n_samples=20000)
+    load_workload(conv, w, np.float32)
+    got = conv.convolve(0).cpu().numpy()
+    want = oracle_detector(w, 0, slice(None), np.float32)
+    e = rel_err(got, want)
+    say(f"c1 fp32 max rel err {e:.3e}")
+    assert e <= F32_TOL
+
+
+def test_c2_fp32_sampled(conv, torch):
+    """configs[1] shape (nside 512, 201^2 elliptical beam, CES) on 2e5 samples;
+    the oracle checks an evenly spread subset."""
+    say("case: c2 fp32 2e5 samples, 1500 checked")
+    w = W.c2(n_samples=200_000)
+    load_workload(conv, w, np.float32)
+    got = conv.convolve(0).cpu().numpy()
+    idx = np.linspace(0, w.detectors[0].n - 1, 1500).astype(np.int64)
+    want = oracle_detector(w, 0, idx, np.float32)
+    e = rel_err(got[idx], want)
+    say(f"c2 fp32 max rel err {e:.3e}")
+    assert e <= F32_TOL
+
+
+def _small_workload(nside, dets, seed=0):
+    from synth.sky import make_sky
+
+    sky = tuple(make_sky(nside, 3 * nside - 1, 2.0, seed=seed))
+    return Workload("edge", nside, sky, dets)
+
+
+def _det(bs, th, ph, ps, zeta=0.3, eps=0.02, s=1.1, rmin=0.0, rmax=0.1, norm=W.NORM_PER_SAMPLE, scale=1.0):
+    return Detector(bs, B.DetectorParams(zeta, eps, s), rmin, rmax, norm, scale, np.asarray(th, float),
+                    np.asarray(ph, float), np.asarray(ps, float))
+
+
+def _gauss(n, span_deg, fwhm_deg, e=0.1, o=0.5, leak=0.01):
+    T, u, v, rho, sig = B.tangent_grid(n, span_deg * D2R)
+    g = B.elliptical_gaussian(rho, sig, fwhm_deg * D2R, e, o)
+    return B.with_qu_leakage(B.ideal_beamsor(g, T), g, leak)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, F64_TOL), (np.float32, F32_TOL)])
+def test_edge_geometry(conv, torch, dtype, tol):
+    """Poles inside the disc, boresight exactly on a pole, longitude wrap-around,
+    negative / >2pi longitudes, full rings, coarse maps with wide discs."""
+    say(f"case: edge geometry {np.dtype(dtype).name}")
+    rng = np.random.default_rng(4)
+    th = np.concatenate([[0.0, np.pi, 1e-9, np.pi - 1e-9, 0.05, np.pi - 0.05, 1.0, 2.0],
+                         np.arccos(rng.uniform(-1, 1, 24))])
+    ph = np.concatenate([[0.0, 1.0, 2 * np.pi - 1e-12, -0.3, 7.0, -12.0, 2 * np.pi, 1e-13],
+                         rng.uniform(-10, 10, 24)])
+    ps = rng.uniform(-7, 7, th.size)
+    for nside, span, fwhm, rmax in [(1, 60.0, 40.0, 59.0), (2, 50.0, 30.0, 50.0), (8, 20.0, 8.0, 20.0),
+                                    (32, 10.0, 3.0, 10.0)]:
+        bs = _gauss(81, span, fwhm)
+        w = _small_workload(nside, [_det(bs, th, ph, ps, rmax=rmax * D2R)], seed=nside)
+        load_workload(conv, w, dtype)
+        got = conv.convolve(0).cpu().numpy()
+        want = oracle_detector(w, 0, slice(None), dtype)
+        e = rel_err(got, want)
+        say(f"  nside {nside}: max rel err {e:.3e}")
+        assert e <= tol, (nside, e)
+
+
+@pytest.mark.parametrize("dtype,tol", [(np.float64, F64_TOL), (np.float32, F32_TOL)])
+def test_annulus_stokes_fixed(conv, torch, dtype, tol):
+    """Annulus selection, the Stokes-pickup output and FIXED normalisation; the
+    disc = inner disc + annulus partition holds on the GPU too."""
+    say(f"case: annulus/stokes {np.dtype(dtype).name}")
+    rng = np.random.default_rng(5)
+    n = 200
+    th, ph, ps = np.arccos(rng.uniform(-1, 1, n)), rng.uniform(0, 2 * np.pi, n), rng.uniform(0, 2 * np.pi, n)
+    th[:3] = [0.0, 0.02, np.pi]
+    T, u, v, rho, sig = B.tangent_grid(161, 20 * D2R)
+    g = B.elliptical_gaussian(rho, sig, 2 * D2R) + B.ring_lobe(rho, 10 * D2R, 2 * D2R, 1e-2)
+    bs = B.ideal_beamsor(g, T)
+    nside = 32
+    dets = [_det(bs, th, ph, ps, zeta=0.0, eps=0.0, s=1.0, rmin=r0, rmax=r1, norm=W.NORM_FIXED, scale=1e-3)
+            for r0, r1 in [(0.0, 20 * D2R), (0.0, 5 * D2R), (5 * D2R, 20 * D2R)]]
+    w = _small_workload(nside, dets, seed=7)
+    load_workload(conv, w, dtype)
+    for mode in (oracle.OUT_TOD, oracle.OUT_STOKES):
+        outs = []
+        for k in range(3):
+            got = conv.convolve(k, out_mode=mode).cpu().numpy()
+            want = oracle_detector(w, k, slice(None), dtype, out_mode=mode)
+            e = rel_err(got, want)
+            say(f"  det {k} mode {mode}: max rel err {e:.3e}")
+            assert e <= tol
+            outs.append(got.astype(np.float64))
+        assert rel_err(outs[1] + outs[2], outs[0]) <= 10 * tol
+
+
+def test_delta_and_uniform_closed_forms(conv, torch):
+    say("case: delta beam and uniform sky")
+    nside = 64
+    pix = np.array([0, 7, 1000, 24575, 30000, 49151])
+    th, ph = oracle.pix2ang(nside, pix)
+    rng = np.random.default_rng(1)
+    ps = rng.uniform(0, 2 * np.pi, pix.size)
+    bs = B.delta_beamsor(41, 0.005)
+    w = _small_workload(nside, [_det(bs, th, ph, ps, zeta=0.4, eps=0.1, s=2.0, rmax=np.arctan(0.005))], seed=3)
+    load_workload(conv, w, np.float64)
+    got = conv.convolve(0).cpu().numpy()
+    I, Q, U = (m[pix] for m in w.sky)
+    want = 0.5 * 2.0 * (1.1 * I + 0.9 * (Q * np.cos(2 * (ps + 0.4)) + U * np.sin(2 * (ps + 0.4))))
+    # pixel-centre pointings land within ~1e-16 rad of the centre node: f ~ 1e-12
+    assert np.abs(got - want).max() < 1e-11
+    one = np.ones(12 * nside * nside)
+    w2 = Workload("u", nside, (one, 0 * one, 0 * one),
+                  [_det(_gauss(101, 4.5, 1.5, leak=0.0), np.arccos(rng.uniform(-1, 1, 500)),
+                        rng.uniform(0, 6.3, 500), rng.uniform(0, 6.3, 500), eps=0.0, s=2.0, rmax=4.5 * D2R)])
+    for dtype, tol in [(np.float64, 1e-14), (np.float32, 2e-7)]:
+        load_workload(conv, w2, dtype)
+        got = conv.convolve(0).cpu().numpy()
+        assert np.abs(got - 1.0).max() < tol, dtype
+
+
+def test_psi_plus_pi_and_determinism(conv, torch):
+    say("case: psi+pi, determinism, launch shapes")
+    w = W.c1(n_samples=4000)
+    d = w.detectors[0]
+    load_workload(conv, w, np.float32)
+    a = conv.convolve(0).cpu().numpy()
+    b = conv.convolve(0).cpu().numpy()
+    assert np.array_equal(a, b)
+    for shape in [(1, 1, 1, 1), (7, 2, 3, 8), (256, 8, 1, 1), (64, 4, 2, 8)]:
+        conv.set_launch(*shape)
+        c = conv.convolve(0).cpu().numpy()
+        assert np.array_equal(a, c), shape
+    conv.set_pointing(0, *(torch.from_numpy(x).cuda() for x in (d.theta, d.phi, d.psi + np.pi)))
+    e = conv.convolve(0).cpu().numpy()
+    assert rel_err(e, a) <= 2e-6
+
+
+def test_empty_and_invalid_inputs(conv, torch):
+    from paper_1908_05662_amd import PiscoError
+
+    say("case: empty and invalid inputs")
+    w = W.c1(n_samples=10)
+    load_workload(conv, w, np.float64)
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    conv.set_pointing(0, e, e, e)
+    assert conv.output_samples(0) == 0
+    out = conv.convolve(0)
+    assert out.numel() == 0
+    bad = torch.tensor([np.nan], dtype=torch.float64, device="cuda")
+    one = torch.zeros(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(PiscoError):
+        conv.set_pointing(0, bad, one, one)
+    with pytest.raises(PiscoError):
+        conv.set_pointing(0, one + 4.0, one, one)  # theta > pi
+    with pytest.raises(PiscoError):
+        conv.set_detector(0, 0.0, 0.0, 2.0, 0, 1.0)  # rho_max >= pi/2
+    with pytest.raises(PiscoError):
+        conv.set_sky(3, one, one, one)  # nside not a power of two
+    # a failed call leaves the previous state usable
+    assert conv.output_samples(0) == 0
+
+
+def test_batched_graph_replay_matches_per_detector(conv, torch):
+    """All detectors in one persistent launch, captured once and replayed; every
+    replay (with eager launches in between) equals the per-detector launches."""
+    say("case: batched graph replay")
+    rng = np.random.default_rng(8)
+    nside = 64
+    dets = []
+    for k in range(6):
+        n = int(rng.integers(1, 3000))
+        th, ph, ps = np.arccos(rng.uniform(-1, 1, n)), rng.uniform(0, 6.3, n), rng.uniform(0, 6.3, n)
+        dets.append(_det(_gauss(61, 3.0 + k * 0.3, 1.0 + 0.1 * k, e=0.05 * k, o=k), th, ph, ps,
+                         zeta=0.3 * k, rmax=(3.0 + 0.3 * k) * D2R))
+    w = _small_workload(nside, dets, seed=11)
+    load_workload(conv, w, np.float32)
+    ref = np.concatenate([conv.convolve(k).cpu().numpy() for k in range(6)])
+    s = torch.cuda.Stream()
+    out = torch.empty(conv.output_samples(-1), dtype=torch.float32, device="cuda")
+    for rep in range(4):
+        with torch.cuda.stream(s):
+            out.fill_(np.nan)
+            conv.convolve(-1, out=out, stream=s)
+        s.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), rep
+        _ = conv.convolve(2).cpu()  # eager work between replays
+    idx = np.arange(0, len(dets[3].theta), 97)
+    off = sum(len(d.theta) for d in dets[:3])
+    want = oracle_detector(w, 3, idx, np.float32)
+    assert rel_err(ref[off + idx], want) <= F32_TOL
