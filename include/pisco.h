@@ -64,7 +64,7 @@ typedef enum {
 enum { PISCO_F32 = 0, PISCO_F64 = 1 };
 enum { PISCO_HOST = 0, PISCO_DEVICE = 1 };
 enum { PISCO_NORM_FIXED = 0, PISCO_NORM_PER_SAMPLE = 1 };
-enum { PISCO_OUT_TOD = 0, PISCO_OUT_STOKES = 1 };
+enum { PISCO_OUT_TOD = 0, PISCO_OUT_STOKES = 1, PISCO_OUT_COUNT = 2 };
 
 #define PISCO_MAX_DETECTORS 4096
 #define PISCO_MAX_NSIDE 8192
@@ -140,7 +140,9 @@ pisco_status pisco_set_pointing(pisco_ctx *ctx, int32_t det, int64_t n, const do
  * the configuration and output buffer are unchanged), outputs concatenated in
  * ascending detector order.  out_mode TOD writes one value per sample;
  * STOKES writes three per sample ([t][3]: N sum bT Lambda(-chi) S restricted
- * to I, Q, U, the detector-frame Stokes pickup of the scalar beam bT).
+ * to I, Q, U, the detector-frame Stokes pickup of the scalar beam bT);
+ * COUNT writes, per sample, the number of sky pixels selected (the pairs the
+ * sum runs over, as a floating value), without evaluating them.
  * `out` holds elements of the sky's dtype; mem = DEVICE: written
  * asynchronously on `stream` (a hipStream_t, NULL = default stream);
  * mem = HOST: the call synchronises and copies.

@@ -6,8 +6,8 @@ package is the thin Python binding (``Convolver``) plus host-side beam
 preparation.  There is no CPU fallback: without ``libpisco.so`` and a
 gfx950 device every call raises.
 """
-from ._lib import (DEVICE, F32, F64, HOST, NORM_FIXED, NORM_PER_SAMPLE, OUT_STOKES, OUT_TOD,  # noqa: F401
-                   PiscoError)
+from ._lib import (DEVICE, F32, F64, HOST, NORM_FIXED, NORM_PER_SAMPLE, OUT_COUNT, OUT_STOKES,  # noqa: F401
+                   OUT_TOD, PiscoError)
 from .beamsor import fold_detector, fold_elements, grid_solid_angle  # noqa: F401
 
 

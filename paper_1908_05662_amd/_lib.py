@@ -11,7 +11,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSUPPORTED = range(6)
 F32, F64 = 0, 1
 HOST, DEVICE = 0, 1
 NORM_FIXED, NORM_PER_SAMPLE = 0, 1
-OUT_TOD, OUT_STOKES = 0, 1
+OUT_TOD, OUT_STOKES, OUT_COUNT = 0, 1, 2
 
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",
            EUNSUPPORTED: "EUNSUPPORTED"}

@@ -208,6 +208,10 @@ __device__ inline int wave_inclusive_scan(int v, int lane) {
 
 template <typename T> __device__ inline T lerp(T a, T b, T t) { return fma(t, b - a, a); }
 
+// Reciprocal: the hardware approximation (1 ulp) in FP32, exact division in FP64.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp(double x) { return 1.0 / x; }
+
 // ----------------------------------------------------------------------
 // The kernel
 // ----------------------------------------------------------------------
@@ -239,6 +243,7 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
     const int32_t r_hi = (th0 + rho >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, th0 + rho)) + 1);
 
     Acc<T> acc0, acc1, acc2, accn;
+    int64_t npairs = 0;
 
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
         const int32_t r = rb + lane;
@@ -300,6 +305,10 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
         L.seg_end[2 * lane] = excl + n0;
         L.seg_end[2 * lane + 1] = incl;
         const int32_t total = __shfl(incl, WAVE - 1, WAVE);
+        if (MODE == 2) {  // disc pixel count only
+            npairs += total;
+            continue;
+        }
         wave_sync();
 
         int32_t seg = 0;
@@ -329,7 +338,7 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
             const T omz = fma(R.c, h, R.e);        // 1 - n . p0
             const T xp = fma(cpsi, nth, spsi * nph);
             const T yp = fma(-spsi, nth, cpsi * nph);
-            const T rz = (T)1 / ((T)1 - omz);
+            const T rz = rcp((T)1 - omz);
             const T tu = fma(xp * rz, inv_h, c0);
             const T tv = fma(yp * rz, inv_h, c0);
             if (!(tu >= (T)0 && tu <= tmax && tv >= (T)0 && tv <= tmax)) continue;
@@ -343,7 +352,7 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
             // co-polar direction carried along the great circle, projected on
             // the pixel's theta_hat / phi_hat (all in the boresight sky basis)
             const T w = fma(g1, nth, g2 * nph);
-            const T q = w / ((T)2 - omz);
+            const T q = w * rcp((T)2 - omz);
             const T eth = fma(-q, nth, g1);
             const T eph = fma(-q, nph, g2);
             const T cth = fma(-R.f, h, R.cdt);      // theta_hat_k . theta_hat0
@@ -371,6 +380,10 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
         wave_sync();
     }
 
+    if (MODE == 2) {
+        if (lane == 0) reinterpret_cast<T *>(A.out)[D.out_offset + t] = (T)npairs;
+        return;
+    }
     accn.wave_reduce();
     acc0.wave_reduce();
     if (MODE == 1) {
@@ -457,8 +470,10 @@ static hipError_t launch_conv_t(const ConvArgs &a, int waves, int groups, hipStr
     const size_t lds = sizeof(WaveLds<T>) * (size_t)waves;
     if (a.out_mode == 0)
         hipLaunchKernelGGL((conv_kernel<T, 0>), dim3(groups), dim3(WAVE * waves), lds, s, a);
-    else
+    else if (a.out_mode == 1)
         hipLaunchKernelGGL((conv_kernel<T, 1>), dim3(groups), dim3(WAVE * waves), lds, s, a);
+    else
+        hipLaunchKernelGGL((conv_kernel<T, 2>), dim3(groups), dim3(WAVE * waves), lds, s, a);
     return hipGetLastError();
 }
 

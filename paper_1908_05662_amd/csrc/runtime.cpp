@@ -516,7 +516,8 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
     if (!c) return PISCO_EINVAL;
     c->err.clear();
     if (!c->sky) return fail(c, PISCO_ESTATE, "no sky set");
-    if (out_mode != PISCO_OUT_TOD && out_mode != PISCO_OUT_STOKES) return fail(c, PISCO_EINVAL, "bad out_mode %d", out_mode);
+    if (out_mode != PISCO_OUT_TOD && out_mode != PISCO_OUT_STOKES && out_mode != PISCO_OUT_COUNT)
+        return fail(c, PISCO_EINVAL, "bad out_mode %d", out_mode);
     if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
     if (det < -1) return fail(c, PISCO_EINVAL, "bad detector %d", det);
     if (det >= 0) {
