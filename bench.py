@@ -74,9 +74,10 @@ def cpu_baseline(w, got, seconds):
             tot_s += idx.size
         return tot_s, errs
 
+    # calibrate on a pass large enough to keep every host thread busy
     t = time.perf_counter()
-    run(1)
-    per_sample = (time.perf_counter() - t) / len(w.detectors)
+    n_cal, _ = run(max(2, oracle.max_threads() // 4))
+    per_sample = (time.perf_counter() - t) / n_cal
     per_det = int(max(2, min(2000, seconds / max(per_sample, 1e-6) / len(w.detectors))))
     t = time.perf_counter()
     n, errs = run(per_det)
