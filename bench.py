@@ -23,15 +23,18 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per (sample, disc pixel) pair of the mixed-precision TOD
-# kernel, counted from the pair arithmetic of the formulation (FMA = 2 flops):
-# longitude offset 3, half-angle sin/cos polynomials 29, h and sin(dphi) 4,
-# offsets from the boresight 5, antenna-frame rotation 6, gnomonic projection 3,
-# grid coordinates and fractions 12, position angle (co-polar vector carried
-# along the great circle, projected on the pixel basis, doubled) 34, bilinear
-# interpolation of 4 channels 36, Stokes rotation 6, contraction 5, two
-# compensated accumulations 12.
-FLOPS_PER_PAIR = 155
+# Algorithmic work per (sample, disc pixel) pair, counted from each path's pair
+# arithmetic (FMA = 2 flops; reciprocals, compares and conversions count 1):
+#  tile path, one-grid beam, TOD: FP64 membership 1 - n.p 6, FP64 rotation into
+#  the antenna frame 12, gnomonic projection 2, grid coordinates 6, fractions 2,
+#  bilinear 9, position angle (co-polar vector carried along the great circle,
+#  projected on the pixel basis, doubled) 32, contraction 5, two compensated
+#  accumulations 12 -> 86.
+#  pixel path, four-channel beam, TOD: longitude offset 3, half-angle sin/cos
+#  polynomials 29, h and sin(dphi) 4, offsets from the boresight 5, rotation 6,
+#  projection 3, grid 12, position angle 34, bilinear x4 channels 36, Stokes
+#  rotation 6, contraction 5, accumulations 12 -> 155.
+FLOPS_PER_PAIR = {(1, "scalar"): 86, (1, "full"): 113, (0, "scalar"): 128, (0, "full"): 155}
 # vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 (FMA)
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 
@@ -41,18 +44,25 @@ def log(msg):
 
 
 def load(conv, w, torch):
-    from paper_1908_05662_amd.beamsor import fold_elements
+    from paper_1908_05662_amd.beamsor import fold_elements, scalar_weights
 
     conv.set_sky(w.nside, *(torch.from_numpy(m.astype(np.float32)).cuda() for m in w.sky), dtype=torch.float32)
-    keep = []
+    keep, kinds = [], set()
     for k, d in enumerate(w.detectors):
         bI, bQ, bU, bT = fold_elements(d.beam.elements, d.beam.n, d.det.eps, d.det.s)
-        conv.set_beam(k, d.beam.n, d.beam.half_span_tan, bI, bQ, bU, bT, dtype=torch.float32)
+        wts = scalar_weights(bI, bQ, bU, bT)
+        if wts is not None:
+            conv.set_beam_scalar(k, d.beam.n, d.beam.half_span_tan, bT, *wts, 1.0, dtype=torch.float32)
+            kinds.add("scalar")
+        else:
+            conv.set_beam(k, d.beam.n, d.beam.half_span_tan, bI, bQ, bU, bT, dtype=torch.float32)
+            kinds.add("full")
         conv.set_detector(k, d.det.zeta, d.rho_min, d.rho_max, d.norm_mode, d.norm_scale)
         arrs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (d.theta, d.phi, d.psi)]
         conv.set_pointing(k, *arrs)
         keep.append(arrs)
-    return keep
+    assert len(kinds) == 1
+    return keep, kinds.pop()
 
 
 def cpu_baseline(w, got, seconds):
@@ -95,7 +105,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
-    ap.add_argument("--launch", type=str, default="", help="spt,wpg,gpc,xq")
+    ap.add_argument("--launch", type=str, default="", help="key=value,... fields of pisco_launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the path is data-parallel over "
@@ -113,9 +123,12 @@ def main():
     w = W.c3()
     log(f"workload c3: {len(w.detectors)} detectors, {w.n_samples} samples, setup {time.perf_counter() - t0:.1f}s")
     conv = Convolver(0)
-    keep = load(conv, w, torch)
+    keep, kind = load(conv, w, torch)
     if args.launch:
-        conv.set_launch(*[int(x) for x in args.launch.split(",")])
+        kv = dict(x.split("=") for x in args.launch.split(","))
+        conv.set_launch(**{k: (float(v) if k == "coherence" else int(v)) for k, v in kv.items()})
+    launch = conv.get_launch()
+    flops_per_pair = FLOPS_PER_PAIR[(launch["algorithm"], kind)]
     n = conv.output_samples(-1)
     stream = torch.cuda.Stream()
     out = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -151,7 +164,7 @@ def main():
     ms_step = wall * 1e3 / args.steps
     k_ms = kms / max(launches, 1)
     value = n / (ms_step / 1e3)
-    achieved = FLOPS_PER_PAIR * pairs / (k_ms / 1e3) / 1e12
+    achieved = flops_per_pair * pairs / (k_ms / 1e3) / 1e12
     got = out.cpu().numpy()
     log(f"{ms_step:.2f} ms/step, kernel {k_ms:.2f} ms, {value:.4g} samples/s, {pairs / (k_ms / 1e3):.4g} pairs/s")
 
@@ -182,12 +195,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "nside-1024 batched detectors: 64 dets, 201^2 elliptical beams, CES scan, "
                                "disc 2 deg (configs[2])", "samples": n, "pairs": pairs,
-                   "launch": list(conv.get_launch())},
+                   "launch": launch, "beam": kind},
         "macs_per_s": pairs / (ms_step / 1e3),
         "kernel_ms": k_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_pair": FLOPS_PER_PAIR},
+                     "flops_per_pair": flops_per_pair},
         "cpu_baseline": cpu,
         "parity_max_rel_err": parity,
     }

@@ -109,6 +109,18 @@ pisco_status pisco_set_beam(pisco_ctx *ctx, int32_t det, int32_t n, double half_
                             const void *bI, const void *bQ, const void *bU, const void *bT,
                             int dtype, int mem);
 
+/*
+ * Scalar beam of detector `det`: the Mueller field factors into one n x n grid
+ * b(u, v) (same node layout as pisco_set_beam) times constant channel weights,
+ * bI = wI b, bQ = wQ b, bU = wU b, bT = wT b -- e.g. an ideal beamsor b (x) I
+ * (Sec. 3) folded with the detector row gives wI = (s/2)(1+eps),
+ * wQ = (s/2)(1-eps), wU = 0, wT = 1.  Stored as one record per grid cell with
+ * the cell's four corners, so each bilinear lookup is a single load.  In
+ * STOKES mode the scalar beam is wT b.
+ */
+pisco_status pisco_set_beam_scalar(pisco_ctx *ctx, int32_t det, int32_t n, double half_span_tan, const void *b,
+                                   double wI, double wQ, double wU, double wT, int dtype, int mem);
+
 /* Let detector `det` use the beam of detector `src` (no copy; e.g. one shared
  * far-sidelobe grid).  `src` must already have a beam. */
 pisco_status pisco_share_beam(pisco_ctx *ctx, int32_t det, int32_t src);
@@ -153,17 +165,38 @@ pisco_status pisco_convolve(pisco_ctx *ctx, int32_t det, int out_mode, void *out
 int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
 
 /*
- * Launch shape of the convolution kernel.  samples_per_tile: consecutive
- * samples one wavefront processes before taking new work (1..65536);
- * waves_per_group: wavefronts per workgroup (1, 2, 4 or 8); groups_per_cu:
- * resident workgroups launched per compute unit (1..16); xcd_queues: 1 = one
- * shared work queue, 8 = one queue per accelerator die so neighbouring tiles
- * share its L2.  Zero keeps the current value.
+ * Launch shape of the convolution.
+ *   algorithm        PISCO_ALGO_PIXEL: a wavefront takes one sample at a time and
+ *                    its lanes stride that sample's disc pixels (used for FP64
+ *                    and for incoherent pointing).  PISCO_ALGO_TILE (FP32): the
+ *                    lanes of a wavefront take 64 consecutive samples and walk
+ *                    the pixels of the union of their discs together; tiles
+ *                    whose samples are not within `coherence` disc radii of
+ *                    their mean direction fall back to the pixel path.
+ *   samples_per_tile consecutive samples a wavefront takes per queue pop (1..65536)
+ *   waves_per_group  wavefronts per workgroup (1, 2, 4 or 8)
+ *   groups_per_cu    workgroups launched per compute unit (1..16)
+ *   xcd_queues       1: one shared work queue; 8: one queue per accelerator
+ *                    die, each holding a contiguous block of tiles
+ *   chunk            tile path: union pixels staged in LDS per pass (64, 128, 256)
+ *   coherence        tile path: see algorithm, in (0, 4]
+ * Results are bitwise reproducible for a given launch shape.  They do not
+ * depend on the shape except through the algorithm (the two paths round
+ * differently) and, on the tile path, through samples_per_tile when it is not
+ * a multiple of 64 (it decides which samples share a tile frame).
  */
-pisco_status pisco_set_launch(pisco_ctx *ctx, int32_t samples_per_tile, int32_t waves_per_group,
-                              int32_t groups_per_cu, int32_t xcd_queues);
-pisco_status pisco_get_launch(const pisco_ctx *ctx, int32_t *samples_per_tile, int32_t *waves_per_group,
-                              int32_t *groups_per_cu, int32_t *xcd_queues);
+enum { PISCO_ALGO_PIXEL = 0, PISCO_ALGO_TILE = 1 };
+typedef struct {
+    int32_t algorithm;
+    int32_t samples_per_tile;
+    int32_t waves_per_group;
+    int32_t groups_per_cu;
+    int32_t xcd_queues;
+    int32_t chunk;
+    double coherence;
+} pisco_launch;
+pisco_status pisco_set_launch(pisco_ctx *ctx, const pisco_launch *launch);
+pisco_status pisco_get_launch(const pisco_ctx *ctx, pisco_launch *launch);
 
 /*
  * Kernel timing: when enabled, every convolve brackets its kernel launches

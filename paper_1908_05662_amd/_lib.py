@@ -12,6 +12,17 @@ F32, F64 = 0, 1
 HOST, DEVICE = 0, 1
 NORM_FIXED, NORM_PER_SAMPLE = 0, 1
 OUT_TOD, OUT_STOKES, OUT_COUNT = 0, 1, 2
+ALGO_PIXEL, ALGO_TILE = 0, 1
+
+
+class Launch(ctypes.Structure):
+    """Mirror of pisco_launch."""
+    _fields_ = [("algorithm", ctypes.c_int32), ("samples_per_tile", ctypes.c_int32),
+                ("waves_per_group", ctypes.c_int32), ("groups_per_cu", ctypes.c_int32),
+                ("xcd_queues", ctypes.c_int32), ("chunk", ctypes.c_int32), ("coherence", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",
            EUNSUPPORTED: "EUNSUPPORTED"}
@@ -26,13 +37,15 @@ SIGNATURES = [
     ("pisco_last_error", _cp, [_vp]),
     ("pisco_set_sky", ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
     ("pisco_set_beam", ctypes.c_int, [_vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
+    ("pisco_set_beam_scalar", ctypes.c_int, [_vp, _i32, _i32, _dbl, _vp, _dbl, _dbl, _dbl, _dbl, ctypes.c_int,
+                                             ctypes.c_int]),
     ("pisco_share_beam", ctypes.c_int, [_vp, _i32, _i32]),
     ("pisco_set_detector", ctypes.c_int, [_vp, _i32, _dbl, _dbl, _dbl, ctypes.c_int, _dbl]),
     ("pisco_set_pointing", ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, ctypes.c_int]),
     ("pisco_convolve", ctypes.c_int, [_vp, _i32, ctypes.c_int, _vp, ctypes.c_int, _vp]),
     ("pisco_output_samples", _i64, [_vp, _i32]),
-    ("pisco_set_launch", ctypes.c_int, [_vp, _i32, _i32, _i32, _i32]),
-    ("pisco_get_launch", ctypes.c_int, [_vp, _ip, _ip, _ip, _ip]),
+    ("pisco_set_launch", ctypes.c_int, [_vp, ctypes.c_void_p]),
+    ("pisco_get_launch", ctypes.c_int, [_vp, ctypes.c_void_p]),
     ("pisco_set_timing", ctypes.c_int, [_vp, ctypes.c_int]),
     ("pisco_kernel_time", ctypes.c_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64), ctypes.c_int]),
 ]

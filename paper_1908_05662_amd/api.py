@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 
 from . import _lib as L
-from .beamsor import fold_detector
+from .beamsor import fold_detector, scalar_weights
 
 
 def _torch():
@@ -92,10 +92,27 @@ class Convolver:
         self._check(self._lib.pisco_set_beam(self._h, int(det), int(n), float(half_span_tan),
                                              *(t.data_ptr() for t in ts), self._code(dtype), mems.pop()))
 
-    def set_beamsor(self, det: int, mueller: np.ndarray, half_span_tan: float, eps: float, s: float, dtype=None):
-        """Fold a (n, n, 4, 4) Mueller field with the detector row and upload it."""
+    def set_beam_scalar(self, det: int, n: int, half_span_tan: float, b, wI: float, wQ: float, wU: float,
+                        wT: float = 1.0, dtype=None):
+        dtype = dtype or self.dtype or _torch().float32
+        t = self._as_tensor(b, dtype).reshape(-1)
+        self._check(self._lib.pisco_set_beam_scalar(self._h, int(det), int(n), float(half_span_tan), t.data_ptr(),
+                                                    float(wI), float(wQ), float(wU), float(wT), self._code(dtype),
+                                                    self._mem(t)))
+
+    def set_beamsor(self, det: int, mueller: np.ndarray, half_span_tan: float, eps: float, s: float, dtype=None,
+                    allow_scalar: bool = True):
+        """Fold a (n, n, 4, 4) Mueller field with the detector row and upload it;
+        uses the one-grid form when every folded channel is a constant multiple
+        of B_TT (to 1e-12 relative)."""
         bI, bQ, bU, bT = fold_detector(mueller, eps, s)
+        if allow_scalar:
+            w = scalar_weights(bI, bQ, bU, bT)
+            if w is not None:
+                self.set_beam_scalar(det, bT.shape[0], half_span_tan, bT, *w, 1.0, dtype=dtype)
+                return "scalar"
         self.set_beam(det, bI.shape[0], half_span_tan, bI, bQ, bU, bT, dtype)
+        return "full"
 
     def share_beam(self, det: int, src: int):
         self._check(self._lib.pisco_share_beam(self._h, int(det), int(src)))
@@ -138,13 +155,18 @@ class Convolver:
                                              ctypes.c_void_p(s.cuda_stream)))
         return out
 
-    def set_launch(self, samples_per_tile=0, waves_per_group=0, groups_per_cu=0, xcd_queues=0):
-        self._check(self._lib.pisco_set_launch(self._h, samples_per_tile, waves_per_group, groups_per_cu, xcd_queues))
+    def set_launch(self, **kw):
+        """Update fields of the launch shape (see pisco_launch); returns the new shape."""
+        cur = self.get_launch()
+        cur.update(kw)
+        l = L.Launch(**cur)
+        self._check(self._lib.pisco_set_launch(self._h, ctypes.byref(l)))
+        return self.get_launch()
 
-    def get_launch(self):
-        v = [ctypes.c_int32() for _ in range(4)]
-        self._check(self._lib.pisco_get_launch(self._h, *(ctypes.byref(x) for x in v)))
-        return tuple(x.value for x in v)
+    def get_launch(self) -> dict:
+        l = L.Launch()
+        self._check(self._lib.pisco_get_launch(self._h, ctypes.byref(l)))
+        return l.as_dict()
 
     def set_timing(self, on: bool = True):
         self._check(self._lib.pisco_set_timing(self._h, int(bool(on))))

@@ -50,3 +50,20 @@ def grid_solid_angle(bT: np.ndarray, half_span_tan: float, rho_max: float | None
         w = w * (np.arctan(np.sqrt(r2)) <= rho_max)
     h = 2.0 * T / (n - 1)
     return float(np.sum(bT * w) * h * h)
+
+
+def scalar_weights(bI, bQ, bU, bT, rtol: float = 1e-12):
+    """(wI, wQ, wU) if every channel is a constant multiple of bT, else None."""
+    bT = np.asarray(bT, dtype=np.float64)
+    k = np.unravel_index(np.argmax(np.abs(bT)), bT.shape)
+    if bT[k] == 0.0:
+        return None
+    scale = np.abs(bT).max()
+    out = []
+    for b in (bI, bQ, bU):
+        b = np.asarray(b, dtype=np.float64)
+        w = b[k] / bT[k]
+        if np.abs(b - w * bT).max() > rtol * max(scale * abs(w), scale):
+            return None
+        out.append(float(w))
+    return tuple(out)

@@ -213,13 +213,44 @@ __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double rcp(double x) { return 1.0 / x; }
 
 // ----------------------------------------------------------------------
-// The kernel
+// Beam grids
+//   FULL   : one record (bI, bQ, bU, bT) per node, n*n records
+//   SCALAR : beam = b(u, v) * (wI, wQ, wU, wT); one record per cell holding
+//            the cell's four corner values (b00, b10, b01, b11), (n-1)^2 records,
+//            so a bilinear lookup is a single 16/32-byte load
 // ----------------------------------------------------------------------
-template <typename T, int MODE>
+template <typename T>
+struct BeamVals {
+    T bI, bQ, bU, bT;
+};
+
+template <typename T, int BEAM>
+__device__ inline BeamVals<T> beam_lookup(const void *beam, int32_t n, int32_t iu, int32_t iv, T fu, T fv) {
+    using R4 = typename Rec4<T>::type;
+    const R4 *__restrict__ g = reinterpret_cast<const R4 *>(beam);
+    BeamVals<T> o;
+    if (BEAM == BEAM_FULL) {
+        const int32_t b00 = iv * n + iu;
+        const R4 q00 = g[b00], q10 = g[b00 + 1], q01 = g[b00 + n], q11 = g[b00 + n + 1];
+        o.bI = lerp(lerp(q00.x, q10.x, fu), lerp(q01.x, q11.x, fu), fv);
+        o.bQ = lerp(lerp(q00.y, q10.y, fu), lerp(q01.y, q11.y, fu), fv);
+        o.bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
+        o.bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
+    } else {
+        const R4 c = g[iv * (n - 1) + iu];
+        o.bT = lerp(lerp(c.x, c.y, fu), lerp(c.z, c.w, fu), fv);
+        o.bI = o.bQ = o.bU = o.bT;
+    }
+    return o;
+}
+
+// ----------------------------------------------------------------------
+// Pixel-parallel path: one sample at a time, lanes over its disc pixels
+// ----------------------------------------------------------------------
+template <typename T, int MODE, int BEAM>
 __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, WaveLds<T> &L, int lane) {
     using R4 = typename Rec4<T>::type;
     const R4 *__restrict__ sky = reinterpret_cast<const R4 *>(A.sky);
-    const R4 *__restrict__ beam = reinterpret_cast<const R4 *>(D.beam);
     const int32_t N = (int32_t)A.nside;
 
     // FP64 set-up of the sample's frame
@@ -236,6 +267,7 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
     const T inv_h = (T)D.inv_h;
     const T c0 = (T)(0.5 * (n - 1));
     const T tmax = (T)(n - 1);
+    const T wI = (T)D.w[0], wQ = (T)D.w[1], wU = (T)D.w[2];
 
     const int32_t nring = 4 * N - 1;
     const double rho = D.rho_max;
@@ -305,7 +337,7 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
         L.seg_end[2 * lane] = excl + n0;
         L.seg_end[2 * lane + 1] = incl;
         const int32_t total = __shfl(incl, WAVE - 1, WAVE);
-        if (MODE == 2) {  // disc pixel count only
+        if (MODE == MODE_COUNT) {
             npairs += total;
             continue;
         }
@@ -345,8 +377,7 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
             const int32_t iu = min((int32_t)tu, n - 2);
             const int32_t iv = min((int32_t)tv, n - 2);
             const T fu = tu - (T)iu, fv = tv - (T)iv;
-            const int32_t b00 = iv * n + iu;
-            const R4 q00 = beam[b00], q10 = beam[b00 + 1], q01 = beam[b00 + n], q11 = beam[b00 + n + 1];
+            const BeamVals<T> bv = beam_lookup<T, BEAM>(D.beam, n, iu, iv, fu, fv);
             const R4 pix = sky[R.first + j];
 
             // co-polar direction carried along the great circle, projected on
@@ -362,45 +393,45 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
             const T c2 = fma(cc, cc, -ss * ss);
             const T s2 = (T)2 * cc * ss;
 
-            const T bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
             const T qr = fma(c2, pix.y, s2 * pix.z);    // Q rotated into the detector frame
             const T ur = fma(-s2, pix.y, c2 * pix.z);   // U rotated into the detector frame
-            accn.add(bT);
-            if (MODE == 0) {
-                const T bI = lerp(lerp(q00.x, q10.x, fu), lerp(q01.x, q11.x, fu), fv);
-                const T bQ = lerp(lerp(q00.y, q10.y, fu), lerp(q01.y, q11.y, fu), fv);
-                const T bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
-                acc0.add(fma(bI, pix.x, fma(bQ, qr, bU * ur)));
+            accn.add(bv.bT);
+            if (MODE == MODE_TOD) {
+                if (BEAM == BEAM_FULL)
+                    acc0.add(fma(bv.bI, pix.x, fma(bv.bQ, qr, bv.bU * ur)));
+                else
+                    acc0.add(bv.bT * fma(wI, pix.x, fma(wQ, qr, wU * ur)));
             } else {
-                acc0.add(bT * pix.x);
-                acc1.add(bT * qr);
-                acc2.add(bT * ur);
+                acc0.add(bv.bT * pix.x);
+                acc1.add(bv.bT * qr);
+                acc2.add(bv.bT * ur);
             }
         }
         wave_sync();
     }
 
-    if (MODE == 2) {
+    if (MODE == MODE_COUNT) {
         if (lane == 0) reinterpret_cast<T *>(A.out)[D.out_offset + t] = (T)npairs;
         return;
     }
     accn.wave_reduce();
     acc0.wave_reduce();
-    if (MODE == 1) {
+    if (MODE == MODE_STOKES) {
         acc1.wave_reduce();
         acc2.wave_reduce();
     }
     if (lane == 0) {
         double Nrm = D.norm_scale;
         if (D.norm_mode == 1) {
-            const double sn = accn.value();
+            const double sn = accn.value() * (BEAM == BEAM_SCALAR ? D.w[3] : 1.0);
             Nrm = (sn != 0.0) ? D.norm_scale / sn : 0.0;
         }
         T *out = reinterpret_cast<T *>(A.out);
         const int64_t o = D.out_offset + t;
-        if (MODE == 0) {
+        if (MODE == MODE_TOD) {
             out[o] = (T)(acc0.value() * Nrm);
         } else {
+            if (BEAM == BEAM_SCALAR) Nrm *= D.w[3];  // the Stokes pickup uses the scalar beam wT b
             out[3 * o + 0] = (T)(acc0.value() * Nrm);
             out[3 * o + 1] = (T)(acc1.value() * Nrm);
             out[3 * o + 2] = (T)(acc2.value() * Nrm);
@@ -408,7 +439,301 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
     }
 }
 
-template <typename T, int MODE>
+// ----------------------------------------------------------------------
+// Sample-parallel path: lane l owns sample begin + l of a tile of consecutive
+// samples.  The wave stages the pixels of the union of the tile's discs (a
+// cap around the tile centre) in LDS, a chunk at a time, and every lane walks
+// the same pixel records (LDS broadcasts), testing its own disc membership in
+// FP64.  Beam lookups of neighbouring lanes fall on neighbouring beam cells.
+// ----------------------------------------------------------------------
+struct PixRec {
+    double X, Y, W;     // n = X e1 + Y e2 + (1 - W) c in the tile frame
+    float xf, yf, zf;   // the same in FP32 (zf = 1 - W)
+    float tx, ty, tz;   // the pixel's theta_hat in the tile frame
+    float fx, fy, fz;   // the pixel's phi_hat in the tile frame
+    float a, b, c;      // scalar beam, TOD: wI I, wQ Q + wU U, wQ U - wU Q; otherwise I, Q, U
+};
+
+struct UnionRing {
+    double phi0, dphi, z, s;
+    int32_t first, n, j0, cnt;  // pixels j0 .. j0 + cnt - 1 (mod n)
+};
+
+template <int CH>
+struct TileLds {
+    UnionRing ring[WAVE];
+    int32_t seg_end[WAVE];
+    PixRec rec[CH];
+};
+
+template <int MODE, int BEAM, int CH>
+__device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
+                              int lane) {
+    const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
+    const int32_t N = (int32_t)A.nside;
+    const bool valid = lane < cnt;
+    const int64_t t = begin + (valid ? lane : 0);
+
+    // FP64 frame of this lane's sample
+    const double th0 = D.theta[t], ph0 = D.phi[t], ps0 = D.psi[t];
+    double st, ct, sf, cf, sp, cp, sg, cg;
+    sincos(th0, &st, &ct);
+    sincos(ph0, &sf, &cf);
+    sincos(ps0, &sp, &cp);
+    sincos(ps0 + D.zeta, &sg, &cg);
+    const double p[3] = {st * cf, st * sf, ct};
+    const double th[3] = {ct * cf, ct * sf, -st};
+    const double ph[3] = {-sf, cf, 0.0};
+    double ta[3], tb[3], tg[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ta[i] = cp * th[i] + sp * ph[i];   // theta'_0
+        tb[i] = -sp * th[i] + cp * ph[i];  // phi'_0
+        tg[i] = cg * th[i] + sg * ph[i];   // co-polar direction at the boresight
+    }
+
+    // tile centre c = normalised mean boresight; e1, e2 = its theta_hat, phi_hat
+    double sx = valid ? p[0] : 0.0, sy = valid ? p[1] : 0.0, sz = valid ? p[2] : 0.0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        sx += __shfl_xor(sx, m, WAVE);
+        sy += __shfl_xor(sy, m, WAVE);
+        sz += __shfl_xor(sz, m, WAVE);
+    }
+    const double sn = sqrt(sx * sx + sy * sy + sz * sz);
+    const double c[3] = {sx / sn, sy / sn, sz / sn};
+    const double rxy = sqrt(c[0] * c[0] + c[1] * c[1]);
+    const double thc = atan2(rxy, c[2]);
+    double phc = atan2(c[1], c[0]);
+    if (phc < 0.0) phc += TWO_PI;
+    double sfc, cfc;
+    sincos(phc, &sfc, &cfc);
+    const double e1[3] = {c[2] * cfc, c[2] * sfc, -rxy};
+    const double e2[3] = {-sfc, cfc, 0.0};
+
+    // lane's pointing in the tile frame
+    const double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
+    const double om = 0.5 * (dx * dx + dy * dy + dz * dz);  // 1 - p.c
+    const double p1 = p[0] * e1[0] + p[1] * e1[1] + p[2] * e1[2];
+    const double p2 = p[0] * e2[0] + p[1] * e2[1] + p[2] * e2[2];
+    const double p3 = 1.0 - om;
+    const double a1 = ta[0] * e1[0] + ta[1] * e1[1] + ta[2] * e1[2];
+    const double a2 = ta[0] * e2[0] + ta[1] * e2[1] + ta[2] * e2[2];
+    const double a3 = ta[0] * c[0] + ta[1] * c[1] + ta[2] * c[2];
+    const double b1 = tb[0] * e1[0] + tb[1] * e1[1] + tb[2] * e1[2];
+    const double b2 = tb[0] * e2[0] + tb[1] * e2[1] + tb[2] * e2[2];
+    const double b3 = tb[0] * c[0] + tb[1] * c[1] + tb[2] * c[2];
+    const float g1 = (float)(tg[0] * e1[0] + tg[1] * e1[1] + tg[2] * e1[2]);
+    const float g2 = (float)(tg[0] * e2[0] + tg[1] * e2[1] + tg[2] * e2[2]);
+    const float g3 = (float)(tg[0] * c[0] + tg[1] * c[1] + tg[2] * c[2]);
+    const float pf1 = (float)p1, pf2 = (float)p2, pf3 = (float)p3;
+
+    // union cap: radius = disc radius + the farthest sample from the centre
+    double dist = valid ? 2.0 * asin(fmin(1.0, 0.5 * sqrt(2.0 * om))) : 0.0;  // angle from the centre
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) dist = fmax(dist, __shfl_xor(dist, m, WAVE));
+    const double Ru = D.rho_max + dist + 1e-9;
+    const double zc = cos(thc), sc = sin(thc);
+    const double cosRu = cos(Ru);
+
+    const int32_t n = D.n;
+    const float inv_h = (float)D.inv_h;
+    const float c0 = (float)(0.5 * (n - 1));
+    const float tmax = (float)(n - 1);
+    const double omax = D.omega_max, omin = D.omega_min;
+    const bool inner = D.has_inner != 0;
+    const bool clip = D.needs_clip != 0;
+    const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
+
+    Acc<float> acc0, acc1, acc2, accn;
+    int64_t npairs = 0;
+
+    const int32_t nring = 4 * N - 1;
+    const int32_t r_lo = (thc - Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, thc - Ru)) - 1);
+    const int32_t r_hi = (thc + Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, thc + Ru)) + 1);
+
+    for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
+        // union ring intervals, one ring per lane
+        const int32_t r = rb + lane;
+        int32_t rc = 0;
+        if (r <= r_hi) {
+            const RingGeom g = ring_geom(N, r);
+            int32_t jc = (int32_t)rint((phc - g.phi0) / g.dphi);
+            jc %= g.n;
+            if (jc < 0) jc += g.n;
+            double dphic = g.phi0 + (double)jc * g.dphi - phc;
+            if (dphic > PI) dphic -= TWO_PI;
+            else if (dphic < -PI) dphic += TWO_PI;
+            int32_t lo, k;
+            ring_interval(cosRu, zc, sc, g, dphic, lo, k);
+            int32_t j0 = jc + lo;
+            j0 %= g.n;
+            if (j0 < 0) j0 += g.n;
+            UnionRing u;
+            u.phi0 = g.phi0;
+            u.dphi = g.dphi;
+            u.z = g.z;
+            u.s = g.s;
+            u.first = g.first;
+            u.n = g.n;
+            u.j0 = j0;
+            u.cnt = k;
+            L.ring[lane] = u;
+            rc = k;
+        }
+        const int32_t incl = wave_inclusive_scan(rc, lane);
+        L.seg_end[lane] = incl;
+        const int32_t total = __shfl(incl, WAVE - 1, WAVE);
+        wave_sync();
+
+        for (int32_t pb = 0; pb < total; pb += CH) {
+            const int32_t m_end = min(CH, total - pb);
+            // fill: one pixel record per lane
+            int32_t seg = 0;
+            for (int32_t m = lane; m < m_end; m += WAVE) {
+                const int32_t f = pb + m;
+                while (f >= L.seg_end[seg]) ++seg;
+                const int32_t start = (seg == 0) ? 0 : L.seg_end[seg - 1];
+                const UnionRing &u = L.ring[seg];
+                int32_t j = u.j0 + (f - start);
+                if (j >= u.n) j -= u.n;
+                const double phi = u.phi0 + (double)j * u.dphi;
+                double sph, cph;
+                sincos(phi, &sph, &cph);
+                const double nx = u.s * cph, ny = u.s * sph, nz = u.z;
+                PixRec R;
+                R.X = nx * e1[0] + ny * e1[1] + nz * e1[2];
+                R.Y = nx * e2[0] + ny * e2[1];
+                const double ex = nx - c[0], ey = ny - c[1], ez = nz - c[2];
+                R.W = 0.5 * (ex * ex + ey * ey + ez * ez);
+                R.xf = (float)R.X;
+                R.yf = (float)R.Y;
+                R.zf = (float)(1.0 - R.W);
+                const double tx = u.z * cph, ty = u.z * sph, tz = -u.s;
+                R.tx = (float)(tx * e1[0] + ty * e1[1] + tz * e1[2]);
+                R.ty = (float)(tx * e2[0] + ty * e2[1]);
+                R.tz = (float)(tx * c[0] + ty * c[1] + tz * c[2]);
+                R.fx = (float)(-sph * e1[0] + cph * e1[1]);
+                R.fy = (float)(-sph * e2[0] + cph * e2[1]);
+                R.fz = (float)(-sph * c[0] + cph * c[1]);
+                const float4 sv = sky[u.first + j];
+                if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
+                    R.a = wI * sv.x;
+                    R.b = fmaf(wQ, sv.y, wU * sv.z);
+                    R.c = fmaf(wQ, sv.z, -wU * sv.y);
+                } else {
+                    R.a = sv.x;
+                    R.b = sv.y;
+                    R.c = sv.z;
+                }
+                L.rec[m] = R;
+            }
+            wave_sync();
+
+            // consume: every lane (sample) against every staged pixel
+            if (valid) {
+                for (int32_t m = 0; m < m_end; ++m) {
+                    const PixRec &R = L.rec[m];
+                    const double omg = fma(-R.Y, p2, fma(-R.X, p1, fma(R.W, p3, om)));  // 1 - n.p
+                    if (omg > omax || (inner && !(omg > omin))) continue;
+                    if (MODE == MODE_COUNT) {
+                        ++npairs;
+                        continue;
+                    }
+                    const double xd = fma(R.Y, a2, fma(R.X, a1, fma(-R.W, a3, a3)));  // n . theta'_0
+                    const double yd = fma(R.Y, b2, fma(R.X, b1, fma(-R.W, b3, b3)));  // n . phi'_0
+                    const float wf = (float)omg;
+                    const float rz = rcp(1.0f - wf);
+                    const float tu = fmaf((float)xd * rz, inv_h, c0);
+                    const float tv = fmaf((float)yd * rz, inv_h, c0);
+                    if (clip && !(tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax)) continue;
+                    const int32_t iu = max(0, min((int32_t)tu, n - 2));
+                    const int32_t iv = max(0, min((int32_t)tv, n - 2));
+                    const float fu = tu - (float)iu, fv = tv - (float)iv;
+                    const BeamVals<float> bv = beam_lookup<float, BEAM>(D.beam, n, iu, iv, fu, fv);
+
+                    // co-polar vector carried from the boresight to the pixel along the great circle
+                    const float gn = fmaf(g1, R.xf, fmaf(g2, R.yf, g3 * R.zf));
+                    const float q = gn * rcp(2.0f - wf);
+                    const float ex = fmaf(-q, pf1 + R.xf, g1);
+                    const float ey = fmaf(-q, pf2 + R.yf, g2);
+                    const float ez = fmaf(-q, pf3 + R.zf, g3);
+                    const float cc = fmaf(ex, R.tx, fmaf(ey, R.ty, ez * R.tz));
+                    const float ss = fmaf(ex, R.fx, fmaf(ey, R.fy, ez * R.fz));
+                    const float c2 = fmaf(cc, cc, -ss * ss);
+                    const float s2 = 2.0f * cc * ss;
+                    accn.add(bv.bT);
+                    if (MODE == MODE_TOD) {
+                        if (BEAM == BEAM_SCALAR) {
+                            acc0.add(bv.bT * fmaf(c2, R.b, fmaf(s2, R.c, R.a)));
+                        } else {
+                            const float bq = fmaf(bv.bQ, R.b, bv.bU * R.c);
+                            const float bu = fmaf(bv.bQ, R.c, -bv.bU * R.b);
+                            acc0.add(fmaf(bv.bI, R.a, fmaf(c2, bq, s2 * bu)));
+                        }
+                    } else {
+                        acc0.add(bv.bT * R.a);
+                        acc1.add(bv.bT * fmaf(c2, R.b, s2 * R.c));
+                        acc2.add(bv.bT * fmaf(-s2, R.b, c2 * R.c));
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+
+    if (!valid) return;
+    float *out = reinterpret_cast<float *>(A.out);
+    const int64_t o = D.out_offset + t;
+    if (MODE == MODE_COUNT) {
+        out[o] = (float)npairs;
+        return;
+    }
+    double Nrm = D.norm_scale;
+    if (D.norm_mode == 1) {
+        const double snm = accn.value() * (BEAM == BEAM_SCALAR ? D.w[3] : 1.0);
+        Nrm = (snm != 0.0) ? D.norm_scale / snm : 0.0;
+    }
+    if (MODE == MODE_TOD) {
+        out[o] = (float)(acc0.value() * Nrm);
+    } else {
+        if (BEAM == BEAM_SCALAR) Nrm *= D.w[3];
+        out[3 * o + 0] = (float)(acc0.value() * Nrm);
+        out[3 * o + 1] = (float)(acc1.value() * Nrm);
+        out[3 * o + 2] = (float)(acc2.value() * Nrm);
+    }
+}
+
+// Whether a tile's discs overlap enough for the shared-union path: its samples
+// lie within `frac` disc radii of their mean direction.
+__device__ inline bool tile_is_coherent(const DetDesc &D, int64_t begin, int32_t cnt, int lane, double frac) {
+    const bool valid = lane < cnt;
+    const int64_t t = begin + (valid ? lane : 0);
+    double st, ct, sf, cf;
+    sincos(D.theta[t], &st, &ct);
+    sincos(D.phi[t], &sf, &cf);
+    const double p[3] = {st * cf, st * sf, ct};
+    double sx = valid ? p[0] : 0.0, sy = valid ? p[1] : 0.0, sz = valid ? p[2] : 0.0;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        sx += __shfl_xor(sx, m, WAVE);
+        sy += __shfl_xor(sy, m, WAVE);
+        sz += __shfl_xor(sz, m, WAVE);
+    }
+    const double sn = sqrt(sx * sx + sy * sy + sz * sz);
+    if (!(sn > 0.5 * cnt)) return false;
+    const double dx = p[0] - sx / sn, dy = p[1] - sy / sn, dz = p[2] - sz / sn;
+    double d = valid ? sqrt(dx * dx + dy * dy + dz * dz) : 0.0;  // chord
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) d = fmax(d, __shfl_xor(d, m, WAVE));
+    const double lim = frac * D.rho_max;
+    return (d <= lim) && (D.rho_max + lim < 0.45 * PI);
+}
+
+// ----------------------------------------------------------------------
+// Kernels
+// ----------------------------------------------------------------------
+template <typename T, int MODE, int BEAM>
 __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & (WAVE - 1);
@@ -427,7 +752,40 @@ __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
         }
         const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
         const DetDesc &D = A.dets[tl.det];
-        for (int64_t t = tl.begin; t < tl.begin + tl.count; ++t) convolve_sample<T, MODE>(A, D, t, L, lane);
+        for (int64_t t = tl.begin; t < tl.begin + tl.count; ++t) convolve_sample<T, MODE, BEAM>(A, D, t, L, lane);
+    }
+}
+
+template <int MODE, int BEAM, int CH>
+__global__ void __launch_bounds__(512) tile_kernel(ConvArgs A) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = threadIdx.x / WAVE;
+    constexpr size_t slice = sizeof(TileLds<CH>) > sizeof(WaveLds<float>) ? sizeof(TileLds<CH>) : sizeof(WaveLds<float>);
+    unsigned char *mine = lds_raw + (size_t)wid * ((slice + 15) & ~size_t(15));
+    int32_t q = (A.n_queues > 1) ? (int32_t)(blockIdx.x % (uint32_t)A.n_queues) : 0;
+    int32_t exhausted = 0;
+    while (exhausted < A.n_queues) {
+        int32_t ti = 0;
+        if (lane == 0) ti = atomicAdd(&A.counters[q], 1);
+        ti = __shfl(ti, 0, WAVE);
+        if (ti >= A.queue_len[q]) {
+            q = (q + 1 == A.n_queues) ? 0 : q + 1;
+            ++exhausted;
+            continue;
+        }
+        const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
+        const DetDesc &D = A.dets[tl.det];
+        // tiles longer than a wave are taken 64 samples at a time
+        for (int64_t b = tl.begin; b < tl.begin + tl.count; b += WAVE) {
+            const int32_t cnt = (int32_t)min((int64_t)WAVE, tl.begin + tl.count - b);
+            if (tile_is_coherent(D, b, cnt, lane, A.coherence)) {
+                convolve_tile<MODE, BEAM, CH>(A, D, b, cnt, *reinterpret_cast<TileLds<CH> *>(mine), lane);
+            } else {
+                for (int64_t t = b; t < b + cnt; ++t)
+                    convolve_sample<float, MODE, BEAM>(A, D, t, *reinterpret_cast<WaveLds<float> *>(mine), lane);
+            }
+        }
     }
 }
 
@@ -449,6 +807,22 @@ __global__ void repack4_kernel(const T *a, const T *b, const T *c, const T *d, t
     out[i] = r;
 }
 
+// Scalar beam: one record per cell with the cell's four corner node values.
+template <typename T>
+__global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::type *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t m = (int64_t)(n - 1) * (n - 1);
+    if (i >= m) return;
+    const int32_t iv = (int32_t)(i / (n - 1)), iu = (int32_t)(i % (n - 1));
+    const int64_t k = (int64_t)iv * n + iu;
+    typename Rec4<T>::type r;
+    r.x = b[k];
+    r.y = b[k + 1];
+    r.z = b[k + n];
+    r.w = b[k + n + 1];
+    out[i] = r;
+}
+
 __global__ void check_pointing_kernel(const double *th, const double *ph, const double *ps, int64_t n,
                                       int32_t *bad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -465,21 +839,60 @@ hipError_t launch_zero_counters(int32_t *counters, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_conv_t(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+template <typename T, int MODE>
+static hipError_t launch_pixel(const ConvArgs &a, int waves, int groups, hipStream_t s) {
     const size_t lds = sizeof(WaveLds<T>) * (size_t)waves;
-    if (a.out_mode == 0)
-        hipLaunchKernelGGL((conv_kernel<T, 0>), dim3(groups), dim3(WAVE * waves), lds, s, a);
-    else if (a.out_mode == 1)
-        hipLaunchKernelGGL((conv_kernel<T, 1>), dim3(groups), dim3(WAVE * waves), lds, s, a);
+    if (a.beam_kind == BEAM_FULL)
+        hipLaunchKernelGGL((conv_kernel<T, MODE, BEAM_FULL>), dim3(groups), dim3(WAVE * waves), lds, s, a);
     else
-        hipLaunchKernelGGL((conv_kernel<T, 2>), dim3(groups), dim3(WAVE * waves), lds, s, a);
+        hipLaunchKernelGGL((conv_kernel<T, MODE, BEAM_SCALAR>), dim3(groups), dim3(WAVE * waves), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_conv(const ConvArgs &a, bool f64, int waves_per_group, int groups, hipStream_t s) {
-    return f64 ? launch_conv_t<double>(a, waves_per_group, groups, s)
-               : launch_conv_t<float>(a, waves_per_group, groups, s);
+template <int MODE, int BEAM, int CH>
+static hipError_t launch_tile_t(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+    constexpr size_t slice = sizeof(TileLds<CH>) > sizeof(WaveLds<float>) ? sizeof(TileLds<CH>) : sizeof(WaveLds<float>);
+    const size_t lds = ((slice + 15) & ~size_t(15)) * (size_t)waves;
+    hipLaunchKernelGGL((tile_kernel<MODE, BEAM, CH>), dim3(groups), dim3(WAVE * waves), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_tile(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+    const bool full = a.beam_kind == BEAM_FULL;
+    switch (a.chunk) {
+        case 64:
+            return full ? launch_tile_t<MODE, BEAM_FULL, 64>(a, waves, groups, s)
+                        : launch_tile_t<MODE, BEAM_SCALAR, 64>(a, waves, groups, s);
+        case 256:
+            return full ? launch_tile_t<MODE, BEAM_FULL, 256>(a, waves, groups, s)
+                        : launch_tile_t<MODE, BEAM_SCALAR, 256>(a, waves, groups, s);
+        default:
+            return full ? launch_tile_t<MODE, BEAM_FULL, 128>(a, waves, groups, s)
+                        : launch_tile_t<MODE, BEAM_SCALAR, 128>(a, waves, groups, s);
+    }
+}
+
+hipError_t launch_conv(const ConvArgs &a, bool f64, int waves, int groups, hipStream_t s) {
+    if (f64) {
+        switch (a.out_mode) {
+            case MODE_TOD: return launch_pixel<double, MODE_TOD>(a, waves, groups, s);
+            case MODE_STOKES: return launch_pixel<double, MODE_STOKES>(a, waves, groups, s);
+            default: return launch_pixel<double, MODE_COUNT>(a, waves, groups, s);
+        }
+    }
+    if (a.algo == ALGO_TILE) {
+        switch (a.out_mode) {
+            case MODE_TOD: return launch_tile<MODE_TOD>(a, waves, groups, s);
+            case MODE_STOKES: return launch_tile<MODE_STOKES>(a, waves, groups, s);
+            default: return launch_tile<MODE_COUNT>(a, waves, groups, s);
+        }
+    }
+    switch (a.out_mode) {
+        case MODE_TOD: return launch_pixel<float, MODE_TOD>(a, waves, groups, s);
+        case MODE_STOKES: return launch_pixel<float, MODE_STOKES>(a, waves, groups, s);
+        default: return launch_pixel<float, MODE_COUNT>(a, waves, groups, s);
+    }
 }
 
 hipError_t launch_repack4(const void *a, const void *b, const void *c, const void *d, void *out, int64_t n,
@@ -493,6 +906,20 @@ hipError_t launch_repack4(const void *a, const void *b, const void *c, const voi
     else
         hipLaunchKernelGGL(repack4_kernel<float>, dim3((unsigned)g), dim3(bs), 0, s, (const float *)a,
                            (const float *)b, (const float *)c, (const float *)d, (float4 *)out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, hipStream_t s) {
+    const int bs = 256;
+    const int64_t m = (int64_t)(n - 1) * (n - 1);
+    const int64_t g = (m + bs - 1) / bs;
+    if (g == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(repack_cells_kernel<double>, dim3((unsigned)g), dim3(bs), 0, s, (const double *)b, n,
+                           (double4 *)out);
+    else
+        hipLaunchKernelGGL(repack_cells_kernel<float>, dim3((unsigned)g), dim3(bs), 0, s, (const float *)b, n,
+                           (float4 *)out);
     return hipGetLastError();
 }
 

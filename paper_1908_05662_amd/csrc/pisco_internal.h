@@ -6,6 +6,10 @@
 
 namespace pisco {
 
+enum { MODE_TOD = 0, MODE_STOKES = 1, MODE_COUNT = 2 };
+enum { BEAM_FULL = 0, BEAM_SCALAR = 1 };
+enum { ALGO_PIXEL = 0, ALGO_TILE = 1 };
+
 // Per-detector description, read by the kernel from device memory.
 struct DetDesc {
     const void *beam;      // n*n records (float4 or double4): bI, bQ, bU, bT
@@ -21,10 +25,13 @@ struct DetDesc {
     double norm_scale;
     double half_span_tan;  // T
     double inv_h;          // (n - 1) / (2T)
+    double omega_max;      // 1 - cos(rho_max), computed as 2 sin^2(rho_max / 2)
+    double omega_min;      // 1 - cos(rho_min)
+    double w[4];           // scalar beam weights (wI, wQ, wU, wT); unused for full beams
     int32_t n;             // grid nodes per side
     int32_t norm_mode;     // 0 fixed, 1 per sample
     int32_t has_inner;     // rho_min > 0
-    int32_t pad;
+    int32_t needs_clip;    // the disc can reach beyond the grid
 };
 
 // A tile: `count` consecutive samples of detector `det` starting at `begin`.
@@ -44,8 +51,11 @@ struct ConvArgs {
     int32_t n_queues;        // 1 or 8
     int32_t tiles_per_queue; // padded queue length
     const int32_t *queue_len;
-    int32_t out_mode;        // 0 TOD, 1 STOKES
-    int32_t pad;
+    int32_t out_mode;        // MODE_*
+    int32_t beam_kind;       // BEAM_* (uniform over the launch)
+    int32_t algo;            // ALGO_*
+    int32_t chunk;           // pixel records staged per pass (64, 128, 256)
+    double coherence;        // tile path: samples within this many disc radii of the tile centre
 };
 
 // Launch helpers (conv_kernel.hip).  Return the launch error.
@@ -53,6 +63,7 @@ hipError_t launch_zero_counters(int32_t *counters, int n, hipStream_t s);
 hipError_t launch_conv(const ConvArgs &a, bool f64, int waves_per_group, int groups, hipStream_t s);
 hipError_t launch_repack4(const void *a, const void *b, const void *c, const void *d, void *out, int64_t n,
                           bool f64, hipStream_t s);
+hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, hipStream_t s);
 hipError_t launch_check_pointing(const double *theta, const double *phi, const double *psi, int64_t n,
                                  int32_t *bad, hipStream_t s);
 

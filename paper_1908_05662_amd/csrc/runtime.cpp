@@ -27,6 +27,8 @@ struct DetState {
     int32_t n = 0;
     double T = 0.0;
     int beam_dtype = -1;
+    int beam_kind = pisco::BEAM_FULL;
+    double w[4] = {1.0, 1.0, 1.0, 1.0};
     double zeta = 0.0, rho_min = 0.0, rho_max = 0.0, norm_scale = 1.0;
     int norm_mode = 0;
     int64_t nsamp = 0;
@@ -55,13 +57,15 @@ struct Plan {
     int32_t spt = 0, xq = 0;
     int32_t tiles_per_queue = 0, queues = 1;
     int64_t out_samples = 0;
+    int32_t beam_kind = 0;
     // captured launch
     hipGraphExec_t gexec = nullptr;
     uint64_t g_gen = 0;
     void *g_out = nullptr;
     hipStream_t g_stream = nullptr;
     int g_mode = -1;
-    int32_t g_wpg = 0, g_gpc = 0;
+    int32_t g_wpg = 0, g_gpc = 0, g_algo = -1, g_chunk = 0;
+    double g_coh = 0.0;
 };
 
 struct pisco_ctx {
@@ -76,6 +80,8 @@ struct pisco_ctx {
 
     // launch shape
     int32_t spt = 64, wpg = 4, gpc = 2, xq = 8;
+    int32_t algo = PISCO_ALGO_TILE, chunk = 128;
+    double coherence = 0.5;
 
     Plan plans[2];            // [0] batched (det = -1), [1] single detector
     int32_t *d_flag = nullptr;
@@ -242,11 +248,16 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         x.norm_scale = d.norm_scale;
         x.half_span_tan = d.T;
         x.inv_h = (double)(d.n - 1) / (2.0 * d.T);
+        x.omega_max = 2.0 * std::sin(0.5 * d.rho_max) * std::sin(0.5 * d.rho_max);
+        x.omega_min = 2.0 * std::sin(0.5 * d.rho_min) * std::sin(0.5 * d.rho_min);
+        for (int i = 0; i < 4; ++i) x.w[i] = d.w[i];
+        x.needs_clip = (std::tan(d.rho_max) < d.T * (1.0 - 1e-6)) ? 0 : 1;
         x.n = d.n;
         x.norm_mode = d.norm_mode;
         x.has_inner = d.rho_min > 0.0 ? 1 : 0;
         descs.push_back(x);
         out_off += d.nsamp;
+        p.beam_kind = d.beam_kind;
     }
     // tiles in (detector, time) order, then split into contiguous queue blocks
     std::vector<Tile> tiles;
@@ -301,6 +312,10 @@ ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode) {
     a.n_queues = p.queues;
     a.tiles_per_queue = p.tiles_per_queue;
     a.out_mode = out_mode;
+    a.beam_kind = p.beam_kind;
+    a.algo = c->algo;
+    a.chunk = c->chunk;
+    a.coherence = c->coherence;
     return a;
 }
 
@@ -400,6 +415,57 @@ pisco_status pisco_set_beam(pisco_ctx *c, int32_t det, int32_t n, double T, cons
     d->n = n;
     d->T = T;
     d->beam_dtype = dtype;
+    d->beam_kind = pisco::BEAM_FULL;
+    for (int i = 0; i < 4; ++i) d->w[i] = 1.0;
+    d->has_beam = true;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_beam_scalar(pisco_ctx *c, int32_t det, int32_t n, double T, const void *b, double wI,
+                                   double wQ, double wU, double wT, int dtype, int mem) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    DetState *d = det_slot(c, det);
+    if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    if (n < 3 || n > 8191 || (n % 2) == 0) return fail(c, PISCO_EINVAL, "grid size %d must be odd in [3, 8191]", n);
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(c, PISCO_EINVAL, "half_span_tan must be finite and > 0");
+    if (!std::isfinite(wI) || !std::isfinite(wQ) || !std::isfinite(wU) || !std::isfinite(wT))
+        return fail(c, PISCO_EINVAL, "non-finite beam weight");
+    if (dtype != PISCO_F32 && dtype != PISCO_F64) return fail(c, PISCO_EINVAL, "bad dtype %d", dtype);
+    if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
+    if (!b) return fail(c, PISCO_EINVAL, "null beam");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t nodes = (size_t)n * n, cells = (size_t)(n - 1) * (n - 1);
+    void *src = nullptr;
+    pisco_status st = PISCO_OK;
+    if (mem == PISCO_DEVICE) src = const_cast<void *>(b);
+    else st = to_device(c, b, el_bytes(dtype) * nodes, PISCO_HOST, &src);
+    if (st != PISCO_OK) return st;
+    void *rec = nullptr;
+    if (hipMalloc(&rec, rec_bytes(dtype) * cells) != hipSuccess) {
+        if (mem == PISCO_HOST) (void)hipFree(src);
+        return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * cells);
+    }
+    hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (mem == PISCO_HOST) (void)hipFree(src);
+    if (e != hipSuccess) {
+        (void)hipFree(rec);
+        return fail(c, PISCO_EDEVICE, "beam repack failed: %s", hipGetErrorString(e));
+    }
+    release_beam(c, det);
+    d = &c->dets[det];
+    d->beam = rec;
+    d->beam_owned = true;
+    d->n = n;
+    d->T = T;
+    d->beam_dtype = dtype;
+    d->beam_kind = pisco::BEAM_SCALAR;
+    d->w[0] = wI;
+    d->w[1] = wQ;
+    d->w[2] = wU;
+    d->w[3] = wT;
     d->has_beam = true;
     ++c->generation;
     return PISCO_OK;
@@ -422,6 +488,8 @@ pisco_status pisco_share_beam(pisco_ctx *c, int32_t det, int32_t src) {
     d->n = s.n;
     d->T = s.T;
     d->beam_dtype = s.beam_dtype;
+    d->beam_kind = s.beam_kind;
+    for (int i = 0; i < 4; ++i) d->w[i] = s.w[i];
     d->has_beam = true;
     ++c->generation;
     return PISCO_OK;
@@ -525,6 +593,7 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
             return fail(c, PISCO_ESTATE, "detector %d lacks a beam, parameters or pointing", det);
     }
     bool any = false;
+    int first_kind = -1;
     const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
     for (int32_t k = lo; k <= hi; ++k) {
         const DetState &d = c->dets[k];
@@ -532,6 +601,9 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
         any = true;
         if (d.beam_dtype != c->sky_dtype)
             return fail(c, PISCO_EINVAL, "detector %d beam dtype differs from the sky dtype", k);
+        if (first_kind < 0) first_kind = d.beam_kind;
+        if (d.beam_kind != first_kind)
+            return fail(c, PISCO_EINVAL, "detectors in one launch must all have full or all scalar beams");
     }
     if (!any) return fail(c, PISCO_ESTATE, "no detector is ready");
     HIP_TRY(c, hipSetDevice(c->device));
@@ -559,7 +631,8 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
     const bool use_graph = (det < 0) && (s != nullptr);
     if (use_graph) {
         if (!p.gexec || p.g_gen != p.gen || p.g_out != dout || p.g_stream != s || p.g_mode != out_mode ||
-            p.g_wpg != c->wpg || p.g_gpc != c->gpc) {
+            p.g_wpg != c->wpg || p.g_gpc != c->gpc || p.g_algo != c->algo || p.g_chunk != c->chunk ||
+            p.g_coh != c->coherence) {
             drop_graph(p);
             hipGraph_t g = nullptr;
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
@@ -577,6 +650,9 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
                 p.g_mode = out_mode;
                 p.g_wpg = c->wpg;
                 p.g_gpc = c->gpc;
+                p.g_algo = c->algo;
+                p.g_chunk = c->chunk;
+                p.g_coh = c->coherence;
             } else {
                 p.gexec = nullptr;
             }
@@ -601,26 +677,41 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
     return PISCO_OK;
 }
 
-pisco_status pisco_set_launch(pisco_ctx *c, int32_t spt, int32_t wpg, int32_t gpc, int32_t xq) {
-    if (!c) return PISCO_EINVAL;
+pisco_status pisco_set_launch(pisco_ctx *c, const pisco_launch *l) {
+    if (!c || !l) return PISCO_EINVAL;
     c->err.clear();
-    if (spt < 0 || spt > 65536) return fail(c, PISCO_EINVAL, "samples_per_tile out of range");
-    if (wpg != 0 && wpg != 1 && wpg != 2 && wpg != 4 && wpg != 8) return fail(c, PISCO_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
-    if (gpc < 0 || gpc > 16) return fail(c, PISCO_EINVAL, "groups_per_cu out of range");
-    if (xq != 0 && xq != 1 && xq != 8) return fail(c, PISCO_EINVAL, "xcd_queues must be 1 or 8");
-    if (spt) c->spt = spt;
-    if (wpg) c->wpg = wpg;
-    if (gpc) c->gpc = gpc;
-    if (xq) c->xq = xq;
+    if (l->algorithm != PISCO_ALGO_PIXEL && l->algorithm != PISCO_ALGO_TILE)
+        return fail(c, PISCO_EINVAL, "bad algorithm %d", l->algorithm);
+    if (l->samples_per_tile < 1 || l->samples_per_tile > 65536) return fail(c, PISCO_EINVAL, "samples_per_tile out of range");
+    const int w = l->waves_per_group;
+    if (w != 1 && w != 2 && w != 4 && w != 8) return fail(c, PISCO_EINVAL, "waves_per_group must be 1, 2, 4 or 8");
+    if (l->groups_per_cu < 1 || l->groups_per_cu > 16) return fail(c, PISCO_EINVAL, "groups_per_cu out of range");
+    if (l->xcd_queues != 1 && l->xcd_queues != 8) return fail(c, PISCO_EINVAL, "xcd_queues must be 1 or 8");
+    if (l->chunk != 64 && l->chunk != 128 && l->chunk != 256) return fail(c, PISCO_EINVAL, "chunk must be 64, 128 or 256");
+    if (!(l->coherence > 0.0 && l->coherence <= 4.0)) return fail(c, PISCO_EINVAL, "coherence must be in (0, 4]");
+    // LDS per workgroup must fit the 160 KiB of a compute unit
+    const size_t tile_slice = 64 * 48 + 64 * 4 + (size_t)l->chunk * 72;
+    if (l->algorithm == PISCO_ALGO_TILE && tile_slice * (size_t)w > 160 * 1024)
+        return fail(c, PISCO_EINVAL, "chunk %d with %d waves per group exceeds the LDS of a compute unit", l->chunk, w);
+    c->algo = l->algorithm;
+    c->spt = l->samples_per_tile;
+    c->wpg = w;
+    c->gpc = l->groups_per_cu;
+    c->xq = l->xcd_queues;
+    c->chunk = l->chunk;
+    c->coherence = l->coherence;
     return PISCO_OK;
 }
 
-pisco_status pisco_get_launch(const pisco_ctx *c, int32_t *spt, int32_t *wpg, int32_t *gpc, int32_t *xq) {
-    if (!c) return PISCO_EINVAL;
-    if (spt) *spt = c->spt;
-    if (wpg) *wpg = c->wpg;
-    if (gpc) *gpc = c->gpc;
-    if (xq) *xq = c->xq;
+pisco_status pisco_get_launch(const pisco_ctx *c, pisco_launch *l) {
+    if (!c || !l) return PISCO_EINVAL;
+    l->algorithm = c->algo;
+    l->samples_per_tile = c->spt;
+    l->waves_per_group = c->wpg;
+    l->groups_per_cu = c->gpc;
+    l->xcd_queues = c->xq;
+    l->chunk = c->chunk;
+    l->coherence = c->coherence;
     return PISCO_OK;
 }
 

@@ -11,8 +11,9 @@ def rounded(x, dtype):
     return np.asarray(x, dtype=dtype).astype(np.float64)
 
 
-def load_workload(conv, w, dtype, dets=None, device_pointing=True):
-    """Upload sky, beams, detector parameters and pointing; returns the detector ids used."""
+def load_workload(conv, w, dtype, dets=None, device_pointing=True, beam="auto"):
+    """Upload sky, beams, detector parameters and pointing; returns the detector ids used.
+    beam: "auto" (one-grid form when the folded channels are proportional) or "full"."""
     import torch
 
     tdt = torch.float64 if dtype == np.float64 else torch.float32
@@ -20,7 +21,8 @@ def load_workload(conv, w, dtype, dets=None, device_pointing=True):
     ids = list(range(len(w.detectors))) if dets is None else list(dets)
     for k in ids:
         d = w.detectors[k]
-        conv.set_beamsor(k, d.beam.dense(), d.beam.half_span_tan, d.det.eps, d.det.s, dtype=tdt)
+        conv.set_beamsor(k, d.beam.dense(), d.beam.half_span_tan, d.det.eps, d.det.s, dtype=tdt,
+                         allow_scalar=(beam == "auto"))
         conv.set_detector(k, d.det.zeta, d.rho_min, d.rho_max, d.norm_mode, d.norm_scale)
         arrs = [torch.from_numpy(np.ascontiguousarray(x)) for x in (d.theta, d.phi, d.psi)]
         if device_pointing:

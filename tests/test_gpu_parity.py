@@ -33,6 +33,10 @@ def conv(torch):
     c.close()
 
 
+ALGOS = [0, 1]          # pixel-parallel, sample-parallel tile path
+BEAMS = ["full", "auto"]  # four-channel grid, one-grid (scalar) form
+
+
 def test_c1_fp64_full_stream(conv, torch):
     """configs[0] at full size: 1e5 samples, FP64 kernel, every sample vs the oracle."""
     say("case: c1 fp64 1e5 samples")
@@ -45,10 +49,13 @@ def test_c1_fp64_full_stream(conv, torch):
     assert e <= F64_TOL
 
 
-def test_c1_fp32_mixed(conv, torch):
-    say("case: c1 fp32 2e4 samples")
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("beam", BEAMS)
+def test_c1_fp32_mixed(conv, torch, algo, beam):
+    say(f"case: c1 fp32 2e4 samples algo {algo} beam {beam}")
     w = W.c1(n_samples=20000)
-    load_workload(conv, w, np.float32)
+    conv.set_launch(algorithm=algo)
+    load_workload(conv, w, np.float32, beam=beam)
     got = conv.convolve(0).cpu().numpy()
     want = oracle_detector(w, 0, slice(None), np.float32)
     e = rel_err(got, want)
@@ -56,12 +63,15 @@ def test_c1_fp32_mixed(conv, torch):
     assert e <= F32_TOL
 
 
-def test_c2_fp32_sampled(conv, torch):
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("beam", BEAMS)
+def test_c2_fp32_sampled(conv, torch, algo, beam):
     """configs[1] shape (nside 512, 201^2 elliptical beam, CES) on 2e5 samples;
     the oracle checks an evenly spread subset."""
-    say("case: c2 fp32 2e5 samples, 1500 checked")
+    say(f"case: c2 fp32 2e5 samples, 1500 checked, algo {algo} beam {beam}")
     w = W.c2(n_samples=200_000)
-    load_workload(conv, w, np.float32)
+    conv.set_launch(algorithm=algo)
+    load_workload(conv, w, np.float32, beam=beam)
     got = conv.convolve(0).cpu().numpy()
     idx = np.linspace(0, w.detectors[0].n - 1, 1500).astype(np.int64)
     want = oracle_detector(w, 0, idx, np.float32)
@@ -88,11 +98,13 @@ def _gauss(n, span_deg, fwhm_deg, e=0.1, o=0.5, leak=0.01):
     return B.with_qu_leakage(B.ideal_beamsor(g, T), g, leak)
 
 
-@pytest.mark.parametrize("dtype,tol", [(np.float64, F64_TOL), (np.float32, F32_TOL)])
-def test_edge_geometry(conv, torch, dtype, tol):
+@pytest.mark.parametrize("dtype,tol,algo", [(np.float64, F64_TOL, 0), (np.float32, F32_TOL, 0),
+                                            (np.float32, F32_TOL, 1)])
+def test_edge_geometry(conv, torch, dtype, tol, algo):
     """Poles inside the disc, boresight exactly on a pole, longitude wrap-around,
     negative / >2pi longitudes, full rings, coarse maps with wide discs."""
-    say(f"case: edge geometry {np.dtype(dtype).name}")
+    say(f"case: edge geometry {np.dtype(dtype).name} algo {algo}")
+    conv.set_launch(algorithm=algo)
     rng = np.random.default_rng(4)
     th = np.concatenate([[0.0, np.pi, 1e-9, np.pi - 1e-9, 0.05, np.pi - 0.05, 1.0, 2.0],
                          np.arccos(rng.uniform(-1, 1, 24))])
@@ -111,15 +123,32 @@ def test_edge_geometry(conv, torch, dtype, tol):
         assert e <= tol, (nside, e)
 
 
-@pytest.mark.parametrize("dtype,tol", [(np.float64, F64_TOL), (np.float32, F32_TOL)])
-def test_annulus_stokes_fixed(conv, torch, dtype, tol):
+def _pole_crossing_scan(n):
+    """Slow scans that pass over both poles and across phi = 0: consecutive
+    samples overlap (tile path) while the discs contain a pole or wrap."""
+    s = np.linspace(-1, 1, n // 2)
+    th1, ph1 = np.abs(0.3 * s) + 1e-12, np.where(s < 0, 0.7, 0.7 + np.pi)
+    th2, ph2 = np.pi - np.abs(0.3 * s), np.where(s < 0, 2 * np.pi - 1e-9, np.pi - 1e-9)
+    th = np.concatenate([th1, th2])
+    ph = np.concatenate([ph1, ph2])
+    ps = np.linspace(0, 3, th.size)
+    return th, ph, ps
+
+
+@pytest.mark.parametrize("dtype,tol,algo,scan", [(np.float64, F64_TOL, 0, "random"), (np.float32, F32_TOL, 0, "random"),
+                                                 (np.float32, F32_TOL, 1, "random"), (np.float32, F32_TOL, 1, "poles"),
+                                                 (np.float64, F64_TOL, 0, "poles")])
+def test_annulus_stokes_fixed(conv, torch, dtype, tol, algo, scan):
     """Annulus selection, the Stokes-pickup output and FIXED normalisation; the
     disc = inner disc + annulus partition holds on the GPU too."""
-    say(f"case: annulus/stokes {np.dtype(dtype).name}")
+    say(f"case: annulus/stokes {np.dtype(dtype).name} algo {algo} scan {scan}")
+    conv.set_launch(algorithm=algo)
     rng = np.random.default_rng(5)
     n = 200
     th, ph, ps = np.arccos(rng.uniform(-1, 1, n)), rng.uniform(0, 2 * np.pi, n), rng.uniform(0, 2 * np.pi, n)
     th[:3] = [0.0, 0.02, np.pi]
+    if scan == "poles":
+        th, ph, ps = _pole_crossing_scan(256)
     T, u, v, rho, sig = B.tangent_grid(161, 20 * D2R)
     g = B.elliptical_gaussian(rho, sig, 2 * D2R) + B.ring_lobe(rho, 10 * D2R, 2 * D2R, 1e-2)
     bs = B.ideal_beamsor(g, T)
@@ -131,6 +160,11 @@ def test_annulus_stokes_fixed(conv, torch, dtype, tol):
     for mode in (oracle.OUT_TOD, oracle.OUT_STOKES):
         outs = []
         for k in range(3):
+            if mode == oracle.OUT_TOD and k == 0:
+                # pixel counts are integers: exact against the oracle's own disc scan
+                cnt = conv.convolve(k, out_mode=2).cpu().numpy()
+                want_cnt = np.array([oracle.disc(nside, a, b, 20 * D2R).size for a, b in zip(th, ph)])
+                assert np.array_equal(cnt.astype(np.int64), want_cnt)
             got = conv.convolve(k, out_mode=mode).cpu().numpy()
             want = oracle_detector(w, k, slice(None), dtype, out_mode=mode)
             e = rel_err(got, want)
@@ -165,18 +199,24 @@ def test_delta_and_uniform_closed_forms(conv, torch):
         assert np.abs(got - 1.0).max() < tol, dtype
 
 
-def test_psi_plus_pi_and_determinism(conv, torch):
-    say("case: psi+pi, determinism, launch shapes")
-    w = W.c1(n_samples=4000)
+@pytest.mark.parametrize("algo", ALGOS)
+def test_psi_plus_pi_and_determinism(conv, torch, algo):
+    say(f"case: psi+pi, determinism, launch shapes, algo {algo}")
+    w = W.c2(n_samples=4000)
     d = w.detectors[0]
+    conv.set_launch(algorithm=algo)
     load_workload(conv, w, np.float32)
     a = conv.convolve(0).cpu().numpy()
     b = conv.convolve(0).cpu().numpy()
     assert np.array_equal(a, b)
-    for shape in [(1, 1, 1, 1), (7, 2, 3, 8), (256, 8, 1, 1), (64, 4, 2, 8)]:
-        conv.set_launch(*shape)
+    for shape in [(64, 1, 1, 1, 64), (192, 2, 3, 8, 128), (256, 8, 1, 1, 128), (64, 4, 2, 8, 256)]:
+        spt, wpg, gpc, xq, ch = shape
+        conv.set_launch(samples_per_tile=spt, waves_per_group=wpg, groups_per_cu=gpc, xcd_queues=xq, chunk=ch)
         c = conv.convolve(0).cpu().numpy()
         assert np.array_equal(a, c), shape
+    if algo == 0:
+        conv.set_launch(samples_per_tile=7)
+        assert np.array_equal(a, conv.convolve(0).cpu().numpy())
     conv.set_pointing(0, *(torch.from_numpy(x).cuda() for x in (d.theta, d.phi, d.psi + np.pi)))
     e = conv.convolve(0).cpu().numpy()
     assert rel_err(e, a) <= 2e-6
@@ -207,16 +247,23 @@ def test_empty_and_invalid_inputs(conv, torch):
     assert conv.output_samples(0) == 0
 
 
-def test_batched_graph_replay_matches_per_detector(conv, torch):
+@pytest.mark.parametrize("algo", ALGOS)
+def test_batched_graph_replay_matches_per_detector(conv, torch, algo):
     """All detectors in one persistent launch, captured once and replayed; every
     replay (with eager launches in between) equals the per-detector launches."""
-    say("case: batched graph replay")
+    say(f"case: batched graph replay algo {algo}")
+    conv.set_launch(algorithm=algo)
     rng = np.random.default_rng(8)
     nside = 64
     dets = []
     for k in range(6):
         n = int(rng.integers(1, 3000))
-        th, ph, ps = np.arccos(rng.uniform(-1, 1, n)), rng.uniform(0, 6.3, n), rng.uniform(0, 6.3, n)
+        if k % 2:
+            th, ph, ps = np.arccos(rng.uniform(-1, 1, n)), rng.uniform(0, 6.3, n), rng.uniform(0, 6.3, n)
+        else:  # a slow great-circle-ish sweep: coherent tiles
+            s0 = rng.uniform(0, 6.3)
+            th = 1.0 + 0.4 * np.sin(np.linspace(0, 2, n) + s0)
+            ph, ps = np.linspace(s0, s0 + 1.5, n), np.linspace(0, 4, n)
         dets.append(_det(_gauss(61, 3.0 + k * 0.3, 1.0 + 0.1 * k, e=0.05 * k, o=k), th, ph, ps,
                          zeta=0.3 * k, rmax=(3.0 + 0.3 * k) * D2R))
     w = _small_workload(nside, dets, seed=11)
