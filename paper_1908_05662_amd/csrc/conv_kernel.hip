@@ -443,20 +443,41 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
 // Sample-parallel path: lane l owns sample begin + l of a tile of consecutive
 // samples.  The wave stages the pixels of the union of the tile's discs (a
 // cap around the tile centre) in LDS, a chunk at a time, and every lane walks
-// the same pixel records (LDS broadcasts), testing its own disc membership in
-// FP64.  Beam lookups of neighbouring lanes fall on neighbouring beam cells.
+// the same pixel records (LDS broadcasts), testing its own disc membership.
+// FP64 is used for the tile and ring set-up; pixel records and pairs are FP32
+// differences from the tile centre.  Beam lookups of neighbouring lanes fall
+// on neighbouring beam cells.
 // ----------------------------------------------------------------------
+// Wave-uniform values kept in scalar registers.
+__device__ inline double uniform(double x) {
+    const unsigned long long b = __double_as_longlong(x);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+// Beam records read through a global-address-space pointer (global rather
+// than flat loads).
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef const f4v __attribute__((address_space(1))) *global_f4;
+__device__ inline float4 ld4(global_f4 p, int32_t i) {
+    const f4v v = p[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 struct PixRec {
-    double X, Y, W;     // n = X e1 + Y e2 + (1 - W) c in the tile frame
-    float xf, yf, zf;   // the same in FP32 (zf = 1 - W)
-    float tx, ty, tz;   // the pixel's theta_hat in the tile frame
-    float fx, fy, fz;   // the pixel's phi_hat in the tile frame
+    float X, Y, W;      // n = X e1 + Y e2 + (1 - W) c in the tile frame
+    float t1, t2, t3;   // the pixel's theta_hat in the tile frame
+    float f1, f2, f3;   // the pixel's phi_hat in the tile frame
     float a, b, c;      // scalar beam, TOD: wI I, wQ Q + wU U, wQ U - wU Q; otherwise I, Q, U
 };
 
+// One ring of the union cap, with the ring's coefficients relative to the
+// tile centre (the same difference formulas as the pixel path, with the
+// centre in place of the boresight).
 struct UnionRing {
-    double phi0, dphi, z, s;
-    int32_t first, n, j0, cnt;  // pixels j0 .. j0 + cnt - 1 (mod n)
+    float a, b, c, e, s, z, cdt, f, g, dphic, dphi, pad;
+    int32_t first, n, jc, lo;   // pixels k = lo .. lo + cnt - 1 counted from the pixel nearest the centre
 };
 
 template <int CH>
@@ -466,15 +487,24 @@ struct TileLds {
     PixRec rec[CH];
 };
 
-template <int MODE, int BEAM, int CH>
-__device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
-                              int lane) {
-    const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
-    const int32_t N = (int32_t)A.nside;
-    const bool valid = lane < cnt;
-    const int64_t t = begin + (valid ? lane : 0);
+// Per-lane sample frame in the tile frame (all FP32; the small quantities keep
+// relative precision because they are formed in FP64 first).
+struct LaneFrame {
+    float om, p1, p2, p3;   // 1 - p.c and p
+    float a1, a2, a3;       // theta'_0
+    float b1, b2, b3;       // phi'_0
+    float g1, g2, g3;       // co-polar direction at the boresight
+};
 
-    // FP64 frame of this lane's sample
+struct TileFrame {
+    double thc, phc, zc, sc, Ru;
+};
+
+// FP64 set-up of a tile: the centre c (normalised mean boresight), the union
+// radius, and each lane's sample expressed in the frame (e1, e2, c) with
+// e1 = theta_hat(c), e2 = phi_hat(c).  Not inlined: its transcendental
+// constants stay out of the pixel loops.
+__device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int64_t t, bool valid, LaneFrame &F) {
     const double th0 = D.theta[t], ph0 = D.phi[t], ps0 = D.psi[t];
     double st, ct, sf, cf, sp, cp, sg, cg;
     sincos(th0, &st, &ct);
@@ -484,15 +514,6 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const double p[3] = {st * cf, st * sf, ct};
     const double th[3] = {ct * cf, ct * sf, -st};
     const double ph[3] = {-sf, cf, 0.0};
-    double ta[3], tb[3], tg[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        ta[i] = cp * th[i] + sp * ph[i];   // theta'_0
-        tb[i] = -sp * th[i] + cp * ph[i];  // phi'_0
-        tg[i] = cg * th[i] + sg * ph[i];   // co-polar direction at the boresight
-    }
-
-    // tile centre c = normalised mean boresight; e1, e2 = its theta_hat, phi_hat
     double sx = valid ? p[0] : 0.0, sy = valid ? p[1] : 0.0, sz = valid ? p[2] : 0.0;
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) {
@@ -503,119 +524,156 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const double sn = sqrt(sx * sx + sy * sy + sz * sz);
     const double c[3] = {sx / sn, sy / sn, sz / sn};
     const double rxy = sqrt(c[0] * c[0] + c[1] * c[1]);
-    const double thc = atan2(rxy, c[2]);
-    double phc = atan2(c[1], c[0]);
-    if (phc < 0.0) phc += TWO_PI;
+    TileFrame T;
+    T.thc = atan2(rxy, c[2]);
+    T.phc = atan2(c[1], c[0]);
+    if (T.phc < 0.0) T.phc += TWO_PI;
+    T.zc = c[2];
+    T.sc = rxy;
     double sfc, cfc;
-    sincos(phc, &sfc, &cfc);
+    sincos(T.phc, &sfc, &cfc);
     const double e1[3] = {c[2] * cfc, c[2] * sfc, -rxy};
     const double e2[3] = {-sfc, cfc, 0.0};
-
-    // lane's pointing in the tile frame
     const double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
     const double om = 0.5 * (dx * dx + dy * dy + dz * dz);  // 1 - p.c
-    const double p1 = p[0] * e1[0] + p[1] * e1[1] + p[2] * e1[2];
-    const double p2 = p[0] * e2[0] + p[1] * e2[1] + p[2] * e2[2];
-    const double p3 = 1.0 - om;
-    const double a1 = ta[0] * e1[0] + ta[1] * e1[1] + ta[2] * e1[2];
-    const double a2 = ta[0] * e2[0] + ta[1] * e2[1] + ta[2] * e2[2];
-    const double a3 = ta[0] * c[0] + ta[1] * c[1] + ta[2] * c[2];
-    const double b1 = tb[0] * e1[0] + tb[1] * e1[1] + tb[2] * e1[2];
-    const double b2 = tb[0] * e2[0] + tb[1] * e2[1] + tb[2] * e2[2];
-    const double b3 = tb[0] * c[0] + tb[1] * c[1] + tb[2] * c[2];
-    const float g1 = (float)(tg[0] * e1[0] + tg[1] * e1[1] + tg[2] * e1[2]);
-    const float g2 = (float)(tg[0] * e2[0] + tg[1] * e2[1] + tg[2] * e2[2]);
-    const float g3 = (float)(tg[0] * c[0] + tg[1] * c[1] + tg[2] * c[2]);
-    const float pf1 = (float)p1, pf2 = (float)p2, pf3 = (float)p3;
-
-    // union cap: radius = disc radius + the farthest sample from the centre
+    double ta[3], tb[3], tg[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        ta[i] = cp * th[i] + sp * ph[i];   // theta'_0
+        tb[i] = -sp * th[i] + cp * ph[i];  // phi'_0
+        tg[i] = cg * th[i] + sg * ph[i];   // co-polar direction at the boresight
+    }
+    F.om = (float)om;
+    F.p1 = (float)(p[0] * e1[0] + p[1] * e1[1] + p[2] * e1[2]);
+    F.p2 = (float)(p[0] * e2[0] + p[1] * e2[1]);
+    F.p3 = (float)(1.0 - om);
+    F.a1 = (float)(ta[0] * e1[0] + ta[1] * e1[1] + ta[2] * e1[2]);
+    F.a2 = (float)(ta[0] * e2[0] + ta[1] * e2[1]);
+    F.a3 = (float)(ta[0] * c[0] + ta[1] * c[1] + ta[2] * c[2]);
+    F.b1 = (float)(tb[0] * e1[0] + tb[1] * e1[1] + tb[2] * e1[2]);
+    F.b2 = (float)(tb[0] * e2[0] + tb[1] * e2[1]);
+    F.b3 = (float)(tb[0] * c[0] + tb[1] * c[1] + tb[2] * c[2]);
+    F.g1 = (float)(tg[0] * e1[0] + tg[1] * e1[1] + tg[2] * e1[2]);
+    F.g2 = (float)(tg[0] * e2[0] + tg[1] * e2[1]);
+    F.g3 = (float)(tg[0] * c[0] + tg[1] * c[1] + tg[2] * c[2]);
     double dist = valid ? 2.0 * asin(fmin(1.0, 0.5 * sqrt(2.0 * om))) : 0.0;  // angle from the centre
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) dist = fmax(dist, __shfl_xor(dist, m, WAVE));
-    const double Ru = D.rho_max + dist + 1e-9;
-    const double zc = cos(thc), sc = sin(thc);
+    T.Ru = D.rho_max + dist + 1e-9;
+    return T;
+}
+
+// FP64 set-up of one union ring: its pixel interval within the cap and its
+// coefficients relative to the tile centre.  Returns the pixel count.
+__device__ __attribute__((noinline)) int32_t union_ring_setup(int32_t N, int32_t r, double phc, double zc, double sc,
+                                                             double cosRu, UnionRing &u) {
+    const RingGeom g = ring_geom(N, r);
+    const double a = g.s * zc - g.z * sc;
+    const double cdt = g.z * zc + g.s * sc;
+    int32_t jc = (int32_t)rint((phc - g.phi0) / g.dphi);
+    jc %= g.n;
+    if (jc < 0) jc += g.n;
+    double dphic = g.phi0 + (double)jc * g.dphi - phc;
+    if (dphic > PI) dphic -= TWO_PI;
+    else if (dphic < -PI) dphic += TWO_PI;
+    int32_t lo, k;
+    ring_interval(cosRu, zc, sc, g, dphic, lo, k);
+    u.a = (float)a;
+    u.b = (float)(g.s * zc);
+    u.c = (float)(g.s * sc);
+    u.e = (float)(a * a / (1.0 + cdt));
+    u.s = (float)g.s;
+    u.z = (float)g.z;
+    u.cdt = (float)cdt;
+    u.f = (float)(g.z * zc);
+    u.g = (float)(g.z * sc);
+    u.dphic = (float)dphic;
+    u.dphi = (float)g.dphi;
+    u.pad = 0.0f;
+    u.first = g.first;
+    u.n = g.n;
+    u.jc = jc;
+    u.lo = lo;
+    return k;
+}
+
+template <int MODE, int BEAM, int CH>
+__device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
+                              int lane) {
+    const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
+    const global_f4 beam = (global_f4)D.beam;
+    const int32_t N = (int32_t)A.nside;
+    const bool valid = lane < cnt;
+    const int64_t t = begin + (valid ? lane : 0);
+
+    LaneFrame F;
+    const TileFrame T = tile_setup(D, t, valid, F);
+    const double thc = uniform(T.thc), phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
+    const double Ru = uniform(T.Ru);
     const double cosRu = cos(Ru);
+    const float zcf = (float)zc, scf = (float)sc;
 
     const int32_t n = D.n;
     const float inv_h = (float)D.inv_h;
     const float c0 = (float)(0.5 * (n - 1));
     const float tmax = (float)(n - 1);
-    const double omax = D.omega_max, omin = D.omega_min;
+    const float omax = (float)D.omega_max, omin = (float)D.omega_min;
     const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
 
     Acc<float> acc0, acc1, acc2, accn;
-    int64_t npairs = 0;
+    int32_t npairs = 0;
 
     const int32_t nring = 4 * N - 1;
     const int32_t r_lo = (thc - Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, thc - Ru)) - 1);
     const int32_t r_hi = (thc + Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, thc + Ru)) + 1);
 
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
-        // union ring intervals, one ring per lane
         const int32_t r = rb + lane;
         int32_t rc = 0;
         if (r <= r_hi) {
-            const RingGeom g = ring_geom(N, r);
-            int32_t jc = (int32_t)rint((phc - g.phi0) / g.dphi);
-            jc %= g.n;
-            if (jc < 0) jc += g.n;
-            double dphic = g.phi0 + (double)jc * g.dphi - phc;
-            if (dphic > PI) dphic -= TWO_PI;
-            else if (dphic < -PI) dphic += TWO_PI;
-            int32_t lo, k;
-            ring_interval(cosRu, zc, sc, g, dphic, lo, k);
-            int32_t j0 = jc + lo;
-            j0 %= g.n;
-            if (j0 < 0) j0 += g.n;
             UnionRing u;
-            u.phi0 = g.phi0;
-            u.dphi = g.dphi;
-            u.z = g.z;
-            u.s = g.s;
-            u.first = g.first;
-            u.n = g.n;
-            u.j0 = j0;
-            u.cnt = k;
+            rc = union_ring_setup(N, r, phc, zc, sc, cosRu, u);
             L.ring[lane] = u;
-            rc = k;
         }
         const int32_t incl = wave_inclusive_scan(rc, lane);
         L.seg_end[lane] = incl;
-        const int32_t total = __shfl(incl, WAVE - 1, WAVE);
+        const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
         wave_sync();
 
         for (int32_t pb = 0; pb < total; pb += CH) {
             const int32_t m_end = min(CH, total - pb);
-            // fill: one pixel record per lane
+            // fill: one pixel record per lane, FP32 differences from the centre
             int32_t seg = 0;
             for (int32_t m = lane; m < m_end; m += WAVE) {
                 const int32_t f = pb + m;
                 while (f >= L.seg_end[seg]) ++seg;
                 const int32_t start = (seg == 0) ? 0 : L.seg_end[seg - 1];
                 const UnionRing &u = L.ring[seg];
-                int32_t j = u.j0 + (f - start);
-                if (j >= u.n) j -= u.n;
-                const double phi = u.phi0 + (double)j * u.dphi;
-                double sph, cph;
-                sincos(phi, &sph, &cph);
-                const double nx = u.s * cph, ny = u.s * sph, nz = u.z;
+                const int32_t rn = u.n, half = rn >> 1;
+                int32_t kk = u.lo + (f - start);
+                if (kk >= half) kk -= rn;
+                if (kk >= half) kk -= rn;
+                if (kk < -half) kk += rn;
+                int32_t j = u.jc + kk;
+                if (j < 0) j += rn;
+                else if (j >= rn) j -= rn;
+                const float dph = fmaf((float)kk, u.dphi, u.dphic);
+                float sh, ch;
+                half_sincos(0.5f * dph, sh, ch);
+                const float h = 2.0f * sh * sh;  // 1 - cos(dphi)
+                const float S = 2.0f * sh * ch;  // sin(dphi)
                 PixRec R;
-                R.X = nx * e1[0] + ny * e1[1] + nz * e1[2];
-                R.Y = nx * e2[0] + ny * e2[1];
-                const double ex = nx - c[0], ey = ny - c[1], ez = nz - c[2];
-                R.W = 0.5 * (ex * ex + ey * ey + ez * ez);
-                R.xf = (float)R.X;
-                R.yf = (float)R.Y;
-                R.zf = (float)(1.0 - R.W);
-                const double tx = u.z * cph, ty = u.z * sph, tz = -u.s;
-                R.tx = (float)(tx * e1[0] + ty * e1[1] + tz * e1[2]);
-                R.ty = (float)(tx * e2[0] + ty * e2[1]);
-                R.tz = (float)(tx * c[0] + ty * c[1] + tz * c[2]);
-                R.fx = (float)(-sph * e1[0] + cph * e1[1]);
-                R.fy = (float)(-sph * e2[0] + cph * e2[1]);
-                R.fz = (float)(-sph * c[0] + cph * c[1]);
+                R.X = fmaf(-u.b, h, u.a);
+                R.Y = u.s * S;
+                R.W = fmaf(u.c, h, u.e);
+                R.t1 = fmaf(-u.f, h, u.cdt);
+                R.t2 = u.z * S;
+                R.t3 = fmaf(-u.g, h, -u.a);
+                R.f1 = -zcf * S;
+                R.f2 = 1.0f - h;
+                R.f3 = -scf * S;
                 const float4 sv = sky[u.first + j];
                 if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
                     R.a = wI * sv.x;
@@ -632,49 +690,66 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
 
             // consume: every lane (sample) against every staged pixel
             if (valid) {
-                for (int32_t m = 0; m < m_end; ++m) {
-                    const PixRec &R = L.rec[m];
-                    const double omg = fma(-R.Y, p2, fma(-R.X, p1, fma(R.W, p3, om)));  // 1 - n.p
-                    if (omg > omax || (inner && !(omg > omin))) continue;
-                    if (MODE == MODE_COUNT) {
-                        ++npairs;
-                        continue;
+                if (MODE == MODE_COUNT) {
+                    for (int32_t m = 0; m < m_end; ++m) {
+                        const PixRec R = L.rec[m];
+                        const float omg = fmaf(-R.Y, F.p2, fmaf(-R.X, F.p1, fmaf(R.W, F.p3, F.om)));
+                        npairs += ((omg <= omax) && (!inner || omg > omin)) ? 1 : 0;
                     }
-                    const double xd = fma(R.Y, a2, fma(R.X, a1, fma(-R.W, a3, a3)));  // n . theta'_0
-                    const double yd = fma(R.Y, b2, fma(R.X, b1, fma(-R.W, b3, b3)));  // n . phi'_0
-                    const float wf = (float)omg;
-                    const float rz = rcp(1.0f - wf);
-                    const float tu = fmaf((float)xd * rz, inv_h, c0);
-                    const float tv = fmaf((float)yd * rz, inv_h, c0);
-                    if (clip && !(tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax)) continue;
-                    const int32_t iu = max(0, min((int32_t)tu, n - 2));
-                    const int32_t iv = max(0, min((int32_t)tv, n - 2));
-                    const float fu = tu - (float)iu, fv = tv - (float)iv;
-                    const BeamVals<float> bv = beam_lookup<float, BEAM>(D.beam, n, iu, iv, fu, fv);
-
-                    // co-polar vector carried from the boresight to the pixel along the great circle
-                    const float gn = fmaf(g1, R.xf, fmaf(g2, R.yf, g3 * R.zf));
-                    const float q = gn * rcp(2.0f - wf);
-                    const float ex = fmaf(-q, pf1 + R.xf, g1);
-                    const float ey = fmaf(-q, pf2 + R.yf, g2);
-                    const float ez = fmaf(-q, pf3 + R.zf, g3);
-                    const float cc = fmaf(ex, R.tx, fmaf(ey, R.ty, ez * R.tz));
-                    const float ss = fmaf(ex, R.fx, fmaf(ey, R.fy, ez * R.fz));
-                    const float c2 = fmaf(cc, cc, -ss * ss);
-                    const float s2 = 2.0f * cc * ss;
-                    accn.add(bv.bT);
-                    if (MODE == MODE_TOD) {
+                } else {
+                    for (int32_t m = 0; m < m_end; ++m) {
+                        const PixRec R = L.rec[m];
+                        const float omg = fmaf(-R.Y, F.p2, fmaf(-R.X, F.p1, fmaf(R.W, F.p3, F.om)));  // 1 - n.p
+                        bool in = (omg <= omax) && (!inner || omg > omin);
+                        const float nz = 1.0f - R.W;
+                        const float xp = fmaf(R.Y, F.a2, fmaf(R.X, F.a1, nz * F.a3));  // n . theta'_0
+                        const float yp = fmaf(R.Y, F.b2, fmaf(R.X, F.b1, nz * F.b3));  // n . phi'_0
+                        const float rz = rcp(1.0f - omg);
+                        const float tu = fmaf(xp * rz, inv_h, c0);
+                        const float tv = fmaf(yp * rz, inv_h, c0);
+                        if (clip) in = in && (tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax);
+                        const int32_t iu = max(0, min((int32_t)tu, n - 2));
+                        const int32_t iv = max(0, min((int32_t)tv, n - 2));
+                        const float fu = tu - (float)iu, fv = tv - (float)iv;
+                        float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
                         if (BEAM == BEAM_SCALAR) {
-                            acc0.add(bv.bT * fmaf(c2, R.b, fmaf(s2, R.c, R.a)));
+                            const float4 cl = ld4(beam, iv * (n - 1) + iu);
+                            bT = lerp(lerp(cl.x, cl.y, fu), lerp(cl.z, cl.w, fu), fv);
                         } else {
-                            const float bq = fmaf(bv.bQ, R.b, bv.bU * R.c);
-                            const float bu = fmaf(bv.bQ, R.c, -bv.bU * R.b);
-                            acc0.add(fmaf(bv.bI, R.a, fmaf(c2, bq, s2 * bu)));
+                            const int32_t nd = iv * n + iu;
+                            const float4 q00 = ld4(beam, nd), q10 = ld4(beam, nd + 1), q01 = ld4(beam, nd + n),
+                                         q11 = ld4(beam, nd + n + 1);
+                            bI = lerp(lerp(q00.x, q10.x, fu), lerp(q01.x, q11.x, fu), fv);
+                            bQ = lerp(lerp(q00.y, q10.y, fu), lerp(q01.y, q11.y, fu), fv);
+                            bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
+                            bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
                         }
-                    } else {
-                        acc0.add(bv.bT * R.a);
-                        acc1.add(bv.bT * fmaf(c2, R.b, s2 * R.c));
-                        acc2.add(bv.bT * fmaf(-s2, R.b, c2 * R.c));
+                        // co-polar vector carried from the boresight to the pixel along the great circle
+                        const float gn = fmaf(F.g1, R.X, fmaf(F.g2, R.Y, F.g3 * nz));
+                        const float q = gn * rcp(2.0f - omg);
+                        const float ex = fmaf(-q, F.p1 + R.X, F.g1);
+                        const float ey = fmaf(-q, F.p2 + R.Y, F.g2);
+                        const float ez = fmaf(-q, F.p3 + nz, F.g3);
+                        const float cc = fmaf(ex, R.t1, fmaf(ey, R.t2, ez * R.t3));
+                        const float ss = fmaf(ex, R.f1, fmaf(ey, R.f2, ez * R.f3));
+                        const float c2 = fmaf(cc, cc, -ss * ss);
+                        const float s2 = 2.0f * cc * ss;
+                        accn.add(in ? bT : 0.0f);
+                        if (MODE == MODE_TOD) {
+                            float term;
+                            if (BEAM == BEAM_SCALAR) {
+                                term = bT * fmaf(c2, R.b, fmaf(s2, R.c, R.a));
+                            } else {
+                                const float bq = fmaf(bQ, R.b, bU * R.c);
+                                const float bu = fmaf(bQ, R.c, -bU * R.b);
+                                term = fmaf(bI, R.a, fmaf(c2, bq, s2 * bu));
+                            }
+                            acc0.add(in ? term : 0.0f);
+                        } else {
+                            acc0.add(in ? bT * R.a : 0.0f);
+                            acc1.add(in ? bT * fmaf(c2, R.b, s2 * R.c) : 0.0f);
+                            acc2.add(in ? bT * fmaf(-s2, R.b, c2 * R.c) : 0.0f);
+                        }
                     }
                 }
             }
@@ -704,8 +779,8 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     }
 }
 
-// Whether a tile's discs overlap enough for the shared-union path: its samples
-// lie within `frac` disc radii of their mean direction.
+// Whether a group of consecutive samples overlaps enough for the tile path:
+// its samples lie within `frac` disc radii of their mean direction.
 __device__ inline bool tile_is_coherent(const DetDesc &D, int64_t begin, int32_t cnt, int lane, double frac) {
     const bool valid = lane < cnt;
     const int64_t t = begin + (valid ? lane : 0);
@@ -757,18 +832,17 @@ __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
 }
 
 template <int MODE, int BEAM, int CH>
-__global__ void __launch_bounds__(512) tile_kernel(ConvArgs A) {
+__global__ void __launch_bounds__(512, 4) tile_kernel(ConvArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = threadIdx.x / WAVE;
-    constexpr size_t slice = sizeof(TileLds<CH>) > sizeof(WaveLds<float>) ? sizeof(TileLds<CH>) : sizeof(WaveLds<float>);
-    unsigned char *mine = lds_raw + (size_t)wid * ((slice + 15) & ~size_t(15));
+    TileLds<CH> &L = reinterpret_cast<TileLds<CH> *>(lds_raw)[wid];
     int32_t q = (A.n_queues > 1) ? (int32_t)(blockIdx.x % (uint32_t)A.n_queues) : 0;
     int32_t exhausted = 0;
     while (exhausted < A.n_queues) {
         int32_t ti = 0;
         if (lane == 0) ti = atomicAdd(&A.counters[q], 1);
-        ti = __shfl(ti, 0, WAVE);
+        ti = __builtin_amdgcn_readfirstlane(__shfl(ti, 0, WAVE));
         if (ti >= A.queue_len[q]) {
             q = (q + 1 == A.n_queues) ? 0 : q + 1;
             ++exhausted;
@@ -776,22 +850,27 @@ __global__ void __launch_bounds__(512) tile_kernel(ConvArgs A) {
         }
         const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
         const DetDesc &D = A.dets[tl.det];
-        // tiles longer than a wave are taken 64 samples at a time
-        for (int64_t b = tl.begin; b < tl.begin + tl.count; b += WAVE) {
-            const int32_t cnt = (int32_t)min((int64_t)WAVE, tl.begin + tl.count - b);
-            if (tile_is_coherent(D, b, cnt, lane, A.coherence)) {
-                convolve_tile<MODE, BEAM, CH>(A, D, b, cnt, *reinterpret_cast<TileLds<CH> *>(mine), lane);
-            } else {
-                for (int64_t t = b; t < b + cnt; ++t)
-                    convolve_sample<float, MODE, BEAM>(A, D, t, *reinterpret_cast<WaveLds<float> *>(mine), lane);
-            }
-        }
+        convolve_tile<MODE, BEAM, CH>(A, D, tl.begin, tl.count, L, lane);
     }
 }
 
+// One wavefront per group of up to 64 consecutive samples: flag[g] = 1 when the
+// group is coherent enough for the tile path.
+__global__ void classify_kernel(const DetDesc *dets, const Tile *groups, int32_t n_groups, double frac,
+                                int32_t *flag) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int32_t g = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+    if (g >= n_groups) return;
+    const Tile tl = groups[g];
+    const bool ok = tile_is_coherent(dets[tl.det], tl.begin, tl.count, lane, frac);
+    if (lane == 0) flag[g] = ok ? 1 : 0;
+}
+
+// Clear the work counters of both queue sets: ints [0, 8) and [16, 24) of the
+// plan's control block ([8, 16) and [24, 32) hold the queue lengths).
 __global__ void zero_counters_kernel(int32_t *c, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) c[i] = 0;
+    if (i < n && (i & 8) == 0) c[i] = 0;
 }
 
 template <typename T>
@@ -851,8 +930,12 @@ static hipError_t launch_pixel(const ConvArgs &a, int waves, int groups, hipStre
 
 template <int MODE, int BEAM, int CH>
 static hipError_t launch_tile_t(const ConvArgs &a, int waves, int groups, hipStream_t s) {
-    constexpr size_t slice = sizeof(TileLds<CH>) > sizeof(WaveLds<float>) ? sizeof(TileLds<CH>) : sizeof(WaveLds<float>);
-    const size_t lds = ((slice + 15) & ~size_t(15)) * (size_t)waves;
+    const size_t lds = sizeof(TileLds<CH>) * (size_t)waves;
+    if (lds > 64 * 1024) {  // allow the larger LDS allocations of gfx950 (160 KiB per CU)
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_kernel<MODE, BEAM, CH>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL((tile_kernel<MODE, BEAM, CH>), dim3(groups), dim3(WAVE * waves), lds, s, a);
     return hipGetLastError();
 }
@@ -920,6 +1003,15 @@ hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, hi
     else
         hipLaunchKernelGGL(repack_cells_kernel<float>, dim3((unsigned)g), dim3(bs), 0, s, (const float *)b, n,
                            (float4 *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const DetDesc *dets, const Tile *groups, int32_t n_groups, double frac, int32_t *flag,
+                           hipStream_t s) {
+    if (n_groups <= 0) return hipSuccess;
+    const int per_block = 4;
+    const unsigned blocks = (unsigned)((n_groups + per_block - 1) / per_block);
+    hipLaunchKernelGGL(classify_kernel, dim3(blocks), dim3(WAVE * per_block), 0, s, dets, groups, n_groups, frac, flag);
     return hipGetLastError();
 }
 

@@ -64,6 +64,8 @@ hipError_t launch_conv(const ConvArgs &a, bool f64, int waves_per_group, int gro
 hipError_t launch_repack4(const void *a, const void *b, const void *c, const void *d, void *out, int64_t n,
                           bool f64, hipStream_t s);
 hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, hipStream_t s);
+hipError_t launch_classify(const DetDesc *dets, const Tile *groups, int32_t n_groups, double frac, int32_t *flag,
+                           hipStream_t s);
 hipError_t launch_check_pointing(const double *theta, const double *phi, const double *psi, int64_t n,
                                  int32_t *bad, hipStream_t s);
 

@@ -42,20 +42,30 @@ struct TimedLaunch {
 
 }  // namespace
 
-// A device-side launch plan: detector descriptors, tile queues, work counters
-// and (for the batched plan) the captured graph.  The context keeps one plan
-// for single-detector launches and one for the batched launch so that eager
-// single-detector calls never invalidate the captured batched graph.
+// A set of work queues: tiles[q * per + i], with 8 counters and 8 lengths in
+// the plan's control block.
+struct Queues {
+    Tile *d_tiles = nullptr;
+    size_t cap = 0;
+    int32_t per = 1, nq = 1;
+    int64_t ntiles = 0;
+};
+
+// A device-side launch plan: detector descriptors, the tile-path and
+// pixel-path work queues, and (for the batched plan) the captured graph.  The
+// context keeps one plan for single-detector launches and one for the batched
+// launch so that eager single-detector calls never invalidate the graph.
 struct Plan {
     DetDesc *d_dets = nullptr;
     size_t d_dets_cap = 0;
-    Tile *d_tiles = nullptr;
-    size_t d_tiles_cap = 0;
-    int32_t *d_ctrl = nullptr;  // [0..8) counters, [8..16) queue lengths
+    Queues tq, pq;              // tile path (coherent 64-sample groups), pixel path
+    int32_t *d_ctrl = nullptr;  // [0,8) tq counters, [8,16) tq lengths, [16,24) pq counters, [24,32) pq lengths
+    int32_t *d_scratch = nullptr;
+    size_t scratch_cap = 0;     // bytes
     uint64_t gen = 0;
     int32_t det = -2;
-    int32_t spt = 0, xq = 0;
-    int32_t tiles_per_queue = 0, queues = 1;
+    int32_t spt = 0, xq = 0, algo = -1;
+    double coherence = 0.0;
     int64_t out_samples = 0;
     int32_t beam_kind = 0;
     // captured launch
@@ -64,8 +74,7 @@ struct Plan {
     void *g_out = nullptr;
     hipStream_t g_stream = nullptr;
     int g_mode = -1;
-    int32_t g_wpg = 0, g_gpc = 0, g_algo = -1, g_chunk = 0;
-    double g_coh = 0.0;
+    int32_t g_wpg = 0, g_gpc = 0, g_chunk = 0;
 };
 
 struct pisco_ctx {
@@ -156,8 +165,10 @@ void drop_graph(Plan &p) {
 void free_plan(Plan &p) {
     drop_graph(p);
     if (p.d_dets) (void)hipFree(p.d_dets);
-    if (p.d_tiles) (void)hipFree(p.d_tiles);
+    if (p.tq.d_tiles) (void)hipFree(p.tq.d_tiles);
+    if (p.pq.d_tiles) (void)hipFree(p.pq.d_tiles);
     if (p.d_ctrl) (void)hipFree(p.d_ctrl);
+    if (p.d_scratch) (void)hipFree(p.d_scratch);
     p = Plan();
 }
 
@@ -225,9 +236,24 @@ bool grow(pisco_ctx *c, T **p, size_t *cap, size_t need) {
     return true;
 }
 
+// Split tiles into nq contiguous blocks, one per queue.
+void fill_queues(const std::vector<Tile> &tiles, int nq, std::vector<Tile> &qt, int32_t *len, int32_t &per) {
+    const size_t ntile = tiles.size();
+    per = std::max<int32_t>(1, (int32_t)((ntile + nq - 1) / nq));
+    qt.assign((size_t)per * nq, Tile{});
+    for (int q = 0; q < 8; ++q) len[q] = 0;
+    for (int q = 0; q < nq; ++q) {
+        const size_t b = std::min(ntile, (size_t)q * per), e = std::min(ntile, b + per);
+        for (size_t i = b; i < e; ++i) qt[(size_t)q * per + (i - b)] = tiles[i];
+        len[q] = (int32_t)(e - b);
+    }
+}
+
 // Build and upload the tile plan for `det` (-1 = all ready detectors).
 pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
-    if (p.gen == c->generation && p.det == det && p.spt == c->spt && p.xq == c->xq) return PISCO_OK;
+    if (p.gen == c->generation && p.det == det && p.spt == c->spt && p.xq == c->xq && p.algo == c->algo &&
+        p.coherence == c->coherence)
+        return PISCO_OK;
     std::vector<DetDesc> descs;
     int64_t out_off = 0;
     const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
@@ -259,70 +285,120 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         out_off += d.nsamp;
         p.beam_kind = d.beam_kind;
     }
-    // tiles in (detector, time) order, then split into contiguous queue blocks
-    std::vector<Tile> tiles;
+    hipError_t e = hipDeviceSynchronize();  // no launch may still read the old plan
+    if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "synchronise failed: %s", hipGetErrorString(e));
+    if (!p.d_ctrl && hipMalloc(&p.d_ctrl, 32 * sizeof(int32_t)) != hipSuccess)
+        return fail(c, PISCO_ENOMEM, "plan allocation failed");
+    if (!grow(c, &p.d_dets, &p.d_dets_cap, std::max<size_t>(descs.size(), 1)))
+        return fail(c, PISCO_ENOMEM, "plan allocation failed");
+    if (!descs.empty()) HIP_TRY(c, hipMemcpy(p.d_dets, descs.data(), descs.size() * sizeof(DetDesc), hipMemcpyHostToDevice));
+
+    // groups of up to 64 consecutive samples; on the tile path each group is
+    // classified on the device as coherent (tile kernel) or not (pixel kernel)
+    std::vector<Tile> groups;
     for (size_t i = 0; i < descs.size(); ++i)
-        for (int64_t b = 0; b < descs[i].n_samples; b += c->spt) {
+        for (int64_t b = 0; b < descs[i].n_samples; b += 64) {
             Tile t;
             t.det = (int32_t)i;
             t.begin = b;
-            t.count = (int32_t)std::min<int64_t>(c->spt, descs[i].n_samples - b);
-            tiles.push_back(t);
+            t.count = (int32_t)std::min<int64_t>(64, descs[i].n_samples - b);
+            groups.push_back(t);
         }
-    const int nq = std::max<int32_t>(1, std::min<int32_t>(c->xq, 8));
-    const size_t ntile = tiles.size();
-    const int32_t per = std::max<int32_t>(1, (int32_t)((ntile + nq - 1) / nq));
-    std::vector<Tile> qt((size_t)per * nq);
-    int32_t ctrl[16] = {0};
-    for (int q = 0; q < nq; ++q) {
-        const size_t b = std::min(ntile, (size_t)q * per), e = std::min(ntile, b + per);
-        for (size_t i = b; i < e; ++i) qt[(size_t)q * per + (i - b)] = tiles[i];
-        ctrl[8 + q] = (int32_t)(e - b);
+    std::vector<int32_t> flag(groups.size(), 0);
+    const bool tile_path = (c->algo == PISCO_ALGO_TILE) && (c->sky_dtype == PISCO_F32);
+    if (tile_path && !groups.empty()) {
+        const size_t need = groups.size() * (sizeof(Tile) + sizeof(int32_t));
+        if (p.scratch_cap < need) {
+            if (p.d_scratch) (void)hipFree(p.d_scratch);
+            p.d_scratch = nullptr;
+            p.scratch_cap = 0;
+            if (hipMalloc(&p.d_scratch, need) != hipSuccess) return fail(c, PISCO_ENOMEM, "plan scratch allocation failed");
+            p.scratch_cap = need;
+        }
+        Tile *dg = reinterpret_cast<Tile *>(p.d_scratch);
+        int32_t *df = reinterpret_cast<int32_t *>(dg + groups.size());
+        HIP_TRY(c, hipMemcpy(dg, groups.data(), groups.size() * sizeof(Tile), hipMemcpyHostToDevice));
+        HIP_TRY(c, pisco::launch_classify(p.d_dets, dg, (int32_t)groups.size(), c->coherence, df, nullptr));
+        HIP_TRY(c, hipMemcpy(flag.data(), df, groups.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     }
-    hipError_t e = hipDeviceSynchronize();  // no launch may still read the old plan
-    if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "synchronise failed: %s", hipGetErrorString(e));
-    if (!p.d_ctrl && hipMalloc(&p.d_ctrl, 16 * sizeof(int32_t)) != hipSuccess)
+    std::vector<Tile> ttiles, ptiles;
+    for (size_t g = 0; g < groups.size(); ++g) {
+        if (flag[g]) {
+            ttiles.push_back(groups[g]);
+            continue;
+        }
+        // pixel path: merge runs of incoherent groups of one detector, then cut into spt-sample tiles
+        const Tile &x = groups[g];
+        if (!ptiles.empty() && ptiles.back().det == x.det && ptiles.back().begin + ptiles.back().count == x.begin &&
+            ptiles.back().count < c->spt) {
+            Tile &b = ptiles.back();
+            const int32_t room = c->spt - b.count, take = std::min(room, x.count);
+            b.count += take;
+            if (take < x.count) {
+                Tile t;
+                t.det = x.det;
+                t.begin = x.begin + take;
+                t.count = x.count - take;
+                ptiles.push_back(t);
+            }
+        } else {
+            ptiles.push_back(x);
+        }
+    }
+    const int nq = std::max<int32_t>(1, std::min<int32_t>(c->xq, 8));
+    int32_t lens[32] = {0};
+    std::vector<Tile> tq, pq;
+    fill_queues(ttiles, nq, tq, lens + 8, p.tq.per);
+    fill_queues(ptiles, nq, pq, lens + 24, p.pq.per);
+    if (!grow(c, &p.tq.d_tiles, &p.tq.cap, tq.size()) || !grow(c, &p.pq.d_tiles, &p.pq.cap, pq.size()))
         return fail(c, PISCO_ENOMEM, "plan allocation failed");
-    if (!grow(c, &p.d_dets, &p.d_dets_cap, std::max<size_t>(descs.size(), 1)) ||
-        !grow(c, &p.d_tiles, &p.d_tiles_cap, qt.size()))
-        return fail(c, PISCO_ENOMEM, "plan allocation failed");
-    if (!descs.empty()) HIP_TRY(c, hipMemcpy(p.d_dets, descs.data(), descs.size() * sizeof(DetDesc), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(p.d_tiles, qt.data(), qt.size() * sizeof(Tile), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(p.d_ctrl, ctrl, sizeof(ctrl), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(p.tq.d_tiles, tq.data(), tq.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(p.pq.d_tiles, pq.data(), pq.size() * sizeof(Tile), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(p.d_ctrl, lens, sizeof(lens), hipMemcpyHostToDevice));
+    p.tq.nq = p.pq.nq = nq;
+    p.tq.ntiles = (int64_t)ttiles.size();
+    p.pq.ntiles = (int64_t)ptiles.size();
     p.gen = c->generation;
     p.det = det;
     p.spt = c->spt;
     p.xq = c->xq;
-    p.tiles_per_queue = per;
-    p.queues = nq;
+    p.algo = c->algo;
+    p.coherence = c->coherence;
     p.out_samples = out_off;
     drop_graph(p);
     return PISCO_OK;
 }
 
-ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode) {
+ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode, bool tile) {
     ConvArgs a{};
+    const Queues &q = tile ? p.tq : p.pq;
     a.sky = c->sky;
     a.dets = p.d_dets;
-    a.tiles = p.d_tiles;
-    a.counters = p.d_ctrl;
-    a.queue_len = p.d_ctrl + 8;
+    a.tiles = q.d_tiles;
+    a.counters = p.d_ctrl + (tile ? 0 : 16);
+    a.queue_len = p.d_ctrl + (tile ? 8 : 24);
     a.out = out;
     a.nside = c->nside;
-    a.n_queues = p.queues;
-    a.tiles_per_queue = p.tiles_per_queue;
+    a.n_queues = q.nq;
+    a.tiles_per_queue = q.per;
     a.out_mode = out_mode;
     a.beam_kind = p.beam_kind;
-    a.algo = c->algo;
+    a.algo = tile ? pisco::ALGO_TILE : pisco::ALGO_PIXEL;
     a.chunk = c->chunk;
     a.coherence = c->coherence;
     return a;
 }
 
-hipError_t enqueue(pisco_ctx *c, const Plan &p, const ConvArgs &a, hipStream_t s) {
-    hipError_t e = pisco::launch_zero_counters(p.d_ctrl, 8, s);
+hipError_t enqueue(pisco_ctx *c, const Plan &p, void *out, int out_mode, hipStream_t s) {
+    hipError_t e = pisco::launch_zero_counters(p.d_ctrl, 32, s);
     if (e != hipSuccess) return e;
-    return pisco::launch_conv(a, c->sky_dtype == PISCO_F64, c->wpg, c->gpc * c->num_cu, s);
+    const bool f64 = c->sky_dtype == PISCO_F64;
+    if (p.tq.ntiles > 0) {
+        e = pisco::launch_conv(make_args(c, p, out, out_mode, true), f64, c->wpg, c->gpc * c->num_cu, s);
+        if (e != hipSuccess) return e;
+    }
+    if (p.pq.ntiles > 0) e = pisco::launch_conv(make_args(c, p, out, out_mode, false), f64, c->wpg, c->gpc * c->num_cu, s);
+    return e;
 }
 
 }  // namespace
@@ -620,7 +696,6 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
         if (hipMalloc(&dout, el_bytes(c->sky_dtype) * (size_t)nout) != hipSuccess)
             return fail(c, PISCO_ENOMEM, "output staging allocation failed");
     }
-    const ConvArgs a = make_args(c, p, dout, out_mode);
     TimedLaunch tl{};
     if (c->timing) {
         HIP_TRY(c, hipEventCreate(&tl.a));
@@ -631,13 +706,12 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
     const bool use_graph = (det < 0) && (s != nullptr);
     if (use_graph) {
         if (!p.gexec || p.g_gen != p.gen || p.g_out != dout || p.g_stream != s || p.g_mode != out_mode ||
-            p.g_wpg != c->wpg || p.g_gpc != c->gpc || p.g_algo != c->algo || p.g_chunk != c->chunk ||
-            p.g_coh != c->coherence) {
+            p.g_wpg != c->wpg || p.g_gpc != c->gpc || p.g_chunk != c->chunk) {
             drop_graph(p);
             hipGraph_t g = nullptr;
             e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t e1 = enqueue(c, p, a, s);
+                const hipError_t e1 = enqueue(c, p, dout, out_mode, s);
                 e = hipStreamEndCapture(s, &g);
                 if (e1 != hipSuccess) e = e1;
             }
@@ -650,16 +724,14 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
                 p.g_mode = out_mode;
                 p.g_wpg = c->wpg;
                 p.g_gpc = c->gpc;
-                p.g_algo = c->algo;
                 p.g_chunk = c->chunk;
-                p.g_coh = c->coherence;
             } else {
                 p.gexec = nullptr;
             }
         }
         if (e == hipSuccess) e = hipGraphLaunch(p.gexec, s);
     } else {
-        e = enqueue(c, p, a, s);
+        e = enqueue(c, p, dout, out_mode, s);
     }
     if (e != hipSuccess) {
         if (mem == PISCO_HOST) (void)hipFree(dout);

@@ -161,10 +161,17 @@ def test_annulus_stokes_fixed(conv, torch, dtype, tol, algo, scan):
         outs = []
         for k in range(3):
             if mode == oracle.OUT_TOD and k == 0:
-                # pixel counts are integers: exact against the oracle's own disc scan
-                cnt = conv.convolve(k, out_mode=2).cpu().numpy()
+                # pixel counts are integers.  The pixel path decides membership in
+                # FP64 like the oracle: exact.  The tile path decides it in FP32 on
+                # differences from the tile centre: a pixel within ~1e-7 of the
+                # disc edge may flip, so at most a rare +-1.
+                cnt = conv.convolve(k, out_mode=2).cpu().numpy().astype(np.int64)
                 want_cnt = np.array([oracle.disc(nside, a, b, 20 * D2R).size for a, b in zip(th, ph)])
-                assert np.array_equal(cnt.astype(np.int64), want_cnt)
+                if algo == 0:
+                    assert np.array_equal(cnt, want_cnt)
+                else:
+                    d = np.abs(cnt - want_cnt)
+                    assert d.max() <= 1 and (d > 0).mean() <= 0.01
             got = conv.convolve(k, out_mode=mode).cpu().numpy()
             want = oracle_detector(w, k, slice(None), dtype, out_mode=mode)
             e = rel_err(got, want)
