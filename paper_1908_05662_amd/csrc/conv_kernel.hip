@@ -371,12 +371,15 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
             const T xp = fma(cpsi, nth, spsi * nph);
             const T yp = fma(-spsi, nth, cpsi * nph);
             const T rz = rcp((T)1 - omz);
-            const T tu = fma(xp * rz, inv_h, c0);
-            const T tv = fma(yp * rz, inv_h, c0);
+            const T su = xp * rz, sv = yp * rz;  // gnomonic u, v
+            const T tu = fma(su, inv_h, c0);
+            const T tv = fma(sv, inv_h, c0);
             if (!(tu >= (T)0 && tu <= tmax && tv >= (T)0 && tv <= tmax)) continue;
             const int32_t iu = min((int32_t)tu, n - 2);
             const int32_t iv = min((int32_t)tv, n - 2);
-            const T fu = tu - (T)iu, fv = tv - (T)iv;
+            // fraction relative to the chosen node in one rounding (tu itself is
+            // rounded at the scale of the grid offset c0)
+            const T fu = fma(su, inv_h, c0 - (T)iu), fv = fma(sv, inv_h, c0 - (T)iv);
             const BeamVals<T> bv = beam_lookup<T, BEAM>(D.beam, n, iu, iv, fu, fv);
             const R4 pix = sky[R.first + j];
 
@@ -705,12 +708,13 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         const float xp = fmaf(R.Y, F.a2, fmaf(R.X, F.a1, nz * F.a3));  // n . theta'_0
                         const float yp = fmaf(R.Y, F.b2, fmaf(R.X, F.b1, nz * F.b3));  // n . phi'_0
                         const float rz = rcp(1.0f - omg);
-                        const float tu = fmaf(xp * rz, inv_h, c0);
-                        const float tv = fmaf(yp * rz, inv_h, c0);
+                        const float su = xp * rz, sv = yp * rz;  // gnomonic u, v
+                        const float tu = fmaf(su, inv_h, c0);
+                        const float tv = fmaf(sv, inv_h, c0);
                         if (clip) in = in && (tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax);
                         const int32_t iu = max(0, min((int32_t)tu, n - 2));
                         const int32_t iv = max(0, min((int32_t)tv, n - 2));
-                        const float fu = tu - (float)iu, fv = tv - (float)iv;
+                        const float fu = fmaf(su, inv_h, c0 - (float)iu), fv = fmaf(sv, inv_h, c0 - (float)iv);
                         float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
                         if (BEAM == BEAM_SCALAR) {
                             const float4 cl = ld4(beam, iv * (n - 1) + iu);
