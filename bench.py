@@ -43,6 +43,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter runs, or None once the kernel source has changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_conv_c3.json")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["traffic_bytes_per_launch"] if sha == rec["source_sha256"] else None
+
+
 def load(conv, w, torch):
     from paper_1908_05662_amd.beamsor import fold_elements, scalar_weights
 
@@ -199,7 +213,7 @@ def main():
         "macs_per_s": pairs / (ms_step / 1e3),
         "kernel_ms": k_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_pair": flops_per_pair},
         "cpu_baseline": cpu,
         "parity_max_rel_err": parity,

@@ -280,7 +280,9 @@ int orc_tod(int64_t nside, const double *I, const double *Q, const double *U,
 #else
     (void)nthreads;
 #endif
-    #pragma omp parallel for schedule(dynamic, 16)
+    /* one sample costs ~1e5-1e7 flops: hand them out one at a time so that
+       small calls still spread over every thread */
+    #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nsamp; ++t)
         one_sample(nside, I, Q, U, n, T, grid, zeta, eps, s_resp, rho_min, rho_max, norm_mode, norm_scale,
                    theta[t], phi[t], psi[t], out_mode, out + t * width);

@@ -137,14 +137,15 @@ __device__ inline void half_sincos(float x, float &s, float &c) {
 }
 __device__ inline void half_sincos(double x, double &s, double &c) { sincos(x, &s, &c); }
 
-// Per-lane accumulator: compensated (TwoSum) in FP32, plain in FP64.
+// Per-lane accumulator: compensated (Kahan) in FP32, plain in FP64.  The
+// compensated sum is s - c.
 template <typename T> struct Acc;
 template <> struct Acc<float> {
     float s = 0.0f, c = 0.0f;
     __device__ inline void add(float x) {
-        const float t = s + x;
-        const float bp = t - s;
-        c += (s - (t - bp)) + (x - bp);
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
         s = t;
     }
     __device__ inline void wave_reduce() {
@@ -156,7 +157,7 @@ template <> struct Acc<float> {
             c += oc;
         }
     }
-    __device__ inline double value() const { return (double)s + (double)c; }
+    __device__ inline double value() const { return (double)s - (double)c; }
 };
 template <> struct Acc<double> {
     double s = 0.0;
@@ -483,13 +484,6 @@ struct UnionRing {
     int32_t first, n, jc, lo;   // pixels k = lo .. lo + cnt - 1 counted from the pixel nearest the centre
 };
 
-template <int CH>
-struct TileLds {
-    UnionRing ring[WAVE];
-    int32_t seg_end[WAVE];
-    PixRec rec[CH];
-};
-
 // Per-lane sample frame in the tile frame (all FP32; the small quantities keep
 // relative precision because they are formed in FP64 first).
 struct LaneFrame {
@@ -497,6 +491,17 @@ struct LaneFrame {
     float a1, a2, a3;       // theta'_0
     float b1, b2, b3;       // phi'_0
     float g1, g2, g3;       // co-polar direction at the boresight
+};
+
+// The set-up helpers below are not inlined (their FP64 constants must not be
+// hoisted into the pixel loops); they write their per-lane results straight
+// into this LDS slice instead of returning them through the stack.
+template <int CH>
+struct TileLds {
+    UnionRing ring[WAVE];
+    LaneFrame lane[WAVE];
+    int32_t seg_end[WAVE];
+    PixRec rec[CH];
 };
 
 struct TileFrame {
@@ -507,7 +512,7 @@ struct TileFrame {
 // radius, and each lane's sample expressed in the frame (e1, e2, c) with
 // e1 = theta_hat(c), e2 = phi_hat(c).  Not inlined: its transcendental
 // constants stay out of the pixel loops.
-__device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int64_t t, bool valid, LaneFrame &F) {
+__device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int64_t t, bool valid, LaneFrame *out) {
     const double th0 = D.theta[t], ph0 = D.phi[t], ps0 = D.psi[t];
     double st, ct, sf, cf, sp, cp, sg, cg;
     sincos(th0, &st, &ct);
@@ -546,6 +551,7 @@ __device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int6
         tb[i] = -sp * th[i] + cp * ph[i];  // phi'_0
         tg[i] = cg * th[i] + sg * ph[i];   // co-polar direction at the boresight
     }
+    LaneFrame F;
     F.om = (float)om;
     F.p1 = (float)(p[0] * e1[0] + p[1] * e1[1] + p[2] * e1[2]);
     F.p2 = (float)(p[0] * e2[0] + p[1] * e2[1]);
@@ -559,6 +565,7 @@ __device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int6
     F.g1 = (float)(tg[0] * e1[0] + tg[1] * e1[1] + tg[2] * e1[2]);
     F.g2 = (float)(tg[0] * e2[0] + tg[1] * e2[1]);
     F.g3 = (float)(tg[0] * c[0] + tg[1] * c[1] + tg[2] * c[2]);
+    *out = F;
     double dist = valid ? 2.0 * asin(fmin(1.0, 0.5 * sqrt(2.0 * om))) : 0.0;  // angle from the centre
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) dist = fmax(dist, __shfl_xor(dist, m, WAVE));
@@ -569,7 +576,7 @@ __device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int6
 // FP64 set-up of one union ring: its pixel interval within the cap and its
 // coefficients relative to the tile centre.  Returns the pixel count.
 __device__ __attribute__((noinline)) int32_t union_ring_setup(int32_t N, int32_t r, double phc, double zc, double sc,
-                                                             double cosRu, UnionRing &u) {
+                                                             double cosRu, UnionRing *out) {
     const RingGeom g = ring_geom(N, r);
     const double a = g.s * zc - g.z * sc;
     const double cdt = g.z * zc + g.s * sc;
@@ -581,6 +588,7 @@ __device__ __attribute__((noinline)) int32_t union_ring_setup(int32_t N, int32_t
     else if (dphic < -PI) dphic += TWO_PI;
     int32_t lo, k;
     ring_interval(cosRu, zc, sc, g, dphic, lo, k);
+    UnionRing u;
     u.a = (float)a;
     u.b = (float)(g.s * zc);
     u.c = (float)(g.s * sc);
@@ -597,6 +605,7 @@ __device__ __attribute__((noinline)) int32_t union_ring_setup(int32_t N, int32_t
     u.n = g.n;
     u.jc = jc;
     u.lo = lo;
+    *out = u;
     return k;
 }
 
@@ -609,8 +618,8 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const bool valid = lane < cnt;
     const int64_t t = begin + (valid ? lane : 0);
 
-    LaneFrame F;
-    const TileFrame T = tile_setup(D, t, valid, F);
+    const TileFrame T = tile_setup(D, t, valid, &L.lane[lane]);
+    const LaneFrame F = L.lane[lane];
     const double thc = uniform(T.thc), phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
     const double Ru = uniform(T.Ru);
     const double cosRu = cos(Ru);
@@ -623,6 +632,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float omax = (float)D.omega_max, omin = (float)D.omega_min;
     const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
+    const bool per_sample = D.norm_mode == 1;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
 
     Acc<float> acc0, acc1, acc2, accn;
@@ -635,11 +645,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
         const int32_t r = rb + lane;
         int32_t rc = 0;
-        if (r <= r_hi) {
-            UnionRing u;
-            rc = union_ring_setup(N, r, phc, zc, sc, cosRu, u);
-            L.ring[lane] = u;
-        }
+        if (r <= r_hi) rc = union_ring_setup(N, r, phc, zc, sc, cosRu, &L.ring[lane]);
         const int32_t incl = wave_inclusive_scan(rc, lane);
         L.seg_end[lane] = incl;
         const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
@@ -738,7 +744,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         const float ss = fmaf(ex, R.f1, fmaf(ey, R.f2, ez * R.f3));
                         const float c2 = fmaf(cc, cc, -ss * ss);
                         const float s2 = 2.0f * cc * ss;
-                        accn.add(in ? bT : 0.0f);
+                        if (per_sample) accn.add(in ? bT : 0.0f);
                         if (MODE == MODE_TOD) {
                             float term;
                             if (BEAM == BEAM_SCALAR) {

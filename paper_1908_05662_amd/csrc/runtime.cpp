@@ -762,7 +762,7 @@ pisco_status pisco_set_launch(pisco_ctx *c, const pisco_launch *l) {
     if (l->chunk != 64 && l->chunk != 128 && l->chunk != 256) return fail(c, PISCO_EINVAL, "chunk must be 64, 128 or 256");
     if (!(l->coherence > 0.0 && l->coherence <= 4.0)) return fail(c, PISCO_EINVAL, "coherence must be in (0, 4]");
     // LDS per workgroup must fit the 160 KiB of a compute unit
-    const size_t tile_slice = 64 * 48 + 64 * 4 + (size_t)l->chunk * 72;
+    const size_t tile_slice = 64 * 64 + 64 * 52 + 64 * 4 + (size_t)l->chunk * 48;
     if (l->algorithm == PISCO_ALGO_TILE && tile_slice * (size_t)w > 160 * 1024)
         return fail(c, PISCO_EINVAL, "chunk %d with %d waves per group exceeds the LDS of a compute unit", l->chunk, w);
     c->algo = l->algorithm;
