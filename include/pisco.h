@@ -207,6 +207,53 @@ pisco_status pisco_get_launch(const pisco_ctx *ctx, pisco_launch *launch);
 pisco_status pisco_set_timing(pisco_ctx *ctx, int on);
 pisco_status pisco_kernel_time(pisco_ctx *ctx, double *total_ms, int64_t *launches, int reset);
 
+/* ------------------------------------------------------------------------
+ * Far-sidelobe surrogate network.
+ *
+ * The exact wide-disc convolution is the reference for a learned stand-in of
+ * the far sidelobe: an MLP maps a pointing (unit vector, sin psi, cos psi) to
+ * the detector-frame Stokes pickup (OUT_STOKES) of the sidelobe annulus, so
+ * that TOD = exact main-beam TOD + sum_c coef[c] * pickup[c].  Weights are
+ * used in BF16 with FP32 accumulation on the matrix cores; FP32 master
+ * weights and Adam moments live on the device.
+ *
+ * Network: 5 -> [width, SiLU] x hidden_layers -> 3.  Parameters are one FP32
+ * array: for each linear map l = 0..hidden_layers, W_l (rows x cols,
+ * row-major, rows = output units) followed by b_l; pisco_mlp_layout gives the
+ * offsets.  All data pointers below are device pointers unless `mem` says
+ * otherwise; x is [n][5], targets and outputs [n][3], float32.
+ * ------------------------------------------------------------------------ */
+typedef struct pisco_mlp pisco_mlp;
+
+/* width: multiple of 64 in [64, 512]; max_batch: multiple of 64 (rows per
+ * internal pass); seed: initial weights U(-1/sqrt(fan_in), 1/sqrt(fan_in)),
+ * zero biases.  Errors are reported through pisco_last_error(ctx). */
+pisco_status pisco_mlp_create(pisco_ctx *ctx, int32_t width, int32_t hidden_layers, int32_t max_batch, uint64_t seed,
+                              pisco_mlp **out);
+void pisco_mlp_destroy(pisco_mlp *mlp);
+int64_t pisco_mlp_param_count(const pisco_mlp *mlp);
+pisco_status pisco_mlp_layout(const pisco_mlp *mlp, int32_t layer, int64_t *w_offset, int64_t *b_offset,
+                              int32_t *rows, int32_t *cols);
+/* Replace the FP32 master weights (host or device); resets the Adam state. */
+pisco_status pisco_mlp_set_params(pisco_mlp *mlp, const float *params, int mem);
+pisco_status pisco_mlp_get_params(const pisco_mlp *mlp, float *params, int mem);
+/* Inference with the BF16 weights, any n >= 0. */
+pisco_status pisco_mlp_forward(pisco_mlp *mlp, const float *x, int64_t n, float *y, void *stream);
+/* Mean squared error over the n x 3 outputs and its gradient (FP32, parameter
+ * layout) for one batch, without updating; n a multiple of 64, <= max_batch. */
+pisco_status pisco_mlp_gradient(pisco_mlp *mlp, const float *x, const float *targets, int32_t n, float *grad,
+                                float *loss, void *stream);
+/* One Adam step on that loss (bias-corrected; lr, beta1, beta2, eps as usual). */
+pisco_status pisco_mlp_train_step(pisco_mlp *mlp, const float *x, const float *targets, int32_t n, float lr,
+                                  float beta1, float beta2, float eps, float *loss, void *stream);
+/* Features of detector `det`'s pointing: x[t] = (sin th cos ph, sin th sin ph, cos th, sin psi, cos psi). */
+pisco_status pisco_sidelobe_features(pisco_ctx *ctx, int32_t det, float *x, void *stream);
+/* tod[t] += sum_c coef[c] (mean[c] + stdv[c] y[t][c]) with y the network's
+ * output for detector `det`'s pointing; mean, stdv (3 floats) and coef (3
+ * doubles) are host arrays, tod a device float array of the detector's samples. */
+pisco_status pisco_sidelobe_apply(pisco_ctx *ctx, pisco_mlp *mlp, int32_t det, const float *mean, const float *stdv,
+                                  const double *coef, float *tod, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

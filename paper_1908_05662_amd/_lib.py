@@ -48,6 +48,19 @@ SIGNATURES = [
     ("pisco_get_launch", ctypes.c_int, [_vp, ctypes.c_void_p]),
     ("pisco_set_timing", ctypes.c_int, [_vp, ctypes.c_int]),
     ("pisco_kernel_time", ctypes.c_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64), ctypes.c_int]),
+    ("pisco_mlp_create", ctypes.c_int, [_vp, _i32, _i32, _i32, ctypes.c_uint64, ctypes.POINTER(_vp)]),
+    ("pisco_mlp_destroy", None, [_vp]),
+    ("pisco_mlp_param_count", _i64, [_vp]),
+    ("pisco_mlp_layout", ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _ip, _ip]),
+    ("pisco_mlp_set_params", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    ("pisco_mlp_get_params", ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    ("pisco_mlp_forward", ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    ("pisco_mlp_gradient", ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    ("pisco_mlp_train_step", ctypes.c_int, [_vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                            ctypes.c_float, _vp, _vp]),
+    ("pisco_sidelobe_features", ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    ("pisco_sidelobe_apply", ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_float),
+                                            ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_dbl), _vp, _vp]),
 ]
 
 _lib = None

@@ -175,3 +175,96 @@ class Convolver:
         ms, k = ctypes.c_double(), ctypes.c_int64()
         self._check(self._lib.pisco_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(k), int(reset)))
         return ms.value, k.value
+
+
+class Mlp:
+    """Far-sidelobe network on the convolver's device (``pisco_mlp_*``)."""
+
+    def __init__(self, conv: Convolver, width: int = 256, hidden_layers: int = 4, max_batch: int = 16384,
+                 seed: int = 0):
+        self.conv = conv
+        self._lib = conv._lib
+        h = ctypes.c_void_p()
+        conv._check(self._lib.pisco_mlp_create(conv._h, int(width), int(hidden_layers), int(max_batch),
+                                               ctypes.c_uint64(seed), ctypes.byref(h)))
+        self._h = h
+        self.width, self.hidden, self.max_batch = int(width), int(hidden_layers), int(max_batch)
+        self.n_params = int(self._lib.pisco_mlp_param_count(h))
+        torch = _torch()
+        dev = conv.torch_device
+        self._loss = torch.zeros(1, dtype=torch.float32, device=dev)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pisco_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self, stream):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.conv.torch_device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def layout(self, layer: int):
+        wo, bo = ctypes.c_int64(), ctypes.c_int64()
+        r, c = ctypes.c_int32(), ctypes.c_int32()
+        self.conv._check(self._lib.pisco_mlp_layout(self._h, int(layer), ctypes.byref(wo), ctypes.byref(bo),
+                                                    ctypes.byref(r), ctypes.byref(c)))
+        return wo.value, bo.value, r.value, c.value
+
+    def get_params(self):
+        torch = _torch()
+        out = torch.empty(self.n_params, dtype=torch.float32)
+        self.conv._check(self._lib.pisco_mlp_get_params(self._h, out.data_ptr(), L.HOST))
+        return out
+
+    def set_params(self, params):
+        torch = _torch()
+        t = self.conv._as_tensor(params, torch.float32).reshape(-1)
+        if t.numel() != self.n_params:
+            raise ValueError("wrong parameter count")
+        self.conv._check(self._lib.pisco_mlp_set_params(self._h, t.data_ptr(), self.conv._mem(t)))
+
+    def forward(self, x, stream=None):
+        torch = _torch()
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], 3), dtype=torch.float32, device=x.device)
+        self.conv._check(self._lib.pisco_mlp_forward(self._h, x.data_ptr(), x.shape[0], y.data_ptr(),
+                                                     self._stream(stream)))
+        return y
+
+    def gradient(self, x, t, stream=None):
+        torch = _torch()
+        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
+        self.conv._check(self._lib.pisco_mlp_gradient(self._h, x.contiguous().data_ptr(), t.contiguous().data_ptr(),
+                                                      x.shape[0], g.data_ptr(), self._loss.data_ptr(),
+                                                      self._stream(stream)))
+        return self._loss.clone(), g
+
+    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        """One Adam step; returns the (device) loss tensor of the batch before the update."""
+        self.conv._check(self._lib.pisco_mlp_train_step(self._h, x.data_ptr(), t.data_ptr(), x.shape[0],
+                                                        float(lr), float(beta1), float(beta2), float(eps),
+                                                        self._loss.data_ptr(), self._stream(stream)))
+        return self._loss
+
+    def features(self, det: int, stream=None):
+        torch = _torch()
+        n = self.conv.output_samples(det)
+        x = torch.empty((n, 5), dtype=torch.float32, device=self.conv.torch_device)
+        self.conv._check(self._lib.pisco_sidelobe_features(self.conv._h, int(det), x.data_ptr(),
+                                                           self._stream(stream)))
+        return x
+
+    def apply(self, det: int, mean, std, coef, tod, stream=None):
+        m = (ctypes.c_float * 3)(*[float(v) for v in mean])
+        s = (ctypes.c_float * 3)(*[float(v) for v in std])
+        c = (ctypes.c_double * 3)(*[float(v) for v in coef])
+        self.conv._check(self._lib.pisco_sidelobe_apply(self.conv._h, self._h, int(det), m, s, c, tod.data_ptr(),
+                                                        self._stream(stream)))
+        return tod

@@ -1,0 +1,34 @@
+// Internal declarations of the sidelobe-network kernels (mlp_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MLP_IN 5
+#define MLP_OUT 3
+
+namespace pisco {
+
+enum { MLP_EPI_FWD = 0, MLP_EPI_BWD_D = 1, MLP_EPI_BWD_W = 2 };
+
+hipError_t mlp_in_fwd(const float *x, const __bf16 *w0, const float *b0, int32_t n, int32_t H, float *z, __bf16 *a,
+                      hipStream_t s);
+hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t asm_, int64_t ask, const __bf16 *b, int64_t bsk, int64_t bsn,
+                    int32_t M, int32_t N, int32_t K, int32_t k_slice, const float *bias, float *z_out, __bf16 *a_out,
+                    const float *z_prev, float *partial, hipStream_t s);
+hipError_t mlp_out(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n, int32_t H,
+                   float *y, const float *tgt, float inv_count, __bf16 *dz, float *part_w, float *part_b,
+                   float *part_loss, int32_t waves, int32_t rows_per_wave, hipStream_t s);
+hipError_t mlp_colsum(const __bf16 *m, int32_t n, int32_t H, int32_t rows, int32_t blocks, float *part, hipStream_t s);
+hipError_t mlp_in_grad(const __bf16 *dz, const float *x, int32_t n, int32_t H, int32_t rows, int32_t blocks,
+                       float *part, hipStream_t s);
+hipError_t mlp_reduce(const float *part, int32_t slices, int64_t count, float *out, hipStream_t s);
+hipError_t mlp_adam(float *w, float *m, float *v, const float *g, __bf16 *wb, int64_t count, float lr_t, float b1,
+                    float b2, float eps, float inv_bc2_sqrt, hipStream_t s);
+hipError_t mlp_to_bf16(const float *w, __bf16 *wb, int64_t count, hipStream_t s);
+hipError_t mlp_loss_sum(const float *part, int32_t count, float inv_count, float *loss, hipStream_t s);
+hipError_t mlp_features(const double *th, const double *ph, const double *ps, int64_t n, float *x, hipStream_t s);
+hipError_t mlp_apply(const float *y, int64_t n, const float *mean, const float *stdv, const double *coef, float *tod,
+                     hipStream_t s);
+
+}  // namespace pisco

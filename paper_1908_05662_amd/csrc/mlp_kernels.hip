@@ -1,0 +1,400 @@
+// Far-sidelobe surrogate network on gfx950: BF16 weights and activations,
+// FP32 accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Network: x (5) -> [Linear + SiLU] x L -> Linear -> y (3), hidden width H.
+// Input features are the pointing unit vector and (sin psi, cos psi); the
+// outputs are the standardised Stokes pickup of the far sidelobe.
+//
+// Kernels
+//   in_fwd      layer 0 (K = 5) on the vector ALU: Z1 = X W0^T + b0, A1 = SiLU(Z1)
+//   gemm        H x H layers on MFMA, three operand layouts:
+//                 FWD   Z = A W^T + b -> Z (fp32), SiLU(Z) (bf16)
+//                 BWD_D dZ_prev = (dZ W) * SiLU'(Z_prev)   (bf16)
+//                 BWD_W partial dW = dZ^T A over one batch slice (fp32, split-K)
+//   out_fwd_bwd output layer (N = 3): Y, MSE loss, dY, dZ_L = (dY W_out) * SiLU'(Z_L),
+//               per-block partial sums of dW_out and db_out
+//   colsum      per-block partial column sums (bias gradients)
+//   in_grad     per-block partials of dW0 = dZ1^T X
+//   reduce      fixed-order sums of partials (deterministic gradients)
+//   adam        Adam on FP32 master weights, refreshing the BF16 copy
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mlp_internal.h"
+
+namespace pisco {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float silu_grad(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// ----------------------------------------------------------------------
+// GEMM: C[M x N] = A[M x K] B[K x N], element (m, k) of A at a[m*asm + k*ask],
+// element (k, n) of B at b[k*bsk + n*bsn]; M, N multiples of 64, K of 32.
+// Workgroup tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA 16x16x32 tiles).
+// ----------------------------------------------------------------------
+constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;  // padded LDS rows
+
+enum { EPI_FWD = MLP_EPI_FWD, EPI_BWD_D = MLP_EPI_BWD_D, EPI_BWD_W = MLP_EPI_BWD_W };
+
+struct GemmArgs {
+    const __bf16 *a;
+    const __bf16 *b;
+    int64_t asm_, ask, bsk, bsn;
+    int32_t M, N, K;
+    int32_t k_slice;       // split-K slice length (multiple of 32)
+    const float *bias;     // FWD
+    float *z_out;          // FWD: pre-activation (ldc = N)
+    __bf16 *a_out;         // FWD: SiLU(Z); BWD_D: dZ_prev
+    const float *z_prev;   // BWD_D: pre-activation of the previous layer
+    float *partial;        // BWD_W: [slice][M][N]
+};
+
+// Load a 64 x 32 tile of an operand into LDS as rows[r][k] (r = m or n), where
+// the tile's element (r, k) sits at p[r*sr + k*sk].
+__device__ inline void load_tile(const __bf16 *__restrict__ p, int64_t sr, int64_t sk, int r0, int k0,
+                                 __bf16 (*dst)[LDK], int tid) {
+    if (sk == 1) {
+        // 8 consecutive k per thread: one 16-byte load
+        const int r = tid >> 2, kk = (tid & 3) * 8;
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(p + (int64_t)(r0 + r) * sr + (k0 + kk));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[r][kk + i] = v[i];
+    } else {
+        // rows contiguous (sr == 1): 8 consecutive r per thread for one k
+        const int kk = tid >> 3, r = (tid & 7) * 8;
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(p + (int64_t)(k0 + kk) * sk + (r0 + r));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[r + i][kk] = v[i];
+    }
+}
+
+template <int EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+    __shared__ __align__(16) __bf16 As[TM][LDK];
+    __shared__ __align__(16) __bf16 Bs[TN][LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int kb = blockIdx.z * g.k_slice, ke = min(g.K, kb + g.k_slice);
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+        load_tile(g.a, g.asm_, g.ask, m0, k0, As, tid);
+        load_tile(g.b, g.bsn, g.bsk, n0, k0, Bs, tid);
+        __syncthreads();
+        const int r = lane & 15, kq = (lane >> 4) * 8;
+        bf16x8 af[2], bfr[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + r][kq]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * j + r][kq]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+
+    // epilogue: lane holds C[row0 + 4 (lane/16) + q][col0 + lane%16], q = 0..3
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
+                const int col = n0 + wn + 16 * j + (lane & 15);
+                const float v = acc[i][j][q];
+                const int64_t o = (int64_t)row * g.N + col;
+                if (EPI == EPI_FWD) {
+                    const float z = v + g.bias[col];
+                    g.z_out[o] = z;
+                    g.a_out[o] = (__bf16)silu(z);
+                } else if (EPI == EPI_BWD_D) {
+                    g.a_out[o] = (__bf16)(v * silu_grad(g.z_prev[o]));
+                } else {
+                    g.partial[(int64_t)blockIdx.z * g.M * g.N + o] = v;
+                }
+            }
+}
+
+// ----------------------------------------------------------------------
+// Small layers and reductions
+// ----------------------------------------------------------------------
+// Layer 0: one thread per (row, unit).  W0 is [H][5] (bf16-rounded).
+__global__ void in_fwd_kernel(const float *x, const __bf16 *w0, const float *b0, int32_t n, int32_t H, float *z,
+                              __bf16 *a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * H) return;
+    const int64_t r = i / H;
+    const int u = (int)(i % H);
+    float s = b0[u];
+#pragma unroll
+    for (int k = 0; k < MLP_IN; ++k) s = fmaf(x[r * MLP_IN + k], (float)w0[u * MLP_IN + k], s);
+    if (z) z[i] = s;
+    a[i] = (__bf16)silu(s);
+}
+
+// Output layer with loss: one wave per row, lanes over the H units (H % 64 == 0).
+// Writes y; if targets are given also the loss partial, dY, dZ_L and per-wave
+// partials of dW_out [3][H] and db_out [3].
+__global__ void out_kernel(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n,
+                           int32_t H, float *y, const float *tgt, float inv_count, __bf16 *dz, float *part_w,
+                           float *part_b, float *part_loss, int32_t waves, int32_t rows_per_wave) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (wv >= waves) return;
+    const int per = H / 64;
+    float gw[MLP_OUT][8];
+    float gb[MLP_OUT] = {0.0f, 0.0f, 0.0f};
+    float gl = 0.0f;
+#pragma unroll
+    for (int c = 0; c < MLP_OUT; ++c)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) gw[c][k] = 0.0f;
+    for (int64_t r = wv * rows_per_wave; r < min((int64_t)n, (wv + 1) * rows_per_wave); ++r) {
+        float av[8], s[MLP_OUT] = {0.0f, 0.0f, 0.0f};
+        for (int k = 0; k < per; ++k) {
+            const int u = lane + 64 * k;
+            av[k] = (float)a[r * H + u];
+#pragma unroll
+            for (int c = 0; c < MLP_OUT; ++c) s[c] = fmaf(av[k], (float)wout[c * H + u], s[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < MLP_OUT; ++c) {
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) s[c] += __shfl_xor(s[c], m, 64);
+            s[c] += bout[c];
+        }
+        if (lane == 0)
+            for (int c = 0; c < MLP_OUT; ++c) y[r * MLP_OUT + c] = s[c];
+        if (!tgt) continue;
+        float dy[MLP_OUT];
+#pragma unroll
+        for (int c = 0; c < MLP_OUT; ++c) {
+            const float e = s[c] - tgt[r * MLP_OUT + c];
+            gl += e * e;
+            dy[c] = 2.0f * e * inv_count;
+            gb[c] += dy[c];
+        }
+        for (int k = 0; k < per; ++k) {
+            const int u = lane + 64 * k;
+            float da = 0.0f;
+#pragma unroll
+            for (int c = 0; c < MLP_OUT; ++c) {
+                da = fmaf(dy[c], (float)wout[c * H + u], da);
+                gw[c][k] = fmaf(dy[c], av[k], gw[c][k]);
+            }
+            dz[r * H + u] = (__bf16)(da * silu_grad(zL[r * H + u]));
+        }
+    }
+    if (!tgt) return;
+    for (int k = 0; k < per; ++k)
+#pragma unroll
+        for (int c = 0; c < MLP_OUT; ++c) part_w[(wv * MLP_OUT + c) * H + lane + 64 * k] = gw[c][k];
+    if (lane == 0) {
+        for (int c = 0; c < MLP_OUT; ++c) part_b[wv * MLP_OUT + c] = gb[c];
+        part_loss[wv] = gl;  // lane 0 saw every row's error (the sums were reduced)
+    }
+}
+
+// Per-block partial column sums of a [n][H] bf16 matrix: block b covers rows
+// [b*rows, (b+1)*rows), thread u sums column u (blockDim = H).
+__global__ void colsum_kernel(const __bf16 *m, int32_t n, int32_t H, int32_t rows, float *part) {
+    const int u = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min((int64_t)n, r0 + rows);
+    float s = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) s += (float)m[r * H + u];
+    part[(int64_t)blockIdx.x * H + u] = s;
+}
+
+// Per-block partials of dW0 = dZ1^T X: thread u of block b sums over its rows.
+__global__ void in_grad_kernel(const __bf16 *dz, const float *x, int32_t n, int32_t H, int32_t rows, float *part) {
+    const int u = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min((int64_t)n, r0 + rows);
+    float s[MLP_IN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t r = r0; r < r1; ++r) {
+        const float d = (float)dz[r * H + u];
+#pragma unroll
+        for (int k = 0; k < MLP_IN; ++k) s[k] = fmaf(d, x[r * MLP_IN + k], s[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < MLP_IN; ++k) part[((int64_t)blockIdx.x * H + u) * MLP_IN + k] = s[k];
+}
+
+// out[i] = sum_s part[s * count + i] in order s = 0, 1, ...
+__global__ void reduce_kernel(const float *part, int32_t slices, int64_t count, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.0f;
+    for (int k = 0; k < slices; ++k) s += part[(int64_t)k * count + i];
+    out[i] = s;
+}
+
+// Adam on FP32 master weights (bias-corrected step size given), BF16 copy refreshed.
+__global__ void adam_kernel(float *w, float *m, float *v, const float *g, __bf16 *wb, int64_t count, float lr_t,
+                            float b1, float b2, float eps, float inv_bc2_sqrt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr_t * mi / (sqrtf(vi) * inv_bc2_sqrt + eps);
+    w[i] = wi;
+    wb[i] = (__bf16)wi;
+}
+
+__global__ void to_bf16_kernel(const float *w, __bf16 *wb, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) wb[i] = (__bf16)w[i];
+}
+
+__global__ void loss_sum_kernel(const float *part, int32_t count, float inv_count, float *loss) {
+    // one wave; fixed order
+    const int lane = threadIdx.x;
+    float s = 0.0f;
+    for (int i = lane; i < count; i += 64) s += part[i];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
+    if (lane == 0) *loss = s * inv_count;
+}
+
+// Features of a pointing stream: (sin th cos ph, sin th sin ph, cos th, sin psi, cos psi).
+__global__ void features_kernel(const double *th, const double *ph, const double *ps, int64_t n, float *x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double st, ct, sf, cf, sp, cp;
+    sincos(th[i], &st, &ct);
+    sincos(ph[i], &sf, &cf);
+    sincos(ps[i], &sp, &cp);
+    x[i * 5 + 0] = (float)(st * cf);
+    x[i * 5 + 1] = (float)(st * sf);
+    x[i * 5 + 2] = (float)ct;
+    x[i * 5 + 3] = (float)sp;
+    x[i * 5 + 4] = (float)cp;
+}
+
+// tod[i] += sum_c coef[c] (mean[c] + std[c] y[i][c])
+__global__ void apply_kernel(const float *y, int64_t n, float m0, float m1, float m2, float s0, float s1, float s2,
+                             double c0, double c1, double c2, float *tod) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double p0 = m0 + (double)s0 * y[i * 3 + 0];
+    const double p1 = m1 + (double)s1 * y[i * 3 + 1];
+    const double p2 = m2 + (double)s2 * y[i * 3 + 2];
+    tod[i] = (float)((double)tod[i] + c0 * p0 + c1 * p1 + c2 * p2);
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ----------------------------------------------------------------------
+// Launch wrappers
+// ----------------------------------------------------------------------
+hipError_t mlp_in_fwd(const float *x, const __bf16 *w0, const float *b0, int32_t n, int32_t H, float *z, __bf16 *a,
+                      hipStream_t s) {
+    const int64_t tot = (int64_t)n * H;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(in_fwd_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, x, w0, b0, n, H, z, a);
+    return hipGetLastError();
+}
+
+hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t asm_, int64_t ask, const __bf16 *b, int64_t bsk, int64_t bsn,
+                    int32_t M, int32_t N, int32_t K, int32_t k_slice, const float *bias, float *z_out, __bf16 *a_out,
+                    const float *z_prev, float *partial, hipStream_t s) {
+    GemmArgs g;
+    g.a = a;
+    g.b = b;
+    g.asm_ = asm_;
+    g.ask = ask;
+    g.bsk = bsk;
+    g.bsn = bsn;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.k_slice = k_slice;
+    g.bias = bias;
+    g.z_out = z_out;
+    g.a_out = a_out;
+    g.z_prev = z_prev;
+    g.partial = partial;
+    const dim3 grid(N / TN, M / TM, (K + k_slice - 1) / k_slice);
+    if (epi == EPI_FWD) hipLaunchKernelGGL(gemm_kernel<EPI_FWD>, grid, dim3(256), 0, s, g);
+    else if (epi == EPI_BWD_D) hipLaunchKernelGGL(gemm_kernel<EPI_BWD_D>, grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL(gemm_kernel<EPI_BWD_W>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t mlp_out(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n, int32_t H,
+                   float *y, const float *tgt, float inv_count, __bf16 *dz, float *part_w, float *part_b,
+                   float *part_loss, int32_t waves, int32_t rows_per_wave, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const int wpb = 4;
+    hipLaunchKernelGGL(out_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, a, zL, wout, bout,
+                       n, H, y, tgt, inv_count, dz, part_w, part_b, part_loss, waves, rows_per_wave);
+    return hipGetLastError();
+}
+
+hipError_t mlp_colsum(const __bf16 *m, int32_t n, int32_t H, int32_t rows, int32_t blocks, float *part, hipStream_t s) {
+    hipLaunchKernelGGL(colsum_kernel, dim3(blocks), dim3(H), 0, s, m, n, H, rows, part);
+    return hipGetLastError();
+}
+
+hipError_t mlp_in_grad(const __bf16 *dz, const float *x, int32_t n, int32_t H, int32_t rows, int32_t blocks,
+                       float *part, hipStream_t s) {
+    hipLaunchKernelGGL(in_grad_kernel, dim3(blocks), dim3(H), 0, s, dz, x, n, H, rows, part);
+    return hipGetLastError();
+}
+
+hipError_t mlp_reduce(const float *part, int32_t slices, int64_t count, float *out, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, part, slices, count, out);
+    return hipGetLastError();
+}
+
+hipError_t mlp_adam(float *w, float *m, float *v, const float *g, __bf16 *wb, int64_t count, float lr_t, float b1,
+                    float b2, float eps, float inv_bc2_sqrt, hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, w, m, v, g, wb, count, lr_t, b1, b2,
+                       eps, inv_bc2_sqrt);
+    return hipGetLastError();
+}
+
+hipError_t mlp_to_bf16(const float *w, __bf16 *wb, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, w, wb, count);
+    return hipGetLastError();
+}
+
+hipError_t mlp_loss_sum(const float *part, int32_t count, float inv_count, float *loss, hipStream_t s) {
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(64), 0, s, part, count, inv_count, loss);
+    return hipGetLastError();
+}
+
+hipError_t mlp_features(const double *th, const double *ph, const double *ps, int64_t n, float *x, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, th, ph, ps, n, x);
+    return hipGetLastError();
+}
+
+hipError_t mlp_apply(const float *y, int64_t n, const float *mean, const float *stdv, const double *coef, float *tod,
+                     hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(apply_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, y, n, mean[0], mean[1], mean[2],
+                       stdv[0], stdv[1], stdv[2], coef[0], coef[1], coef[2], tod);
+    return hipGetLastError();
+}
+
+}  // namespace pisco

@@ -403,6 +403,23 @@ hipError_t enqueue(pisco_ctx *c, const Plan &p, void *out, int out_mode, hipStre
 
 }  // namespace
 
+namespace pisco {
+void set_error(pisco_ctx *c, const char *msg) {
+    if (c) c->err = msg;
+}
+int ctx_device(const pisco_ctx *c) { return c->device; }
+bool ctx_pointing(const pisco_ctx *c, int32_t det, const double **th, const double **ph, const double **ps,
+                  int64_t *n) {
+    if (det < 0 || (size_t)det >= c->dets.size() || !c->dets[det].has_pointing) return false;
+    const DetState &d = c->dets[det];
+    *th = d.th;
+    *ph = d.ph;
+    *ps = d.ps;
+    *n = d.nsamp;
+    return true;
+}
+}  // namespace pisco
+
 extern "C" {
 
 int pisco_abi_version(void) { return 100; }
