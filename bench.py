@@ -110,6 +110,36 @@ def cpu_baseline(w, got, seconds):
     return n, dt, err, per_det
 
 
+def surrogate_leg(epochs):
+    """Exact main beam + trained far-sidelobe network against the exact 20 deg
+    disc on the nside-256 far-sidelobe workload: 1e6 training and 1e6 held-out
+    pointings uniform on the sphere (put in spatial order), error judged by the
+    exact annulus convolution."""
+    from paper_1908_05662_amd import surrogate as SG
+    from paper_1908_05662_amd.api import Convolver
+    from synth import workloads as W
+
+    def ordered(w):
+        d = w.detectors[0]
+        o = SG.spatial_order(d.theta, d.phi)
+        return d.theta[o], d.phi[o], d.psi[o]
+
+    wtr = W.c4(1_000_000, stream=1)
+    wte = W.c4(1_000_000, stream=2, sky=wtr.sky)
+    d = wtr.detectors[0]
+    T, g = W.sidelobe_beam(401, 20.0, 1.0)
+    conv = Convolver(0)
+    r = SG.experiment(conv, wtr.nside, wtr.sky, g, T, (d.det.zeta, d.det.eps, d.det.s), d.norm_scale,
+                      wtr.meta["r_main"], d.rho_max, ordered(wtr), ordered(wte), epochs=epochs)
+    conv.close()
+    r["workload"] = ("nside-256 smooth sky, 401^2 beam over +-20 deg (1 deg Gaussian + -40 dB ring at 10 deg), "
+                     "main disc 5 deg, annulus (5, 20] deg; network 5 -> 4 x 256 SiLU -> 3, BF16 weights")
+    r["error_unit"] = "RMS(d_sl_hat - d_sl) / RMS(d_main) on held-out samples"
+    log(f"surrogate: sidelobe error {r['sidelobe_error']:.3e} (main only {r['main_only_error']:.3e}), "
+        f"{r['samples_per_s_surrogate']:.4g} vs exact {r['samples_per_s_exact']:.4g} samples/s")
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +150,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
     ap.add_argument("--launch", type=str, default="", help="key=value,... fields of pisco_launch")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the far-sidelobe surrogate leg")
+    ap.add_argument("--surrogate-epochs", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the path is data-parallel over "
@@ -208,7 +240,7 @@ def main():
         "dtype": "f32 (f64 geometry set-up)",
         "data": "synthetic",
         "config": {"workload": "nside-1024 batched detectors: 64 dets, 201^2 elliptical beams, CES scan, "
-                               "disc 2 deg (configs[2])", "samples": n, "pairs": pairs,
+                               "disc 2 deg", "samples": n, "pairs": pairs,
                    "launch": launch, "beam": kind},
         "macs_per_s": pairs / (ms_step / 1e3),
         "kernel_ms": k_ms,
@@ -218,9 +250,12 @@ def main():
         "cpu_baseline": cpu,
         "parity_max_rel_err": parity,
     }
-    print(json.dumps(rec), flush=True)
     conv.close()
-    del keep
+    del keep, out
+    torch.cuda.empty_cache()
+    if not args.no_surrogate:
+        rec["surrogate"] = surrogate_leg(args.surrogate_epochs)
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -38,7 +38,7 @@ BEAMS = ["full", "auto"]  # four-channel grid, one-grid (scalar) form
 
 
 def test_c1_fp64_full_stream(conv, torch):
-    """configs[0] at full size: 1e5 samples, FP64 kernel, every sample vs the oracle."""
+    """nside-64 FP64 workload at full size: 1e5 samples, FP64 kernel, every sample vs the oracle."""
     say("case: c1 fp64 1e5 samples")
     w = W.c1()
     load_workload(conv, w, np.float64)
@@ -66,7 +66,7 @@ def test_c1_fp32_mixed(conv, torch, algo, beam):
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("beam", BEAMS)
 def test_c2_fp32_sampled(conv, torch, algo, beam):
-    """configs[1] shape (nside 512, 201^2 elliptical beam, CES) on 2e5 samples;
+    """Precision workload shape (nside 512, 201^2 elliptical beam, CES) on 2e5 samples;
     the oracle checks an evenly spread subset."""
     say(f"case: c2 fp32 2e5 samples, 1500 checked, algo {algo} beam {beam}")
     w = W.c2(n_samples=200_000)
