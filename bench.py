@@ -151,6 +151,8 @@ def main():
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
     ap.add_argument("--launch", type=str, default="", help="key=value,... fields of pisco_launch")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the far-sidelobe surrogate leg")
+    ap.add_argument("--tune", choices=("auto", "off", "force"), default="auto",
+                    help="launch-shape autotuning: auto = use the cached shape or search once, force = search again")
     ap.add_argument("--surrogate-epochs", type=int, default=40)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -170,6 +172,15 @@ def main():
     log(f"workload c3: {len(w.detectors)} detectors, {w.n_samples} samples, setup {time.perf_counter() - t0:.1f}s")
     conv = Convolver(0)
     keep, kind = load(conv, w, torch)
+    tuned = None
+    if args.tune != "off":
+        from paper_1908_05662_amd.autotune import tune
+
+        cache = os.path.join(ROOT, "paper_1908_05662_amd", "launch.tune.json")
+        tuned = tune(conv, -1, subsample=0.25, cache=cache, force=(args.tune == "force"), extra_key="batched-1024",
+                     log=log)
+        log(f"autotune: {tuned['launch']} ({tuned['speedup']:.3f}x over the default on the subsample, "
+            f"{'cached' if tuned['cached'] else 'searched'} in {tuned['seconds']:.1f}s)")
     if args.launch:
         kv = dict(x.split("=") for x in args.launch.split(","))
         conv.set_launch(**{k: (float(v) if k == "coherence" else int(v)) for k, v in kv.items()})
@@ -248,6 +259,8 @@ def main():
                      "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "flops_per_pair": flops_per_pair},
         "cpu_baseline": cpu,
+        "autotune": None if tuned is None else {k: tuned[k] for k in ("launch", "ms", "default_ms", "speedup",
+                                                                        "cached", "seconds", "subsample")},
         "parity_max_rel_err": parity,
     }
     conv.close()
