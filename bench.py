@@ -24,17 +24,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic work per (sample, disc pixel) pair, counted from each path's pair
-# arithmetic (FMA = 2 flops; reciprocals, compares and conversions count 1):
-#  tile path, one-grid beam, TOD: FP64 membership 1 - n.p 6, FP64 rotation into
-#  the antenna frame 12, gnomonic projection 2, grid coordinates 6, fractions 2,
-#  bilinear 9, position angle (co-polar vector carried along the great circle,
-#  projected on the pixel basis, doubled) 32, contraction 5, two compensated
-#  accumulations 12 -> 86.
+# arithmetic (FMA = 2; reciprocals, clamps, floors and single ops count 1;
+# compares, selects and address arithmetic are not counted):
+#  tile path, one-grid beam, TOD: membership 1 - n.p 6, rotation into the
+#  antenna frame 12, gnomonic projection (1 - z', reciprocal, two products) 4,
+#  grid coordinates, clamps and fractions 14, bilinear cell polynomial 6,
+#  position angle (co-polar vector carried along the great circle, projected
+#  on the pixel basis, doubled angle) 32, contraction 5, compensated
+#  accumulation 4 -> 83.
 #  pixel path, four-channel beam, TOD: longitude offset 3, half-angle sin/cos
 #  polynomials 29, h and sin(dphi) 4, offsets from the boresight 5, rotation 6,
 #  projection 3, grid 12, position angle 34, bilinear x4 channels 36, Stokes
 #  rotation 6, contraction 5, accumulations 12 -> 155.
-FLOPS_PER_PAIR = {(1, "scalar"): 86, (1, "full"): 113, (0, "scalar"): 128, (0, "full"): 155}
+FLOPS_PER_PAIR = {(1, "scalar"): 83, (1, "full"): 113, (0, "scalar"): 128, (0, "full"): 155}
 # vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 (FMA)
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 

@@ -98,7 +98,7 @@ pisco_status pisco_set_sky(pisco_ctx *ctx, int64_t nside, const void *I, const v
 
 /*
  * Effective beam of detector `det` (0 <= det < PISCO_MAX_DETECTORS): an n x n
- * grid (n odd, 3..8191) of nodes at u, v in [-T, T] (T = half_span_tan > 0),
+ * grid (n odd, 3..4095) of nodes at u, v in [-T, T] (T = half_span_tan > 0),
  * node (iu, iv) at (-T + iu h, -T + iv h) with h = 2T/(n-1), row-major [iv][iu].
  * bI, bQ, bU, bT are the channels described above, n*n elements of `dtype`
  * each, which must equal the sky's dtype at convolve time.  Between nodes the
@@ -250,7 +250,10 @@ pisco_status pisco_mlp_train_step(pisco_mlp *mlp, const float *x, const float *t
 pisco_status pisco_sidelobe_features(pisco_ctx *ctx, int32_t det, float *x, void *stream);
 /* tod[t] += sum_c coef[c] (mean[c] + stdv[c] y[t][c]) with y the network's
  * output for detector `det`'s pointing; mean, stdv (3 floats) and coef (3
- * doubles) are host arrays, tod a device float array of the detector's samples. */
+ * doubles) are host arrays, tod a device float array of the detector's samples.
+ * One fused launch (features, every layer and the sum on chip, no scratch
+ * memory); the result equals features + pisco_mlp_forward + the sum above,
+ * bit for bit.  Asynchronous on `stream`. */
 pisco_status pisco_sidelobe_apply(pisco_ctx *ctx, pisco_mlp *mlp, int32_t det, const float *mean, const float *stdv,
                                   const double *coef, float *tod, void *stream);
 

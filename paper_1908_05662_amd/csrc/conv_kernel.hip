@@ -238,8 +238,9 @@ __device__ inline BeamVals<T> beam_lookup(const void *beam, int32_t n, int32_t i
         o.bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
         o.bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
     } else {
+        // cell record (b00, b10 - b00, b01 - b00, b11 - b10 - b01 + b00)
         const R4 c = g[iv * (n - 1) + iu];
-        o.bT = lerp(lerp(c.x, c.y, fu), lerp(c.z, c.w, fu), fv);
+        o.bT = fma(fv, fma(fu, c.w, c.z), fma(fu, c.y, c.x));
         o.bI = o.bQ = o.bU = o.bT;
     }
     return o;
@@ -460,13 +461,21 @@ __device__ inline double uniform(double x) {
     return __longlong_as_double(((unsigned long long)hi << 32) | lo);
 }
 
-// Beam records read through a global-address-space pointer (global rather
-// than flat loads).
-typedef float f4v __attribute__((ext_vector_type(4)));
-typedef const f4v __attribute__((address_space(1))) *global_f4;
-__device__ inline float4 ld4(global_f4 p, int32_t i) {
-    const f4v v = p[i];
-    return make_float4(v.x, v.y, v.z, v.w);
+// Beam records through a buffer resource (word 3 = raw 32-bit data format on
+// gfx9-family parts): the offset is a 32-bit VGPR, the base stays in SGPRs.
+struct BeamRsrc {
+    __amdgpu_buffer_rsrc_t r;
+};
+__device__ inline BeamRsrc make_beam_rsrc(const void *p, uint32_t nrec) {
+    const unsigned long long a = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    void *u = (void *)(((unsigned long long)hi << 32) | lo);
+    return BeamRsrc{__builtin_amdgcn_make_buffer_rsrc(u, (short)0, (int)(nrec * 16u), 0x00020000)};
+}
+__device__ inline float4 beam_ld(const BeamRsrc &b, uint32_t off, int32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)off, soff, 0);
+    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
 }
 
 struct PixRec {
@@ -609,11 +618,10 @@ __device__ __attribute__((noinline)) int32_t union_ring_setup(int32_t N, int32_t
     return k;
 }
 
-template <int MODE, int BEAM, int CH>
+template <int MODE, int BEAM, int CH, bool PS>
 __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
                               int lane) {
     const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
-    const global_f4 beam = (global_f4)D.beam;
     const int32_t N = (int32_t)A.nside;
     const bool valid = lane < cnt;
     const int64_t t = begin + (valid ? lane : 0);
@@ -632,8 +640,15 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float omax = (float)D.omega_max, omin = (float)D.omega_min;
     const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
-    const bool per_sample = D.norm_mode == 1;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
+    const float cmax = (float)(n - 2);          // largest cell index
+    const float row = (float)(BEAM == BEAM_SCALAR ? n - 1 : n);
+    const float pp3 = F.p3 + 1.0f;
+    // beam records through a buffer resource: 32-bit byte offsets, reads past
+    // the end return zero
+    const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n - 1) * (n - 1) : n * n);
+    const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
+    const int32_t row_bytes = (int32_t)(16 * n);
 
     Acc<float> acc0, acc1, acc2, accn;
     int32_t npairs = 0;
@@ -687,7 +702,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                 if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
                     R.a = wI * sv.x;
                     R.b = fmaf(wQ, sv.y, wU * sv.z);
-                    R.c = fmaf(wQ, sv.z, -wU * sv.y);
+                    R.c = 2.0f * fmaf(wQ, sv.z, -wU * sv.y);
                 } else {
                     R.a = sv.x;
                     R.b = sv.y;
@@ -706,56 +721,61 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         npairs += ((omg <= omax) && (!inner || omg > omin)) ? 1 : 0;
                     }
                 } else {
+#pragma unroll 2
                     for (int32_t m = 0; m < m_end; ++m) {
                         const PixRec R = L.rec[m];
+                        // n = X e1 + Y e2 + (1 - W) c in the tile frame
                         const float omg = fmaf(-R.Y, F.p2, fmaf(-R.X, F.p1, fmaf(R.W, F.p3, F.om)));  // 1 - n.p
                         bool in = (omg <= omax) && (!inner || omg > omin);
-                        const float nz = 1.0f - R.W;
-                        const float xp = fmaf(R.Y, F.a2, fmaf(R.X, F.a1, nz * F.a3));  // n . theta'_0
-                        const float yp = fmaf(R.Y, F.b2, fmaf(R.X, F.b1, nz * F.b3));  // n . phi'_0
+                        const float xp = fmaf(-R.W, F.a3, fmaf(R.Y, F.a2, fmaf(R.X, F.a1, F.a3)));  // n . theta'_0
+                        const float yp = fmaf(-R.W, F.b3, fmaf(R.Y, F.b2, fmaf(R.X, F.b1, F.b3)));  // n . phi'_0
                         const float rz = rcp(1.0f - omg);
                         const float su = xp * rz, sv = yp * rz;  // gnomonic u, v
                         const float tu = fmaf(su, inv_h, c0);
                         const float tv = fmaf(sv, inv_h, c0);
                         if (clip) in = in && (tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax);
-                        const int32_t iu = max(0, min((int32_t)tu, n - 2));
-                        const int32_t iv = max(0, min((int32_t)tv, n - 2));
-                        const float fu = fmaf(su, inv_h, c0 - (float)iu), fv = fmaf(sv, inv_h, c0 - (float)iv);
+                        // cell indices (clamped: pairs outside the disc are masked below)
+                        const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, cmax));
+                        const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, cmax));
+                        const float fu = fmaf(su, inv_h, c0 - ku), fv = fmaf(sv, inv_h, c0 - kv);
+                        const uint32_t off = (uint32_t)fmaf(kv, row, ku) << 4;  // exact: row^2 < 2^24
                         float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
                         if (BEAM == BEAM_SCALAR) {
-                            const float4 cl = ld4(beam, iv * (n - 1) + iu);
-                            bT = lerp(lerp(cl.x, cl.y, fu), lerp(cl.z, cl.w, fu), fv);
+                            const float4 cl = beam_ld(beam, off, 0);
+                            bT = fmaf(fv, fmaf(fu, cl.w, cl.z), fmaf(fu, cl.y, cl.x));
                         } else {
-                            const int32_t nd = iv * n + iu;
-                            const float4 q00 = ld4(beam, nd), q10 = ld4(beam, nd + 1), q01 = ld4(beam, nd + n),
-                                         q11 = ld4(beam, nd + n + 1);
+                            const float4 q00 = beam_ld(beam, off, 0), q10 = beam_ld(beam, off + 16, 0),
+                                         q01 = beam_ld(beam, off, row_bytes),
+                                         q11 = beam_ld(beam, off + 16, row_bytes);
                             bI = lerp(lerp(q00.x, q10.x, fu), lerp(q01.x, q11.x, fu), fv);
                             bQ = lerp(lerp(q00.y, q10.y, fu), lerp(q01.y, q11.y, fu), fv);
                             bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
                             bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
                         }
                         // co-polar vector carried from the boresight to the pixel along the great circle
-                        const float gn = fmaf(F.g1, R.X, fmaf(F.g2, R.Y, F.g3 * nz));
+                        const float gn = fmaf(-R.W, F.g3, fmaf(F.g2, R.Y, fmaf(F.g1, R.X, F.g3)));
                         const float q = gn * rcp(2.0f - omg);
                         const float ex = fmaf(-q, F.p1 + R.X, F.g1);
                         const float ey = fmaf(-q, F.p2 + R.Y, F.g2);
-                        const float ez = fmaf(-q, F.p3 + nz, F.g3);
+                        const float ez = fmaf(-q, pp3 - R.W, F.g3);
                         const float cc = fmaf(ex, R.t1, fmaf(ey, R.t2, ez * R.t3));
                         const float ss = fmaf(ex, R.f1, fmaf(ey, R.f2, ez * R.f3));
                         const float c2 = fmaf(cc, cc, -ss * ss);
-                        const float s2 = 2.0f * cc * ss;
-                        if (per_sample) accn.add(in ? bT : 0.0f);
+                        if (PS) accn.add(in ? bT : 0.0f);
                         if (MODE == MODE_TOD) {
                             float term;
                             if (BEAM == BEAM_SCALAR) {
-                                term = bT * fmaf(c2, R.b, fmaf(s2, R.c, R.a));
+                                // R.c holds twice the U-like coefficient: sin 2chi / 2 = cc ss
+                                term = bT * fmaf(c2, R.b, fmaf(cc * ss, R.c, R.a));
                             } else {
+                                const float s2 = 2.0f * cc * ss;
                                 const float bq = fmaf(bQ, R.b, bU * R.c);
                                 const float bu = fmaf(bQ, R.c, -bU * R.b);
                                 term = fmaf(bI, R.a, fmaf(c2, bq, s2 * bu));
                             }
                             acc0.add(in ? term : 0.0f);
                         } else {
+                            const float s2 = 2.0f * cc * ss;
                             acc0.add(in ? bT * R.a : 0.0f);
                             acc1.add(in ? bT * fmaf(c2, R.b, s2 * R.c) : 0.0f);
                             acc2.add(in ? bT * fmaf(-s2, R.b, c2 * R.c) : 0.0f);
@@ -775,7 +795,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
         return;
     }
     double Nrm = D.norm_scale;
-    if (D.norm_mode == 1) {
+    if (PS && D.norm_mode == 1) {
         const double snm = accn.value() * (BEAM == BEAM_SCALAR ? D.w[3] : 1.0);
         Nrm = (snm != 0.0) ? D.norm_scale / snm : 0.0;
     }
@@ -841,7 +861,7 @@ __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
     }
 }
 
-template <int MODE, int BEAM, int CH>
+template <int MODE, int BEAM, int CH, bool PS>
 __global__ void __launch_bounds__(512, 4) tile_kernel(ConvArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & (WAVE - 1);
@@ -860,7 +880,7 @@ __global__ void __launch_bounds__(512, 4) tile_kernel(ConvArgs A) {
         }
         const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
         const DetDesc &D = A.dets[tl.det];
-        convolve_tile<MODE, BEAM, CH>(A, D, tl.begin, tl.count, L, lane);
+        convolve_tile<MODE, BEAM, CH, PS>(A, D, tl.begin, tl.count, L, lane);
     }
 }
 
@@ -896,7 +916,10 @@ __global__ void repack4_kernel(const T *a, const T *b, const T *c, const T *d, t
     out[i] = r;
 }
 
-// Scalar beam: one record per cell with the cell's four corner node values.
+// Scalar beam: one record per cell holding the bilinear interpolant of its
+// four corner nodes as a polynomial in the cell fractions (fu, fv):
+// b = b00 + fu (b10 - b00) + fv (b01 - b00) + fu fv (b11 - b10 - b01 + b00).
+// The differences are formed in FP64 and rounded once.
 template <typename T>
 __global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::type *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -904,11 +927,12 @@ __global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::typ
     if (i >= m) return;
     const int32_t iv = (int32_t)(i / (n - 1)), iu = (int32_t)(i % (n - 1));
     const int64_t k = (int64_t)iv * n + iu;
+    const double b00 = b[k], b10 = b[k + 1], b01 = b[k + n], b11 = b[k + n + 1];
     typename Rec4<T>::type r;
-    r.x = b[k];
-    r.y = b[k + 1];
-    r.z = b[k + n];
-    r.w = b[k + n + 1];
+    r.x = (T)b00;
+    r.y = (T)(b10 - b00);
+    r.z = (T)(b01 - b00);
+    r.w = (T)((b11 - b10) - (b01 - b00));
     out[i] = r;
 }
 
@@ -938,32 +962,35 @@ static hipError_t launch_pixel(const ConvArgs &a, int waves, int groups, hipStre
     return hipGetLastError();
 }
 
-template <int MODE, int BEAM, int CH>
+template <int MODE, int BEAM, int CH, bool PS>
 static hipError_t launch_tile_t(const ConvArgs &a, int waves, int groups, hipStream_t s) {
     const size_t lds = sizeof(TileLds<CH>) * (size_t)waves;
     if (lds > 64 * 1024) {  // allow the larger LDS allocations of gfx950 (160 KiB per CU)
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_kernel<MODE, BEAM, CH>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_kernel<MODE, BEAM, CH, PS>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((tile_kernel<MODE, BEAM, CH>), dim3(groups), dim3(WAVE * waves), lds, s, a);
+    hipLaunchKernelGGL((tile_kernel<MODE, BEAM, CH, PS>), dim3(groups), dim3(WAVE * waves), lds, s, a);
     return hipGetLastError();
+}
+
+template <int MODE, int BEAM, bool PS>
+static hipError_t launch_tile_c(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+    switch (a.chunk) {
+        case 64: return launch_tile_t<MODE, BEAM, 64, PS>(a, waves, groups, s);
+        case 256: return launch_tile_t<MODE, BEAM, 256, PS>(a, waves, groups, s);
+        default: return launch_tile_t<MODE, BEAM, 128, PS>(a, waves, groups, s);
+    }
 }
 
 template <int MODE>
 static hipError_t launch_tile(const ConvArgs &a, int waves, int groups, hipStream_t s) {
     const bool full = a.beam_kind == BEAM_FULL;
-    switch (a.chunk) {
-        case 64:
-            return full ? launch_tile_t<MODE, BEAM_FULL, 64>(a, waves, groups, s)
-                        : launch_tile_t<MODE, BEAM_SCALAR, 64>(a, waves, groups, s);
-        case 256:
-            return full ? launch_tile_t<MODE, BEAM_FULL, 256>(a, waves, groups, s)
-                        : launch_tile_t<MODE, BEAM_SCALAR, 256>(a, waves, groups, s);
-        default:
-            return full ? launch_tile_t<MODE, BEAM_FULL, 128>(a, waves, groups, s)
-                        : launch_tile_t<MODE, BEAM_SCALAR, 128>(a, waves, groups, s);
-    }
+    if (MODE != MODE_COUNT && a.per_sample)
+        return full ? launch_tile_c<MODE, BEAM_FULL, true>(a, waves, groups, s)
+                    : launch_tile_c<MODE, BEAM_SCALAR, true>(a, waves, groups, s);
+    return full ? launch_tile_c<MODE, BEAM_FULL, false>(a, waves, groups, s)
+                : launch_tile_c<MODE, BEAM_SCALAR, false>(a, waves, groups, s);
 }
 
 hipError_t launch_conv(const ConvArgs &a, bool f64, int waves, int groups, hipStream_t s) {

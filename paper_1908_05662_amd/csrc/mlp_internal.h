@@ -10,6 +10,20 @@
 namespace pisco {
 
 enum { MLP_EPI_FWD = 0, MLP_EPI_BWD_D = 1, MLP_EPI_BWD_W = 2 };
+#define MLP_MAX_L 16
+
+// Fused inference + TOD epilogue over a pointing stream (infer_kernel).
+struct MlpInferArgs {
+    const double *th, *ph, *ps;  // pointing, n samples
+    int64_t n;
+    int32_t H, L;                // width, hidden layers
+    const __bf16 *wb;            // bf16 parameter copy (weights used from it)
+    const float *w;              // fp32 parameters (biases used from it)
+    int64_t off_w[MLP_MAX_L + 1], off_b[MLP_MAX_L + 1];
+    float mean[3], stdv[3];
+    double coef[3];
+    float *tod;
+};
 
 hipError_t mlp_in_fwd(const float *x, const __bf16 *w0, const float *b0, int32_t n, int32_t H, float *z, __bf16 *a,
                       hipStream_t s);
@@ -28,6 +42,7 @@ hipError_t mlp_adam(float *w, float *m, float *v, const float *g, __bf16 *wb, in
 hipError_t mlp_to_bf16(const float *w, __bf16 *wb, int64_t count, hipStream_t s);
 hipError_t mlp_loss_sum(const float *part, int32_t count, float inv_count, float *loss, hipStream_t s);
 hipError_t mlp_features(const double *th, const double *ph, const double *ps, int64_t n, float *x, hipStream_t s);
+hipError_t mlp_infer_apply(const MlpInferArgs &a, hipStream_t s);
 hipError_t mlp_apply(const float *y, int64_t n, const float *mean, const float *stdv, const double *coef, float *tod,
                      hipStream_t s);
 

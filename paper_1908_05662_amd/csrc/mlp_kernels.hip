@@ -28,9 +28,12 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware exponential and reciprocal
+// (about 1 ulp); z -> -inf gives -0, z -> +inf gives z.
+__device__ inline float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ inline float silu(float z) { return z * sigmoid(z); }
 __device__ inline float silu_grad(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigmoid(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -298,6 +301,146 @@ __global__ void apply_kernel(const float *y, int64_t n, float m0, float m1, floa
     tod[i] = (float)((double)tod[i] + c0 * p0 + c1 * p1 + c2 * p2);
 }
 
+// ----------------------------------------------------------------------
+// Fused inference with the TOD epilogue: IR pointings per workgroup of four
+// waves.  Features, layer 0, the H x H layers, the output layer and
+// tod += sum_c coef_c (mean_c + std_c y_c) stay on chip: activations in LDS
+// (two buffers), weights read from L2.  The H x H layers use the operand
+// fragments and K order of gemm_kernel, layer 0 the FMA chain of
+// in_fwd_kernel, the output layer the per-lane order and butterfly of
+// out_kernel and the epilogue apply_kernel's arithmetic, so the result equals
+// the layer-by-layer forward pass followed by apply, bit for bit.
+// ----------------------------------------------------------------------
+constexpr int IR = 64;        // rows per workgroup
+constexpr int XLD = 8;        // feature row stride in LDS (floats)
+
+__device__ inline void features_of(const double *th, const double *ph, const double *ps, int64_t i, float *f) {
+    double st, ct, sf, cf, sp, cp;
+    sincos(th[i], &st, &ct);
+    sincos(ph[i], &sf, &cf);
+    sincos(ps[i], &sp, &cp);
+    f[0] = (float)(st * cf);
+    f[1] = (float)(st * sf);
+    f[2] = (float)ct;
+    f[3] = (float)sp;
+    f[4] = (float)cp;
+}
+
+__global__ void __launch_bounds__(256) infer_kernel(MlpInferArgs g) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int H = g.H, LD = H + 8;
+    float *X = reinterpret_cast<float *>(lds);
+    __bf16 *buf0 = reinterpret_cast<__bf16 *>(lds + IR * XLD * sizeof(float));
+    __bf16 *buf1 = buf0 + IR * LD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * IR;
+
+    if (tid < IR) {
+        float f[MLP_IN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (r0 + tid < g.n) features_of(g.th, g.ph, g.ps, r0 + tid, f);
+#pragma unroll
+        for (int k = 0; k < MLP_IN; ++k) X[tid * XLD + k] = f[k];
+    }
+    __syncthreads();
+
+    // layer 0 (K = 5) on the vector ALU: thread u owns unit u for every row
+    for (int u = tid; u < H; u += 256) {
+        float w0[MLP_IN];
+#pragma unroll
+        for (int k = 0; k < MLP_IN; ++k) w0[k] = (float)g.wb[g.off_w[0] + u * MLP_IN + k];
+        const float b0 = g.w[g.off_b[0] + u];
+        for (int r = 0; r < IR; ++r) {
+            float s = b0;
+#pragma unroll
+            for (int k = 0; k < MLP_IN; ++k) s = fmaf(X[r * XLD + k], w0[k], s);
+            buf0[r * LD + u] = (__bf16)silu(s);
+        }
+    }
+    __syncthreads();
+
+    // H x H layers: wave w computes column groups w, w + 4, ... of 64 units for
+    // all IR rows (4 x 4 MFMA tiles); B fragments of the next K step are
+    // fetched while the current step's MFMAs run
+    __bf16 *cur = buf0, *nxt = buf1;
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    for (int l = 1; l < g.L; ++l) {
+        const __bf16 *__restrict__ W = g.wb + g.off_w[l];
+        const float *__restrict__ bias = g.w + g.off_b[l];
+        for (int cg = wave; cg < H / 64; cg += 4) {
+            const int n0 = cg * 64;
+            f32x4 acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            bf16x8 bfr[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(n0 + 16 * j + r16) * H + kq);
+            for (int k0 = 0; k0 < H; k0 += 32) {
+                bf16x8 bnx[4];
+                const int k1 = (k0 + 32 < H) ? k0 + 32 : k0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    bnx[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(n0 + 16 * j + r16) * H + k1 + kq);
+                bf16x8 af[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(cur + (16 * i + r16) * LD + k0 + kq);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bfr[j] = bnx[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int col = n0 + 16 * j + r16;
+                const float bc = bias[col];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = 16 * i + 4 * (lane >> 4) + q;
+                        nxt[row * LD + col] = (__bf16)silu(acc[i][j][q] + bc);
+                    }
+            }
+        }
+        __syncthreads();
+        __bf16 *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+
+    // output layer (N = 3): wave w takes rows w * IR/4 ...; lanes over units
+    const __bf16 *__restrict__ Wo = g.wb + g.off_w[g.L];
+    const float *__restrict__ bo = g.w + g.off_b[g.L];
+    const int per = H / 64;
+    for (int rr = 0; rr < IR / 4; ++rr) {
+        const int r = wave * (IR / 4) + rr;
+        float sc[MLP_OUT] = {0.0f, 0.0f, 0.0f};
+        for (int k = 0; k < per; ++k) {
+            const int u = lane + 64 * k;
+            const float av = (float)cur[r * LD + u];
+#pragma unroll
+            for (int c = 0; c < MLP_OUT; ++c) sc[c] = fmaf(av, (float)Wo[c * H + u], sc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < MLP_OUT; ++c) {
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) sc[c] += __shfl_xor(sc[c], m, 64);
+            sc[c] += bo[c];
+        }
+        const int64_t i = r0 + r;
+        if (lane == 0 && i < g.n) {
+            const double p0 = g.mean[0] + (double)g.stdv[0] * sc[0];
+            const double p1 = g.mean[1] + (double)g.stdv[1] * sc[1];
+            const double p2 = g.mean[2] + (double)g.stdv[2] * sc[2];
+            g.tod[i] = (float)((double)g.tod[i] + g.coef[0] * p0 + g.coef[1] * p1 + g.coef[2] * p2);
+        }
+    }
+}
+
 inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -386,6 +529,18 @@ hipError_t mlp_loss_sum(const float *part, int32_t count, float inv_count, float
 hipError_t mlp_features(const double *th, const double *ph, const double *ps, int64_t n, float *x, hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(features_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, th, ph, ps, n, x);
+    return hipGetLastError();
+}
+
+hipError_t mlp_infer_apply(const MlpInferArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    const size_t lds = (size_t)IR * XLD * sizeof(float) + 2 * (size_t)IR * (a.H + 8) * sizeof(__bf16);
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&infer_kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(infer_kernel, dim3(blocks_for(a.n, IR)), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 

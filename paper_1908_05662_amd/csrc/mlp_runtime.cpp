@@ -293,14 +293,28 @@ pisco_status pisco_sidelobe_apply(pisco_ctx *ctx, pisco_mlp *m, int32_t det, con
         pisco::set_error(ctx, "detector has no pointing");
         return PISCO_ESTATE;
     }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int64_t b = 0; b < n; b += m->max_batch) {
-        const int32_t c = (int32_t)std::min<int64_t>(m->max_batch, n - b);
-        MLP_TRY(m, pisco::mlp_features(th + b, ph + b, ps + b, c, m->xbuf, s));
-        const pisco_status st = run(m, m->xbuf, nullptr, c, m->ybuf, nullptr, nullptr, s);
-        if (st != PISCO_OK) return st;
-        MLP_TRY(m, pisco::mlp_apply(m->ybuf, c, mean, stdv, coef, tod + b, s));
+    // one fused launch over the whole stream (features, every layer and the
+    // epilogue on chip); equal bit for bit to features + forward + apply
+    pisco::MlpInferArgs a{};
+    a.th = th;
+    a.ph = ph;
+    a.ps = ps;
+    a.n = n;
+    a.H = m->H;
+    a.L = m->L;
+    a.wb = m->wb;
+    a.w = m->w;
+    for (int l = 0; l <= m->L; ++l) {
+        a.off_w[l] = m->off_w[l];
+        a.off_b[l] = m->off_b[l];
     }
+    for (int c = 0; c < MLP_OUT; ++c) {
+        a.mean[c] = mean[c];
+        a.stdv[c] = stdv[c];
+        a.coef[c] = coef[c];
+    }
+    a.tod = tod;
+    MLP_TRY(m, pisco::mlp_infer_apply(a, static_cast<hipStream_t>(stream)));
     return PISCO_OK;
 }
 

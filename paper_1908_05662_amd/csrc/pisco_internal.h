@@ -56,6 +56,8 @@ struct ConvArgs {
     int32_t algo;            // ALGO_*
     int32_t chunk;           // pixel records staged per pass (64, 128, 256)
     double coherence;        // tile path: samples within this many disc radii of the tile centre
+    int32_t per_sample;      // some detector of the launch uses per-sample normalisation
+    int32_t pad_;
 };
 
 // Launch helpers (conv_kernel.hip).  Return the launch error.

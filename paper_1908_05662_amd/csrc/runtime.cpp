@@ -68,6 +68,7 @@ struct Plan {
     double coherence = 0.0;
     int64_t out_samples = 0;
     int32_t beam_kind = 0;
+    int32_t per_sample = 0;  // some detector of the plan normalises per sample
     // captured launch
     hipGraphExec_t gexec = nullptr;
     uint64_t g_gen = 0;
@@ -256,6 +257,7 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         return PISCO_OK;
     std::vector<DetDesc> descs;
     int64_t out_off = 0;
+    p.per_sample = 0;
     const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
     for (int32_t k = lo; k <= hi; ++k) {
         const DetState &d = c->dets[k];
@@ -277,13 +279,15 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         x.omega_max = 2.0 * std::sin(0.5 * d.rho_max) * std::sin(0.5 * d.rho_max);
         x.omega_min = 2.0 * std::sin(0.5 * d.rho_min) * std::sin(0.5 * d.rho_min);
         for (int i = 0; i < 4; ++i) x.w[i] = d.w[i];
-        x.needs_clip = (std::tan(d.rho_max) < d.T * (1.0 - 1e-6)) ? 0 : 1;
+        // a disc inside the grid's square maps every member into the grid (|u|, |v| <= tan rho)
+        x.needs_clip = (std::tan(d.rho_max) <= d.T * (1.0 + 1e-12)) ? 0 : 1;
         x.n = d.n;
         x.norm_mode = d.norm_mode;
         x.has_inner = d.rho_min > 0.0 ? 1 : 0;
         descs.push_back(x);
         out_off += d.nsamp;
         p.beam_kind = d.beam_kind;
+        if (d.norm_mode == PISCO_NORM_PER_SAMPLE) p.per_sample = 1;
     }
     hipError_t e = hipDeviceSynchronize();  // no launch may still read the old plan
     if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "synchronise failed: %s", hipGetErrorString(e));
@@ -386,6 +390,7 @@ ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode, bool ti
     a.algo = tile ? pisco::ALGO_TILE : pisco::ALGO_PIXEL;
     a.chunk = c->chunk;
     a.coherence = c->coherence;
+    a.per_sample = p.per_sample;
     return a;
 }
 
@@ -491,7 +496,7 @@ pisco_status pisco_set_beam(pisco_ctx *c, int32_t det, int32_t n, double T, cons
     c->err.clear();
     DetState *d = det_slot(c, det);
     if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
-    if (n < 3 || n > 8191 || (n % 2) == 0) return fail(c, PISCO_EINVAL, "grid size %d must be odd in [3, 8191]", n);
+    if (n < 3 || n > 4095 || (n % 2) == 0) return fail(c, PISCO_EINVAL, "grid size %d must be odd in [3, 4095]", n);
     if (!(T > 0.0) || !std::isfinite(T)) return fail(c, PISCO_EINVAL, "half_span_tan must be finite and > 0");
     if (dtype != PISCO_F32 && dtype != PISCO_F64) return fail(c, PISCO_EINVAL, "bad dtype %d", dtype);
     if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
@@ -521,7 +526,7 @@ pisco_status pisco_set_beam_scalar(pisco_ctx *c, int32_t det, int32_t n, double 
     c->err.clear();
     DetState *d = det_slot(c, det);
     if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
-    if (n < 3 || n > 8191 || (n % 2) == 0) return fail(c, PISCO_EINVAL, "grid size %d must be odd in [3, 8191]", n);
+    if (n < 3 || n > 4095 || (n % 2) == 0) return fail(c, PISCO_EINVAL, "grid size %d must be odd in [3, 4095]", n);
     if (!(T > 0.0) || !std::isfinite(T)) return fail(c, PISCO_EINVAL, "half_span_tan must be finite and > 0");
     if (!std::isfinite(wI) || !std::isfinite(wQ) || !std::isfinite(wU) || !std::isfinite(wT))
         return fail(c, PISCO_EINVAL, "non-finite beam weight");

@@ -55,6 +55,15 @@ def detector_coef(zeta: float, eps: float, s: float):
     return (0.5 * s * (1 + eps), 0.5 * s * (1 - eps) * math.cos(2 * zeta), 0.5 * s * (1 - eps) * math.sin(2 * zeta))
 
 
+# dense BF16 matrix-core peak of the MI355X (no sparsity)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def network_flops_per_sample(width: int = 256, hidden: int = 4) -> int:
+    """Multiply-adds x 2 of one forward pass: 5 -> width, (hidden - 1) x width^2, width -> 3."""
+    return 2 * (5 * width + (hidden - 1) * width * width + width * 3)
+
+
 def rms(x) -> float:
     import torch
 
@@ -130,7 +139,7 @@ class SidelobeModel:
         return y * torch.from_numpy(self.std).to(dev) + torch.from_numpy(self.mean).to(dev)
 
     def apply(self, det: int, coef, tod, stream=None):
-        """tod += sum_c coef[c] P_hat[c] for detector slot det's pointing (one fused pass per batch)."""
+        """tod += sum_c coef[c] P_hat[c] for detector slot det's pointing (one fused launch)."""
         return self.net.apply(det, self.mean, self.std, coef, tod, stream)
 
 
@@ -225,9 +234,14 @@ def experiment(conv: Convolver, nside: int, sky, beam, half_span_tan: float, det
     t_full = time_call(lambda: conv.convolve(4, out=out_full))
     t_main = time_call(lambda: conv.convolve(2, out=out_main))
     t_sur = time_call(lambda: model.apply(2, coef, conv.convolve(2, out=out_main)))
+    t_net = time_call(lambda: model.apply(2, coef, out_main))
     n = test[0].size
+    flops = n * network_flops_per_sample(width, hidden)
     res.update({"samples_per_s_exact": n / t_full, "samples_per_s_main_only": n / t_main,
-                "samples_per_s_surrogate": n / t_sur, "speedup": t_full / t_sur})
+                "samples_per_s_surrogate": n / t_sur, "speedup": t_full / t_sur,
+                "network": {"samples_per_s": n / t_net, "ms": t_net * 1e3, "flops_per_sample": flops / n,
+                            "achieved_tflops": flops / t_net / 1e12, "peak_tflops": BF16_PEAK_TFLOPS,
+                            "frac": flops / t_net / 1e12 / BF16_PEAK_TFLOPS}})
     model.close()
     del keep
     return res
