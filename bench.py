@@ -142,6 +142,180 @@ def surrogate_leg(epochs):
     return r
 
 
+def full_scale_leg(epochs, n_train, width, hidden, lr):
+    """The nside-2048 full-scale workload on one GPU: 256 detectors x 390,625 CES
+    samples (1e8), each with its own 151^2 elliptical main beam (disc 1.5 deg),
+    plus the shared -40 dB ring at 10 deg on a 401^2 grid over +-20 deg for the
+    annulus (1.5, 20] deg.  Exact main beam + network against the exact main
+    beam + exact annulus.  The exact annulus is timed on 1024 samples of every
+    detector (four runs of 256 consecutive samples, 262,144 in all, also the
+    held-out set) and its rate extrapolated to the whole job; everything else
+    runs on the whole job."""
+    import torch
+
+    import oracle
+    from paper_1908_05662_amd import OUT_STOKES, OUT_TOD
+    from paper_1908_05662_amd import surrogate as SG
+    from paper_1908_05662_amd.api import Convolver
+    from synth import scans as S
+    from synth import workloads as W
+
+    t0 = time.perf_counter()
+    w = W.c5()
+    n = w.n_samples
+    log(f"full scale: {len(w.detectors)} detectors, {n} samples, nside {w.nside}, setup {time.perf_counter() - t0:.1f}s")
+    r_main = w.meta["r_main"]
+    d0 = w.detectors[0]
+    norm = d0.norm_scale
+    stream = torch.cuda.Stream()
+
+    # main beams, exact, whole job: one batched graph launch
+    cm = Convolver(0)
+    keep_m, kind = load(cm, w, torch)
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(stream):
+        cm.convolve(-1, OUT_TOD, out=out, stream=stream)
+    stream.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        cm.convolve(-1, OUT_TOD, out=out, stream=stream)
+        b.record(stream)
+    b.synchronize()
+    t_main = a.elapsed_time(b) / 1e3
+    d_main_all = out.clone()
+    log(f"main exact: {t_main:.3f} s for {n} samples")
+
+    # annulus context: the ring grid, training pointings and the held-out runs
+    T, g = W.sidelobe_beam(401, 20.0, 0.25)
+    cs = Convolver(0)
+    cs.set_sky(w.nside, *(torch.from_numpy(m.astype(np.float32)).cuda() for m in w.sky), dtype=torch.float32)
+    cs.set_beam_scalar(0, 401, T, torch.from_numpy(g.astype(np.float32)).cuda(), 0.5, 0.5, 0.0, 1.0,
+                       dtype=torch.float32)
+    rng = np.random.Generator(np.random.PCG64([W.SEED_BASE + 5, 7]))
+    th, ph, ps = S.uniform_sphere(n_train, rng)
+    o = SG.spatial_order(th, ph)
+    train = [torch.from_numpy(np.ascontiguousarray(x[o])).cuda() for x in (th, ph, ps)]
+    offs = np.cumsum([0] + [d.n for d in w.detectors])
+    idx, det_of = [], []
+    for k, d in enumerate(w.detectors):
+        for q in range(4):
+            s0 = (q * d.n) // 4
+            idx.append(offs[k] + s0 + np.arange(256))
+            det_of.append(np.full(256, k))
+    idx = np.concatenate(idx)
+    det_of = np.concatenate(det_of)
+    all_th = np.concatenate([d.theta for d in w.detectors])
+    all_ph = np.concatenate([d.phi for d in w.detectors])
+    all_ps = np.concatenate([d.psi for d in w.detectors])
+    held = [torch.from_numpy(np.ascontiguousarray(x[idx])).cuda() for x in (all_th, all_ph, all_ps)]
+    for k in (1, 2, 3):
+        cs.share_beam(k, 0)
+    cs.set_detector(0, 0.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm)
+    cs.set_detector(1, 0.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm)
+    cs.set_detector(2, 0.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm)
+    cs.set_pointing(0, *train)
+    cs.set_pointing(1, *held)
+    cs.set_pointing(2, *held)
+
+    t1 = time.perf_counter()
+    p_train = cs.convolve(0, OUT_STOKES)
+    model = SG.SidelobeModel(cs, width, hidden, 16384, 1)
+    x_train = model.features(0)
+    torch.cuda.synchronize()
+    t_targets = time.perf_counter() - t1
+    log(f"targets: {n_train} samples in {t_targets:.2f} s")
+    t1 = time.perf_counter()
+    hist = model.fit(x_train, p_train, epochs=epochs, batch=8192, lr=lr, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    del x_train, p_train
+
+    # held-out judgement by the exact annulus
+    p_held = cs.convolve(1, OUT_STOKES).double()
+    coef = np.array([SG.detector_coef(d.det.zeta, d.det.eps, d.det.s) for d in w.detectors])
+    cvec = torch.from_numpy(coef[det_of]).cuda()
+    d_sl = (p_held * cvec).sum(1)
+    p_hat = model.predict(model.features(1)).double()
+    d_sl_hat = (p_hat * cvec).sum(1)
+    d_main = d_main_all[torch.from_numpy(idx).cuda()].double()
+    ref = SG.rms(d_main)
+    err = SG.rms(d_sl_hat - d_sl) / ref
+    err0 = SG.rms(d_sl) / ref
+
+    # exact annulus rate on the held-out runs (TOD of a zeta = 0 detector)
+    t_ann = SG.time_call(lambda: cs.convolve(2, OUT_TOD), reps=2)
+    per_sample_ann = t_ann / idx.size
+
+    # surrogate form over the whole job: main exact + the fused network per detector
+    def surrogate_pass():
+        with torch.cuda.stream(stream):
+            cm.convolve(-1, OUT_TOD, out=out, stream=stream)
+            for k, d in enumerate(w.detectors):
+                model.apply(k, coef[k], out[offs[k]:offs[k + 1]], stream=stream, conv=cm)
+
+    surrogate_pass()
+    stream.synchronize()
+    with torch.cuda.stream(stream):
+        a.record(stream)
+    surrogate_pass()
+    with torch.cuda.stream(stream):
+        b.record(stream)
+    b.synchronize()
+    t_sur = a.elapsed_time(b) / 1e3
+
+    # parity of sampled outputs at full size (oracle, FP64 on the host)
+    sky64 = [m.astype(np.float32).astype(np.float64) for m in w.sky]
+    pm_err = 0.0
+    for k in range(0, len(w.detectors), 32):
+        d = w.detectors[k]
+        j = np.array([0, d.n // 2, d.n - 1])
+        want = oracle.tod(w.nside, *sky64, d.beam.dense().astype(np.float32).astype(np.float64),
+                          d.beam.half_span_tan, d.det.zeta, d.det.eps, d.det.s, d.rho_min, d.rho_max, d.norm_mode,
+                          d.norm_scale, d.theta[j], d.phi[j], d.psi[j])
+        got = d_main_all[torch.from_numpy(offs[k] + j).cuda()].double().cpu().numpy()
+        pm_err = max(pm_err, float(np.abs(got - want).max() / np.abs(want).max()))
+    from synth import beams as B
+
+    ring_dense = B.ideal_beamsor(g.astype(np.float32).astype(np.float64), T).dense()
+    jj = np.linspace(0, idx.size - 1, 6).astype(int)
+    want = oracle.tod(w.nside, *sky64, ring_dense, T, 0.0, 0.0, 1.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm,
+                      held[0].cpu().numpy()[jj], held[1].cpu().numpy()[jj], held[2].cpu().numpy()[jj],
+                      oracle.OUT_STOKES)
+    got = p_held.cpu().numpy()[jj]
+    pa_err = float(np.abs(got - want).max() / np.abs(want).max())
+    log(f"full scale: sidelobe error {err:.3e} (main only {err0:.3e}); parity main {pm_err:.2e} annulus {pa_err:.2e}")
+
+    t_exact = t_main + per_sample_ann * n
+    res = {
+        "workload": "nside-2048 sky (l <= 4095), 256 detectors x 390,625 CES samples, 151^2 elliptical main beams "
+                    "(disc 1.5 deg) + shared 401^2 ring grid over +-20 deg (annulus (1.5, 20] deg)",
+        "samples": n,
+        "main_exact_s": t_main,
+        "main_exact_samples_per_s": n / t_main,
+        "surrogate_s": t_sur,
+        "samples_per_s_surrogate": n / t_sur,
+        "annulus_exact_samples_per_s": 1.0 / per_sample_ann,
+        "annulus_timed_samples": int(idx.size),
+        "exact_s_extrapolated": t_exact,
+        "samples_per_s_exact_extrapolated": n / t_exact,
+        "speedup": t_exact / t_sur,
+        "sidelobe_error": err,
+        "main_only_error": err0,
+        "error_unit": "RMS(d_sl_hat - d_sl) / RMS(d_main) on the 262,144 held-out scan samples",
+        "network": f"5 -> {hidden} x {width} SiLU -> 3, BF16 weights",
+        "network_flops_per_sample": SG.network_flops_per_sample(width, hidden),
+        "train_samples": n_train, "epochs": epochs, "lr": lr, "final_loss": hist[-1], "targets_s": t_targets,
+        "train_s": t_train,
+        "parity_main_max_rel_err": pm_err, "parity_annulus_max_rel_err": pa_err,
+    }
+    model.close()
+    cs.close()
+    cm.close()
+    del keep_m
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +327,13 @@ def main():
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
     ap.add_argument("--launch", type=str, default="", help="key=value,... fields of pisco_launch")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the far-sidelobe surrogate leg")
+    ap.add_argument("--full-scale", action="store_true",
+                    help="also run the nside-2048, 1e8-sample surrogate-vs-exact leg (about 3 minutes)")
+    ap.add_argument("--full-scale-train", type=int, default=6_000_000)
+    ap.add_argument("--full-scale-epochs", type=int, default=120)
+    ap.add_argument("--full-scale-net", type=str, default="512x10",
+                    help="network width x hidden layers for the full-scale leg")
+    ap.add_argument("--full-scale-lr", type=float, default=7e-4)
     ap.add_argument("--tune", choices=("auto", "off", "force"), default="auto",
                     help="launch-shape autotuning: auto = use the cached shape or search once, force = search again")
     ap.add_argument("--surrogate-epochs", type=int, default=40)
@@ -270,6 +451,11 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_surrogate:
         rec["surrogate"] = surrogate_leg(args.surrogate_epochs)
+    if args.full_scale:
+        torch.cuda.empty_cache()
+        width, hidden = (int(v) for v in args.full_scale_net.split("x"))
+        rec["full_scale"] = full_scale_leg(args.full_scale_epochs, args.full_scale_train, width, hidden,
+                                           args.full_scale_lr)
     print(json.dumps(rec), flush=True)
 
 

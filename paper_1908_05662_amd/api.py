@@ -253,18 +253,24 @@ class Mlp:
                                                         self._loss.data_ptr(), self._stream(stream)))
         return self._loss
 
-    def features(self, det: int, stream=None):
+    def features(self, det: int, stream=None, conv=None):
+        """Features of detector `det` of `conv` (default: the network's convolver)."""
         torch = _torch()
-        n = self.conv.output_samples(det)
-        x = torch.empty((n, 5), dtype=torch.float32, device=self.conv.torch_device)
-        self.conv._check(self._lib.pisco_sidelobe_features(self.conv._h, int(det), x.data_ptr(),
-                                                           self._stream(stream)))
+        cv = conv or self.conv
+        n = cv.output_samples(det)
+        x = torch.empty((n, 5), dtype=torch.float32, device=cv.torch_device)
+        cv._check(self._lib.pisco_sidelobe_features(cv._h, int(det), x.data_ptr(), self._stream(stream)))
         return x
 
-    def apply(self, det: int, mean, std, coef, tod, stream=None):
+    def apply(self, det: int, mean, std, coef, tod, stream=None, conv=None):
+        """tod += sum_c coef[c] (mean[c] + std[c] y[c]) over detector `det` of
+        `conv` (default: the network's convolver; any convolver on the same device)."""
+        cv = conv or self.conv
         m = (ctypes.c_float * 3)(*[float(v) for v in mean])
         s = (ctypes.c_float * 3)(*[float(v) for v in std])
         c = (ctypes.c_double * 3)(*[float(v) for v in coef])
-        self.conv._check(self._lib.pisco_sidelobe_apply(self.conv._h, self._h, int(det), m, s, c, tod.data_ptr(),
-                                                        self._stream(stream)))
+        if tod.numel() != cv.output_samples(det) or not tod.is_cuda or tod.dtype != _torch().float32:
+            raise ValueError("tod must be a float32 device tensor with one value per sample of the detector")
+        cv._check(self._lib.pisco_sidelobe_apply(cv._h, self._h, int(det), m, s, c, tod.data_ptr(),
+                                                 self._stream(stream)))
         return tod

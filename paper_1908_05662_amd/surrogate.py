@@ -138,9 +138,9 @@ class SidelobeModel:
         dev = y.device
         return y * torch.from_numpy(self.std).to(dev) + torch.from_numpy(self.mean).to(dev)
 
-    def apply(self, det: int, coef, tod, stream=None):
+    def apply(self, det: int, coef, tod, stream=None, conv=None):
         """tod += sum_c coef[c] P_hat[c] for detector slot det's pointing (one fused launch)."""
-        return self.net.apply(det, self.mean, self.std, coef, tod, stream)
+        return self.net.apply(det, self.mean, self.std, coef, tod, stream, conv)
 
 
 def time_call(fn, reps: int = 5) -> float:
