@@ -24,19 +24,27 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic work per (sample, disc pixel) pair, counted from each path's pair
-# arithmetic (FMA = 2; reciprocals, clamps, floors and single ops count 1;
-# compares, selects and address arithmetic are not counted):
+# arithmetic, as (vector ALU flops, matrix-core flops) (FMA = 2; reciprocals,
+# clamps, floors and single ops count 1; compares, selects and address
+# arithmetic are not counted):
 #  tile path, one-grid beam, TOD: membership 1 - n.p 6, rotation into the
 #  antenna frame 12, gnomonic projection (1 - z', reciprocal, two products) 4,
 #  grid coordinates, clamps and fractions 14, bilinear cell polynomial 6,
 #  position angle (co-polar vector carried along the great circle, projected
 #  on the pixel basis, doubled angle) 32, contraction 5, compensated
 #  accumulation 4 -> 83.
+#  tile path on the matrix cores, one-grid beam, TOD: eight 16x16x4 FP32 MFMAs
+#  per 16 pixels x 16 samples give 1 - n.p, the antenna-frame coordinates, g.n
+#  and the four co-polar projections (64 matrix flops per pair); on the vector
+#  ALU: projection 4, grid 14, bilinear 6, q = g.n / (2 - 1 + n.p) 3, carried
+#  projections 4, doubled angle 4, contraction 5, accumulation 4 -> 44.
+#  Four-channel beams: bilinear 36 and the Stokes rotation 11 instead -> 81.
 #  pixel path, four-channel beam, TOD: longitude offset 3, half-angle sin/cos
 #  polynomials 29, h and sin(dphi) 4, offsets from the boresight 5, rotation 6,
 #  projection 3, grid 12, position angle 34, bilinear x4 channels 36, Stokes
-#  rotation 6, contraction 5, accumulations 12 -> 155.
-FLOPS_PER_PAIR = {(1, "scalar"): 83, (1, "full"): 113, (0, "scalar"): 128, (0, "full"): 155}
+#  rotation 6, contraction 5, accumulations 12 -> 155 (one-grid beam: 125).
+FLOPS_PER_PAIR = {(1, "scalar"): (83, 0), (1, "full"): (113, 0), (2, "scalar"): (44, 64), (2, "full"): (81, 64),
+                  (0, "scalar"): (125, 0), (0, "full"): (155, 0)}
 # vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 (FMA)
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 
@@ -45,9 +53,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(launch):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter runs, or None once the kernel source has changed since."""
+    counter runs, or None once the kernel source or the launch shape differs
+    from the one the counters were taken with."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic_conv_c3.json")
@@ -56,7 +65,8 @@ def measured_traffic():
         sha = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
     except (OSError, KeyError, ValueError):
         return None
-    return rec["traffic_bytes_per_launch"] if sha == rec["source_sha256"] else None
+    same = sha == rec["source_sha256"] and all(launch.get(k) == v for k, v in rec.get("launch", {}).items())
+    return rec["traffic_bytes_per_launch"] if same else None
 
 
 def load(conv, w, torch):
@@ -368,7 +378,7 @@ def main():
         kv = dict(x.split("=") for x in args.launch.split(","))
         conv.set_launch(**{k: (float(v) if k == "coherence" else int(v)) for k, v in kv.items()})
     launch = conv.get_launch()
-    flops_per_pair = FLOPS_PER_PAIR[(launch["algorithm"], kind)]
+    flops_per_pair, mfma_per_pair = FLOPS_PER_PAIR[(launch["algorithm"], kind)]
     n = conv.output_samples(-1)
     stream = torch.cuda.Stream()
     out = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -439,8 +449,9 @@ def main():
         "macs_per_s": pairs / (ms_step / 1e3),
         "kernel_ms": k_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "flops_per_pair": flops_per_pair},
+                     "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(launch),
+                     "flops_per_pair": flops_per_pair,
+                     "matrix_tflops": mfma_per_pair * pairs / (k_ms / 1e3) / 1e12},
         "cpu_baseline": cpu,
         "autotune": None if tuned is None else {k: tuned[k] for k in ("launch", "ms", "default_ms", "speedup",
                                                                         "cached", "seconds", "subsample")},

@@ -173,19 +173,23 @@ int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
  *                    the pixels of the union of their discs together; tiles
  *                    whose samples are not within `coherence` disc radii of
  *                    their mean direction fall back to the pixel path.
+ *                    PISCO_ALGO_TILE_MX (FP32): the tile path with the
+ *                    pixel-linear quantities of every (pixel, sample) pair
+ *                    (1 - n.p, the antenna-frame coordinates, the co-polar
+ *                    projections) formed by FP32 matrix-core products.
  *   samples_per_tile consecutive samples a wavefront takes per queue pop (1..65536)
  *   waves_per_group  wavefronts per workgroup (1, 2, 4 or 8)
  *   groups_per_cu    workgroups launched per compute unit (1..16)
  *   xcd_queues       1: one shared work queue; 8: one queue per accelerator
  *                    die, each holding a contiguous block of tiles
- *   chunk            tile path: union pixels staged in LDS per pass (64, 128, 256)
- *   coherence        tile path: see algorithm, in (0, 4]
+ *   chunk            tile paths: union pixels staged in LDS per pass (64, 128, 256)
+ *   coherence        tile paths: see algorithm, in (0, 4]
  * Results are bitwise reproducible for a given launch shape.  They do not
  * depend on the shape except through the algorithm (the two paths round
  * differently) and, on the tile path, through samples_per_tile when it is not
  * a multiple of 64 (it decides which samples share a tile frame).
  */
-enum { PISCO_ALGO_PIXEL = 0, PISCO_ALGO_TILE = 1 };
+enum { PISCO_ALGO_PIXEL = 0, PISCO_ALGO_TILE = 1, PISCO_ALGO_TILE_MX = 2 };
 typedef struct {
     int32_t algorithm;
     int32_t samples_per_tile;

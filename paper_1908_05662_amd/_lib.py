@@ -12,7 +12,7 @@ F32, F64 = 0, 1
 HOST, DEVICE = 0, 1
 NORM_FIXED, NORM_PER_SAMPLE = 0, 1
 OUT_TOD, OUT_STOKES, OUT_COUNT = 0, 1, 2
-ALGO_PIXEL, ALGO_TILE = 0, 1
+ALGO_PIXEL, ALGO_TILE, ALGO_TILE_MX = 0, 1, 2
 
 
 class Launch(ctypes.Structure):

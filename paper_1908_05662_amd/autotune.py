@@ -19,7 +19,7 @@ from . import _lib as L
 
 # search space, in sweep order; fields marked tile-only do not affect the pixel path
 SPACE = [
-    ("algorithm", (L.ALGO_TILE, L.ALGO_PIXEL)),
+    ("algorithm", (L.ALGO_TILE, L.ALGO_TILE_MX, L.ALGO_PIXEL)),
     ("chunk", (64, 128, 256)),
     ("waves_per_group", (2, 4, 8)),
     ("groups_per_cu", (1, 2, 4)),
@@ -135,7 +135,7 @@ def tune(conv, det: int = -1, subsample: float = 0.25, reps: int = 3, cache: str
         for _ in range(max_passes):
             pass_start = best_ms
             for field, values in SPACE:
-                if field in TILE_ONLY and best["algorithm"] != L.ALGO_TILE:
+                if field in TILE_ONLY and best["algorithm"] == L.ALGO_PIXEL:
                     continue
                 for v in values:
                     if v == best[field]:

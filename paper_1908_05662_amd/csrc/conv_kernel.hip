@@ -618,6 +618,111 @@ __device__ __attribute__((noinline)) int32_t union_ring_setup(int32_t N, int32_t
     return k;
 }
 
+// Per-sample constants of the tile consume loop.
+struct PairCtx {
+    LaneFrame F;
+    float omax, omin;
+    bool inner, clip;
+    float inv_h, c0, tmax, cmax, row, pp3;
+    int32_t row_bytes;
+};
+
+// Masked contributions of NP consecutive (pixel record, sample) pairs,
+// summed in FP32: v0 (TOD term or I pickup), v1, v2 (Q, U pickups), vn (beam
+// value for the normaliser); a pixel outside the sample's disc adds zero.
+// The NP pairs are interleaved phase by phase (geometry, beam loads, position
+// angle, terms) so their beam loads are in flight together.
+struct PairOut {
+    float v0, v1, v2, vn;
+};
+// Records per consume step (their beam loads are in flight together) and the
+// minimum waves per SIMD the tile kernel is compiled for (2: up to 256 VGPRs;
+// the persistent launch keeps two waves per SIMD).
+constexpr int TILE_NP = 4;
+#define TILE_MINW 2
+
+template <int MODE, int BEAM, bool PS, int NP>
+__device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C, const BeamRsrc &beam) {
+    const LaneFrame &F = C.F;
+    PixRec R[NP];
+    float omg[NP], xp[NP], yp[NP], rzh[NP], fu[NP], fv[NP];
+    bool in[NP];
+    uint32_t off[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        R[k] = Rp[k];
+        // n = X e1 + Y e2 + (1 - W) c in the tile frame
+        omg[k] = fmaf(-R[k].Y, F.p2, fmaf(-R[k].X, F.p1, fmaf(R[k].W, F.p3, F.om)));  // 1 - n.p
+        in[k] = (omg[k] <= C.omax) && (!C.inner || omg[k] > C.omin);
+        xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));  // n . theta'_0
+        yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));  // n . phi'_0
+        rzh[k] = rcp(1.0f - omg[k]) * C.inv_h;  // gnomonic scale in grid units
+        const float tu = fmaf(xp[k], rzh[k], C.c0);
+        const float tv = fmaf(yp[k], rzh[k], C.c0);
+        if (C.clip) in[k] = in[k] && (tu >= 0.0f && tu <= C.tmax && tv >= 0.0f && tv <= C.tmax);
+        // cell indices (clamped: pairs outside the disc are masked below)
+        const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
+        const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
+        fu[k] = fmaf(xp[k], rzh[k], C.c0 - ku);
+        fv[k] = fmaf(yp[k], rzh[k], C.c0 - kv);
+        off[k] = (uint32_t)fmaf(kv, C.row, ku) << 4;  // exact: row^2 < 2^24
+    }
+    float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        cl[k][0] = beam_ld(beam, off[k], 0);
+        if (BEAM != BEAM_SCALAR) {
+            cl[k][1] = beam_ld(beam, off[k] + 16, 0);
+            cl[k][2] = beam_ld(beam, off[k], C.row_bytes);
+            cl[k][3] = beam_ld(beam, off[k] + 16, C.row_bytes);
+        }
+    }
+    PairOut o{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        // co-polar vector carried from the boresight to the pixel along the great circle
+        const float gn = fmaf(-R[k].W, F.g3, fmaf(F.g2, R[k].Y, fmaf(F.g1, R[k].X, F.g3)));
+        const float q = gn * rcp(2.0f - omg[k]);
+        const float ex = fmaf(-q, F.p1 + R[k].X, F.g1);
+        const float ey = fmaf(-q, F.p2 + R[k].Y, F.g2);
+        const float ez = fmaf(-q, C.pp3 - R[k].W, F.g3);
+        const float cc = fmaf(ex, R[k].t1, fmaf(ey, R[k].t2, ez * R[k].t3));
+        const float ss = fmaf(ex, R[k].f1, fmaf(ey, R[k].f2, ez * R[k].f3));
+        const float c2 = fmaf(cc, cc, -ss * ss);
+        float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
+        if (BEAM == BEAM_SCALAR) {
+            const float4 c = cl[k][0];
+            bT = fmaf(fv[k], fmaf(fu[k], c.w, c.z), fmaf(fu[k], c.y, c.x));
+        } else {
+            const float4 q00 = cl[k][0], q10 = cl[k][1], q01 = cl[k][2], q11 = cl[k][3];
+            bI = lerp(lerp(q00.x, q10.x, fu[k]), lerp(q01.x, q11.x, fu[k]), fv[k]);
+            bQ = lerp(lerp(q00.y, q10.y, fu[k]), lerp(q01.y, q11.y, fu[k]), fv[k]);
+            bU = lerp(lerp(q00.z, q10.z, fu[k]), lerp(q01.z, q11.z, fu[k]), fv[k]);
+            bT = lerp(lerp(q00.w, q10.w, fu[k]), lerp(q01.w, q11.w, fu[k]), fv[k]);
+        }
+        if (PS) o.vn += in[k] ? bT : 0.0f;
+        if (MODE == MODE_TOD) {
+            float term;
+            if (BEAM == BEAM_SCALAR) {
+                // R.c holds twice the U-like coefficient: sin 2chi / 2 = cc ss
+                term = bT * fmaf(c2, R[k].b, fmaf(cc * ss, R[k].c, R[k].a));
+            } else {
+                const float s2 = 2.0f * cc * ss;
+                const float bq = fmaf(bQ, R[k].b, bU * R[k].c);
+                const float bu = fmaf(bQ, R[k].c, -bU * R[k].b);
+                term = fmaf(bI, R[k].a, fmaf(c2, bq, s2 * bu));
+            }
+            o.v0 += in[k] ? term : 0.0f;
+        } else {
+            const float s2 = 2.0f * cc * ss;
+            o.v0 += in[k] ? bT * R[k].a : 0.0f;
+            o.v1 += in[k] ? bT * fmaf(c2, R[k].b, s2 * R[k].c) : 0.0f;
+            o.v2 += in[k] ? bT * fmaf(-s2, R[k].b, c2 * R[k].c) : 0.0f;
+        }
+    }
+    return o;
+}
+
 template <int MODE, int BEAM, int CH, bool PS>
 __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
                               int lane) {
@@ -721,65 +826,28 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         npairs += ((omg <= omax) && (!inner || omg > omin)) ? 1 : 0;
                     }
                 } else {
-#pragma unroll 2
-                    for (int32_t m = 0; m < m_end; ++m) {
-                        const PixRec R = L.rec[m];
-                        // n = X e1 + Y e2 + (1 - W) c in the tile frame
-                        const float omg = fmaf(-R.Y, F.p2, fmaf(-R.X, F.p1, fmaf(R.W, F.p3, F.om)));  // 1 - n.p
-                        bool in = (omg <= omax) && (!inner || omg > omin);
-                        const float xp = fmaf(-R.W, F.a3, fmaf(R.Y, F.a2, fmaf(R.X, F.a1, F.a3)));  // n . theta'_0
-                        const float yp = fmaf(-R.W, F.b3, fmaf(R.Y, F.b2, fmaf(R.X, F.b1, F.b3)));  // n . phi'_0
-                        const float rz = rcp(1.0f - omg);
-                        const float su = xp * rz, sv = yp * rz;  // gnomonic u, v
-                        const float tu = fmaf(su, inv_h, c0);
-                        const float tv = fmaf(sv, inv_h, c0);
-                        if (clip) in = in && (tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax);
-                        // cell indices (clamped: pairs outside the disc are masked below)
-                        const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, cmax));
-                        const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, cmax));
-                        const float fu = fmaf(su, inv_h, c0 - ku), fv = fmaf(sv, inv_h, c0 - kv);
-                        const uint32_t off = (uint32_t)fmaf(kv, row, ku) << 4;  // exact: row^2 < 2^24
-                        float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
-                        if (BEAM == BEAM_SCALAR) {
-                            const float4 cl = beam_ld(beam, off, 0);
-                            bT = fmaf(fv, fmaf(fu, cl.w, cl.z), fmaf(fu, cl.y, cl.x));
-                        } else {
-                            const float4 q00 = beam_ld(beam, off, 0), q10 = beam_ld(beam, off + 16, 0),
-                                         q01 = beam_ld(beam, off, row_bytes),
-                                         q11 = beam_ld(beam, off + 16, row_bytes);
-                            bI = lerp(lerp(q00.x, q10.x, fu), lerp(q01.x, q11.x, fu), fv);
-                            bQ = lerp(lerp(q00.y, q10.y, fu), lerp(q01.y, q11.y, fu), fv);
-                            bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
-                            bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
+                    // two records per step: their masked terms are added in FP32
+                    // and the pair enters the compensated sums (halves the
+                    // compensation work; each pre-sum rounds once)
+                    const PairCtx C{F, omax, omin, inner, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes};
+                    int32_t m = 0;
+                    for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
+                        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP>(&L.rec[m], C, beam);
+                        acc0.add(a.v0);
+                        if (MODE == MODE_STOKES) {
+                            acc1.add(a.v1);
+                            acc2.add(a.v2);
                         }
-                        // co-polar vector carried from the boresight to the pixel along the great circle
-                        const float gn = fmaf(-R.W, F.g3, fmaf(F.g2, R.Y, fmaf(F.g1, R.X, F.g3)));
-                        const float q = gn * rcp(2.0f - omg);
-                        const float ex = fmaf(-q, F.p1 + R.X, F.g1);
-                        const float ey = fmaf(-q, F.p2 + R.Y, F.g2);
-                        const float ez = fmaf(-q, pp3 - R.W, F.g3);
-                        const float cc = fmaf(ex, R.t1, fmaf(ey, R.t2, ez * R.t3));
-                        const float ss = fmaf(ex, R.f1, fmaf(ey, R.f2, ez * R.f3));
-                        const float c2 = fmaf(cc, cc, -ss * ss);
-                        if (PS) accn.add(in ? bT : 0.0f);
-                        if (MODE == MODE_TOD) {
-                            float term;
-                            if (BEAM == BEAM_SCALAR) {
-                                // R.c holds twice the U-like coefficient: sin 2chi / 2 = cc ss
-                                term = bT * fmaf(c2, R.b, fmaf(cc * ss, R.c, R.a));
-                            } else {
-                                const float s2 = 2.0f * cc * ss;
-                                const float bq = fmaf(bQ, R.b, bU * R.c);
-                                const float bu = fmaf(bQ, R.c, -bU * R.b);
-                                term = fmaf(bI, R.a, fmaf(c2, bq, s2 * bu));
-                            }
-                            acc0.add(in ? term : 0.0f);
-                        } else {
-                            const float s2 = 2.0f * cc * ss;
-                            acc0.add(in ? bT * R.a : 0.0f);
-                            acc1.add(in ? bT * fmaf(c2, R.b, s2 * R.c) : 0.0f);
-                            acc2.add(in ? bT * fmaf(-s2, R.b, c2 * R.c) : 0.0f);
+                        if (PS) accn.add(a.vn);
+                    }
+                    for (; m < m_end; ++m) {
+                        const PairOut a = tile_pairs<MODE, BEAM, PS, 1>(&L.rec[m], C, beam);
+                        acc0.add(a.v0);
+                        if (MODE == MODE_STOKES) {
+                            acc1.add(a.v1);
+                            acc2.add(a.v2);
                         }
+                        if (PS) accn.add(a.vn);
                     }
                 }
             }
@@ -806,6 +874,321 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
         out[3 * o + 0] = (float)(acc0.value() * Nrm);
         out[3 * o + 1] = (float)(acc1.value() * Nrm);
         out[3 * o + 2] = (float)(acc2.value() * Nrm);
+    }
+}
+
+// ----------------------------------------------------------------------
+// Sample-parallel path with the pixel-linear parts of every pair on the
+// matrix cores.  For a tile of 64 samples and a group of 16 staged pixels,
+// FP32 MFMAs (16 x 16 x 4) form, for every (pixel, sample) pair, the
+// quantities that are linear in the pixel record:
+//   1 - n.p, n.theta'_0, n.phi'_0, g.n   on the pixel basis (1, X, Y, W)
+//   g.theta_hat_k, p.theta_hat_k         on the pixel basis (t1, t2, t3, 0)
+//   g.phi_hat_k, p.phi_hat_k             on the pixel basis (f1, f2, f3, 0)
+// with g the co-polar direction at the boresight.  The co-polar vector carried
+// to the pixel, e = g - q (p + n) with q = g.n / (1 + n.p), projects on the
+// pixel's basis as e.theta_hat_k = g.theta_hat_k - q p.theta_hat_k (theta_hat_k
+// and phi_hat_k are normal to n), so only the nonlinear steps of a pair run on
+// the vector ALU.  MFMA operands: A = pixel basis (lane l: pixel l % 16,
+// component l / 16), B = per-sample coefficients (lane l: component l / 16,
+// sample l % 16 of a 16-sample block); lane l receives pixels 4 (l / 16) + i
+// for sample l % 16 and keeps that sample's sums, reduced over the four lane
+// groups at the end of the tile.
+// ----------------------------------------------------------------------
+template <int CH, int NACC>
+struct TileLdsMx {
+    UnionRing ring[WAVE];
+    LaneFrame lane[WAVE];
+    int32_t seg_end[WAVE];
+    float b1[4][CH];          // (1, X, Y, W)
+    float bt[4][CH];          // the pixel's theta_hat (t1, t2, t3, 0)
+    float bf[4][CH];          // the pixel's phi_hat (f1, f2, f3, 0)
+    float4 sky[CH];           // (a, b, c, 0) as in PixRec
+    float acc[4][NACC][WAVE]; // running sums of the four 16-sample blocks
+};
+
+template <int MODE>
+constexpr int mx_nacc() { return MODE == MODE_STOKES ? 8 : 4; }
+
+typedef float mx4 __attribute__((ext_vector_type(4)));
+
+__device__ inline mx4 mx(float a, float b) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, mx4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+}
+
+// Compensated sums over the four lane groups l / 16 (lanes l, l ^ 16, l ^ 32, l ^ 48).
+__device__ inline void reduce_groups(Acc<float> &a) {
+#pragma unroll
+    for (int m = 16; m <= 32; m <<= 1) {
+        const float os = __shfl_xor(a.s, m, WAVE);
+        const float oc = __shfl_xor(a.c, m, WAVE);
+        a.add(os);
+        a.c += oc;
+    }
+}
+
+template <int MODE, int BEAM, int CH, bool PS>
+__device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt,
+                                 TileLdsMx<CH, mx_nacc<MODE>()> &L, int lane) {
+    constexpr int NACC = mx_nacc<MODE>();
+    const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
+    const int32_t N = (int32_t)A.nside;
+    const bool valid = lane < cnt;
+    const int64_t t = begin + (valid ? lane : 0);
+
+    const TileFrame T = tile_setup(D, t, valid, &L.lane[lane]);
+    const double thc = uniform(T.thc), phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
+    const double Ru = uniform(T.Ru);
+    const double cosRu = cos(Ru);
+    const float zcf = (float)zc, scf = (float)sc;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int a = 0; a < NACC; ++a) L.acc[j][a][lane] = 0.0f;
+    wave_sync();  // lanes read the frames of a 16-sample block below
+
+    const int32_t n = D.n;
+    const float inv_h = (float)D.inv_h;
+    const float c0 = (float)(0.5 * (n - 1));
+    const float tmax = (float)(n - 1);
+    const float omax = (float)D.omega_max, omin = (float)D.omega_min;
+    const bool inner = D.has_inner != 0;
+    const bool clip = D.needs_clip != 0;
+    const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
+    const float cmax = (float)(n - 2);
+    const float row = (float)(BEAM == BEAM_SCALAR ? n - 1 : n);
+    const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n - 1) * (n - 1) : n * n);
+    const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
+    const int32_t row_bytes = (int32_t)(16 * n);
+    const int k4 = lane >> 4, c16 = lane & 15;
+
+    const int32_t nring = 4 * N - 1;
+    const int32_t r_lo = (thc - Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, thc - Ru)) - 1);
+    const int32_t r_hi = (thc + Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, thc + Ru)) + 1);
+
+    for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
+        const int32_t r = rb + lane;
+        int32_t rc = 0;
+        if (r <= r_hi) rc = union_ring_setup(N, r, phc, zc, sc, cosRu, &L.ring[lane]);
+        const int32_t incl = wave_inclusive_scan(rc, lane);
+        L.seg_end[lane] = incl;
+        const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
+        wave_sync();
+
+        for (int32_t pb = 0; pb < total; pb += CH) {
+            const int32_t m_end = min(CH, total - pb);
+            const int32_t m_pad = (m_end + 15) & ~15;
+            // fill: one pixel record per lane; padding records lie outside every disc
+            int32_t seg = 0;
+            for (int32_t m = lane; m < m_pad; m += WAVE) {
+                if (m < m_end) {
+                    const int32_t f = pb + m;
+                    while (f >= L.seg_end[seg]) ++seg;
+                    const int32_t start = (seg == 0) ? 0 : L.seg_end[seg - 1];
+                    const UnionRing &u = L.ring[seg];
+                    const int32_t rn = u.n, half = rn >> 1;
+                    int32_t kk = u.lo + (f - start);
+                    if (kk >= half) kk -= rn;
+                    if (kk >= half) kk -= rn;
+                    if (kk < -half) kk += rn;
+                    int32_t j = u.jc + kk;
+                    if (j < 0) j += rn;
+                    else if (j >= rn) j -= rn;
+                    const float dph = fmaf((float)kk, u.dphi, u.dphic);
+                    float sh, ch;
+                    half_sincos(0.5f * dph, sh, ch);
+                    const float h = 2.0f * sh * sh;  // 1 - cos(dphi)
+                    const float S = 2.0f * sh * ch;  // sin(dphi)
+                    L.b1[0][m] = 1.0f;
+                    L.b1[1][m] = fmaf(-u.b, h, u.a);
+                    L.b1[2][m] = u.s * S;
+                    L.b1[3][m] = fmaf(u.c, h, u.e);
+                    L.bt[0][m] = fmaf(-u.f, h, u.cdt);
+                    L.bt[1][m] = u.z * S;
+                    L.bt[2][m] = fmaf(-u.g, h, -u.a);
+                    L.bt[3][m] = 0.0f;
+                    L.bf[0][m] = -zcf * S;
+                    L.bf[1][m] = 1.0f - h;
+                    L.bf[2][m] = -scf * S;
+                    L.bf[3][m] = 0.0f;
+                    const float4 sv = sky[u.first + j];
+                    float4 rec;
+                    if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
+                        rec.x = wI * sv.x;
+                        rec.y = fmaf(wQ, sv.y, wU * sv.z);
+                        rec.z = 2.0f * fmaf(wQ, sv.z, -wU * sv.y);
+                    } else {
+                        rec.x = sv.x;
+                        rec.y = sv.y;
+                        rec.z = sv.z;
+                    }
+                    rec.w = 0.0f;
+                    L.sky[m] = rec;
+                } else {
+                    // 1 - n.p = om + 4 p3 > 1 for every sample: never inside a disc
+                    L.b1[0][m] = 1.0f;
+                    L.b1[1][m] = 0.0f;
+                    L.b1[2][m] = 0.0f;
+                    L.b1[3][m] = 4.0f;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        L.bt[c][m] = 0.0f;
+                        L.bf[c][m] = 0.0f;
+                    }
+                    L.sky[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                }
+            }
+            wave_sync();
+
+            // one pass per 16-sample block: its coefficients and running sums
+            // come from LDS, so little stays live across the pixel groups
+#pragma unroll 1
+            for (int jb = 0; jb < 4; ++jb) {
+                const LaneFrame &G = L.lane[16 * jb + c16];
+                const float Bo = k4 == 0 ? G.om : k4 == 1 ? -G.p1 : k4 == 2 ? -G.p2 : G.p3;
+                if (MODE == MODE_COUNT) {
+                    float cntf = L.acc[jb][0][lane];
+                    for (int32_t g = 0; g < m_pad; g += 16) {
+                        const mx4 vo = mx(L.b1[k4][g + c16], Bo);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) cntf += ((vo[q] <= omax) && (!inner || vo[q] > omin)) ? 1.0f : 0.0f;
+                    }
+                    L.acc[jb][0][lane] = cntf;
+                    continue;
+                }
+                const float Bx = k4 == 0 ? G.a3 : k4 == 1 ? G.a1 : k4 == 2 ? G.a2 : -G.a3;
+                const float By = k4 == 0 ? G.b3 : k4 == 1 ? G.b1 : k4 == 2 ? G.b2 : -G.b3;
+                const float Bn = k4 == 0 ? G.g3 : k4 == 1 ? G.g1 : k4 == 2 ? G.g2 : -G.g3;
+                const float Bg = k4 == 0 ? G.g1 : k4 == 1 ? G.g2 : k4 == 2 ? G.g3 : 0.0f;
+                const float Bp = k4 == 0 ? G.p1 : k4 == 1 ? G.p2 : k4 == 2 ? G.p3 : 0.0f;
+                Acc<float> a0, a1s, a2s, an;
+                a0.s = L.acc[jb][0][lane];
+                a0.c = L.acc[jb][1][lane];
+                if (PS) {
+                    an.s = L.acc[jb][2][lane];
+                    an.c = L.acc[jb][3][lane];
+                }
+                if (MODE == MODE_STOKES) {
+                    a1s.s = L.acc[jb][4][lane];
+                    a1s.c = L.acc[jb][5][lane];
+                    a2s.s = L.acc[jb][6][lane];
+                    a2s.c = L.acc[jb][7][lane];
+                }
+                for (int32_t g = 0; g < m_pad; g += 16) {
+                    const float p1v = L.b1[k4][g + c16], ptv = L.bt[k4][g + c16], pfv = L.bf[k4][g + c16];
+                    const mx4 vo = mx(p1v, Bo), vx = mx(p1v, Bx), vy = mx(p1v, By), vn = mx(p1v, Bn);
+                    const mx4 gt = mx(ptv, Bg), pt = mx(ptv, Bp), gf = mx(pfv, Bg), pf = mx(pfv, Bp);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float4 sk = L.sky[g + 4 * k4 + q];
+                        const float omg = vo[q];  // 1 - n.p
+                        bool in = (omg <= omax) && (!inner || omg > omin);
+                        const float rz = rcp(1.0f - omg);
+                        const float su = vx[q] * rz, sv = vy[q] * rz;  // gnomonic u, v
+                        const float tu = fmaf(su, inv_h, c0);
+                        const float tv = fmaf(sv, inv_h, c0);
+                        if (clip) in = in && (tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax);
+                        const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, cmax));
+                        const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, cmax));
+                        const float fu = fmaf(su, inv_h, c0 - ku), fv = fmaf(sv, inv_h, c0 - kv);
+                        const uint32_t off = (uint32_t)fmaf(kv, row, ku) << 4;
+                        float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
+                        if (BEAM == BEAM_SCALAR) {
+                            const float4 cl = beam_ld(beam, off, 0);
+                            bT = fmaf(fv, fmaf(fu, cl.w, cl.z), fmaf(fu, cl.y, cl.x));
+                        } else {
+                            const float4 q00 = beam_ld(beam, off, 0), q10 = beam_ld(beam, off + 16, 0),
+                                         q01 = beam_ld(beam, off, row_bytes),
+                                         q11 = beam_ld(beam, off + 16, row_bytes);
+                            bI = lerp(lerp(q00.x, q10.x, fu), lerp(q01.x, q11.x, fu), fv);
+                            bQ = lerp(lerp(q00.y, q10.y, fu), lerp(q01.y, q11.y, fu), fv);
+                            bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
+                            bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
+                        }
+                        const float qq = vn[q] * rcp(2.0f - omg);
+                        const float cc = fmaf(-qq, pt[q], gt[q]);  // e . theta_hat_k
+                        const float ss = fmaf(-qq, pf[q], gf[q]);  // e . phi_hat_k
+                        const float c2 = fmaf(cc, cc, -ss * ss);
+                        if (PS) an.add(in ? bT : 0.0f);
+                        if (MODE == MODE_TOD) {
+                            float term;
+                            if (BEAM == BEAM_SCALAR) {
+                                term = bT * fmaf(c2, sk.y, fmaf(cc * ss, sk.z, sk.x));
+                            } else {
+                                const float s2 = 2.0f * cc * ss;
+                                const float bq = fmaf(bQ, sk.y, bU * sk.z);
+                                const float bu = fmaf(bQ, sk.z, -bU * sk.y);
+                                term = fmaf(bI, sk.x, fmaf(c2, bq, s2 * bu));
+                            }
+                            a0.add(in ? term : 0.0f);
+                        } else {
+                            const float s2 = 2.0f * cc * ss;
+                            a0.add(in ? bT * sk.x : 0.0f);
+                            a1s.add(in ? bT * fmaf(c2, sk.y, s2 * sk.z) : 0.0f);
+                            a2s.add(in ? bT * fmaf(-s2, sk.y, c2 * sk.z) : 0.0f);
+                        }
+                    }
+                }
+                L.acc[jb][0][lane] = a0.s;
+                L.acc[jb][1][lane] = a0.c;
+                if (PS) {
+                    L.acc[jb][2][lane] = an.s;
+                    L.acc[jb][3][lane] = an.c;
+                }
+                if (MODE == MODE_STOKES) {
+                    L.acc[jb][4][lane] = a1s.s;
+                    L.acc[jb][5][lane] = a1s.c;
+                    L.acc[jb][6][lane] = a2s.s;
+                    L.acc[jb][7][lane] = a2s.c;
+                }
+            }
+            wave_sync();
+        }
+    }
+
+    float *out = reinterpret_cast<float *>(A.out);
+#pragma unroll 1
+    for (int jb = 0; jb < 4; ++jb) {
+        const int smp = 16 * jb + c16;
+        if (MODE == MODE_COUNT) {
+            float v = L.acc[jb][0][lane];
+            v += __shfl_xor(v, 16, WAVE);
+            v += __shfl_xor(v, 32, WAVE);
+            if (k4 == 0 && smp < cnt) out[D.out_offset + begin + smp] = v;
+            continue;
+        }
+        Acc<float> a0, a1s, a2s, an;
+        a0.s = L.acc[jb][0][lane];
+        a0.c = L.acc[jb][1][lane];
+        reduce_groups(a0);
+        if (PS) {
+            an.s = L.acc[jb][2][lane];
+            an.c = L.acc[jb][3][lane];
+            reduce_groups(an);
+        }
+        if (MODE == MODE_STOKES) {
+            a1s.s = L.acc[jb][4][lane];
+            a1s.c = L.acc[jb][5][lane];
+            a2s.s = L.acc[jb][6][lane];
+            a2s.c = L.acc[jb][7][lane];
+            reduce_groups(a1s);
+            reduce_groups(a2s);
+        }
+        if (k4 != 0 || smp >= cnt) continue;
+        double Nrm = D.norm_scale;
+        if (PS && D.norm_mode == 1) {
+            const double snm = an.value() * (BEAM == BEAM_SCALAR ? D.w[3] : 1.0);
+            Nrm = (snm != 0.0) ? D.norm_scale / snm : 0.0;
+        }
+        const int64_t o = D.out_offset + begin + smp;
+        if (MODE == MODE_TOD) {
+            out[o] = (float)(a0.value() * Nrm);
+        } else {
+            if (BEAM == BEAM_SCALAR) Nrm *= D.w[3];
+            out[3 * o + 0] = (float)(a0.value() * Nrm);
+            out[3 * o + 1] = (float)(a1s.value() * Nrm);
+            out[3 * o + 2] = (float)(a2s.value() * Nrm);
+        }
     }
 }
 
@@ -862,7 +1245,7 @@ __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
 }
 
 template <int MODE, int BEAM, int CH, bool PS>
-__global__ void __launch_bounds__(512, 4) tile_kernel(ConvArgs A) {
+__global__ void __launch_bounds__(512, TILE_MINW) tile_kernel(ConvArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = threadIdx.x / WAVE;
@@ -881,6 +1264,30 @@ __global__ void __launch_bounds__(512, 4) tile_kernel(ConvArgs A) {
         const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
         const DetDesc &D = A.dets[tl.det];
         convolve_tile<MODE, BEAM, CH, PS>(A, D, tl.begin, tl.count, L, lane);
+    }
+}
+
+template <int MODE, int BEAM, int CH, bool PS>
+__global__ void __launch_bounds__(512, 2) tile_mx_kernel(ConvArgs A) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wid = threadIdx.x / WAVE;
+    TileLdsMx<CH, mx_nacc<MODE>()> &L = reinterpret_cast<TileLdsMx<CH, mx_nacc<MODE>()> *>(lds_raw)[wid];
+    int32_t q = (A.n_queues > 1) ? (int32_t)(blockIdx.x % (uint32_t)A.n_queues) : 0;
+    int32_t exhausted = 0;
+    while (exhausted < A.n_queues) {
+        int32_t ti = 0;
+        if (lane == 0) ti = atomicAdd(&A.counters[q], 1);
+        ti = __builtin_amdgcn_readfirstlane(__shfl(ti, 0, WAVE));
+        if (ti >= A.queue_len[q]) {
+            q = (q + 1 == A.n_queues) ? 0 : q + 1;
+            ++exhausted;
+            continue;
+        }
+        const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
+        const DetDesc &D = A.dets[tl.det];
+        convolve_tile_mx<MODE, BEAM, CH, PS>(A, D, tl.begin, tl.count, L, lane);
+        wave_sync();  // the next tile's set-up overwrites the frames this one read
     }
 }
 
@@ -974,8 +1381,35 @@ static hipError_t launch_tile_t(const ConvArgs &a, int waves, int groups, hipStr
     return hipGetLastError();
 }
 
+template <int MODE, int BEAM, int CH, bool PS>
+static hipError_t launch_tile_mx_t(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+    // the Stokes sums need more LDS per wave: keep a workgroup within one
+    // compute unit's 160 KiB by splitting it (waves are independent)
+    const size_t slice = sizeof(TileLdsMx<CH, mx_nacc<MODE>()>);
+    const int wmax = (int)((160 * 1024) / slice);
+    if (waves > wmax) {
+        groups = (int)(((int64_t)groups * waves + wmax - 1) / wmax);
+        waves = wmax;
+    }
+    const size_t lds = slice * (size_t)waves;
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_mx_kernel<MODE, BEAM, CH, PS>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((tile_mx_kernel<MODE, BEAM, CH, PS>), dim3(groups), dim3(WAVE * waves), lds, s, a);
+    return hipGetLastError();
+}
+
 template <int MODE, int BEAM, bool PS>
 static hipError_t launch_tile_c(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+    if (a.algo == ALGO_TILE_MX) {
+        switch (a.chunk) {
+            case 64: return launch_tile_mx_t<MODE, BEAM, 64, PS>(a, waves, groups, s);
+            case 256: return launch_tile_mx_t<MODE, BEAM, 256, PS>(a, waves, groups, s);
+            default: return launch_tile_mx_t<MODE, BEAM, 128, PS>(a, waves, groups, s);
+        }
+    }
     switch (a.chunk) {
         case 64: return launch_tile_t<MODE, BEAM, 64, PS>(a, waves, groups, s);
         case 256: return launch_tile_t<MODE, BEAM, 256, PS>(a, waves, groups, s);
@@ -1001,7 +1435,7 @@ hipError_t launch_conv(const ConvArgs &a, bool f64, int waves, int groups, hipSt
             default: return launch_pixel<double, MODE_COUNT>(a, waves, groups, s);
         }
     }
-    if (a.algo == ALGO_TILE) {
+    if (a.algo == ALGO_TILE || a.algo == ALGO_TILE_MX) {
         switch (a.out_mode) {
             case MODE_TOD: return launch_tile<MODE_TOD>(a, waves, groups, s);
             case MODE_STOKES: return launch_tile<MODE_STOKES>(a, waves, groups, s);

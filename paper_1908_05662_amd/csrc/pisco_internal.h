@@ -8,7 +8,7 @@ namespace pisco {
 
 enum { MODE_TOD = 0, MODE_STOKES = 1, MODE_COUNT = 2 };
 enum { BEAM_FULL = 0, BEAM_SCALAR = 1 };
-enum { ALGO_PIXEL = 0, ALGO_TILE = 1 };
+enum { ALGO_PIXEL = 0, ALGO_TILE = 1, ALGO_TILE_MX = 2 };
 
 // Per-detector description, read by the kernel from device memory.
 struct DetDesc {

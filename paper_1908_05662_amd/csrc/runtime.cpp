@@ -309,7 +309,7 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
             groups.push_back(t);
         }
     std::vector<int32_t> flag(groups.size(), 0);
-    const bool tile_path = (c->algo == PISCO_ALGO_TILE) && (c->sky_dtype == PISCO_F32);
+    const bool tile_path = (c->algo == PISCO_ALGO_TILE || c->algo == PISCO_ALGO_TILE_MX) && (c->sky_dtype == PISCO_F32);
     if (tile_path && !groups.empty()) {
         const size_t need = groups.size() * (sizeof(Tile) + sizeof(int32_t));
         if (p.scratch_cap < need) {
@@ -387,7 +387,7 @@ ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode, bool ti
     a.tiles_per_queue = q.per;
     a.out_mode = out_mode;
     a.beam_kind = p.beam_kind;
-    a.algo = tile ? pisco::ALGO_TILE : pisco::ALGO_PIXEL;
+    a.algo = tile ? (c->algo == PISCO_ALGO_TILE_MX ? pisco::ALGO_TILE_MX : pisco::ALGO_TILE) : pisco::ALGO_PIXEL;
     a.chunk = c->chunk;
     a.coherence = c->coherence;
     a.per_sample = p.per_sample;
@@ -774,7 +774,7 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
 pisco_status pisco_set_launch(pisco_ctx *c, const pisco_launch *l) {
     if (!c || !l) return PISCO_EINVAL;
     c->err.clear();
-    if (l->algorithm != PISCO_ALGO_PIXEL && l->algorithm != PISCO_ALGO_TILE)
+    if (l->algorithm != PISCO_ALGO_PIXEL && l->algorithm != PISCO_ALGO_TILE && l->algorithm != PISCO_ALGO_TILE_MX)
         return fail(c, PISCO_EINVAL, "bad algorithm %d", l->algorithm);
     if (l->samples_per_tile < 1 || l->samples_per_tile > 65536) return fail(c, PISCO_EINVAL, "samples_per_tile out of range");
     const int w = l->waves_per_group;
@@ -784,8 +784,13 @@ pisco_status pisco_set_launch(pisco_ctx *c, const pisco_launch *l) {
     if (l->chunk != 64 && l->chunk != 128 && l->chunk != 256) return fail(c, PISCO_EINVAL, "chunk must be 64, 128 or 256");
     if (!(l->coherence > 0.0 && l->coherence <= 4.0)) return fail(c, PISCO_EINVAL, "coherence must be in (0, 4]");
     // LDS per workgroup must fit the 160 KiB of a compute unit
-    const size_t tile_slice = 64 * 64 + 64 * 52 + 64 * 4 + (size_t)l->chunk * 48;
-    if (l->algorithm == PISCO_ALGO_TILE && tile_slice * (size_t)w > 160 * 1024)
+    // LDS per wave: rings, frames and segment ends, the staged records and, on
+    // the matrix-core path, the running sums of TOD launches (Stokes launches
+    // split workgroups that would not fit)
+    const size_t tile_slice = 64 * 64 + 64 * 52 + 64 * 4 +
+                              (l->algorithm == PISCO_ALGO_TILE_MX ? (size_t)l->chunk * 64 + 4 * 4 * 64 * 4
+                                                                   : (size_t)l->chunk * 48);
+    if (l->algorithm != PISCO_ALGO_PIXEL && tile_slice * (size_t)w > 160 * 1024)
         return fail(c, PISCO_EINVAL, "chunk %d with %d waves per group exceeds the LDS of a compute unit", l->chunk, w);
     c->algo = l->algorithm;
     c->spt = l->samples_per_tile;

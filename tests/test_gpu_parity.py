@@ -33,7 +33,7 @@ def conv(torch):
     c.close()
 
 
-ALGOS = [0, 1]          # pixel-parallel, sample-parallel tile path
+ALGOS = [0, 1, 2]       # pixel-parallel, sample-parallel tile path, tile path on the matrix cores
 BEAMS = ["full", "auto"]  # four-channel grid, one-grid (scalar) form
 
 
@@ -99,7 +99,7 @@ def _gauss(n, span_deg, fwhm_deg, e=0.1, o=0.5, leak=0.01):
 
 
 @pytest.mark.parametrize("dtype,tol,algo", [(np.float64, F64_TOL, 0), (np.float32, F32_TOL, 0),
-                                            (np.float32, F32_TOL, 1)])
+                                            (np.float32, F32_TOL, 1), (np.float32, F32_TOL, 2)])
 def test_edge_geometry(conv, torch, dtype, tol, algo):
     """Poles inside the disc, boresight exactly on a pole, longitude wrap-around,
     negative / >2pi longitudes, full rings, coarse maps with wide discs."""
@@ -137,6 +137,7 @@ def _pole_crossing_scan(n):
 
 @pytest.mark.parametrize("dtype,tol,algo,scan", [(np.float64, F64_TOL, 0, "random"), (np.float32, F32_TOL, 0, "random"),
                                                  (np.float32, F32_TOL, 1, "random"), (np.float32, F32_TOL, 1, "poles"),
+                                                 (np.float32, F32_TOL, 2, "random"), (np.float32, F32_TOL, 2, "poles"),
                                                  (np.float64, F64_TOL, 0, "poles")])
 def test_annulus_stokes_fixed(conv, torch, dtype, tol, algo, scan):
     """Annulus selection, the Stokes-pickup output and FIXED normalisation; the

@@ -40,7 +40,7 @@ def _sorted(w):
     return w
 
 
-@pytest.mark.parametrize("algo", [0, 1])
+@pytest.mark.parametrize("algo", [0, 1, 2])
 def test_annulus_targets_match_oracle(conv, torch, algo):
     """The network's training targets are exact annulus pickups: check sampled
     ones of the full 1e6-sample held-out set against the oracle."""
