@@ -645,7 +645,7 @@ template <int MODE, int BEAM, bool PS, int NP>
 __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C, const BeamRsrc &beam) {
     const LaneFrame &F = C.F;
     PixRec R[NP];
-    float omg[NP], xp[NP], yp[NP], rzh[NP], fu[NP], fv[NP];
+    float omg[NP], xp[NP], yp[NP], rzh[NP], rq[NP], fu[NP], fv[NP];
     bool in[NP];
     uint32_t off[NP];
 #pragma unroll
@@ -656,7 +656,11 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C
         in[k] = (omg[k] <= C.omax) && (!C.inner || omg[k] > C.omin);
         xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));  // n . theta'_0
         yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));  // n . phi'_0
-        rzh[k] = rcp(1.0f - omg[k]) * C.inv_h;  // gnomonic scale in grid units
+        // one reciprocal for both divisions of the pair: 1 / (z' (1 + z')), z' = n.p
+        const float zp = 1.0f - omg[k], zq = 2.0f - omg[k];
+        const float rr = rcp(zp * zq);
+        rzh[k] = rr * zq * C.inv_h;  // gnomonic scale 1 / z' in grid units
+        rq[k] = rr * zp;             // 1 / (1 + z')
         const float tu = fmaf(xp[k], rzh[k], C.c0);
         const float tv = fmaf(yp[k], rzh[k], C.c0);
         if (C.clip) in[k] = in[k] && (tu >= 0.0f && tu <= C.tmax && tv >= 0.0f && tv <= C.tmax);
@@ -682,7 +686,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C
     for (int k = 0; k < NP; ++k) {
         // co-polar vector carried from the boresight to the pixel along the great circle
         const float gn = fmaf(-R[k].W, F.g3, fmaf(F.g2, R[k].Y, fmaf(F.g1, R[k].X, F.g3)));
-        const float q = gn * rcp(2.0f - omg[k]);
+        const float q = gn * rq[k];
         const float ex = fmaf(-q, F.p1 + R[k].X, F.g1);
         const float ey = fmaf(-q, F.p2 + R[k].Y, F.g2);
         const float ez = fmaf(-q, C.pp3 - R[k].W, F.g3);
@@ -704,8 +708,12 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C
         if (MODE == MODE_TOD) {
             float term;
             if (BEAM == BEAM_SCALAR) {
-                // R.c holds twice the U-like coefficient: sin 2chi / 2 = cc ss
-                term = bT * fmaf(c2, R[k].b, fmaf(cc * ss, R[k].c, R[k].a));
+                // R.c holds twice the U-like coefficient: sin 2chi / 2 = cc ss;
+                // the mask goes on the beam value (every factor is finite)
+                const float bTm = in[k] ? bT : 0.0f;
+                term = bTm * fmaf(c2, R[k].b, fmaf(cc * ss, R[k].c, R[k].a));
+                o.v0 += term;
+                continue;
             } else {
                 const float s2 = 2.0f * cc * ss;
                 const float bq = fmaf(bQ, R[k].b, bU * R[k].c);
