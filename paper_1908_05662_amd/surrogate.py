@@ -29,25 +29,37 @@ from . import _lib as L
 from .api import Convolver, Mlp
 
 
+def _hilbert_index(n: int, x, y):
+    """Position along a Hilbert curve of an n x n grid (n a power of two) of the
+    integer cells (x, y), vectorised (the standard quadrant-rotation recursion)."""
+    x = np.asarray(x, dtype=np.int64).copy()
+    y = np.asarray(y, dtype=np.int64).copy()
+    d = np.zeros_like(x)
+    s = n // 2
+    while s > 0:
+        rx = ((x & s) > 0).astype(np.int64)
+        ry = ((y & s) > 0).astype(np.int64)
+        d += s * s * ((3 * rx) ^ ry)
+        low = ry == 0
+        flip = low & (rx == 1)
+        x = np.where(flip, s - 1 - x, x)
+        y = np.where(flip, s - 1 - y, y)
+        x, y = np.where(low, y, x), np.where(low, x, y)
+        s //= 2
+    return d
+
+
 def spatial_order(theta, phi) -> np.ndarray:
-    """Permutation that puts nearby pointings next to each other (Morton order
-    on the equal-area (z, phi) square).  Samples are independent, so any order
+    """Permutation that puts nearby pointings next to each other: Hilbert order
+    on the equal-area (phi, z) square.  Samples are independent, so any order
     gives the same per-sample result; this one lets 64 consecutive samples
-    share one disc union (the tile kernel)."""
-    z = np.cos(np.asarray(theta, dtype=np.float64))
+    share one compact disc union (the tile kernels)."""
+    n = 1 << 16
     f = np.mod(np.asarray(phi, dtype=np.float64), 2 * np.pi) / (2 * np.pi)
-    qx = np.clip((f * 65536).astype(np.uint64), 0, 65535)
-    qy = np.clip(((z + 1.0) * 0.5 * 65536).astype(np.uint64), 0, 65535)
-
-    def spread(v):
-        v = (v | (v << np.uint64(8))) & np.uint64(0x00FF00FF)
-        v = (v | (v << np.uint64(4))) & np.uint64(0x0F0F0F0F)
-        v = (v | (v << np.uint64(2))) & np.uint64(0x33333333)
-        v = (v | (v << np.uint64(1))) & np.uint64(0x55555555)
-        return v
-
-    key = spread(qx) | (spread(qy) << np.uint64(1))
-    return np.argsort(key, kind="stable")
+    z = (np.cos(np.asarray(theta, dtype=np.float64)) + 1.0) * 0.5
+    qx = np.clip((f * n).astype(np.int64), 0, n - 1)
+    qy = np.clip((z * n).astype(np.int64), 0, n - 1)
+    return np.argsort(_hilbert_index(n, qx, qy), kind="stable")
 
 
 def detector_coef(zeta: float, eps: float, s: float):
