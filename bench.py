@@ -152,6 +152,101 @@ def surrogate_leg(epochs):
     return r
 
 
+# Wall times of the paper's whole-sky benchmark (Sec. 5.3, Table 1): one PSB (2
+# detectors, Gaussian FWHM 1.5 deg) at every nside-128 pixel centre and psi in
+# {0, 45, 90} deg, 1,179,648 samples, on one GTX 1080, including the assembly
+# of the beam interpolation grid and host-device copies.  Context, not a target.
+PAPER_TABLE1 = [(5.0, 374, 1471.41), (7.5, 832, 3135.19), (10.0, 1506, 5560.25), (15.0, 3360, 12719.56),
+                (20.0, 5938, 23190.68), (25.0, 9218, 39447.70), (30.0, 13174, 53800.74)]
+
+
+def paper_shape_leg():
+    """The paper's benchmark workload on this GPU: the same sample pattern and disc
+    radii (synthetic nside-128 sky, 0.1 deg tangent grid over +-rho_max, per-sample
+    normalisation).  Timed kernel-only (inputs resident) in the given sample order
+    (consecutive samples are neighbouring pixels of a ring, so a 64-sample group
+    spans ~29 deg and runs on the pixel path) and in Hilbert order (compact
+    groups, tile path); and end to end from host arrays in the given order
+    (pointing and beam upload, convolution, TOD download)."""
+    import torch
+
+    import oracle
+    from paper_1908_05662_amd import OUT_COUNT, OUT_TOD
+    from paper_1908_05662_amd.api import Convolver
+    from paper_1908_05662_amd.surrogate import spatial_order
+    from synth import workloads as W
+
+    sky = W.sky_for(128, 383, 2.0, 6)
+    sky64 = [m.astype(np.float32).astype(np.float64) for m in sky]
+    rows = []
+    conv = Convolver(0)
+    conv.set_sky(128, *(torch.from_numpy(m.astype(np.float32)).cuda() for m in sky), dtype=torch.float32)
+    stream = torch.cuda.Stream()
+    worst = 0.0
+
+    def run(out):
+        with torch.cuda.stream(stream):
+            conv.convolve(-1, OUT_TOD, out=out, stream=stream)
+        stream.synchronize()
+
+    def kernel_time(out, reps=3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            for _ in range(reps):
+                conv.convolve(-1, OUT_TOD, out=out, stream=stream)
+            b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
+
+    for rho, n_pix, paper_ms in PAPER_TABLE1:
+        w = W.paper_shape(rho, nside=128, sky=sky)
+        n = w.n_samples
+        out = torch.empty(n, dtype=torch.float32, device="cuda")
+
+        def upload(order=None):
+            for k, d in enumerate(w.detectors):
+                conv.set_beamsor(k, d.beam.dense(), d.beam.half_span_tan, d.det.eps, d.det.s, dtype=torch.float32)
+                conv.set_detector(k, d.det.zeta, d.rho_min, d.rho_max, d.norm_mode, d.norm_scale)
+                pts = (d.theta, d.phi, d.psi) if order is None else (d.theta[order], d.phi[order], d.psi[order])
+                conv.set_pointing(k, *pts)   # host arrays: copied
+
+        upload()
+        run(out)                       # plan, graph
+        t0 = time.perf_counter()
+        upload()
+        run(out)
+        host = out.cpu().numpy()
+        t_e2e = time.perf_counter() - t0
+        pairs = float(conv.convolve(-1, OUT_COUNT).double().sum())
+        t_given = kernel_time(out)
+        # parity of sampled outputs (given order)
+        d = w.detectors[1]
+        j = np.linspace(0, d.n - 1, 8).astype(int)
+        want = oracle.tod(w.nside, *sky64, d.beam.dense().astype(np.float32).astype(np.float64),
+                          d.beam.half_span_tan, d.det.zeta, d.det.eps, d.det.s, d.rho_min, d.rho_max, d.norm_mode,
+                          d.norm_scale, d.theta[j], d.phi[j], d.psi[j])
+        got = host[w.detectors[0].n + j].astype(np.float64)
+        worst = max(worst, float(np.abs(got - want).max() / np.abs(want).max()))
+        # the same samples in Hilbert order
+        order = spatial_order(w.detectors[0].theta, w.detectors[0].phi)
+        upload(order)
+        run(out)
+        t_hil = kernel_time(out)
+        rows.append({"rho_max_deg": rho, "pixels_max_paper": n_pix, "pairs_per_sample": pairs / n,
+                     "kernel_ms_given_order": t_given * 1e3, "kernel_ms_hilbert_order": t_hil * 1e3,
+                     "end_to_end_ms_given_order": t_e2e * 1e3, "paper_ms": paper_ms,
+                     "speedup_end_to_end": paper_ms / (t_e2e * 1e3),
+                     "pairs_per_s_hilbert_order": pairs / t_hil})
+        log(f"paper shape rho {rho}: kernel {t_given * 1e3:.2f} ms given order, {t_hil * 1e3:.2f} ms Hilbert "
+            f"order; end to end {t_e2e * 1e3:.1f} ms (paper {paper_ms} ms on a GTX 1080)")
+    conv.close()
+    return {"workload": "the paper's whole-sky benchmark pattern: 2 detectors x 3 psi x 196,608 nside-128 pixel "
+                        "centres = 1,179,648 samples, Gaussian FWHM 1.5 deg, per-sample normalisation",
+            "paper_hardware": "1x NVIDIA GTX 1080, wall time incl. beam-grid assembly and host-device copies",
+            "rows": rows, "parity_max_rel_err": worst}
+
+
 def full_scale_leg(epochs, n_train, width, hidden, lr):
     """The nside-2048 full-scale workload on one GPU: 256 detectors x 390,625 CES
     samples (1e8), each with its own 151^2 elliptical main beam (disc 1.5 deg),
@@ -337,6 +432,7 @@ def main():
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
     ap.add_argument("--launch", type=str, default="", help="key=value,... fields of pisco_launch")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the far-sidelobe surrogate leg")
+    ap.add_argument("--no-paper-shape", action="store_true", help="skip the paper's benchmark-pattern leg")
     ap.add_argument("--full-scale", action="store_true",
                     help="also run the nside-2048, 1e8-sample surrogate-vs-exact leg (about 3 minutes)")
     ap.add_argument("--full-scale-train", type=int, default=6_000_000)
@@ -462,6 +558,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_surrogate:
         rec["surrogate"] = surrogate_leg(args.surrogate_epochs)
+    if not args.no_paper_shape:
+        torch.cuda.empty_cache()
+        rec["paper_shape"] = paper_shape_leg()
     if args.full_scale:
         torch.cuda.empty_cache()
         width, hidden = (int(v) for v in args.full_scale_net.split("x"))
