@@ -53,6 +53,9 @@ def _lib():
         h.orc_tod.argtypes = [i64, dp, dp, dp, i32, dbl, dp, dbl, dbl, dbl, dbl, dbl, i32, dbl,
                               i64, dp, dp, dp, i32, dp, i32]
         h.orc_tod.restype = i32
+        h.orc_tod_iquv.argtypes = [i64, dp, dp, dp, dp, i32, dbl, dp, dbl, dbl, dbl, dbl, dbl, i32, dbl,
+                                   i64, dp, dp, dp, dp, i32, dp, i32]
+        h.orc_tod_iquv.restype = i32
         h.orc_disc.argtypes = [i64, dbl, dbl, dbl, lp, i64]
         h.orc_disc.restype = i64
         h.orc_disc_counts.argtypes = [i64, i64, dp, dp, dbl, lp, i32]
@@ -130,24 +133,34 @@ def disc_counts(nside: int, theta, phi, rho: float, nthreads: int = 0) -> np.nda
 
 def tod(nside: int, I, Q, U, beamsor, half_span_tan: float, zeta: float, eps: float, s: float,
         rho_min: float, rho_max: float, norm_mode: int, norm_scale: float,
-        theta, phi, psi, out_mode: int = OUT_TOD, nthreads: int = 0) -> np.ndarray:
+        theta, phi, psi, out_mode: int = OUT_TOD, nthreads: int = 0, V=None, hwp=None) -> np.ndarray:
     """FP64 convolution of one detector's stream.
 
     beamsor : (n, n, 4, 4) Mueller field M[iv, iu, out, in] over u, v in [-T, T]
+    V       : optional V map (zero when None)
+    hwp     : optional per-sample half-wave-plate angle (radians); the beamsor
+              of sample t becomes M . H(hwp[t])
     returns (nsamp,) for OUT_TOD or (nsamp, 3) for OUT_STOKES.
     """
     I, Q, U = _f64(I), _f64(Q), _f64(U)
+    Vv = None if V is None else _f64(V)
     g = _f64(beamsor)
     n = g.shape[0]
     if g.shape != (n, n, 4, 4):
         raise ValueError("beamsor must be (n, n, 4, 4)")
     th, ph, ps = _f64(theta), _f64(phi), _f64(psi)
     m = th.size
+    hw = None if hwp is None else _f64(hwp)
+    if hw is not None and hw.size != m:
+        raise ValueError("hwp must have one angle per sample")
+    if Vv is not None and Vv.size != I.size:
+        raise ValueError("V must match I")
     width = 3 if out_mode == OUT_STOKES else 1
     out = np.empty(m * width)
-    rc = _lib().orc_tod(nside, _dp(I), _dp(Q), _dp(U), n, half_span_tan, _dp(g), zeta, eps, s,
-                        rho_min, rho_max, norm_mode, norm_scale, m, _dp(th), _dp(ph), _dp(ps),
-                        out_mode, _dp(out), nthreads)
+    null = ctypes.POINTER(ctypes.c_double)()
+    rc = _lib().orc_tod_iquv(nside, _dp(I), _dp(Q), _dp(U), null if Vv is None else _dp(Vv), n, half_span_tan,
+                             _dp(g), zeta, eps, s, rho_min, rho_max, norm_mode, norm_scale, m, _dp(th), _dp(ph),
+                             _dp(ps), null if hw is None else _dp(hw), out_mode, _dp(out), nthreads)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return out.reshape(m, 3) if width == 3 else out

@@ -21,7 +21,13 @@
  *   - (rho, sigma, chi) from the spherical trigonometry of Appendix A,
  *   - N = norm_scale (FIXED) or norm_scale / sum_k B_TT(k) (PER_SAMPLE): the
  *     beamsor's 1/Omega~ normalisation (Sec. 3, equation beamsor), taken either
- *     as a given constant or as the discrete sum over the same pixels.
+ *     as a given constant or as the discrete sum over the same pixels,
+ *   - S_k = (I, Q, U, V) of pixel k (V = 0 when no V map is given).
+ * Modulation (Sec. 7 notes that a modulated beamsor model is all PISCO needs
+ * for a half-wave plate): with a per-sample plate angle phi_t the beamsor of
+ * sample t is B_k . H(phi_t), H(phi) = Lambda(phi) . diag(1, 1, -1, -1) .
+ * Lambda(-phi) the Mueller matrix of an ideal half-wave plate whose axis lies
+ * at phi from the antenna frame's reference direction, sky side of the beam.
  * Every quantity is double precision; sums use long double accumulators in
  * ascending pixel order.  HEALPix pixel centres follow the closed forms of
  * Gorski et al. 2005 (the paper stores maps in HEALPix, Sec. 5.1).
@@ -167,6 +173,22 @@ static int interp_beamsor(int n, double T, const double *grid, double u, double 
     return 1;
 }
 
+/* Ideal half-wave plate at angle phi: Lambda(phi) diag(1, 1, -1, -1) Lambda(-phi), formed as that product */
+static void lambda_mat(double x, double L[4][4]);
+static void hwp_mat(double phi, double H[4][4]) {
+    double Lp[4][4], Lm[4][4], P[4][4];
+    lambda_mat(phi, Lp);
+    lambda_mat(-phi, Lm);
+    const double M0[4] = {1.0, 1.0, -1.0, -1.0};
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) P[a][b] = M0[a] * Lm[a][b];
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            H[a][b] = 0.0;
+            for (int c = 0; c < 4; ++c) H[a][b] += Lp[a][c] * P[c][b];
+        }
+}
+
 /* Lambda(x) of Sec. 4.1 */
 static void lambda_mat(double x, double L[4][4]) {
     memset(L, 0, sizeof(double) * 16);
@@ -188,11 +210,14 @@ enum { ORC_OUT_TOD = 0, ORC_OUT_STOKES = 1 };
  * One sample.  out[0] = TOD (OUT_TOD) or out[0..2] = N sum_k B_TT(k) Lambda(-chi_k) S_k
  * restricted to (T, Q, U) (OUT_STOKES: the Stokes pickup of the scalar beam B_TT).
  */
-static void one_sample(int64_t N, const double *I, const double *Q, const double *U,
+static void one_sample(int64_t N, const double *I, const double *Q, const double *U, const double *V,
                        int n, double T, const double *grid,
                        double zeta, double eps, double s_resp,
                        double rho_min, double rho_max, int norm_mode, double norm_scale,
-                       double theta0, double phi0, double psi0, int out_mode, double *out) {
+                       double theta0, double phi0, double psi0, int has_hwp, double hwp_phi, int out_mode,
+                       double *out) {
+    double H[4][4];
+    if (has_hwp) hwp_mat(hwp_phi, H);
     const double z0 = cos(theta0), s0 = sin(theta0);
     const double cmax = cos(rho_max);
     const double cmin = cos(rho_min);
@@ -217,14 +242,22 @@ static void one_sample(int64_t N, const double *I, const double *Q, const double
             const double u = t * cos(sigma), v = t * sin(sigma);
             double M[4][4];
             if (!interp_beamsor(n, T, grid, u, v, M)) continue;
-            const double S[4] = {I[p], Q[p], U[p], 0.0};
+            const double S[4] = {I[p], Q[p], U[p], V ? V[p] : 0.0};
             double Lm[4][4], Lp[4][4];
             lambda_mat(-chi, Lm);
             lambda_mat(chi, Lp);
-            double rs[4]; /* Lambda(-chi) S */
+            double rs[4]; /* Lambda(-chi) S, then H(phi_t) Lambda(-chi) S with a plate */
             for (int a = 0; a < 4; ++a) {
                 rs[a] = 0.0;
                 for (int b = 0; b < 4; ++b) rs[a] += Lm[a][b] * S[b];
+            }
+            if (has_hwp) {
+                double hs[4];
+                for (int a = 0; a < 4; ++a) {
+                    hs[a] = 0.0;
+                    for (int b = 0; b < 4; ++b) hs[a] += H[a][b] * rs[b];
+                }
+                for (int a = 0; a < 4; ++a) rs[a] = hs[a];
             }
             norm_sum += M[0][0];
             if (out_mode == ORC_OUT_STOKES) {
@@ -265,12 +298,31 @@ static void one_sample(int64_t N, const double *I, const double *Q, const double
  *   nthreads     : OpenMP threads (0 = runtime default)
  * Returns 0, or -1 on invalid arguments.
  */
+int orc_tod_iquv(int64_t nside, const double *I, const double *Q, const double *U, const double *V,
+                 int n, double T, const double *grid,
+                 double zeta, double eps, double s_resp,
+                 double rho_min, double rho_max, int norm_mode, double norm_scale,
+                 int64_t nsamp, const double *theta, const double *phi, const double *psi, const double *hwp,
+                 int out_mode, double *out, int nthreads);
+
 int orc_tod(int64_t nside, const double *I, const double *Q, const double *U,
             int n, double T, const double *grid,
             double zeta, double eps, double s_resp,
             double rho_min, double rho_max, int norm_mode, double norm_scale,
             int64_t nsamp, const double *theta, const double *phi, const double *psi,
             int out_mode, double *out, int nthreads) {
+    return orc_tod_iquv(nside, I, Q, U, NULL, n, T, grid, zeta, eps, s_resp, rho_min, rho_max, norm_mode,
+                        norm_scale, nsamp, theta, phi, psi, NULL, out_mode, out, nthreads);
+}
+
+/* As orc_tod with an optional V map and an optional per-sample half-wave-plate
+ * angle stream (NULL: none). */
+int orc_tod_iquv(int64_t nside, const double *I, const double *Q, const double *U, const double *V,
+                 int n, double T, const double *grid,
+                 double zeta, double eps, double s_resp,
+                 double rho_min, double rho_max, int norm_mode, double norm_scale,
+                 int64_t nsamp, const double *theta, const double *phi, const double *psi, const double *hwp,
+                 int out_mode, double *out, int nthreads) {
     if (nside < 1 || n < 3 || !(T > 0.0) || !(rho_max > 0.0) || rho_max >= M_PI / 2 || rho_min < 0.0 ||
         rho_min >= rho_max || nsamp < 0)
         return -1;
@@ -284,8 +336,8 @@ int orc_tod(int64_t nside, const double *I, const double *Q, const double *U,
        small calls still spread over every thread */
     #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t t = 0; t < nsamp; ++t)
-        one_sample(nside, I, Q, U, n, T, grid, zeta, eps, s_resp, rho_min, rho_max, norm_mode, norm_scale,
-                   theta[t], phi[t], psi[t], out_mode, out + t * width);
+        one_sample(nside, I, Q, U, V, n, T, grid, zeta, eps, s_resp, rho_min, rho_max, norm_mode, norm_scale,
+                   theta[t], phi[t], psi[t], hwp != NULL, hwp ? hwp[t] : 0.0, out_mode, out + t * width);
     return 0;
 }
 
