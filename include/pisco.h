@@ -96,6 +96,11 @@ const char *pisco_last_error(const pisco_ctx *ctx);
 pisco_status pisco_set_sky(pisco_ctx *ctx, int64_t nside, const void *I, const void *Q, const void *U,
                            int dtype, int mem);
 
+/* As pisco_set_sky with the fourth Stokes map V (circular polarisation; the
+ * discrete sum of Sec. 4.2 runs over T, Q, U, V).  V may be NULL (zero). */
+pisco_status pisco_set_sky_iquv(pisco_ctx *ctx, int64_t nside, const void *I, const void *Q, const void *U,
+                                const void *V, int dtype, int mem);
+
 /*
  * Effective beam of detector `det` (0 <= det < PISCO_MAX_DETECTORS): an n x n
  * grid (n odd, 3..4095) of nodes at u, v in [-T, T] (T = half_span_tan > 0),
@@ -120,6 +125,34 @@ pisco_status pisco_set_beam(pisco_ctx *ctx, int32_t det, int32_t n, double half_
  */
 pisco_status pisco_set_beam_scalar(pisco_ctx *ctx, int32_t det, int32_t n, double half_span_tan, const void *b,
                                    double wI, double wQ, double wU, double wT, int dtype, int mem);
+
+/*
+ * Beams that couple the sky's V into the measurement (the beamsor's V column,
+ * Sec. 3 equation beamsor; the detector row of Sec. 4.1 has no V entry, so
+ * D(0) B contributes bV = (s/2)[(1+eps) B_TV + (1-eps) B_QV] per pixel):
+ * pisco_set_beam_v takes a fifth channel bV on the same node grid (NULL: none;
+ * stored as cell polynomials beside the four-channel records);
+ * pisco_set_beam_scalar_v a V weight, bV = wV b.  Per pair the term gains
+ * bV V (V is not rotated by Lambda).
+ */
+pisco_status pisco_set_beam_v(pisco_ctx *ctx, int32_t det, int32_t n, double half_span_tan, const void *bI,
+                              const void *bQ, const void *bU, const void *bV, const void *bT, int dtype, int mem);
+pisco_status pisco_set_beam_scalar_v(pisco_ctx *ctx, int32_t det, int32_t n, double half_span_tan, const void *b,
+                                     double wI, double wQ, double wU, double wV, double wT, int dtype, int mem);
+
+/*
+ * Rotating half-wave plate: a modulated beamsor (the paper's conclusions note
+ * that modulation needs nothing more than a modulated beamsor model).  Sample
+ * t of detector `det` uses B(u, v) H(phi_t) with H(phi) = Lambda(phi)
+ * diag(1, 1, -1, -1) Lambda(-phi) (Lambda of Sec. 4.1): an ideal plate, sky
+ * side of the beam, its axis at angle phi_t (rad) from the antenna frame's
+ * reference direction.  Per pair the Stokes rotation angle becomes
+ * 2 chi + 4 phi_t and the U-row and V terms change sign.  `angle` holds n
+ * values (n must equal the detector's sample count at convolve time); host
+ * arrays are copied, device arrays borrowed.  angle = NULL or n = 0 removes
+ * the plate.
+ */
+pisco_status pisco_set_hwp(pisco_ctx *ctx, int32_t det, int64_t n, const double *angle, int mem);
 
 /* Let detector `det` use the beam of detector `src` (no copy; e.g. one shared
  * far-sidelobe grid).  `src` must already have a beam. */
@@ -177,6 +210,8 @@ int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
  *                    pixel-linear quantities of every (pixel, sample) pair
  *                    (1 - n.p, the antenna-frame coordinates, the co-polar
  *                    projections) formed by FP32 matrix-core products.
+ *                    Launches with a half-wave plate or V terms run the
+ *                    PISCO_ALGO_TILE kernels instead.
  *   samples_per_tile consecutive samples a wavefront takes per queue pop (1..65536)
  *   waves_per_group  wavefronts per workgroup (1, 2, 4 or 8)
  *   groups_per_cu    workgroups launched per compute unit (1..16)

@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 
 from . import _lib as L
-from .beamsor import fold_detector, scalar_weights
+from .beamsor import fold_detector, fold_v, scalar_weights
 
 
 def _torch():
@@ -35,7 +35,8 @@ class Convolver:
         if st != L.OK:
             raise L.PiscoError(st, "pisco_create failed (device must be gfx950)")
         self._h = h
-        self._keep = {}      # borrowed device tensors, per detector
+        self._keep = {}      # borrowed device pointing tensors, per detector
+        self._keep_hwp = {}  # borrowed device plate-angle tensors, per detector
         self.dtype = None    # torch dtype of the sky
         self._sizes = {}
 
@@ -49,6 +50,7 @@ class Convolver:
             self._lib.pisco_destroy(self._h)
             self._h = None
             self._keep.clear()
+            self._keep_hwp.clear()
 
     def __del__(self):  # pragma: no cover
         try:
@@ -71,31 +73,47 @@ class Convolver:
         return L.F64 if dtype == torch.float64 else L.F32
 
     # -- C ABI ------------------------------------------------------------
-    def set_sky(self, nside: int, I, Q, U, dtype=None):
+    def set_sky(self, nside: int, I, Q, U, dtype=None, V=None):
+        """Stokes maps in RING order; V (circular polarisation) is optional."""
         torch = _torch()
         dtype = dtype or torch.float32
-        ts = [self._as_tensor(m, dtype) for m in (I, Q, U)]
+        ts = [self._as_tensor(m, dtype) for m in ((I, Q, U) if V is None else (I, Q, U, V))]
         mems = {self._mem(t) for t in ts}
         if len(mems) != 1:
-            raise ValueError("I, Q, U must all live on the host or all on the device")
-        self._check(self._lib.pisco_set_sky(self._h, int(nside), *(t.data_ptr() for t in ts), self._code(dtype),
-                                            mems.pop()))
+            raise ValueError("the maps must all live on the host or all on the device")
+        if V is None:
+            self._check(self._lib.pisco_set_sky(self._h, int(nside), *(t.data_ptr() for t in ts),
+                                                self._code(dtype), mems.pop()))
+        else:
+            self._check(self._lib.pisco_set_sky_iquv(self._h, int(nside), *(t.data_ptr() for t in ts),
+                                                     self._code(dtype), mems.pop()))
         self.dtype = dtype
         self.nside = int(nside)
 
-    def set_beam(self, det: int, n: int, half_span_tan: float, bI, bQ, bU, bT, dtype=None):
+    def set_beam(self, det: int, n: int, half_span_tan: float, bI, bQ, bU, bT, dtype=None, bV=None):
+        """Four-channel beam (bI, bQ, bU, bT); bV couples the sky's V (optional)."""
         dtype = dtype or self.dtype or _torch().float32
-        ts = [self._as_tensor(b, dtype).reshape(-1) for b in (bI, bQ, bU, bT)]
+        chans = (bI, bQ, bU, bT) if bV is None else (bI, bQ, bU, bV, bT)
+        ts = [self._as_tensor(b, dtype).reshape(-1) for b in chans]
         mems = {self._mem(t) for t in ts}
         if len(mems) != 1:
             raise ValueError("beam channels must all live on the host or all on the device")
-        self._check(self._lib.pisco_set_beam(self._h, int(det), int(n), float(half_span_tan),
-                                             *(t.data_ptr() for t in ts), self._code(dtype), mems.pop()))
+        if bV is None:
+            self._check(self._lib.pisco_set_beam(self._h, int(det), int(n), float(half_span_tan),
+                                                 *(t.data_ptr() for t in ts), self._code(dtype), mems.pop()))
+        else:
+            self._check(self._lib.pisco_set_beam_v(self._h, int(det), int(n), float(half_span_tan),
+                                                   *(t.data_ptr() for t in ts), self._code(dtype), mems.pop()))
 
     def set_beam_scalar(self, det: int, n: int, half_span_tan: float, b, wI: float, wQ: float, wU: float,
-                        wT: float = 1.0, dtype=None):
+                        wT: float = 1.0, dtype=None, wV: float = 0.0):
         dtype = dtype or self.dtype or _torch().float32
         t = self._as_tensor(b, dtype).reshape(-1)
+        if wV:
+            self._check(self._lib.pisco_set_beam_scalar_v(self._h, int(det), int(n), float(half_span_tan),
+                                                          t.data_ptr(), float(wI), float(wQ), float(wU), float(wV),
+                                                          float(wT), self._code(dtype), self._mem(t)))
+            return
         self._check(self._lib.pisco_set_beam_scalar(self._h, int(det), int(n), float(half_span_tan), t.data_ptr(),
                                                     float(wI), float(wQ), float(wU), float(wT), self._code(dtype),
                                                     self._mem(t)))
@@ -106,13 +124,30 @@ class Convolver:
         uses the one-grid form when every folded channel is a constant multiple
         of B_TT (to 1e-12 relative)."""
         bI, bQ, bU, bT = fold_detector(mueller, eps, s)
+        bV = fold_v(mueller, eps, s)
         if allow_scalar:
             w = scalar_weights(bI, bQ, bU, bT)
-            if w is not None:
-                self.set_beam_scalar(det, bT.shape[0], half_span_tan, bT, *w, 1.0, dtype=dtype)
+            wv = None if bV is None else scalar_weights(bV, bV, bV, bT)
+            if w is not None and (bV is None or wv is not None):
+                self.set_beam_scalar(det, bT.shape[0], half_span_tan, bT, *w, 1.0, dtype=dtype,
+                                     wV=0.0 if wv is None else wv[0])
                 return "scalar"
-        self.set_beam(det, bI.shape[0], half_span_tan, bI, bQ, bU, bT, dtype)
+        self.set_beam(det, bI.shape[0], half_span_tan, bI, bQ, bU, bT, dtype, bV=bV)
         return "full"
+
+    def set_hwp(self, det: int, angle=None):
+        """Per-sample half-wave-plate angle (rad) for detector `det`; None removes the plate."""
+        torch = _torch()
+        if angle is None:
+            self._check(self._lib.pisco_set_hwp(self._h, int(det), 0, None, L.HOST))
+            self._keep_hwp.pop(det, None)
+            return
+        t = self._as_tensor(angle, torch.float64).reshape(-1)
+        self._check(self._lib.pisco_set_hwp(self._h, int(det), t.numel(), t.data_ptr(), self._mem(t)))
+        if t.is_cuda:
+            self._keep_hwp[det] = t     # borrowed by the library
+        else:
+            self._keep_hwp.pop(det, None)
 
     def share_beam(self, det: int, src: int):
         self._check(self._lib.pisco_share_beam(self._h, int(det), int(src)))

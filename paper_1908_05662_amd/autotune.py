@@ -47,17 +47,24 @@ class _Prefix:
         self.conv, self.frac, self.saved = conv, frac, {}
 
     def __enter__(self):
+        self.saved_hwp = {}
         if self.frac < 1.0:
             for det, ts in list(self.conv._keep.items()):
                 n = ts[0].numel()
                 m = min(n, max(64, int(round(n * self.frac))))
                 self.saved[det] = ts
                 self.conv.set_pointing(det, *(t[:m] for t in ts))
+                hw = self.conv._keep_hwp.get(det)
+                if hw is not None:
+                    self.saved_hwp[det] = hw
+                    self.conv.set_hwp(det, hw[:m])
         return self
 
     def __exit__(self, *exc):
         for det, ts in self.saved.items():
             self.conv.set_pointing(det, *ts)
+        for det, hw in self.saved_hwp.items():
+            self.conv.set_hwp(det, hw)
         return False
 
 

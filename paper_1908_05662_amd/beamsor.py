@@ -10,6 +10,7 @@ D(0) = (s/2) [1 + eps, 1 - eps, 0, 0]:
     bQ = (s/2)[(1+eps) M[T,Q] + (1-eps) M[Q,Q]]
     bU = (s/2)[(1+eps) M[T,U] + (1-eps) M[Q,U]]
     bT = M[T,T]                        (the normalising scalar beam, Sec. 3)
+    bV = (s/2)[(1+eps) M[T,V] + (1-eps) M[Q,V]]   (the V column; zero for most beams)
 """
 from __future__ import annotations
 
@@ -26,6 +27,14 @@ def fold_detector(M: np.ndarray, eps: float, s: float):
     bQ = a * M[:, :, 0, 1] + b * M[:, :, 1, 1]
     bU = a * M[:, :, 0, 2] + b * M[:, :, 1, 2]
     return bI, bQ, bU, M[:, :, 0, 0].copy()
+
+
+def fold_v(M: np.ndarray, eps: float, s: float):
+    """The V-column channel bV of a (n, n, 4, 4) Mueller field, or None when it is zero."""
+    M = np.asarray(M, dtype=np.float64)
+    a, b = 0.5 * s * (1.0 + eps), 0.5 * s * (1.0 - eps)
+    bV = a * M[:, :, 0, 3] + b * M[:, :, 1, 3]
+    return None if not np.any(bV) else bV
 
 
 def fold_elements(elements: dict, n: int, eps: float, s: float):

@@ -269,7 +269,19 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
     const T inv_h = (T)D.inv_h;
     const T c0 = (T)(0.5 * (n - 1));
     const T tmax = (T)(n - 1);
-    const T wI = (T)D.w[0], wQ = (T)D.w[1], wU = (T)D.w[2];
+    const T wI = (T)D.w[0], wQ = (T)D.w[1], wU = (T)D.w[2], wV = (T)D.wv;
+    // half-wave plate: the Stokes angle 2 chi becomes 2 chi + 4 phi_t and the
+    // U-row and V terms change sign (no plate: identity)
+    T c4 = (T)1, s4 = (T)0, sg4 = (T)1;
+    if (D.hwp) {
+        double sh4, ch4;
+        sincos(4.0 * D.hwp[t], &sh4, &ch4);
+        c4 = (T)ch4;
+        s4 = (T)sh4;
+        sg4 = (T)-1;
+    }
+    using R4c = typename Rec4<T>::type;
+    const R4c *__restrict__ vcells = reinterpret_cast<const R4c *>(D.beam_v);
 
     const int32_t nring = 4 * N - 1;
     const double rho = D.rho_max;
@@ -395,17 +407,26 @@ __device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, 
             const T cpp = fma(-R.g, h, -R.a);       // theta_hat_k . p0
             const T cc = fma(eth, cth, fma(eph, R.z * S, -w * cpp));
             const T ss = fma(-eth, z0t * S, fma(eph, (T)1 - h, w * s0t * S));
-            const T c2 = fma(cc, cc, -ss * ss);
-            const T s2 = (T)2 * cc * ss;
+            const T c2p = fma(cc, cc, -ss * ss);
+            const T s2p = (T)2 * cc * ss;
+            const T c2 = fma(c4, c2p, -s4 * s2p);   // cos(2 chi + 4 phi)
+            const T s2 = fma(s4, c2p, c4 * s2p);    // sin(2 chi + 4 phi)
 
-            const T qr = fma(c2, pix.y, s2 * pix.z);    // Q rotated into the detector frame
-            const T ur = fma(-s2, pix.y, c2 * pix.z);   // U rotated into the detector frame
+            const T qr = fma(c2, pix.y, s2 * pix.z);          // Q rotated into the detector frame
+            const T ur = sg4 * fma(-s2, pix.y, c2 * pix.z);   // U rotated into the detector frame
+            const T vv = sg4 * pix.w;                         // V (not rotated)
             accn.add(bv.bT);
             if (MODE == MODE_TOD) {
-                if (BEAM == BEAM_FULL)
-                    acc0.add(fma(bv.bI, pix.x, fma(bv.bQ, qr, bv.bU * ur)));
-                else
-                    acc0.add(bv.bT * fma(wI, pix.x, fma(wQ, qr, wU * ur)));
+                if (BEAM == BEAM_FULL) {
+                    T term = fma(bv.bI, pix.x, fma(bv.bQ, qr, bv.bU * ur));
+                    if (vcells) {
+                        const R4c cv = vcells[iv * (n - 1) + iu];
+                        term = fma(fma(fv, fma(fu, cv.w, cv.z), fma(fu, cv.y, cv.x)), vv, term);
+                    }
+                    acc0.add(term);
+                } else {
+                    acc0.add(bv.bT * fma(wI, pix.x, fma(wQ, qr, fma(wU, ur, wV * vv))));
+                }
             } else {
                 acc0.add(bv.bT * pix.x);
                 acc1.add(bv.bT * qr);
@@ -500,6 +521,7 @@ struct LaneFrame {
     float a1, a2, a3;       // theta'_0
     float b1, b2, b3;       // phi'_0
     float g1, g2, g3;       // co-polar direction at the boresight
+    float c4, s4;           // cos, sin of 4 phi_t (half-wave plate; 1, 0 without one)
 };
 
 // The set-up helpers below are not inlined (their FP64 constants must not be
@@ -511,6 +533,7 @@ struct TileLds {
     LaneFrame lane[WAVE];
     int32_t seg_end[WAVE];
     PixRec rec[CH];
+    float vrec[CH];   // V of the staged pixels (full beams with a V column)
 };
 
 struct TileFrame {
@@ -574,6 +597,14 @@ __device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int6
     F.g1 = (float)(tg[0] * e1[0] + tg[1] * e1[1] + tg[2] * e1[2]);
     F.g2 = (float)(tg[0] * e2[0] + tg[1] * e2[1]);
     F.g3 = (float)(tg[0] * c[0] + tg[1] * c[1] + tg[2] * c[2]);
+    F.c4 = 1.0f;
+    F.s4 = 0.0f;
+    if (D.hwp) {
+        double sh4, ch4;
+        sincos(4.0 * D.hwp[t], &sh4, &ch4);
+        F.c4 = (float)ch4;
+        F.s4 = (float)sh4;
+    }
     *out = F;
     double dist = valid ? 2.0 * asin(fmin(1.0, 0.5 * sqrt(2.0 * om))) : 0.0;  // angle from the centre
 #pragma unroll
@@ -625,6 +656,8 @@ struct PairCtx {
     bool inner, clip;
     float inv_h, c0, tmax, cmax, row, pp3;
     int32_t row_bytes;
+    float sg4;            // -1 with a half-wave plate: U-row and V terms change sign
+    float rowc;           // cells per grid row (bV cell polynomials)
 };
 
 // Masked contributions of NP consecutive (pixel record, sample) pairs,
@@ -641,8 +674,9 @@ struct PairOut {
 constexpr int TILE_NP = 4;
 #define TILE_MINW 2
 
-template <int MODE, int BEAM, bool PS, int NP>
-__device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C, const BeamRsrc &beam) {
+template <int MODE, int BEAM, bool PS, int NP, bool HWP>
+__device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp, const PairCtx &C,
+                                              const BeamRsrc &beam, const BeamRsrc &vbeam) {
     const LaneFrame &F = C.F;
     PixRec R[NP];
     float omg[NP], xp[NP], yp[NP], rzh[NP], rq[NP], fu[NP], fv[NP];
@@ -681,6 +715,17 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C
             cl[k][3] = beam_ld(beam, off[k] + 16, C.row_bytes);
         }
     }
+    float vv[NP], vb[NP];
+    if (BEAM == BEAM_FULL && MODE == MODE_TOD && Vp) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            vv[k] = Vp[k];
+            const float ku = floorf(__builtin_amdgcn_fmed3f(fmaf(xp[k], rzh[k], C.c0), 0.0f, C.cmax));
+            const float kv = floorf(__builtin_amdgcn_fmed3f(fmaf(yp[k], rzh[k], C.c0), 0.0f, C.cmax));
+            const float4 c = beam_ld(vbeam, (uint32_t)fmaf(kv, C.rowc, ku) << 4, 0);
+            vb[k] = fmaf(fv[k], fmaf(fu[k], c.w, c.z), fmaf(fu[k], c.y, c.x));
+        }
+    }
     PairOut o{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
@@ -692,7 +737,14 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C
         const float ez = fmaf(-q, C.pp3 - R[k].W, F.g3);
         const float cc = fmaf(ex, R[k].t1, fmaf(ey, R[k].t2, ez * R[k].t3));
         const float ss = fmaf(ex, R[k].f1, fmaf(ey, R[k].f2, ez * R[k].f3));
-        const float c2 = fmaf(cc, cc, -ss * ss);
+        float c2 = fmaf(cc, cc, -ss * ss);   // cos 2chi, then cos(2chi + 4phi) with a plate
+        float sh = cc * ss;                  // sin 2chi / 2, then sin(2chi + 4phi) / 2
+        if (HWP) {
+            const float c2p = c2;
+            c2 = fmaf(-2.0f * F.s4, sh, F.c4 * c2p);
+            sh = fmaf(F.c4, sh, 0.5f * F.s4 * c2p);
+        }
+        const float sgn = HWP ? C.sg4 : 1.0f;
         float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
         if (BEAM == BEAM_SCALAR) {
             const float4 c = cl[k][0];
@@ -708,30 +760,33 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const PairCtx &C
         if (MODE == MODE_TOD) {
             float term;
             if (BEAM == BEAM_SCALAR) {
-                // R.c holds twice the U-like coefficient: sin 2chi / 2 = cc ss;
-                // the mask goes on the beam value (every factor is finite)
+                // R.c holds twice the U-like coefficient (sin / 2 = sh); the
+                // plate's signs are in the records; the mask goes on the beam
+                // value (every factor is finite)
                 const float bTm = in[k] ? bT : 0.0f;
-                term = bTm * fmaf(c2, R[k].b, fmaf(cc * ss, R[k].c, R[k].a));
+                term = bTm * fmaf(c2, R[k].b, fmaf(sh, R[k].c, R[k].a));
                 o.v0 += term;
                 continue;
             } else {
-                const float s2 = 2.0f * cc * ss;
-                const float bq = fmaf(bQ, R[k].b, bU * R[k].c);
-                const float bu = fmaf(bQ, R[k].c, -bU * R[k].b);
+                const float s2 = 2.0f * sh;
+                const float sbU = sgn * bU;
+                const float bq = fmaf(bQ, R[k].b, sbU * R[k].c);
+                const float bu = fmaf(bQ, R[k].c, -sbU * R[k].b);
                 term = fmaf(bI, R[k].a, fmaf(c2, bq, s2 * bu));
+                if (Vp) term = fmaf(sgn * vb[k], vv[k], term);
             }
             o.v0 += in[k] ? term : 0.0f;
         } else {
-            const float s2 = 2.0f * cc * ss;
+            const float s2 = 2.0f * sh;
             o.v0 += in[k] ? bT * R[k].a : 0.0f;
             o.v1 += in[k] ? bT * fmaf(c2, R[k].b, s2 * R[k].c) : 0.0f;
-            o.v2 += in[k] ? bT * fmaf(-s2, R[k].b, c2 * R[k].c) : 0.0f;
+            o.v2 += in[k] ? bT * (sgn * fmaf(-s2, R[k].b, c2 * R[k].c)) : 0.0f;
         }
     }
     return o;
 }
 
-template <int MODE, int BEAM, int CH, bool PS>
+template <int MODE, int BEAM, int CH, bool PS, bool HWP>
 __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
                               int lane) {
     const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
@@ -762,6 +817,12 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n - 1) * (n - 1) : n * n);
     const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
     const int32_t row_bytes = (int32_t)(16 * n);
+    // full beams with a V column: bV cell polynomials, and the V of each staged pixel
+    const bool has_v = (BEAM == BEAM_FULL) && (MODE == MODE_TOD) && D.beam_v != nullptr;
+    const BeamRsrc vbeam = make_beam_rsrc(has_v ? D.beam_v : D.beam, (uint32_t)((n - 1) * (n - 1)));
+    // half-wave plate: U-row and V terms change sign (records of one-grid beams carry it)
+    const float sg4 = D.hwp ? -1.0f : 1.0f;
+    const float wV = (float)D.wv;
 
     Acc<float> acc0, acc1, acc2, accn;
     int32_t npairs = 0;
@@ -813,15 +874,17 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                 R.f3 = -scf * S;
                 const float4 sv = sky[u.first + j];
                 if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
-                    R.a = wI * sv.x;
-                    R.b = fmaf(wQ, sv.y, wU * sv.z);
-                    R.c = 2.0f * fmaf(wQ, sv.z, -wU * sv.y);
+                    const float swU = sg4 * wU;
+                    R.a = fmaf(sg4 * wV, sv.w, wI * sv.x);
+                    R.b = fmaf(wQ, sv.y, swU * sv.z);
+                    R.c = 2.0f * fmaf(wQ, sv.z, -swU * sv.y);
                 } else {
                     R.a = sv.x;
                     R.b = sv.y;
                     R.c = sv.z;
                 }
                 L.rec[m] = R;
+                if (has_v) L.vrec[m] = sv.w;
             }
             wave_sync();
 
@@ -837,10 +900,12 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     // two records per step: their masked terms are added in FP32
                     // and the pair enters the compensated sums (halves the
                     // compensation work; each pre-sum rounds once)
-                    const PairCtx C{F, omax, omin, inner, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes};
+                    const PairCtx C{F, omax, omin, inner, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes, sg4,
+                                    (float)(n - 1)};
                     int32_t m = 0;
                     for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
-                        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP>(&L.rec[m], C, beam);
+                        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP>(
+                            &L.rec[m], has_v ? &L.vrec[m] : nullptr, C, beam, vbeam);
                         acc0.add(a.v0);
                         if (MODE == MODE_STOKES) {
                             acc1.add(a.v1);
@@ -849,7 +914,8 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         if (PS) accn.add(a.vn);
                     }
                     for (; m < m_end; ++m) {
-                        const PairOut a = tile_pairs<MODE, BEAM, PS, 1>(&L.rec[m], C, beam);
+                        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP>(&L.rec[m], has_v ? &L.vrec[m] : nullptr,
+                                                                             C, beam, vbeam);
                         acc0.add(a.v0);
                         if (MODE == MODE_STOKES) {
                             acc1.add(a.v1);
@@ -1252,7 +1318,7 @@ __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
     }
 }
 
-template <int MODE, int BEAM, int CH, bool PS>
+template <int MODE, int BEAM, int CH, bool PS, bool HWP>
 __global__ void __launch_bounds__(512, TILE_MINW) tile_kernel(ConvArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & (WAVE - 1);
@@ -1271,7 +1337,7 @@ __global__ void __launch_bounds__(512, TILE_MINW) tile_kernel(ConvArgs A) {
         }
         const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
         const DetDesc &D = A.dets[tl.det];
-        convolve_tile<MODE, BEAM, CH, PS>(A, D, tl.begin, tl.count, L, lane);
+        convolve_tile<MODE, BEAM, CH, PS, HWP>(A, D, tl.begin, tl.count, L, lane);
     }
 }
 
@@ -1377,16 +1443,22 @@ static hipError_t launch_pixel(const ConvArgs &a, int waves, int groups, hipStre
     return hipGetLastError();
 }
 
-template <int MODE, int BEAM, int CH, bool PS>
-static hipError_t launch_tile_t(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+template <int MODE, int BEAM, int CH, bool PS, bool HWP>
+static hipError_t launch_tile_h(const ConvArgs &a, int waves, int groups, hipStream_t s) {
     const size_t lds = sizeof(TileLds<CH>) * (size_t)waves;
     if (lds > 64 * 1024) {  // allow the larger LDS allocations of gfx950 (160 KiB per CU)
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_kernel<MODE, BEAM, CH, PS>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_kernel<MODE, BEAM, CH, PS, HWP>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((tile_kernel<MODE, BEAM, CH, PS>), dim3(groups), dim3(WAVE * waves), lds, s, a);
+    hipLaunchKernelGGL((tile_kernel<MODE, BEAM, CH, PS, HWP>), dim3(groups), dim3(WAVE * waves), lds, s, a);
     return hipGetLastError();
+}
+
+template <int MODE, int BEAM, int CH, bool PS>
+static hipError_t launch_tile_t(const ConvArgs &a, int waves, int groups, hipStream_t s) {
+    if (MODE != MODE_COUNT && a.hwp) return launch_tile_h<MODE, BEAM, CH, PS, true>(a, waves, groups, s);
+    return launch_tile_h<MODE, BEAM, CH, PS, false>(a, waves, groups, s);
 }
 
 template <int MODE, int BEAM, int CH, bool PS>

@@ -12,7 +12,7 @@ enum { ALGO_PIXEL = 0, ALGO_TILE = 1, ALGO_TILE_MX = 2 };
 
 // Per-detector description, read by the kernel from device memory.
 struct DetDesc {
-    const void *beam;      // n*n records (float4 or double4): bI, bQ, bU, bT
+    const void *beam;      // full: n*n node records (bI, bQ, bU, bT); scalar: (n-1)^2 cell polynomials
     const double *theta;   // pointing, SoA
     const double *phi;
     const double *psi;
@@ -28,6 +28,9 @@ struct DetDesc {
     double omega_max;      // 1 - cos(rho_max), computed as 2 sin^2(rho_max / 2)
     double omega_min;      // 1 - cos(rho_min)
     double w[4];           // scalar beam weights (wI, wQ, wU, wT); unused for full beams
+    const void *beam_v;    // full beams with a V column: (n-1)^2 cell polynomials of bV, else null
+    const double *hwp;     // per-sample half-wave-plate angle, or null (no plate)
+    double wv;             // scalar beam V weight
     int32_t n;             // grid nodes per side
     int32_t norm_mode;     // 0 fixed, 1 per sample
     int32_t has_inner;     // rho_min > 0
@@ -42,7 +45,7 @@ struct Tile {
 };
 
 struct ConvArgs {
-    const void *sky;         // 12 nside^2 records (float4 / double4): I, Q, U, 0
+    const void *sky;         // 12 nside^2 records (float4 / double4): I, Q, U, V
     const DetDesc *dets;
     const Tile *tiles;       // tiles[q * tiles_per_queue + i] for queue q
     int32_t *counters;       // one work counter per queue (zeroed before launch)
@@ -57,7 +60,7 @@ struct ConvArgs {
     int32_t chunk;           // pixel records staged per pass (64, 128, 256)
     double coherence;        // tile path: samples within this many disc radii of the tile centre
     int32_t per_sample;      // some detector of the launch uses per-sample normalisation
-    int32_t pad_;
+    int32_t hwp;             // some detector of the launch has a half-wave plate
 };
 
 // Launch helpers (conv_kernel.hip).  Return the launch error.

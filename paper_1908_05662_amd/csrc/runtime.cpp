@@ -29,6 +29,11 @@ struct DetState {
     int beam_dtype = -1;
     int beam_kind = pisco::BEAM_FULL;
     double w[4] = {1.0, 1.0, 1.0, 1.0};
+    void *beam_v = nullptr;  // full beams: bV cell polynomials (owned with the beam)
+    double wv = 0.0;         // scalar beams: V weight
+    const double *hwp = nullptr;      // plate angle per sample, or null
+    double *owned_hwp = nullptr;
+    int64_t hwp_n = 0;
     double zeta = 0.0, rho_min = 0.0, rho_max = 0.0, norm_scale = 1.0;
     int norm_mode = 0;
     int64_t nsamp = 0;
@@ -69,6 +74,8 @@ struct Plan {
     int64_t out_samples = 0;
     int32_t beam_kind = 0;
     int32_t per_sample = 0;  // some detector of the plan normalises per sample
+    int32_t hwp = 0;         // some detector of the plan has a half-wave plate
+    int32_t extended = 0;    // some detector has a plate or V terms (not on the matrix-core path)
     // captured launch
     hipGraphExec_t gexec = nullptr;
     uint64_t g_gen = 0;
@@ -141,13 +148,24 @@ void release_beam(pisco_ctx *c, int32_t det) {
         for (size_t k = 0; k < c->dets.size(); ++k)
             if ((int32_t)k != det && c->dets[k].beam == d.beam && !c->dets[k].beam_owned) {
                 c->dets[k].beam = nullptr;
+                c->dets[k].beam_v = nullptr;
                 c->dets[k].has_beam = false;
             }
         (void)hipFree(d.beam);
+        if (d.beam_v) (void)hipFree(d.beam_v);
     }
     d.beam = nullptr;
+    d.beam_v = nullptr;
+    d.wv = 0.0;
     d.beam_owned = false;
     d.has_beam = false;
+}
+
+void release_hwp(DetState &d) {
+    if (d.owned_hwp) (void)hipFree(d.owned_hwp);
+    d.owned_hwp = nullptr;
+    d.hwp = nullptr;
+    d.hwp_n = 0;
 }
 
 void release_pointing(DetState &d) {
@@ -258,6 +276,8 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
     std::vector<DetDesc> descs;
     int64_t out_off = 0;
     p.per_sample = 0;
+    p.hwp = 0;
+    p.extended = 0;
     const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
     for (int32_t k = lo; k <= hi; ++k) {
         const DetState &d = c->dets[k];
@@ -279,6 +299,11 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         x.omega_max = 2.0 * std::sin(0.5 * d.rho_max) * std::sin(0.5 * d.rho_max);
         x.omega_min = 2.0 * std::sin(0.5 * d.rho_min) * std::sin(0.5 * d.rho_min);
         for (int i = 0; i < 4; ++i) x.w[i] = d.w[i];
+        x.beam_v = d.beam_v;
+        x.wv = d.wv;
+        x.hwp = d.hwp;
+        if (d.hwp) p.hwp = 1;
+        if (d.beam_v || d.wv != 0.0 || d.hwp) p.extended = 1;
         // a disc inside the grid's square maps every member into the grid (|u|, |v| <= tan rho)
         x.needs_clip = (std::tan(d.rho_max) <= d.T * (1.0 + 1e-12)) ? 0 : 1;
         x.n = d.n;
@@ -387,10 +412,12 @@ ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode, bool ti
     a.tiles_per_queue = q.per;
     a.out_mode = out_mode;
     a.beam_kind = p.beam_kind;
-    a.algo = tile ? (c->algo == PISCO_ALGO_TILE_MX ? pisco::ALGO_TILE_MX : pisco::ALGO_TILE) : pisco::ALGO_PIXEL;
+    a.algo = tile ? ((c->algo == PISCO_ALGO_TILE_MX && !p.extended) ? pisco::ALGO_TILE_MX : pisco::ALGO_TILE)
+                  : pisco::ALGO_PIXEL;
     a.chunk = c->chunk;
     a.coherence = c->coherence;
     a.per_sample = p.per_sample;
+    a.hwp = p.hwp;
     return a;
 }
 
@@ -461,6 +488,7 @@ void pisco_destroy(pisco_ctx *c) {
     for (size_t k = 0; k < c->dets.size(); ++k) {
         release_beam(c, (int32_t)k);
         release_pointing(c->dets[k]);
+        release_hwp(c->dets[k]);
     }
     if (c->sky) (void)hipFree(c->sky);
     if (c->d_flag) (void)hipFree(c->d_flag);
@@ -471,6 +499,11 @@ const char *pisco_last_error(const pisco_ctx *c) { return c ? c->err.c_str() : "
 
 pisco_status pisco_set_sky(pisco_ctx *c, int64_t nside, const void *I, const void *Q, const void *U, int dtype,
                            int mem) {
+    return pisco_set_sky_iquv(c, nside, I, Q, U, nullptr, dtype, mem);
+}
+
+pisco_status pisco_set_sky_iquv(pisco_ctx *c, int64_t nside, const void *I, const void *Q, const void *U,
+                                const void *V, int dtype, int mem) {
     if (!c) return PISCO_EINVAL;
     c->err.clear();
     if (!is_pow2(nside) || nside > PISCO_MAX_NSIDE) return fail(c, PISCO_EINVAL, "nside %lld is not a power of two in [1, %d]", (long long)nside, PISCO_MAX_NSIDE);
@@ -479,7 +512,7 @@ pisco_status pisco_set_sky(pisco_ctx *c, int64_t nside, const void *I, const voi
     if (!I || !Q || !U) return fail(c, PISCO_EINVAL, "null map");
     HIP_TRY(c, hipSetDevice(c->device));
     void *rec = nullptr;
-    const pisco_status st = interleave(c, I, Q, U, nullptr, 12 * nside * nside, dtype, mem, &rec);
+    const pisco_status st = interleave(c, I, Q, U, V, 12 * nside * nside, dtype, mem, &rec);
     if (st != PISCO_OK) return st;
     HIP_TRY(c, hipDeviceSynchronize());
     if (c->sky) (void)hipFree(c->sky);
@@ -588,7 +621,84 @@ pisco_status pisco_share_beam(pisco_ctx *c, int32_t det, int32_t src) {
     d->beam_dtype = s.beam_dtype;
     d->beam_kind = s.beam_kind;
     for (int i = 0; i < 4; ++i) d->w[i] = s.w[i];
+    d->beam_v = s.beam_v;
+    d->wv = s.wv;
     d->has_beam = true;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_beam_v(pisco_ctx *c, int32_t det, int32_t n, double T, const void *bI, const void *bQ,
+                              const void *bU, const void *bV, const void *bT, int dtype, int mem) {
+    if (!c) return PISCO_EINVAL;
+    if (!bV) return pisco_set_beam(c, det, n, T, bI, bQ, bU, bT, dtype, mem);
+    pisco_status st = pisco_set_beam(c, det, n, T, bI, bQ, bU, bT, dtype, mem);
+    if (st != PISCO_OK) return st;
+    const size_t nodes = (size_t)n * n, cells = (size_t)(n - 1) * (n - 1);
+    void *src = nullptr;
+    if (mem == PISCO_DEVICE) src = const_cast<void *>(bV);
+    else if ((st = to_device(c, bV, el_bytes(dtype) * nodes, PISCO_HOST, &src)) != PISCO_OK) return st;
+    void *rec = nullptr;
+    if (hipMalloc(&rec, rec_bytes(dtype) * cells) != hipSuccess) {
+        if (mem == PISCO_HOST) (void)hipFree(src);
+        return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * cells);
+    }
+    hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (mem == PISCO_HOST) (void)hipFree(src);
+    if (e != hipSuccess) {
+        (void)hipFree(rec);
+        return fail(c, PISCO_EDEVICE, "beam repack failed: %s", hipGetErrorString(e));
+    }
+    c->dets[det].beam_v = rec;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_beam_scalar_v(pisco_ctx *c, int32_t det, int32_t n, double T, const void *b, double wI,
+                                     double wQ, double wU, double wV, double wT, int dtype, int mem) {
+    if (!c) return PISCO_EINVAL;
+    if (!std::isfinite(wV)) return fail(c, PISCO_EINVAL, "non-finite beam weight");
+    const pisco_status st = pisco_set_beam_scalar(c, det, n, T, b, wI, wQ, wU, wT, dtype, mem);
+    if (st != PISCO_OK) return st;
+    c->dets[det].wv = wV;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_hwp(pisco_ctx *c, int32_t det, int64_t n, const double *angle, int mem) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    DetState *d = det_slot(c, det);
+    if (!d) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    if (n < 0 || n > ((int64_t)1 << 40)) return fail(c, PISCO_EINVAL, "bad sample count");
+    if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipDeviceSynchronize());
+    if (!angle || n == 0) {
+        release_hwp(*d);
+        ++c->generation;
+        return PISCO_OK;
+    }
+    if (mem == PISCO_HOST) {
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(angle[i])) return fail(c, PISCO_EINVAL, "plate angle %lld is not finite", (long long)i);
+        double *buf = nullptr;
+        if (hipMalloc(&buf, sizeof(double) * (size_t)n) != hipSuccess)
+            return fail(c, PISCO_ENOMEM, "plate-angle allocation failed");
+        const hipError_t e = hipMemcpy(buf, angle, sizeof(double) * (size_t)n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(buf);
+            return fail(c, PISCO_EDEVICE, "plate-angle copy failed: %s", hipGetErrorString(e));
+        }
+        release_hwp(*d);
+        d->owned_hwp = buf;
+        d->hwp = buf;
+    } else {
+        release_hwp(*d);
+        d->hwp = angle;
+    }
+    d->hwp_n = n;
     ++c->generation;
     return PISCO_OK;
 }
@@ -699,6 +809,9 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
         any = true;
         if (d.beam_dtype != c->sky_dtype)
             return fail(c, PISCO_EINVAL, "detector %d beam dtype differs from the sky dtype", k);
+        if (d.hwp && d.hwp_n != d.nsamp)
+            return fail(c, PISCO_EINVAL, "detector %d has %lld plate angles for %lld samples", k, (long long)d.hwp_n,
+                        (long long)d.nsamp);
         if (first_kind < 0) first_kind = d.beam_kind;
         if (d.beam_kind != first_kind)
             return fail(c, PISCO_EINVAL, "detectors in one launch must all have full or all scalar beams");
@@ -787,9 +900,9 @@ pisco_status pisco_set_launch(pisco_ctx *c, const pisco_launch *l) {
     // LDS per wave: rings, frames and segment ends, the staged records and, on
     // the matrix-core path, the running sums of TOD launches (Stokes launches
     // split workgroups that would not fit)
-    const size_t tile_slice = 64 * 64 + 64 * 52 + 64 * 4 +
+    const size_t tile_slice = 64 * 64 + 64 * 60 + 64 * 4 +
                               (l->algorithm == PISCO_ALGO_TILE_MX ? (size_t)l->chunk * 64 + 4 * 4 * 64 * 4
-                                                                   : (size_t)l->chunk * 48);
+                                                                   : (size_t)l->chunk * 52);
     if (l->algorithm != PISCO_ALGO_PIXEL && tile_slice * (size_t)w > 160 * 1024)
         return fail(c, PISCO_EINVAL, "chunk %d with %d waves per group exceeds the LDS of a compute unit", l->chunk, w);
     c->algo = l->algorithm;
