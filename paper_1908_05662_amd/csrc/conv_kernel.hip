@@ -533,8 +533,12 @@ struct TileLds {
     LaneFrame lane[WAVE];
     int32_t seg_end[WAVE];
     PixRec rec[CH];
-    float vrec[CH];   // V of the staged pixels (full beams with a V column)
 };
+static_assert(sizeof(TileLds<256>) == 8192 + 256 * sizeof(PixRec) && sizeof(PixRec) == 48,
+              "the runtime's LDS budget assumes 8 KiB + 48 bytes per staged record and wave");
+// Launches with a V-column beam append one float per staged record and wave
+// after the TileLds array (V of the staged pixels); others do not allocate it,
+// so it costs them no occupancy.
 
 struct TileFrame {
     double thc, phc, zc, sc, Ru;
@@ -788,7 +792,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
 
 template <int MODE, int BEAM, int CH, bool PS, bool HWP>
 __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
-                              int lane) {
+                              float *vrec, int lane) {
     const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
     const int32_t N = (int32_t)A.nside;
     const bool valid = lane < cnt;
@@ -818,7 +822,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
     const int32_t row_bytes = (int32_t)(16 * n);
     // full beams with a V column: bV cell polynomials, and the V of each staged pixel
-    const bool has_v = (BEAM == BEAM_FULL) && (MODE == MODE_TOD) && D.beam_v != nullptr;
+    const bool has_v = (BEAM == BEAM_FULL) && (MODE == MODE_TOD) && D.beam_v != nullptr && vrec != nullptr;
     const BeamRsrc vbeam = make_beam_rsrc(has_v ? D.beam_v : D.beam, (uint32_t)((n - 1) * (n - 1)));
     // half-wave plate: U-row and V terms change sign (records of one-grid beams carry it)
     const float sg4 = D.hwp ? -1.0f : 1.0f;
@@ -884,7 +888,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     R.c = sv.z;
                 }
                 L.rec[m] = R;
-                if (has_v) L.vrec[m] = sv.w;
+                if (has_v) vrec[m] = sv.w;
             }
             wave_sync();
 
@@ -905,7 +909,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     int32_t m = 0;
                     for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
                         const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP>(
-                            &L.rec[m], has_v ? &L.vrec[m] : nullptr, C, beam, vbeam);
+                            &L.rec[m], has_v ? &vrec[m] : nullptr, C, beam, vbeam);
                         acc0.add(a.v0);
                         if (MODE == MODE_STOKES) {
                             acc1.add(a.v1);
@@ -914,7 +918,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         if (PS) accn.add(a.vn);
                     }
                     for (; m < m_end; ++m) {
-                        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP>(&L.rec[m], has_v ? &L.vrec[m] : nullptr,
+                        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP>(&L.rec[m], has_v ? &vrec[m] : nullptr,
                                                                              C, beam, vbeam);
                         acc0.add(a.v0);
                         if (MODE == MODE_STOKES) {
@@ -1324,6 +1328,9 @@ __global__ void __launch_bounds__(512, TILE_MINW) tile_kernel(ConvArgs A) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = threadIdx.x / WAVE;
     TileLds<CH> &L = reinterpret_cast<TileLds<CH> *>(lds_raw)[wid];
+    float *vrec = (BEAM == BEAM_FULL && MODE == MODE_TOD && A.vbeam)
+                      ? reinterpret_cast<float *>(lds_raw + sizeof(TileLds<CH>) * (blockDim.x / WAVE)) + wid * CH
+                      : nullptr;
     int32_t q = (A.n_queues > 1) ? (int32_t)(blockIdx.x % (uint32_t)A.n_queues) : 0;
     int32_t exhausted = 0;
     while (exhausted < A.n_queues) {
@@ -1337,7 +1344,7 @@ __global__ void __launch_bounds__(512, TILE_MINW) tile_kernel(ConvArgs A) {
         }
         const Tile tl = A.tiles[(int64_t)q * A.tiles_per_queue + ti];
         const DetDesc &D = A.dets[tl.det];
-        convolve_tile<MODE, BEAM, CH, PS, HWP>(A, D, tl.begin, tl.count, L, lane);
+        convolve_tile<MODE, BEAM, CH, PS, HWP>(A, D, tl.begin, tl.count, L, vrec, lane);
     }
 }
 
@@ -1445,7 +1452,9 @@ static hipError_t launch_pixel(const ConvArgs &a, int waves, int groups, hipStre
 
 template <int MODE, int BEAM, int CH, bool PS, bool HWP>
 static hipError_t launch_tile_h(const ConvArgs &a, int waves, int groups, hipStream_t s) {
-    const size_t lds = sizeof(TileLds<CH>) * (size_t)waves;
+    const bool v = BEAM == BEAM_FULL && MODE == MODE_TOD && a.vbeam;
+    const size_t lds = (sizeof(TileLds<CH>) + (v ? sizeof(float) * CH : 0)) * (size_t)waves;
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {  // allow the larger LDS allocations of gfx950 (160 KiB per CU)
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&tile_kernel<MODE, BEAM, CH, PS, HWP>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -61,6 +61,7 @@ struct ConvArgs {
     double coherence;        // tile path: samples within this many disc radii of the tile centre
     int32_t per_sample;      // some detector of the launch uses per-sample normalisation
     int32_t hwp;             // some detector of the launch has a half-wave plate
+    int32_t vbeam;           // some detector of the launch has a full beam with a V column
 };
 
 // Launch helpers (conv_kernel.hip).  Return the launch error.

@@ -74,6 +74,7 @@ struct Plan {
     int64_t out_samples = 0;
     int32_t beam_kind = 0;
     int32_t per_sample = 0;  // some detector of the plan normalises per sample
+    int32_t vbeam = 0;       // some detector of the plan has a full beam with a V column
     int32_t hwp = 0;         // some detector of the plan has a half-wave plate
     int32_t extended = 0;    // some detector has a plate or V terms (not on the matrix-core path)
     // captured launch
@@ -277,6 +278,7 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
     int64_t out_off = 0;
     p.per_sample = 0;
     p.hwp = 0;
+    p.vbeam = 0;
     p.extended = 0;
     const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
     for (int32_t k = lo; k <= hi; ++k) {
@@ -303,6 +305,7 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         x.wv = d.wv;
         x.hwp = d.hwp;
         if (d.hwp) p.hwp = 1;
+        if (d.beam_v) p.vbeam = 1;
         if (d.beam_v || d.wv != 0.0 || d.hwp) p.extended = 1;
         // a disc inside the grid's square maps every member into the grid (|u|, |v| <= tan rho)
         x.needs_clip = (std::tan(d.rho_max) <= d.T * (1.0 + 1e-12)) ? 0 : 1;
@@ -418,6 +421,7 @@ ConvArgs make_args(pisco_ctx *c, const Plan &p, void *out, int out_mode, bool ti
     a.coherence = c->coherence;
     a.per_sample = p.per_sample;
     a.hwp = p.hwp;
+    a.vbeam = p.vbeam;
     return a;
 }
 
@@ -812,6 +816,11 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
         if (d.hwp && d.hwp_n != d.nsamp)
             return fail(c, PISCO_EINVAL, "detector %d has %lld plate angles for %lld samples", k, (long long)d.hwp_n,
                         (long long)d.nsamp);
+        // a V column adds 4 bytes of LDS per staged record and wave on the tile path
+        if (d.beam_v && c->algo != PISCO_ALGO_PIXEL && out_mode == PISCO_OUT_TOD &&
+            (size_t)c->wpg * (8192 + 52 * (size_t)c->chunk) > 160 * 1024)
+            return fail(c, PISCO_EINVAL, "detector %d: a V-column beam needs more LDS than chunk %d with %d waves "
+                        "per group leaves; use a smaller chunk or fewer waves", k, c->chunk, c->wpg);
         if (first_kind < 0) first_kind = d.beam_kind;
         if (d.beam_kind != first_kind)
             return fail(c, PISCO_EINVAL, "detectors in one launch must all have full or all scalar beams");
@@ -902,7 +911,7 @@ pisco_status pisco_set_launch(pisco_ctx *c, const pisco_launch *l) {
     // split workgroups that would not fit)
     const size_t tile_slice = 64 * 64 + 64 * 60 + 64 * 4 +
                               (l->algorithm == PISCO_ALGO_TILE_MX ? (size_t)l->chunk * 64 + 4 * 4 * 64 * 4
-                                                                   : (size_t)l->chunk * 52);
+                                                                   : (size_t)l->chunk * 48);
     if (l->algorithm != PISCO_ALGO_PIXEL && tile_slice * (size_t)w > 160 * 1024)
         return fail(c, PISCO_EINVAL, "chunk %d with %d waves per group exceeds the LDS of a compute unit", l->chunk, w);
     c->algo = l->algorithm;
