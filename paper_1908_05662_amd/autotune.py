@@ -4,8 +4,10 @@ workgroup shape, occupancy, queue split, coherence threshold).
 It times real launches through the C ABI on the inputs already loaded in a
 convolver, on a prefix of every detector's pointing stream (scan order keeps
 the prefix representative), and searches the shape by coordinate descent:
-each field in turn is swept with the others held, the best kept, until a full
-pass gains under `min_gain`.  Results are cached per device and workload
+each field in turn is swept with the others held, a value kept only when it
+beats the current best by more than `accept` (timing noise on a loaded GPU is
+about 1%, so ties keep the starting shape), until a full pass gains under
+`min_gain`.  Results are cached per device and workload
 signature in a JSON file, so a later run with the same signature applies the
 tuned shape without searching.
 """
@@ -92,7 +94,8 @@ def _time_shape(conv, det, shape, out, stream, reps):
 
 
 def tune(conv, det: int = -1, subsample: float = 0.25, reps: int = 3, cache: str | None = None,
-         force: bool = False, extra_key: str = "", max_passes: int = 2, min_gain: float = 0.01, log=None) -> dict:
+         force: bool = False, extra_key: str = "", max_passes: int = 2, min_gain: float = 0.01,
+         accept: float = 0.01, log=None) -> dict:
     """Pick and apply the fastest launch shape for the loaded inputs.
 
     Returns {"launch", "ms", "default_ms", "speedup", "trials", "cached", "key", "seconds"}
@@ -150,7 +153,7 @@ def tune(conv, det: int = -1, subsample: float = 0.25, reps: int = 3, cache: str
                     cand = dict(best)
                     cand[field] = v
                     ms = run(cand)
-                    if ms is not None and ms < best_ms:
+                    if ms is not None and ms < best_ms * (1.0 - accept):
                         best, best_ms = cand, ms
             if best_ms > pass_start * (1.0 - min_gain):
                 break

@@ -97,8 +97,8 @@ struct pisco_ctx {
     uint64_t generation = 1;  // bumped whenever anything a launch reads changes
 
     // launch shape
-    int32_t spt = 64, wpg = 4, gpc = 2, xq = 8;
-    int32_t algo = PISCO_ALGO_TILE, chunk = 128;
+    int32_t spt = 64, wpg = 4, gpc = 2, xq = 1;
+    int32_t algo = PISCO_ALGO_TILE, chunk = 256;
     double coherence = 0.5;
 
     Plan plans[2];            // [0] batched (det = -1), [1] single detector
