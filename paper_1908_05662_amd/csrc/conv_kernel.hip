@@ -510,7 +510,7 @@ struct PixRec {
 // tile centre (the same difference formulas as the pixel path, with the
 // centre in place of the boresight).
 struct UnionRing {
-    float a, b, c, e, s, z, cdt, f, g, dphic, dphi, pad;
+    float a, b, c, e, s, z, cdt, f, g, dphic, dphi, dth;   // dth: colatitude minus the centre's
     int32_t first, n, jc, lo;   // pixels k = lo .. lo + cnt - 1 counted from the pixel nearest the centre
 };
 
@@ -644,13 +644,90 @@ __device__ __attribute__((noinline)) int32_t union_ring_setup(int32_t N, int32_t
     u.g = (float)(g.z * sc);
     u.dphic = (float)dphic;
     u.dphi = (float)g.dphi;
-    u.pad = 0.0f;
+    u.dth = (float)atan2(a, cdt);
     u.first = g.first;
     u.n = g.n;
     u.jc = jc;
     u.lo = lo;
     *out = u;
     return k;
+}
+
+// A lane's own disc, for narrowing the union cap ring by ring, in FP32:
+// colatitude offset from the tile centre (FP64 difference, so small offsets
+// keep their precision), 1 / sine of the colatitude, longitude offset from the
+// centre (in (-pi, pi]) and rho_max.  `ok` (uniform) is false when some lane's
+// boresight is within asin(1/4) of a pole or the disc is wider than 1.5 rad.
+struct LaneHull {
+    float dth, rsl, dphl, R;
+    bool ok;
+};
+
+__device__ __attribute__((noinline)) LaneHull lane_hull(const DetDesc &D, int64_t t, bool valid, double phc,
+                                                        double zc, double sc) {
+    double st, ct;
+    sincos(D.theta[t], &st, &ct);
+    double d = D.phi[t] - phc;
+    d -= TWO_PI * rint(d / TWO_PI);
+    LaneHull h;
+    h.dth = (float)atan2(st * zc - ct * sc, ct * zc + st * sc);
+    h.rsl = (float)(1.0 / fmax(st, 0.25));
+    h.dphl = (float)d;
+    h.R = (float)D.rho_max;
+    h.ok = (__ballot(valid && !(st >= 0.25)) == 0) && D.rho_max <= 1.5;
+    return h;
+}
+
+// Narrow each ring of a batch (ring i's union-cap interval in L.ring[i].lo and
+// lane i's `rc`) to the hull of the valid lanes' own disc intervals on it.  A
+// lane's half-width dm on a ring at colatitude offset dtheta from it follows
+// from hav(dm) = sin((rho_max - |dtheta|) / 2) sin((rho_max + |dtheta|) / 2) /
+// (sin theta_ring sin theta_lane) (the law of cosines with the difference of
+// cosines as a product), which keeps relative precision in FP32 down to the
+// tangent ring.  Rounding is covered by raising the first angle by 1.5e-7 rad,
+// hav by a relative 1e-6 and each end by 0.02 pixel, so the hull holds every
+// pixel of every lane's disc; pairs are still tested one by one.  Rings that
+// the cap covers whole or that lie near a pole keep the cap interval.
+__device__ void narrow_rings(UnionRing *ring, int32_t &rc, int32_t nb, const LaneHull &H, bool valid, int lane) {
+    for (int32_t i = 0; i < nb; ++i) {
+        const int32_t cnt = __builtin_amdgcn_readlane(rc, i);
+        const int32_t rn = __builtin_amdgcn_readfirstlane(ring[i].n);
+        const float sr = ring[i].s;
+        if (cnt == 0 || cnt >= rn || !(sr >= 0.25f)) continue;
+        const int32_t lo = __builtin_amdgcn_readfirstlane(ring[i].lo), hi = lo + cnt - 1;
+        const float dth = fabsf(ring[i].dth - H.dth);
+        const float ha = fmaf(0.5f, H.R - dth, 1.5e-7f);
+        int32_t klo = 0x7fffffff, khi = -0x7fffffff;
+        if (valid && ha > 0.0f) {
+            float sa, ca, sb, cb;
+            half_sincos(ha, sa, ca);
+            half_sincos(ha + dth, sb, cb);
+            const float hav = sa * sb * (H.rsl * __builtin_amdgcn_rcpf(sr)) * (1.0f + 1e-6f);
+            if (hav >= 1.0f) {
+                klo = lo;
+                khi = hi;
+            } else {
+                const float dm = 2.0f * asinf(sqrtf(hav));
+                const float inv = __builtin_amdgcn_rcpf(ring[i].dphi);
+                const float base = H.dphl - ring[i].dphic;
+                klo = max(lo, (int32_t)ceilf(fmaf(base - dm, inv, -0.02f)));
+                khi = min(hi, (int32_t)floorf(fmaf(base + dm, inv, 0.02f)));
+            }
+        }
+        klo = __ockl_wfred_min_i32(klo);
+        khi = __ockl_wfred_max_i32(khi);
+        // no lane meets the ring: empty (the sentinels must not enter the
+        // arithmetic); otherwise lo <= nlo and nlo + ncnt - 1 <= hi
+        int32_t nlo = lo, ncnt = 0;
+        if (klo <= khi) {
+            nlo = max(lo, klo);
+            ncnt = max(0, min(hi, khi) - nlo + 1);
+        }
+        if (lane == i) {
+            rc = ncnt;
+            ring[i].lo = nlo;
+        }
+    }
 }
 
 // Per-sample constants of the tile consume loop.
@@ -835,10 +912,16 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const int32_t r_lo = (thc - Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, thc - Ru)) - 1);
     const int32_t r_hi = (thc + Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, thc + Ru)) + 1);
 
+    const LaneHull H = lane_hull(D, t, valid, phc, zc, sc);
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
         const int32_t r = rb + lane;
         int32_t rc = 0;
         if (r <= r_hi) rc = union_ring_setup(N, r, phc, zc, sc, cosRu, &L.ring[lane]);
+        if (H.ok) {
+            wave_sync();
+            narrow_rings(L.ring, rc, min(WAVE, r_hi - rb + 1), H, valid, lane);
+            wave_sync();
+        }
         const int32_t incl = wave_inclusive_scan(rc, lane);
         L.seg_end[lane] = incl;
         const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
@@ -1044,10 +1127,16 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const int32_t r_lo = (thc - Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, thc - Ru)) - 1);
     const int32_t r_hi = (thc + Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, thc + Ru)) + 1);
 
+    const LaneHull H = lane_hull(D, t, valid, phc, zc, sc);
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
         const int32_t r = rb + lane;
         int32_t rc = 0;
         if (r <= r_hi) rc = union_ring_setup(N, r, phc, zc, sc, cosRu, &L.ring[lane]);
+        if (H.ok) {
+            wave_sync();
+            narrow_rings(L.ring, rc, min(WAVE, r_hi - rb + 1), H, valid, lane);
+            wave_sync();
+        }
         const int32_t incl = wave_inclusive_scan(rc, lane);
         L.seg_end[lane] = incl;
         const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
