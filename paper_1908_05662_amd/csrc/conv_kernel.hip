@@ -684,8 +684,9 @@ __device__ __attribute__((noinline)) LaneHull lane_hull(const DetDesc &D, int64_
 // from hav(dm) = sin((rho_max - |dtheta|) / 2) sin((rho_max + |dtheta|) / 2) /
 // (sin theta_ring sin theta_lane) (the law of cosines with the difference of
 // cosines as a product), which keeps relative precision in FP32 down to the
-// tangent ring.  Rounding is covered by raising the first angle by 1.5e-7 rad,
-// hav by a relative 1e-6 and each end by 0.02 pixel, so the hull holds every
+// tangent ring.  Rounding (and the hardware square root, within 1 ulp) is
+// covered by raising the first angle by 1.5e-7 rad, hav by a relative 1e-6 and
+// each end by 0.02 pixel, so the hull holds every
 // pixel of every lane's disc; pairs are still tested one by one.  Rings that
 // the cap covers whole or that lie near a pole keep the cap interval.
 __device__ void narrow_rings(UnionRing *ring, int32_t &rc, int32_t nb, const LaneHull &H, bool valid, int lane) {
@@ -707,7 +708,15 @@ __device__ void narrow_rings(UnionRing *ring, int32_t &rc, int32_t nb, const Lan
                 klo = lo;
                 khi = hi;
             } else {
-                const float dm = 2.0f * asinf(sqrtf(hav));
+                // asin by its odd series to y^11 below 0.3 (truncation 1e-8 and
+                // FP32 rounding 3e-7 relative: under 0.002 pixel), the library above
+                const float y = __builtin_amdgcn_sqrtf(hav), y2 = y * y;
+                float ps = fmaf(y2, 63.0f / 2816.0f, 35.0f / 1152.0f);
+                ps = fmaf(y2, ps, 5.0f / 112.0f);
+                ps = fmaf(y2, ps, 3.0f / 40.0f);
+                ps = fmaf(y2, ps, 1.0f / 6.0f);
+                const float as = (y < 0.3f) ? y * fmaf(y2, ps, 1.0f) : asinf(y);
+                const float dm = 2.0f * as;
                 const float inv = __builtin_amdgcn_rcpf(ring[i].dphi);
                 const float base = H.dphl - ring[i].dphic;
                 klo = max(lo, (int32_t)ceilf(fmaf(base - dm, inv, -0.02f)));
@@ -755,7 +764,7 @@ struct PairOut {
 constexpr int TILE_NP = 4;
 #define TILE_MINW 2
 
-template <int MODE, int BEAM, bool PS, int NP, bool HWP>
+template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP>
 __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp, const PairCtx &C,
                                               const BeamRsrc &beam, const BeamRsrc &vbeam) {
     const LaneFrame &F = C.F;
@@ -768,7 +777,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         R[k] = Rp[k];
         // n = X e1 + Y e2 + (1 - W) c in the tile frame
         omg[k] = fmaf(-R[k].Y, F.p2, fmaf(-R[k].X, F.p1, fmaf(R[k].W, F.p3, F.om)));  // 1 - n.p
-        in[k] = (omg[k] <= C.omax) && (!C.inner || omg[k] > C.omin);
+        in[k] = (omg[k] <= C.omax) & (omg[k] > C.omin);   // omin = -1 without an inner disc
         xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));  // n . theta'_0
         yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));  // n . phi'_0
         // one reciprocal for both divisions of the pair: 1 / (z' (1 + z')), z' = n.p
@@ -778,7 +787,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         rq[k] = rr * zp;             // 1 / (1 + z')
         const float tu = fmaf(xp[k], rzh[k], C.c0);
         const float tv = fmaf(yp[k], rzh[k], C.c0);
-        if (C.clip) in[k] = in[k] && (tu >= 0.0f && tu <= C.tmax && tv >= 0.0f && tv <= C.tmax);
+        if (CLIP) in[k] = in[k] & (tu >= 0.0f) & (tu <= C.tmax) & (tv >= 0.0f) & (tv <= C.tmax);
         // cell indices (clamped: pairs outside the disc are masked below)
         const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
         const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
@@ -867,6 +876,36 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
     return o;
 }
 
+// Every lane (sample) against the staged records [0, m_end): TILE_NP records
+// per step, then the remainder one by one.  CLIP (uniform per detector) adds
+// the disc-versus-grid test; it is a template switch so the common case runs
+// a loop without it.
+template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP>
+__device__ __forceinline__ void consume_records(const PixRec *rec, const float *vrec, int32_t m_end, const PairCtx &C,
+                                                const BeamRsrc &beam, const BeamRsrc &vbeam, Acc<float> &acc0,
+                                                Acc<float> &acc1, Acc<float> &acc2, Acc<float> &accn) {
+    int32_t m = 0;
+    for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
+        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam,
+                                                                         vbeam);
+        acc0.add(a.v0);
+        if (MODE == MODE_STOKES) {
+            acc1.add(a.v1);
+            acc2.add(a.v2);
+        }
+        if (PS) accn.add(a.vn);
+    }
+    for (; m < m_end; ++m) {
+        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP, CLIP>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
+        acc0.add(a.v0);
+        if (MODE == MODE_STOKES) {
+            acc1.add(a.v1);
+            acc2.add(a.v2);
+        }
+        if (PS) accn.add(a.vn);
+    }
+}
+
 template <int MODE, int BEAM, int CH, bool PS, bool HWP>
 __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
                               float *vrec, int lane) {
@@ -886,7 +925,8 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float inv_h = (float)D.inv_h;
     const float c0 = (float)(0.5 * (n - 1));
     const float tmax = (float)(n - 1);
-    const float omax = (float)D.omega_max, omin = (float)D.omega_min;
+    // omin = -1 without an inner disc, so `omg > omin` holds for every pixel (omg >= 0)
+    const float omax = (float)D.omega_max, omin = D.has_inner ? (float)D.omega_min : -1.0f;
     const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
@@ -989,27 +1029,13 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     // compensation work; each pre-sum rounds once)
                     const PairCtx C{F, omax, omin, inner, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes, sg4,
                                     (float)(n - 1)};
-                    int32_t m = 0;
-                    for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
-                        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP>(
-                            &L.rec[m], has_v ? &vrec[m] : nullptr, C, beam, vbeam);
-                        acc0.add(a.v0);
-                        if (MODE == MODE_STOKES) {
-                            acc1.add(a.v1);
-                            acc2.add(a.v2);
-                        }
-                        if (PS) accn.add(a.vn);
-                    }
-                    for (; m < m_end; ++m) {
-                        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP>(&L.rec[m], has_v ? &vrec[m] : nullptr,
-                                                                             C, beam, vbeam);
-                        acc0.add(a.v0);
-                        if (MODE == MODE_STOKES) {
-                            acc1.add(a.v1);
-                            acc2.add(a.v2);
-                        }
-                        if (PS) accn.add(a.vn);
-                    }
+                    const float *vr = has_v ? vrec : nullptr;
+                    if (clip)
+                        consume_records<MODE, BEAM, PS, HWP, true>(L.rec, vr, m_end, C, beam, vbeam, acc0, acc1, acc2,
+                                                                    accn);
+                    else
+                        consume_records<MODE, BEAM, PS, HWP, false>(L.rec, vr, m_end, C, beam, vbeam, acc0, acc1,
+                                                                     acc2, accn);
                 }
             }
             wave_sync();
@@ -1112,7 +1138,8 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const float inv_h = (float)D.inv_h;
     const float c0 = (float)(0.5 * (n - 1));
     const float tmax = (float)(n - 1);
-    const float omax = (float)D.omega_max, omin = (float)D.omega_min;
+    // omin = -1 without an inner disc, so `omg > omin` holds for every pixel (omg >= 0)
+    const float omax = (float)D.omega_max, omin = D.has_inner ? (float)D.omega_min : -1.0f;
     const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
