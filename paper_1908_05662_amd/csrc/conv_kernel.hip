@@ -743,7 +743,7 @@ __device__ void narrow_rings(UnionRing *ring, int32_t &rc, int32_t nb, const Lan
 struct PairCtx {
     LaneFrame F;
     float omax, omin;
-    bool inner, clip;
+    bool clip;
     float inv_h, c0, tmax, cmax, row, pp3;
     int32_t row_bytes;
     float sg4;            // -1 with a half-wave plate: U-row and V terms change sign
@@ -778,12 +778,13 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         // n = X e1 + Y e2 + (1 - W) c in the tile frame
         omg[k] = fmaf(-R[k].Y, F.p2, fmaf(-R[k].X, F.p1, fmaf(R[k].W, F.p3, F.om)));  // 1 - n.p
         in[k] = (omg[k] <= C.omax) & (omg[k] > C.omin);   // omin = -1 without an inner disc
-        xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));  // n . theta'_0
-        yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));  // n . phi'_0
+        // n . theta'_0 and n . phi'_0 in grid units (the lane's rows carry 1 / h)
+        xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));
+        yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));
         // one reciprocal for both divisions of the pair: 1 / (z' (1 + z')), z' = n.p
         const float zp = 1.0f - omg[k], zq = 2.0f - omg[k];
         const float rr = rcp(zp * zq);
-        rzh[k] = rr * zq * C.inv_h;  // gnomonic scale 1 / z' in grid units
+        rzh[k] = rr * zq;            // gnomonic scale 1 / z'
         rq[k] = rr * zp;             // 1 / (1 + z')
         const float tu = fmaf(xp[k], rzh[k], C.c0);
         const float tv = fmaf(yp[k], rzh[k], C.c0);
@@ -791,8 +792,8 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         // cell indices (clamped: pairs outside the disc are masked below)
         const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
         const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
-        fu[k] = fmaf(xp[k], rzh[k], C.c0 - ku);
-        fv[k] = fmaf(yp[k], rzh[k], C.c0 - kv);
+        fu[k] = tu - ku;   // exact; carries the rounding of tu (half an ulp)
+        fv[k] = tv - kv;
         off[k] = (uint32_t)fmaf(kv, C.row, ku) << 4;  // exact: row^2 < 2^24
     }
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
@@ -885,6 +886,19 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
                                                 const BeamRsrc &beam, const BeamRsrc &vbeam, Acc<float> &acc0,
                                                 Acc<float> &acc1, Acc<float> &acc2, Acc<float> &accn) {
     int32_t m = 0;
+    // two groups per compensated add: eight masked terms summed in FP32
+    for (; m + 2 * TILE_NP - 1 < m_end; m += 2 * TILE_NP) {
+        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam,
+                                                                         vbeam);
+        const PairOut b = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP>(
+            &rec[m + TILE_NP], vrec ? &vrec[m + TILE_NP] : nullptr, C, beam, vbeam);
+        acc0.add(a.v0 + b.v0);
+        if (MODE == MODE_STOKES) {
+            acc1.add(a.v1 + b.v1);
+            acc2.add(a.v2 + b.v2);
+        }
+        if (PS) accn.add(a.vn + b.vn);
+    }
     for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
         const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam,
                                                                          vbeam);
@@ -925,9 +939,16 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float inv_h = (float)D.inv_h;
     const float c0 = (float)(0.5 * (n - 1));
     const float tmax = (float)(n - 1);
+    // the lane's theta'_0 and phi'_0 rows scaled to grid units for the pair loop
+    LaneFrame Fg = F;
+    Fg.a1 *= inv_h;
+    Fg.a2 *= inv_h;
+    Fg.a3 *= inv_h;
+    Fg.b1 *= inv_h;
+    Fg.b2 *= inv_h;
+    Fg.b3 *= inv_h;
     // omin = -1 without an inner disc, so `omg > omin` holds for every pixel (omg >= 0)
     const float omax = (float)D.omega_max, omin = D.has_inner ? (float)D.omega_min : -1.0f;
-    const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);          // largest cell index
@@ -1021,13 +1042,13 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     for (int32_t m = 0; m < m_end; ++m) {
                         const PixRec R = L.rec[m];
                         const float omg = fmaf(-R.Y, F.p2, fmaf(-R.X, F.p1, fmaf(R.W, F.p3, F.om)));
-                        npairs += ((omg <= omax) && (!inner || omg > omin)) ? 1 : 0;
+                        npairs += ((omg <= omax) & (omg > omin)) ? 1 : 0;
                     }
                 } else {
                     // two records per step: their masked terms are added in FP32
                     // and the pair enters the compensated sums (halves the
                     // compensation work; each pre-sum rounds once)
-                    const PairCtx C{F, omax, omin, inner, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes, sg4,
+                    const PairCtx C{Fg, omax, omin, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes, sg4,
                                     (float)(n - 1)};
                     const float *vr = has_v ? vrec : nullptr;
                     if (clip)
@@ -1140,7 +1161,6 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const float tmax = (float)(n - 1);
     // omin = -1 without an inner disc, so `omg > omin` holds for every pixel (omg >= 0)
     const float omax = (float)D.omega_max, omin = D.has_inner ? (float)D.omega_min : -1.0f;
-    const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);
@@ -1245,7 +1265,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
                     for (int32_t g = 0; g < m_pad; g += 16) {
                         const mx4 vo = mx(L.b1[k4][g + c16], Bo);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) cntf += ((vo[q] <= omax) && (!inner || vo[q] > omin)) ? 1.0f : 0.0f;
+                        for (int q = 0; q < 4; ++q) cntf += ((vo[q] <= omax) & (vo[q] > omin)) ? 1.0f : 0.0f;
                     }
                     L.acc[jb][0][lane] = cntf;
                     continue;
@@ -1276,12 +1296,12 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
                     for (int q = 0; q < 4; ++q) {
                         const float4 sk = L.sky[g + 4 * k4 + q];
                         const float omg = vo[q];  // 1 - n.p
-                        bool in = (omg <= omax) && (!inner || omg > omin);
+                        bool in = (omg <= omax) & (omg > omin);
                         const float rz = rcp(1.0f - omg);
                         const float su = vx[q] * rz, sv = vy[q] * rz;  // gnomonic u, v
                         const float tu = fmaf(su, inv_h, c0);
                         const float tv = fmaf(sv, inv_h, c0);
-                        if (clip) in = in && (tu >= 0.0f && tu <= tmax && tv >= 0.0f && tv <= tmax);
+                        if (clip) in = in & (tu >= 0.0f) & (tu <= tmax) & (tv >= 0.0f) & (tv <= tmax);
                         const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, cmax));
                         const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, cmax));
                         const float fu = fmaf(su, inv_h, c0 - ku), fv = fmaf(sv, inv_h, c0 - kv);
