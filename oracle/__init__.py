@@ -60,6 +60,7 @@ def _lib():
         h.orc_disc.restype = i64
         h.orc_disc_counts.argtypes = [i64, i64, dp, dp, dbl, lp, i32]
         h.orc_max_threads.restype = i32
+        h.orc_ang2pix.argtypes = [i64, i64, dp, dp, lp]
         _h = h
     return _h
 
@@ -86,6 +87,16 @@ def pix2ang(nside: int, pix):
         _lib().orc_pix2ang(nside, int(p), ctypes.byref(a), ctypes.byref(b))
         th.flat[k], ph.flat[k] = a.value, b.value
     return th, ph
+
+
+def ang2pix(nside: int, theta, phi) -> np.ndarray:
+    """RING pixels containing the directions (theta, phi) (Gorski et al. 2005, Sec. 4)."""
+    th, ph = _f64(theta).ravel(), _f64(phi).ravel()
+    if th.shape != ph.shape:
+        raise ValueError("theta and phi differ in length")
+    out = np.empty(th.size, dtype=np.int64)
+    _lib().orc_ang2pix(nside, th.size, _dp(th), _dp(ph), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out
 
 
 def pix2zphi(nside: int, pix):

@@ -89,6 +89,43 @@ void orc_pix2ang(int64_t N, int64_t pix, double *theta, double *phi) {
     *theta = atan2(s, z);
 }
 
+/*
+ * RING pixel containing the direction (theta, phi), Gorski et al. 2005, Sec. 4:
+ * with t = 2 phi / pi in [0, 4), the equatorial belt (|z| <= 2/3) is tiled by
+ * the two families of lines N (1/2 + t) -/+ (3/4) N z = integer, whose indices
+ * give the ring (counted from z = 2/3) and the position along it; in the polar
+ * caps the lines are tp sqrt(3 (1 - |z|)) N and (1 - tp) sqrt(3 (1 - |z|)) N =
+ * integer, tp being the position within the quadrant, and their sum gives the
+ * ring counted from the pole.
+ */
+static int64_t ang2pix_one(int64_t N, double theta, double phi) {
+    const double z = cos(theta), za = fabs(z);
+    double t = fmod(phi * (2.0 / M_PI), 4.0);
+    if (t < 0.0) t += 4.0;
+    const double NN = (double)N;
+    if (za <= 2.0 / 3.0) {
+        const double a = NN * (0.5 + t), b = 0.75 * NN * z;
+        const int64_t jp = (int64_t)floor(a - b), jm = (int64_t)floor(a + b);
+        const int64_t ir = N + 1 + jp - jm;            /* 1 .. 2N+1 from z = 2/3 */
+        const int64_t odd_shift = 1 - (ir & 1);
+        int64_t ip = (jp + jm - N + odd_shift + 1) / 2;
+        if (ip >= 4 * N) ip -= 4 * N;
+        return 2 * N * (N - 1) + (ir - 1) * 4 * N + ip;
+    }
+    const double tp = t - floor(t);
+    const double w = NN * sqrt(3.0 * (1.0 - za));
+    const int64_t jp = (int64_t)floor(tp * w), jm = (int64_t)floor((1.0 - tp) * w);
+    int64_t ir = jp + jm + 1;                          /* 1 .. N from the pole */
+    if (ir > N) ir = N;
+    int64_t ip = (int64_t)floor(t * (double)ir);
+    if (ip >= 4 * ir) ip -= 4 * ir;
+    return z > 0.0 ? 2 * ir * (ir - 1) + ip : 12 * N * N - 2 * ir * (ir + 1) + ip;
+}
+
+void orc_ang2pix(int64_t N, int64_t m, const double *theta, const double *phi, int64_t *pix) {
+    for (int64_t k = 0; k < m; ++k) pix[k] = ang2pix_one(N, theta[k], phi[k]);
+}
+
 /* Ring i (1..4N-1, north to south): colatitude, pixel count, first pixel. */
 void orc_ring(int64_t N, int64_t i, double *theta, int64_t *count, int64_t *first) {
     const int64_t npix = 12 * N * N;
