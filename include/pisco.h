@@ -219,7 +219,7 @@ int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
  *                    die, each holding a contiguous block of tiles
  *   chunk            tile paths: union pixels staged in LDS per pass (64, 128, 256)
  *   coherence        tile paths: see algorithm, in (0, 4]
- * A new context starts at {PISCO_ALGO_TILE, 64, 4, 2, 1, 256, 0.5}.
+ * A new context starts at {PISCO_ALGO_TILE, 64, 4, 4, 1, 64, 0.5}.
  * Results are bitwise reproducible for a given launch shape.  They do not
  * depend on the shape except through the algorithm (the two paths round
  * differently) and, on the tile path, through samples_per_tile when it is not
@@ -296,6 +296,44 @@ pisco_status pisco_sidelobe_features(pisco_ctx *ctx, int32_t det, float *x, void
  * bit for bit.  Asynchronous on `stream`. */
 pisco_status pisco_sidelobe_apply(pisco_ctx *ctx, pisco_mlp *mlp, int32_t det, const float *mean, const float *stdv,
                                   const double *coef, float *tod, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Binned maps from TOD: the map-making step the TOD are handed to (Sec. 5.1)
+ * and from which the validation maps are made (Sec. 6).
+ *
+ * Measurement model of a sample t of a detector with focal-plane angle zeta,
+ * response s and cross-polar leakage eps, its boresight in RING pixel p of a
+ * map of nside_map (the detector row D of Sec. 4.1 at one pixel):
+ *   d_t = w_t . (I, Q, U)_p,
+ *   w_t = (s/2) ((1 + eps), (1 - eps) cos a_t, (1 - eps) sin a_t),
+ *   a_t = 2 (psi_t + zeta) + 4 phi_t   (phi_t: half-wave-plate angle, 0 without one).
+ *
+ * pisco_map_accumulate adds n samples into `accum`, a caller-owned device
+ * float64 array [12 nside_map^2][10]: per pixel the six distinct entries of
+ * sum w w^T (00, 01, 02, 11, 12, 22), the three of sum w d, and the hit
+ * count.  The caller zeroes it before the first call and may add any number of
+ * detectors.  theta, phi, psi (radians) and hwp (may be null) are device
+ * float64 arrays of n values, tod a device array of n PISCO_F32 or PISCO_F64
+ * values (tod_dtype); all are read on `stream` (hipStream_t, NULL = default)
+ * and must stay valid until the work there is done.  Samples with a non-finite
+ * angle or value are skipped.  The adds are FP64 atomics: each sum is exact up
+ * to the order of its additions, which is not fixed.
+ *
+ * pisco_map_solve: per pixel, rcond = smallest / largest eigenvalue of the
+ * 3 x 3 sum.  rcond >= rcond_min: (I, Q, U) solve the 3 x 3 system;
+ * 0 <= rcond < rcond_min with hits: intensity only, I = sum w_0 d / sum w_0^2,
+ * Q = U = 0; no hits: 0 (rcond 0).  maps: device float64 [3][12 nside_map^2]
+ * (I, Q, U rows); rcond: device float64 [12 nside_map^2], or null.
+ *
+ * Both return PISCO_EINVAL for nside_map not a power of two in [1, 8192], n < 0,
+ * a null array that is needed, a bad dtype, non-finite zeta, eps or s, or
+ * rcond_min outside [0, 1]; launches are asynchronous on `stream`.
+ * ------------------------------------------------------------------------ */
+pisco_status pisco_map_accumulate(pisco_ctx *ctx, int64_t nside_map, int64_t n, const double *theta, const double *phi,
+                                  const double *psi, const double *hwp, const void *tod, int tod_dtype, double zeta,
+                                  double eps, double s, double *accum, void *stream);
+pisco_status pisco_map_solve(pisco_ctx *ctx, int64_t nside_map, const double *accum, double rcond_min, double *maps,
+                             double *rcond, void *stream);
 
 #ifdef __cplusplus
 }

@@ -67,6 +67,9 @@ SIGNATURES = [
     ("pisco_sidelobe_features", ctypes.c_int, [_vp, _i32, _vp, _vp]),
     ("pisco_sidelobe_apply", ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_dbl), _vp, _vp]),
+    ("pisco_map_accumulate", ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _dbl, _dbl, _dbl,
+                                            _vp, _vp]),
+    ("pisco_map_solve", ctypes.c_int, [_vp, _i64, _vp, _dbl, _vp, _vp, _vp]),
 ]
 
 _lib = None

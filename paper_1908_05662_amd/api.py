@@ -309,3 +309,57 @@ class Mlp:
         cv._check(self._lib.pisco_sidelobe_apply(cv._h, self._h, int(det), m, s, c, tod.data_ptr(),
                                                  self._stream(stream)))
         return tod
+
+
+class MapMaker:
+    """Binned (I, Q, U) maps of nside `nside` from TOD on the convolver's device
+    (``pisco_map_accumulate`` / ``pisco_map_solve``); the per-pixel sums live in
+    one device float64 tensor of 10 values per pixel."""
+
+    def __init__(self, conv: Convolver, nside: int):
+        torch = _torch()
+        self.conv, self.nside = conv, int(nside)
+        self.npix = 12 * self.nside * self.nside
+        self._lib = conv._lib
+        self.accum = torch.zeros(self.npix * 10, dtype=torch.float64, device=conv.torch_device)
+
+    def _stream(self, stream):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.conv.torch_device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def clear(self):
+        self.accum.zero_()
+
+    def add(self, theta, phi, psi, tod, zeta: float = 0.0, eps: float = 0.0, s: float = 1.0, hwp=None, stream=None):
+        """Add one detector's samples (device tensors, or arrays copied to the device)."""
+        torch = _torch()
+        dev = self.conv.torch_device
+        th, ph, ps = (self.conv._as_tensor(x, torch.float64).to(dev) for x in (theta, phi, psi))
+        d = tod if (torch.is_tensor(tod) and tod.dtype in (torch.float32, torch.float64)) else \
+            self.conv._as_tensor(tod, torch.float64)
+        d = d.to(dev).contiguous()
+        hw = None if hwp is None else self.conv._as_tensor(hwp, torch.float64).to(dev)
+        n = th.numel()
+        if ph.numel() != n or ps.numel() != n or d.numel() != n or (hw is not None and hw.numel() != n):
+            raise ValueError("theta, phi, psi, tod (and hwp) must have one value per sample")
+        code = L.F64 if d.dtype == torch.float64 else L.F32
+        self.conv._check(self._lib.pisco_map_accumulate(
+            self.conv._h, self.nside, n, th.data_ptr(), ph.data_ptr(), ps.data_ptr(),
+            None if hw is None else hw.data_ptr(), d.data_ptr(), code, float(zeta), float(eps), float(s),
+            self.accum.data_ptr(), self._stream(stream)))
+        if stream is not None:   # the inputs must outlive the queued work
+            stream.synchronize()
+        return self
+
+    def solve(self, rcond_min: float = 1e-6, stream=None):
+        """(maps [3, npix] as I, Q, U rows; rcond [npix]) float64 device tensors."""
+        torch = _torch()
+        maps = torch.empty((3, self.npix), dtype=torch.float64, device=self.conv.torch_device)
+        rc = torch.empty(self.npix, dtype=torch.float64, device=self.conv.torch_device)
+        self.conv._check(self._lib.pisco_map_solve(self.conv._h, self.nside, self.accum.data_ptr(), float(rcond_min),
+                                                   maps.data_ptr(), rc.data_ptr(), self._stream(stream)))
+        return maps, rc
+
+    def hits(self):
+        return self.accum.view(self.npix, 10)[:, 9]

@@ -24,7 +24,7 @@ SPACE = [
     ("algorithm", (L.ALGO_TILE, L.ALGO_TILE_MX, L.ALGO_PIXEL)),
     ("chunk", (64, 128, 256)),
     ("waves_per_group", (2, 4, 8)),
-    ("groups_per_cu", (1, 2, 4)),
+    ("groups_per_cu", (1, 2, 3, 4)),
     ("xcd_queues", (8, 1)),
     ("coherence", (0.25, 0.5, 1.0)),
     ("samples_per_tile", (32, 64, 128)),

@@ -527,15 +527,21 @@ struct LaneFrame {
 // The set-up helpers below are not inlined (their FP64 constants must not be
 // hoisted into the pixel loops); they write their per-lane results straight
 // into this LDS slice instead of returning them through the stack.
+// The lane frames are read into registers before the first record is staged,
+// so they share storage with the records.
 template <int CH>
 struct TileLds {
     UnionRing ring[WAVE];
-    LaneFrame lane[WAVE];
     int32_t seg_end[WAVE];
-    PixRec rec[CH];
+    union {
+        LaneFrame lane[WAVE];
+        PixRec rec[CH];
+    };
 };
-static_assert(sizeof(TileLds<256>) == 8192 + 256 * sizeof(PixRec) && sizeof(PixRec) == 48,
-              "the runtime's LDS budget assumes 8 KiB + 48 bytes per staged record and wave");
+static_assert(sizeof(UnionRing) == 64 && sizeof(LaneFrame) == 60 && sizeof(PixRec) == 48 &&
+                  sizeof(TileLds<64>) == 4352 + 3840 && sizeof(TileLds<128>) == 4352 + 128 * 48 &&
+                  sizeof(TileLds<256>) == 4352 + 256 * 48,
+              "the runtime's LDS budget assumes 4352 bytes + max(3840, 48 per staged record) per wave");
 // Launches with a V-column beam append one float per staged record and wave
 // after the TileLds array (V of the staged pixels); others do not allocate it,
 // so it costs them no occupancy.
@@ -758,11 +764,16 @@ struct PairCtx {
 struct PairOut {
     float v0, v1, v2, vn;
 };
-// Records per consume step (their beam loads are in flight together) and the
-// minimum waves per SIMD the tile kernel is compiled for (2: up to 256 VGPRs;
-// the persistent launch keeps two waves per SIMD).
+// Records per consume step (their beam loads are in flight together), and the
+// minimum waves per SIMD each tile kernel is compiled for: four (at most 128
+// VGPRs) for one-grid TOD and pair counts, whose pair loop fits without spills
+// and gains from the latency hiding; two (up to 256 VGPRs) for four-channel
+// TOD and Stokes pickups, which would spill inside the loop at four.
 constexpr int TILE_NP = 4;
-#define TILE_MINW 2
+template <int MODE, int BEAM>
+constexpr int tile_min_waves() {
+    return (MODE == MODE_STOKES || (MODE == MODE_TOD && BEAM == BEAM_FULL)) ? 2 : 4;
+}
 
 template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP>
 __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp, const PairCtx &C,
@@ -930,6 +941,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
 
     const TileFrame T = tile_setup(D, t, valid, &L.lane[lane]);
     const LaneFrame F = L.lane[lane];
+    wave_sync();   // every lane holds its frame before records overwrite the slice
     const double thc = uniform(T.thc), phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
     const double Ru = uniform(T.Ru);
     const double cosRu = cos(Ru);
@@ -1459,7 +1471,7 @@ __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
 }
 
 template <int MODE, int BEAM, int CH, bool PS, bool HWP>
-__global__ void __launch_bounds__(512, TILE_MINW) tile_kernel(ConvArgs A) {
+__global__ void __launch_bounds__(512, (tile_min_waves<MODE, BEAM>())) tile_kernel(ConvArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wid = threadIdx.x / WAVE;

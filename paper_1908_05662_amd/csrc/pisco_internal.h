@@ -77,11 +77,12 @@ hipError_t launch_check_pointing(const double *theta, const double *phi, const d
 
 }  // namespace pisco
 
-// Context accessors for the sidelobe-network runtime (runtime.cpp).
+// Context accessors for the sidelobe-network and map-making runtimes (runtime.cpp).
 struct pisco_ctx;
 namespace pisco {
 void set_error(pisco_ctx *c, const char *msg);
 int ctx_device(const pisco_ctx *c);
+int ctx_num_cu(const pisco_ctx *c);
 bool ctx_pointing(const pisco_ctx *c, int32_t det, const double **th, const double **ph, const double **ps,
                   int64_t *n);
 }  // namespace pisco

@@ -97,8 +97,8 @@ struct pisco_ctx {
     uint64_t generation = 1;  // bumped whenever anything a launch reads changes
 
     // launch shape
-    int32_t spt = 64, wpg = 4, gpc = 2, xq = 1;
-    int32_t algo = PISCO_ALGO_TILE, chunk = 256;
+    int32_t spt = 64, wpg = 4, gpc = 4, xq = 1;
+    int32_t algo = PISCO_ALGO_TILE, chunk = 64;
     double coherence = 0.5;
 
     Plan plans[2];            // [0] batched (det = -1), [1] single detector
@@ -444,6 +444,7 @@ void set_error(pisco_ctx *c, const char *msg) {
     if (c) c->err = msg;
 }
 int ctx_device(const pisco_ctx *c) { return c->device; }
+int ctx_num_cu(const pisco_ctx *c) { return c->num_cu; }
 bool ctx_pointing(const pisco_ctx *c, int32_t det, const double **th, const double **ph, const double **ps,
                   int64_t *n) {
     if (det < 0 || (size_t)det >= c->dets.size() || !c->dets[det].has_pointing) return false;
@@ -818,7 +819,8 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
                         (long long)d.nsamp);
         // a V column adds 4 bytes of LDS per staged record and wave on the tile path
         if (d.beam_v && c->algo != PISCO_ALGO_PIXEL && out_mode == PISCO_OUT_TOD &&
-            (size_t)c->wpg * (8192 + 52 * (size_t)c->chunk) > 160 * 1024)
+            (size_t)c->wpg * (4352 + std::max<size_t>(3840, 48 * (size_t)c->chunk) + 4 * (size_t)c->chunk) >
+                160 * 1024)
             return fail(c, PISCO_EINVAL, "detector %d: a V-column beam needs more LDS than chunk %d with %d waves "
                         "per group leaves; use a smaller chunk or fewer waves", k, c->chunk, c->wpg);
         if (first_kind < 0) first_kind = d.beam_kind;
@@ -909,9 +911,10 @@ pisco_status pisco_set_launch(pisco_ctx *c, const pisco_launch *l) {
     // LDS per wave: rings, frames and segment ends, the staged records and, on
     // the matrix-core path, the running sums of TOD launches (Stokes launches
     // split workgroups that would not fit)
-    const size_t tile_slice = 64 * 64 + 64 * 60 + 64 * 4 +
-                              (l->algorithm == PISCO_ALGO_TILE_MX ? (size_t)l->chunk * 64 + 4 * 4 * 64 * 4
-                                                                   : (size_t)l->chunk * 48);
+    // (tile path: the lane frames share storage with the staged records)
+    const size_t tile_slice = l->algorithm == PISCO_ALGO_TILE_MX
+                                  ? 64 * 64 + 64 * 60 + 64 * 4 + (size_t)l->chunk * 64 + 4 * 4 * 64 * 4
+                                  : 64 * 64 + 64 * 4 + std::max<size_t>(64 * 60, (size_t)l->chunk * 48);
     if (l->algorithm != PISCO_ALGO_PIXEL && tile_slice * (size_t)w > 160 * 1024)
         return fail(c, PISCO_EINVAL, "chunk %d with %d waves per group exceeds the LDS of a compute unit", l->chunk, w);
     c->algo = l->algorithm;
