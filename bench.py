@@ -47,6 +47,8 @@ FLOPS_PER_PAIR = {(1, "scalar"): (83, 0), (1, "full"): (113, 0), (2, "scalar"): 
                   (0, "scalar"): (125, 0), (0, "full"): (155, 0)}
 # vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 (FMA)
 ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# HBM3E bandwidth of one MI355X (published)
+HBM_PEAK_GBS = 8000.0
 
 
 def log(msg):
@@ -273,6 +275,51 @@ def plate_leg(conv, w, stream, out, steps, warmup, plain_kernel_ms, torch):
             "samples_per_s": n / (wall / steps), "rate_vs_plain": plain_kernel_ms / k_ms}
 
 
+def map_leg(w, keep, out, stream, torch, nside_map=1024, reps=3):
+    """Binned maps of the benchmark TOD: every detector's samples accumulated
+    into nside-1024 per-pixel sums (one launch per detector), then the
+    per-pixel solve; HIP events on the launch stream.  HBM bytes counted: per
+    sample 24 B of pointing and 4 B of TOD read; per pixel the 80-byte sums
+    zeroed and read by the solve, and 32 B of maps and rcond written; per hit
+    pixel the sums read and written once by the accumulation (its updates
+    staying in cache)."""
+    from paper_1908_05662_amd.api import MapMaker
+
+    mm = MapMaker(keep["conv"], nside_map)
+    offs = np.cumsum([0] + [d.n for d in w.detectors])
+
+    def run():
+        mm.clear()
+        for k, d in enumerate(w.detectors):
+            th, ph, ps = keep["pointing"][k]
+            mm.add(th, ph, ps, out[offs[k]:offs[k + 1]], d.det.zeta, d.det.eps, d.det.s, stream=None)
+        return mm.solve(1e-3)
+
+    with torch.cuda.stream(stream):
+        run()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        with torch.cuda.stream(stream):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            maps, rc = run()
+            b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    t = min(times)
+    n = int(offs[-1])
+    npix = 12 * nside_map * nside_map
+    hit = int((mm.hits() > 0).sum().item())
+    good = int((rc >= 1e-3).sum().item())
+    nbytes = 28.0 * n + 80.0 * npix + 160.0 * hit + 80.0 * npix + 32.0 * npix
+    log(f"maps: {t * 1e3:.2f} ms for {n} samples into nside {nside_map} ({hit} pixels hit, {good} solved for I, Q, U)")
+    return {"workload": f"the benchmark TOD ({len(w.detectors)} detectors) binned into nside-{nside_map} I, Q, U maps",
+            "ms": t * 1e3, "samples_per_s": n / t, "pixels_hit": hit, "pixels_iqu": good,
+            "hbm_bytes": nbytes, "achieved_gbs": nbytes / t / 1e9, "peak_gbs": HBM_PEAK_GBS,
+            "frac": nbytes / t / 1e9 / HBM_PEAK_GBS}
+
+
 def full_scale_leg(epochs, n_train, width, hidden, lr):
     """The nside-2048 full-scale workload on one GPU: 256 detectors x 390,625 CES
     samples (1e8), each with its own 151^2 elliptical main beam (disc 1.5 deg),
@@ -438,6 +485,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the far-sidelobe surrogate leg")
     ap.add_argument("--no-paper-shape", action="store_true", help="skip the paper's benchmark-pattern leg")
     ap.add_argument("--no-plate", action="store_true", help="skip the half-wave-plate leg")
+    ap.add_argument("--no-maps", action="store_true", help="skip the map-making leg")
     ap.add_argument("--full-scale", action="store_true",
                     help="also run the nside-2048, 1e8-sample surrogate-vs-exact leg (about 3 minutes)")
     ap.add_argument("--full-scale-train", type=int, default=6_000_000)
@@ -535,6 +583,12 @@ def main():
     plate = None
     if not args.no_plate:
         plate = plate_leg(conv, w, stream, out, args.steps, args.warmup, k_ms, torch)
+    maps = None
+    if not args.no_maps:
+        with torch.cuda.stream(stream):
+            conv.convolve(-1, OUT_TOD, out=out, stream=stream)
+        stream.synchronize()
+        maps = map_leg(w, {"conv": conv, "pointing": keep}, out, stream, torch)
 
     rec = {
         "metric": "TOD samples/s + beam-pixel MACs/s at nside 1024; surrogate vs exact at fixed error",
@@ -563,6 +617,7 @@ def main():
                                                                         "cached", "seconds", "subsample")},
         "parity_max_rel_err": parity,
         "plate": plate,
+        "maps": maps,
     }
     conv.close()
     del keep, out

@@ -40,30 +40,70 @@ __device__ inline int64_t ring_pixel(int64_t N, double theta, double phi) {
     return (z > 0.0) ? 2 * r * (r - 1) + k : 12 * N * N - 2 * r * (r + 1) + k;
 }
 
+// One wave takes 64 consecutive samples per step.  Samples of a scan fall into
+// the same pixel several at a time, so the wave first sums each run of lanes
+// with equal pixels (a segmented scan over the lanes) and only the last lane
+// of a run adds its ten sums to the pixel: far fewer atomics on the same
+// addresses.  Invalid lanes form runs of their own and add nothing.
 template <typename T>
 __global__ void __launch_bounds__(256) map_accum_kernel(MapAccumArgs a, const T *__restrict__ tod) {
+    constexpr int WV = 64;
+    const int lane = threadIdx.x & (WV - 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < a.n; t += stride) {
-        const double th = a.theta[t], ph = a.phi[t], ps = a.psi[t];
-        const double hw = a.hwp ? a.hwp[t] : 0.0;
-        const double d = (double)tod[t];
-        if (!(isfinite(th) && isfinite(ph) && isfinite(ps) && isfinite(hw) && isfinite(d))) continue;
-        const int64_t p = ring_pixel(a.nside, th, ph);
-        if (p < 0 || p >= a.npix) continue;   // only finite directions reach here: never taken
-        double sn, cs;
-        sincos(2.0 * (ps + a.zeta) + 4.0 * hw, &sn, &cs);
-        const double w0 = a.c_int, w1 = a.c_pol * cs, w2 = a.c_pol * sn;
-        double *q = a.accum + 10 * p;
-        unsafeAtomicAdd(q + 0, w0 * w0);
-        unsafeAtomicAdd(q + 1, w0 * w1);
-        unsafeAtomicAdd(q + 2, w0 * w2);
-        unsafeAtomicAdd(q + 3, w1 * w1);
-        unsafeAtomicAdd(q + 4, w1 * w2);
-        unsafeAtomicAdd(q + 5, w2 * w2);
-        unsafeAtomicAdd(q + 6, w0 * d);
-        unsafeAtomicAdd(q + 7, w1 * d);
-        unsafeAtomicAdd(q + 8, w2 * d);
-        unsafeAtomicAdd(q + 9, 1.0);
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~(WV - 1)); t0 < a.n; t0 += stride) {
+        const int64_t t = t0 + lane;
+        int32_t p = -1 - lane;
+        double v[10];
+        for (int k = 0; k < 10; ++k) v[k] = 0.0;
+        if (t < a.n) {
+            const double th = a.theta[t], ph = a.phi[t], ps = a.psi[t];
+            const double hw = a.hwp ? a.hwp[t] : 0.0;
+            const double d = (double)tod[t];
+            if (isfinite(th) && isfinite(ph) && isfinite(ps) && isfinite(hw) && isfinite(d)) {
+                const int64_t q = ring_pixel(a.nside, th, ph);
+                if (q >= 0 && q < a.npix) {   // only finite directions reach here: always true
+                    p = (int32_t)q;
+                    double sn, cs;
+                    sincos(2.0 * (ps + a.zeta) + 4.0 * hw, &sn, &cs);
+                    const double w0 = a.c_int, w1 = a.c_pol * cs, w2 = a.c_pol * sn;
+                    v[0] = w0 * w0;
+                    v[1] = w0 * w1;
+                    v[2] = w0 * w2;
+                    v[3] = w1 * w1;
+                    v[4] = w1 * w2;
+                    v[5] = w2 * w2;
+                    v[6] = w0 * d;
+                    v[7] = w1 * d;
+                    v[8] = w2 * d;
+                    v[9] = 1.0;
+                }
+            }
+        }
+        // first lane of this lane's run: prefix maximum of the run heads
+        const int32_t pu = __shfl_up(p, 1, WV);
+        int start = (lane == 0 || pu != p) ? lane : 0;
+#pragma unroll
+        for (int off = 1; off < WV; off <<= 1) {
+            const int o = __shfl_up(start, off, WV);
+            if (lane >= off) start = max(start, o);
+        }
+        // segmented inclusive sums over [start, lane]
+#pragma unroll
+        for (int off = 1; off < WV; off <<= 1) {
+            const bool take = lane - off >= start;
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                const double x = __shfl_up(v[k], off, WV);
+                if (take) v[k] += x;
+            }
+        }
+        const int32_t pd = __shfl_down(p, 1, WV);
+        const bool last = (lane == WV - 1) || (pd != p);
+        if (last && p >= 0) {
+            double *q = a.accum + 10 * (int64_t)p;
+#pragma unroll
+            for (int k = 0; k < 10; ++k) unsafeAtomicAdd(q + k, v[k]);
+        }
     }
 }
 

@@ -164,6 +164,32 @@ def test_nonfinite_samples_are_skipped_and_errors(conv, torch):
         MapMaker(conv, nside).add(th, ph, ps, d, 0.2, float("nan"), 1.0)
 
 
+def test_runs_of_equal_pixels_with_gaps(conv, torch):
+    """Samples in runs of 1 to 20 equal directions (runs cross wave
+    boundaries), some of them non-finite: the wave-level run sums give the
+    oracle's per-pixel sums (hits exactly)."""
+    from paper_1908_05662_amd.api import MapMaker
+
+    say("case: runs of equal pixels with non-finite samples inside")
+    nside = 32
+    rng = np.random.default_rng(13)
+    reps = rng.integers(1, 21, 4000)
+    th = np.repeat(np.arccos(rng.uniform(-1, 1, reps.size)), reps)
+    ph = np.repeat(rng.uniform(0, 2 * np.pi, reps.size), reps)
+    n = th.size
+    ps = rng.uniform(0, 2 * np.pi, n)
+    d = rng.standard_normal(n)
+    d[rng.uniform(size=n) < 0.05] = np.nan
+    th[rng.uniform(size=n) < 0.02] = np.inf
+    keep = np.isfinite(th) & np.isfinite(d)
+    mm = MapMaker(conv, nside).add(th, ph, ps, d, 0.4, 0.01, 1.2)
+    ata, atd, hits = _oracle_sums(nside, [(th[keep], ph[keep], ps[keep], d[keep], 0.4, 0.01, 1.2, None)])
+    g_ata, g_atd, g_hits = _gpu_sums(mm)
+    assert np.array_equal(g_hits, hits)
+    assert rel_err(g_ata.reshape(-1), ata.reshape(-1)) <= 1e-13
+    assert rel_err(g_atd.reshape(-1), atd.reshape(-1)) <= 1e-13
+
+
 def test_benchmark_detectors_binned_at_nside_1024(conv, torch):
     """Eight detectors of the nside-1024 benchmark workload (their GPU TOD),
     binned at nside 1024: every pixel's sums and maps against the oracle."""
