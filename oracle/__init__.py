@@ -61,6 +61,9 @@ def _lib():
         h.orc_disc_counts.argtypes = [i64, i64, dp, dp, dbl, lp, i32]
         h.orc_max_threads.restype = i32
         h.orc_ang2pix.argtypes = [i64, i64, dp, dp, lp]
+        h.orc_healpix_interp.argtypes = [i64, dp, dbl, dbl]
+        h.orc_healpix_interp.restype = dbl
+        h.orc_healpix_to_grid.argtypes = [i64, dp, dbl, i32, dp]
         _h = h
     return _h
 
@@ -96,6 +99,31 @@ def ang2pix(nside: int, theta, phi) -> np.ndarray:
         raise ValueError("theta and phi differ in length")
     out = np.empty(th.size, dtype=np.int64)
     _lib().orc_ang2pix(nside, th.size, _dp(th), _dp(ph), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out
+
+
+def healpix_interp(nside: int, m, theta, phi) -> np.ndarray:
+    """A RING map read at (theta, phi) by bilinear interpolation on the sphere
+    (two bracketing rings, two bracketing pixels on each; poles = mean of the
+    first / last ring)."""
+    m = _f64(m)
+    if m.size != 12 * nside * nside:
+        raise ValueError("map size does not match nside")
+    th, ph = np.broadcast_arrays(_f64(theta), _f64(phi))
+    out = np.empty(th.shape)
+    for k, (a, b) in enumerate(zip(th.ravel(), ph.ravel())):
+        out.flat[k] = _lib().orc_healpix_interp(nside, _dp(m), float(a), float(b))
+    return out
+
+
+def healpix_to_grid(nside: int, m, half_span_tan: float, n: int) -> np.ndarray:
+    """(n, n) gnomonic grid ([v][u] over [-T, T]^2) read from a map whose north
+    pole is the boresight (theta = rho, phi = sigma)."""
+    m = _f64(m)
+    if m.size != 12 * nside * nside:
+        raise ValueError("map size does not match nside")
+    out = np.empty((n, n))
+    _lib().orc_healpix_to_grid(nside, _dp(m), float(half_span_tan), int(n), _dp(out))
     return out
 
 

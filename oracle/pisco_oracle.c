@@ -145,6 +145,75 @@ void orc_ring(int64_t N, int64_t i, double *theta, int64_t *count, int64_t *firs
     *theta = atan2(s, z);
 }
 
+/*
+ * A RING map read at (theta, phi) by bilinear interpolation on the sphere (the
+ * re-pixelisation of beamsor maps, Sec. 4.2): on each of the two rings whose
+ * colatitudes bracket theta, linear in phi between the two pixels whose
+ * centres bracket phi (cyclically); between the rings, linear in theta.  Above
+ * the first ring the upper "ring" is the north pole, whose value is the mean
+ * of the first ring's four pixels; below the last ring, likewise the south pole.
+ */
+static double ring_value(int64_t N, const double *map, int64_t ring, double phi) {
+    double th;
+    int64_t cnt, first;
+    orc_ring(N, ring, &th, &cnt, &first);
+    double z, s, phi0;
+    orc_pix2zphi(N, first, &z, &s, &phi0);
+    const double dphi = 2.0 * M_PI / (double)cnt;
+    const double x = (phi - phi0) / dphi;
+    const double fl = floor(x);
+    const double w = x - fl;
+    int64_t j0 = (int64_t)fl % cnt;
+    if (j0 < 0) j0 += cnt;
+    const int64_t j1 = (j0 + 1 == cnt) ? 0 : j0 + 1;
+    return (1.0 - w) * map[first + j0] + w * map[first + j1];
+}
+
+static double ring_theta(int64_t N, int64_t ring) {
+    double th;
+    int64_t cnt, first;
+    orc_ring(N, ring, &th, &cnt, &first);
+    return th;
+}
+
+double orc_healpix_interp(int64_t N, const double *map, double theta, double phi) {
+    const int64_t nring = 4 * N - 1;
+    const double th1 = ring_theta(N, 1), thl = ring_theta(N, nring);
+    if (theta < th1) {
+        const double pole = 0.25 * (map[0] + map[1] + map[2] + map[3]);
+        const double t = theta / th1;
+        return (1.0 - t) * pole + t * ring_value(N, map, 1, phi);
+    }
+    if (theta >= thl) {
+        const int64_t np = 12 * N * N;
+        const double pole = 0.25 * (map[np - 4] + map[np - 3] + map[np - 2] + map[np - 1]);
+        const double t = (M_PI - theta) / (M_PI - thl);
+        return (1.0 - t) * pole + t * ring_value(N, map, nring, phi);
+    }
+    /* the ring i with theta_i <= theta < theta_{i+1}, by bisection */
+    int64_t lo = 1, hi = nring;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) / 2;
+        if (ring_theta(N, mid) <= theta) lo = mid;
+        else hi = mid;
+    }
+    const double ta = ring_theta(N, lo), tb = ring_theta(N, lo + 1);
+    const double t = (theta - ta) / (tb - ta);
+    return (1.0 - t) * ring_value(N, map, lo, phi) + t * ring_value(N, map, lo + 1, phi);
+}
+
+/* The n x n gnomonic grid over [-T, T]^2 ([v][u]) sampled from a map whose
+ * north pole is the boresight: node (u, v) reads the map at theta = rho =
+ * atan(sqrt(u^2 + v^2)), phi = sigma = atan2(v, u). */
+void orc_healpix_to_grid(int64_t N, const double *map, double T, int n, double *out) {
+    const double h = 2.0 * T / (double)(n - 1);
+    for (int iv = 0; iv < n; ++iv)
+        for (int iu = 0; iu < n; ++iu) {
+            const double u = -T + iu * h, v = -T + iv * h;
+            out[(int64_t)iv * n + iu] = orc_healpix_interp(N, map, atan(hypot(u, v)), atan2(v, u));
+        }
+}
+
 /* ------------------------------------------------------------------ */
 /* Appendix A: antenna coordinates and polarisation angle               */
 /* ------------------------------------------------------------------ */
