@@ -157,6 +157,31 @@ pisco_status pisco_set_hwp(pisco_ctx *ctx, int32_t det, int64_t n, const double 
 /* Let detector `det` use the beam of detector `src` (no copy; e.g. one shared
  * far-sidelobe grid).  `src` must already have a beam. */
 pisco_status pisco_share_beam(pisco_ctx *ctx, int32_t det, int32_t src);
+/*
+ * Beamsors given as HEALPix maps (the representation the paper stores them
+ * in, Sec. 4.2 and Sec. 5.1, "re-pixelated via interpolation"): RING maps of
+ * 12 nside_beam^2 values with the boresight at the map's north pole, theta
+ * the distance rho from it and phi the antenna-frame azimuth sigma (from
+ * theta'_0 toward phi'_0).  The library resamples them once, on the device,
+ * onto the n x n gnomonic grid over [-half_span_tan, half_span_tan]^2 of
+ * pisco_set_beam: node (u, v) reads the map at theta = atan(sqrt(u^2 + v^2)),
+ * phi = atan2(v, u), linearly in phi between the two bracketing pixels of
+ * each of the two rings that bracket theta and linearly in theta between the
+ * rings (above the first ring the north pole stands in, valued at the mean of
+ * that ring's four pixels; likewise the south pole below the last).  The
+ * convolution then reads the grid as for pisco_set_beam / pisco_set_beam_scalar.
+ * Channels as there (bI, bQ, bU, bT, or one map b with weights); dtype/mem as
+ * for the sky; host maps are copied, device maps are read before the call
+ * returns.  EINVAL: nside_beam not a power of two in [1, 8192], n not odd in
+ * [3, 4095], half_span_tan not finite and > 0, a null map.
+ */
+pisco_status pisco_set_beam_healpix(pisco_ctx *ctx, int32_t det, int64_t nside_beam, const void *bI, const void *bQ,
+                                    const void *bU, const void *bT, int32_t n, double half_span_tan, int dtype,
+                                    int mem);
+pisco_status pisco_set_beam_healpix_scalar(pisco_ctx *ctx, int32_t det, int64_t nside_beam, const void *b, double wI,
+                                           double wQ, double wU, double wT, int32_t n, double half_span_tan,
+                                           int dtype, int mem);
+
 
 /*
  * Detector parameters: zeta (rad, Sec. 3); pixels with rho_min < rho <= rho_max

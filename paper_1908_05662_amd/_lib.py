@@ -40,6 +40,10 @@ SIGNATURES = [
     ("pisco_set_beam_scalar", ctypes.c_int, [_vp, _i32, _i32, _dbl, _vp, _dbl, _dbl, _dbl, _dbl, ctypes.c_int,
                                              ctypes.c_int]),
     ("pisco_share_beam", ctypes.c_int, [_vp, _i32, _i32]),
+    ("pisco_set_beam_healpix", ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, _vp, _i32, _dbl, ctypes.c_int,
+                                              ctypes.c_int]),
+    ("pisco_set_beam_healpix_scalar", ctypes.c_int, [_vp, _i32, _i64, _vp, _dbl, _dbl, _dbl, _dbl, _i32, _dbl,
+                                                     ctypes.c_int, ctypes.c_int]),
     ("pisco_set_sky_iquv", ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int]),
     ("pisco_set_beam_v", ctypes.c_int, [_vp, _i32, _i32, _dbl, _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
                                         ctypes.c_int]),

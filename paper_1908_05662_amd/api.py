@@ -11,7 +11,7 @@ import ctypes
 import numpy as np
 
 from . import _lib as L
-from .beamsor import fold_detector, fold_v, scalar_weights
+from .beamsor import fold_detector, fold_detector_maps, fold_v, scalar_weights
 
 
 def _torch():
@@ -117,6 +117,41 @@ class Convolver:
         self._check(self._lib.pisco_set_beam_scalar(self._h, int(det), int(n), float(half_span_tan), t.data_ptr(),
                                                     float(wI), float(wQ), float(wU), float(wT), self._code(dtype),
                                                     self._mem(t)))
+
+    def set_beam_healpix(self, det: int, nside_beam: int, n: int, half_span_tan: float, bI, bQ, bU, bT, dtype=None):
+        """Four-channel beam given as HEALPix maps (boresight at the north pole),
+        resampled by the library onto the n x n grid over +-half_span_tan."""
+        dtype = dtype or self.dtype or _torch().float32
+        ts = [self._as_tensor(b, dtype).reshape(-1) for b in (bI, bQ, bU, bT)]
+        mems = {self._mem(t) for t in ts}
+        if len(mems) != 1:
+            raise ValueError("beam maps must all live on the host or all on the device")
+        self._check(self._lib.pisco_set_beam_healpix(self._h, int(det), int(nside_beam), *(t.data_ptr() for t in ts),
+                                                     int(n), float(half_span_tan), self._code(dtype), mems.pop()))
+
+    def set_beam_healpix_scalar(self, det: int, nside_beam: int, n: int, half_span_tan: float, b, wI: float,
+                                wQ: float, wU: float, wT: float = 1.0, dtype=None):
+        dtype = dtype or self.dtype or _torch().float32
+        t = self._as_tensor(b, dtype).reshape(-1)
+        self._check(self._lib.pisco_set_beam_healpix_scalar(self._h, int(det), int(nside_beam), t.data_ptr(),
+                                                            float(wI), float(wQ), float(wU), float(wT), int(n),
+                                                            float(half_span_tan), self._code(dtype), self._mem(t)))
+
+    def set_beamsor_healpix(self, det: int, nside_beam: int, mueller_maps: np.ndarray, half_span_tan: float, n: int,
+                            eps: float, s: float, dtype=None, allow_scalar: bool = True):
+        """Fold (npix, 4, 4) Mueller maps with the detector row and upload them
+        as HEALPix beam maps; the one-map form when every folded channel is a
+        constant multiple of B_TT.  A V column is not taken on this route."""
+        bI, bQ, bU, bT, bV = fold_detector_maps(mueller_maps, eps, s)
+        if np.any(bV):
+            raise ValueError("HEALPix beam maps with a V column: resample them onto a grid and use set_beam")
+        if allow_scalar:
+            w = scalar_weights(bI, bQ, bU, bT)
+            if w is not None:
+                self.set_beam_healpix_scalar(det, nside_beam, n, half_span_tan, bT, *w, 1.0, dtype=dtype)
+                return "scalar"
+        self.set_beam_healpix(det, nside_beam, n, half_span_tan, bI, bQ, bU, bT, dtype)
+        return "full"
 
     def set_beamsor(self, det: int, mueller: np.ndarray, half_span_tan: float, eps: float, s: float, dtype=None,
                     allow_scalar: bool = True):

@@ -29,6 +29,15 @@ def fold_detector(M: np.ndarray, eps: float, s: float):
     return bI, bQ, bU, M[:, :, 0, 0].copy()
 
 
+def fold_detector_maps(M: np.ndarray, eps: float, s: float):
+    """M: (npix, 4, 4) Mueller maps (HEALPix) -> (bI, bQ, bU, bT, bV), each (npix,) float64."""
+    M = np.asarray(M, dtype=np.float64)
+    if M.ndim != 3 or M.shape[1:] != (4, 4):
+        raise ValueError("Mueller maps must be (npix, 4, 4)")
+    a, b = 0.5 * s * (1.0 + eps), 0.5 * s * (1.0 - eps)
+    return tuple(a * M[:, 0, k] + b * M[:, 1, k] for k in range(3)) + (M[:, 0, 0].copy(), a * M[:, 0, 3] + b * M[:, 1, 3])
+
+
 def fold_v(M: np.ndarray, eps: float, s: float):
     """The V-column channel bV of a (n, n, 4, 4) Mueller field, or None when it is zero."""
     M = np.asarray(M, dtype=np.float64)

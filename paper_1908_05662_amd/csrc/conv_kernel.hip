@@ -1556,6 +1556,77 @@ __global__ void repack4_kernel(const T *a, const T *b, const T *c, const T *d, t
 // four corner nodes as a polynomial in the cell fractions (fu, fv):
 // b = b00 + fu (b10 - b00) + fv (b01 - b00) + fu fv (b11 - b10 - b01 + b00).
 // The differences are formed in FP64 and rounded once.
+// HEALPix beam maps (beam at the map's north pole, theta = rho, phi = sigma)
+// resampled onto the n x n gnomonic node grid ([v][u] over [-T, T]^2): per
+// node, linear in phi between the two bracketing pixels of each of the two
+// rings that bracket theta, then linear in theta between the rings; above the
+// first ring (below the last) the pole, valued at the mean of that ring's four
+// pixels, takes the place of the missing ring.  FP64 arithmetic.
+__device__ inline double ring_theta(int32_t N, int32_t r) {
+    const RingGeom g = ring_geom(N, r);
+    return atan2(g.s, g.z);
+}
+
+template <typename T>
+__device__ inline double ring_read(const T *__restrict__ map, const RingGeom &g, double phi) {
+    const double x = (phi - g.phi0) / g.dphi;
+    const double fl = floor(x);
+    const double w = x - fl;
+    int64_t j0 = (int64_t)fl % g.n;
+    if (j0 < 0) j0 += g.n;
+    const int64_t j1 = (j0 + 1 == g.n) ? 0 : j0 + 1;
+    return (1.0 - w) * (double)map[g.first + j0] + w * (double)map[g.first + j1];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) healpix_grid_kernel(HpxGridArgs a) {
+    const int64_t nodes = (int64_t)a.n * a.n;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nodes) return;
+    const int32_t iu = (int32_t)(k % a.n), iv = (int32_t)(k / a.n);
+    const double h = 2.0 * a.T / (double)(a.n - 1);
+    const double u = -a.T + iu * h, v = -a.T + iv * h;
+    const double th = atan(sqrt(u * u + v * v)), ph = atan2(v, u);
+    const int32_t N = a.nside, nring = 4 * N - 1;
+    const int64_t npix = 12 * (int64_t)N * N;
+    const double th1 = ring_theta(N, 1), thl = ring_theta(N, nring);
+    int mode = 0;            // 0: between rings ra and ra + 1; 1: north pole and ring 1; 2: ring nring and south pole
+    int32_t ra = 1;
+    double t;
+    if (th < th1) {
+        mode = 1;
+        t = th / th1;
+    } else if (th >= thl) {
+        mode = 2;
+        t = (PI - th) / (PI - thl);
+        ra = nring;
+    } else {
+        ra = (int32_t)floor(ring_of_theta(N, th));
+        ra = ra < 1 ? 1 : (ra > nring - 1 ? nring - 1 : ra);
+        while (ra > 1 && ring_theta(N, ra) > th) --ra;
+        while (ra + 1 < nring && ring_theta(N, ra + 1) <= th) ++ra;
+        const double ta = ring_theta(N, ra), tb = ring_theta(N, ra + 1);
+        t = (th - ta) / (tb - ta);
+    }
+    const RingGeom ga = ring_geom(N, mode == 1 ? 1 : ra);
+    const RingGeom gb = ring_geom(N, mode == 0 ? ra + 1 : ra);
+    for (int c = 0; c < a.nch; ++c) {
+        const T *__restrict__ m = static_cast<const T *>(a.map[c]);
+        double val;
+        if (mode == 1) {
+            const double pole = 0.25 * ((double)m[0] + (double)m[1] + (double)m[2] + (double)m[3]);
+            val = (1.0 - t) * pole + t * ring_read(m, ga, ph);
+        } else if (mode == 2) {
+            const double pole =
+                0.25 * ((double)m[npix - 4] + (double)m[npix - 3] + (double)m[npix - 2] + (double)m[npix - 1]);
+            val = (1.0 - t) * pole + t * ring_read(m, ga, ph);
+        } else {
+            val = (1.0 - t) * ring_read(m, ga, ph) + t * ring_read(m, gb, ph);
+        }
+        static_cast<T *>(a.out[c])[k] = (T)val;
+    }
+}
+
 template <typename T>
 __global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::type *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1697,6 +1768,17 @@ hipError_t launch_repack4(const void *a, const void *b, const void *c, const voi
     else
         hipLaunchKernelGGL(repack4_kernel<float>, dim3((unsigned)g), dim3(bs), 0, s, (const float *)a,
                            (const float *)b, (const float *)c, (const float *)d, (float4 *)out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_healpix_grid(const HpxGridArgs &a, bool f64, hipStream_t s) {
+    const int64_t m = (int64_t)a.n * a.n;
+    const int64_t g = (m + 255) / 256;
+    if (g == 0) return hipSuccess;
+    if (f64)
+        hipLaunchKernelGGL(healpix_grid_kernel<double>, dim3((unsigned)g), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(healpix_grid_kernel<float>, dim3((unsigned)g), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

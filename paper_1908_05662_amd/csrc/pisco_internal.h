@@ -70,6 +70,14 @@ hipError_t launch_conv(const ConvArgs &a, bool f64, int waves_per_group, int gro
 hipError_t launch_repack4(const void *a, const void *b, const void *c, const void *d, void *out, int64_t n,
                           bool f64, hipStream_t s);
 hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, hipStream_t s);
+// HEALPix beam maps (nside, nch channels) resampled onto an n x n node grid over [-T, T]^2.
+struct HpxGridArgs {
+    int32_t nside, n, nch;
+    double T;
+    const void *map[4];
+    void *out[4];
+};
+hipError_t launch_healpix_grid(const HpxGridArgs &a, bool f64, hipStream_t s);
 hipError_t launch_classify(const DetDesc *dets, const Tile *groups, int32_t n_groups, double frac, int32_t *flag,
                            hipStream_t s);
 hipError_t launch_check_pointing(const double *theta, const double *phi, const double *psi, int64_t n,

@@ -558,6 +558,80 @@ pisco_status pisco_set_beam(pisco_ctx *c, int32_t det, int32_t n, double T, cons
     return PISCO_OK;
 }
 
+// HEALPix beam maps resampled onto a temporary n x n node grid (device arrays
+// the caller frees), then uploaded like a node grid.
+static pisco_status healpix_nodes(pisco_ctx *c, int64_t nside_b, const void *const *maps, int nch, int32_t n,
+                                  double T, int dtype, int mem, void **nodes) {
+    if (nside_b < 1 || nside_b > 8192 || !is_pow2(nside_b))
+        return fail(c, PISCO_EINVAL, "beam nside %lld must be a power of two in [1, 8192]", (long long)nside_b);
+    if (n < 3 || n > 4095 || (n % 2) == 0) return fail(c, PISCO_EINVAL, "grid size %d must be odd in [3, 4095]", n);
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(c, PISCO_EINVAL, "half_span_tan must be finite and > 0");
+    if (dtype != PISCO_F32 && dtype != PISCO_F64) return fail(c, PISCO_EINVAL, "bad dtype %d", dtype);
+    if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
+    for (int k = 0; k < nch; ++k)
+        if (!maps[k]) return fail(c, PISCO_EINVAL, "null beam map");
+    HIP_TRY(c, hipSetDevice(c->device));
+    const size_t mbytes = el_bytes(dtype) * (size_t)(12 * nside_b * nside_b);
+    const size_t nbytes = el_bytes(dtype) * (size_t)n * (size_t)n;
+    pisco::HpxGridArgs a{};
+    a.nside = (int32_t)nside_b;
+    a.n = n;
+    a.nch = nch;
+    a.T = T;
+    void *staged[4] = {nullptr, nullptr, nullptr, nullptr};
+    pisco_status st = PISCO_OK;
+    for (int k = 0; k < nch && st == PISCO_OK; ++k) {
+        nodes[k] = nullptr;
+        if (mem == PISCO_HOST) st = to_device(c, maps[k], mbytes, PISCO_HOST, &staged[k]);
+        a.map[k] = mem == PISCO_HOST ? staged[k] : maps[k];
+        if (st == PISCO_OK && hipMalloc(&nodes[k], nbytes) != hipSuccess)
+            st = fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", nbytes);
+        a.out[k] = nodes[k];
+    }
+    if (st == PISCO_OK) {
+        hipError_t e = pisco::launch_healpix_grid(a, dtype == PISCO_F64, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = fail(c, PISCO_EDEVICE, "beam map resampling failed: %s", hipGetErrorString(e));
+    }
+    for (int k = 0; k < nch; ++k)
+        if (staged[k]) (void)hipFree(staged[k]);
+    if (st != PISCO_OK)
+        for (int k = 0; k < nch; ++k)
+            if (nodes[k]) {
+                (void)hipFree(nodes[k]);
+                nodes[k] = nullptr;
+            }
+    return st;
+}
+
+pisco_status pisco_set_beam_healpix(pisco_ctx *c, int32_t det, int64_t nside_beam, const void *bI, const void *bQ,
+                                    const void *bU, const void *bT, int32_t n, double T, int dtype, int mem) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (!det_slot(c, det)) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    const void *maps[4] = {bI, bQ, bU, bT};
+    void *nodes[4] = {nullptr, nullptr, nullptr, nullptr};
+    pisco_status st = healpix_nodes(c, nside_beam, maps, 4, n, T, dtype, mem, nodes);
+    if (st != PISCO_OK) return st;
+    st = pisco_set_beam(c, det, n, T, nodes[0], nodes[1], nodes[2], nodes[3], dtype, PISCO_DEVICE);
+    for (int k = 0; k < 4; ++k) (void)hipFree(nodes[k]);
+    return st;
+}
+
+pisco_status pisco_set_beam_healpix_scalar(pisco_ctx *c, int32_t det, int64_t nside_beam, const void *b, double wI,
+                                           double wQ, double wU, double wT, int32_t n, double T, int dtype, int mem) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (!det_slot(c, det)) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    const void *maps[1] = {b};
+    void *nodes[1] = {nullptr};
+    pisco_status st = healpix_nodes(c, nside_beam, maps, 1, n, T, dtype, mem, nodes);
+    if (st != PISCO_OK) return st;
+    st = pisco_set_beam_scalar(c, det, n, T, nodes[0], wI, wQ, wU, wT, dtype, PISCO_DEVICE);
+    (void)hipFree(nodes[0]);
+    return st;
+}
+
 pisco_status pisco_set_beam_scalar(pisco_ctx *c, int32_t det, int32_t n, double T, const void *b, double wI,
                                    double wQ, double wU, double wT, int dtype, int mem) {
     if (!c) return PISCO_EINVAL;

@@ -98,3 +98,17 @@ class DetectorParams:
     zeta: float = 0.0      # polarisation angle w.r.t. theta'_0 (rad)
     eps: float = 0.0       # 1 - eps = polarisation efficiency
     s: float = 1.0         # responsivity
+
+
+def healpix_beam_map(nside: int, fwhm_rad: float, ellipticity: float = 0.0, orient_rad: float = 0.0,
+                     rho_max_rad: float | None = None) -> np.ndarray:
+    """Elliptical Gaussian (peak 1) sampled at the pixel centres of a RING map
+    whose north pole is the boresight: theta = rho, phi = sigma.  Zero beyond
+    rho_max when given (only the cap needs computing)."""
+    from .rings import pixel_centres
+
+    th, ph = pixel_centres(nside)
+    out = np.zeros(th.size)
+    keep = np.ones(th.size, dtype=bool) if rho_max_rad is None else th <= rho_max_rad
+    out[keep] = elliptical_gaussian(th[keep], ph[keep], fwhm_rad, ellipticity, orient_rad)
+    return out
