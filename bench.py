@@ -178,6 +178,9 @@ def paper_shape_leg():
     from synth import workloads as W
 
     sky = W.sky_for(128, 383, 2.0, 6)
+    from synth import beams as B
+
+    beam_map = B.healpix_beam_map(512, np.deg2rad(1.5), rho_max_rad=np.deg2rad(40.0)).astype(np.float32)
     rows = []
     conv = Convolver(0)
     conv.set_sky(128, *(torch.from_numpy(m.astype(np.float32)).cuda() for m in sky), dtype=torch.float32)
@@ -217,6 +220,25 @@ def paper_shape_leg():
         run(out)
         host = out.cpu().numpy()
         t_e2e = time.perf_counter() - t0
+        # the same, with each detector's beam given as the paper gives it: a HEALPix map of nside 512
+        # (host array), resampled by the library onto the same grid
+        d0 = w.detectors[0]
+        n_grid, T_grid = d0.beam.n, d0.beam.half_span_tan
+
+        def upload_hpx():
+            for k, d in enumerate(w.detectors):
+                conv.set_beam_healpix_scalar(k, 512, n_grid, T_grid, beam_map, 0.5 * d.det.s * (1 + d.det.eps),
+                                             0.5 * d.det.s * (1 - d.det.eps), 0.0, 1.0, dtype=torch.float32)
+                conv.set_detector(k, d.det.zeta, d.rho_min, d.rho_max, d.norm_mode, d.norm_scale)
+                conv.set_pointing(k, d.theta, d.phi, d.psi)
+
+        upload_hpx()
+        run(out)
+        t0 = time.perf_counter()
+        upload_hpx()
+        run(out)
+        _ = out.cpu().numpy()
+        t_e2e_hpx = time.perf_counter() - t0
         pairs = float(conv.convolve(-1, OUT_COUNT).double().sum())
         t_given = kernel_time(out)
         del host
@@ -228,10 +250,12 @@ def paper_shape_leg():
         rows.append({"rho_max_deg": rho, "pixels_max_paper": n_pix, "pairs_per_sample": pairs / n,
                      "kernel_ms_given_order": t_given * 1e3, "kernel_ms_hilbert_order": t_hil * 1e3,
                      "end_to_end_ms_given_order": t_e2e * 1e3, "paper_ms": paper_ms,
+                     "end_to_end_ms_healpix_beam_nside512": t_e2e_hpx * 1e3,
                      "speedup_end_to_end": paper_ms / (t_e2e * 1e3),
                      "pairs_per_s_hilbert_order": pairs / t_hil})
         log(f"paper shape rho {rho}: kernel {t_given * 1e3:.2f} ms given order, {t_hil * 1e3:.2f} ms Hilbert "
-            f"order; end to end {t_e2e * 1e3:.1f} ms (paper {paper_ms} ms on a GTX 1080)")
+            f"order; end to end {t_e2e * 1e3:.1f} ms, {t_e2e_hpx * 1e3:.1f} ms from a HEALPix beam map (paper "
+            f"{paper_ms} ms on a GTX 1080)")
     conv.close()
     return {"workload": "the paper's whole-sky benchmark pattern: 2 detectors x 3 psi x 196,608 nside-128 pixel "
                         "centres = 1,179,648 samples, Gaussian FWHM 1.5 deg, per-sample normalisation",
