@@ -169,6 +169,15 @@ template <> struct Acc<double> {
     __device__ inline double value() const { return s; }
 };
 
+// Tile-path accumulator: FP32 pre-sums of eight terms added in FP64 (a
+// conversion and an FP64 add, cheaper than a compensated FP32 add and more
+// accurate).
+struct AccWide {
+    double s = 0.0;
+    __device__ inline void add(float x) { s += (double)x; }
+    __device__ inline double value() const { return s; }
+};
+
 // One ring's staged record (one per lane of the current 64-ring chunk).
 template <typename T>
 struct RingRec {
@@ -775,7 +784,7 @@ constexpr int tile_min_waves() {
     return (MODE == MODE_STOKES || (MODE == MODE_TOD && BEAM == BEAM_FULL)) ? 2 : 4;
 }
 
-template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP>
+template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER>
 __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp, const PairCtx &C,
                                               const BeamRsrc &beam, const BeamRsrc &vbeam) {
     const LaneFrame &F = C.F;
@@ -788,7 +797,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         R[k] = Rp[k];
         // n = X e1 + Y e2 + (1 - W) c in the tile frame
         omg[k] = fmaf(-R[k].Y, F.p2, fmaf(-R[k].X, F.p1, fmaf(R[k].W, F.p3, F.om)));  // 1 - n.p
-        in[k] = (omg[k] <= C.omax) & (omg[k] > C.omin);   // omin = -1 without an inner disc
+        in[k] = INNER ? ((omg[k] <= C.omax) & (omg[k] > C.omin)) : (omg[k] <= C.omax);
         // n . theta'_0 and n . phi'_0 in grid units (the lane's rows carry 1 / h)
         xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));
         yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));
@@ -889,19 +898,19 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
 }
 
 // Every lane (sample) against the staged records [0, m_end): TILE_NP records
-// per step, then the remainder one by one.  CLIP (uniform per detector) adds
-// the disc-versus-grid test; it is a template switch so the common case runs
-// a loop without it.
-template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP>
+// per step, then the remainder one by one.  CLIP (the disc-versus-grid test)
+// and INNER (the inner-disc test of an annulus) are uniform per detector and
+// template switches, so the common case runs a loop without either.
+template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER>
 __device__ __forceinline__ void consume_records(const PixRec *rec, const float *vrec, int32_t m_end, const PairCtx &C,
-                                                const BeamRsrc &beam, const BeamRsrc &vbeam, Acc<float> &acc0,
-                                                Acc<float> &acc1, Acc<float> &acc2, Acc<float> &accn) {
+                                                const BeamRsrc &beam, const BeamRsrc &vbeam, AccWide &acc0,
+                                                AccWide &acc1, AccWide &acc2, AccWide &accn) {
     int32_t m = 0;
     // two groups per compensated add: eight masked terms summed in FP32
     for (; m + 2 * TILE_NP - 1 < m_end; m += 2 * TILE_NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam,
-                                                                         vbeam);
-        const PairOut b = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP>(
+        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER>(&rec[m], vrec ? &vrec[m] : nullptr, C,
+                                                                                beam, vbeam);
+        const PairOut b = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER>(
             &rec[m + TILE_NP], vrec ? &vrec[m + TILE_NP] : nullptr, C, beam, vbeam);
         acc0.add(a.v0 + b.v0);
         if (MODE == MODE_STOKES) {
@@ -911,8 +920,8 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
         if (PS) accn.add(a.vn + b.vn);
     }
     for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam,
-                                                                         vbeam);
+        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER>(&rec[m], vrec ? &vrec[m] : nullptr, C,
+                                                                                beam, vbeam);
         acc0.add(a.v0);
         if (MODE == MODE_STOKES) {
             acc1.add(a.v1);
@@ -921,7 +930,8 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
         if (PS) accn.add(a.vn);
     }
     for (; m < m_end; ++m) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP, CLIP>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
+        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP, CLIP, INNER>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam,
+                                                                          vbeam);
         acc0.add(a.v0);
         if (MODE == MODE_STOKES) {
             acc1.add(a.v1);
@@ -961,6 +971,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     Fg.b3 *= inv_h;
     // omin = -1 without an inner disc, so `omg > omin` holds for every pixel (omg >= 0)
     const float omax = (float)D.omega_max, omin = D.has_inner ? (float)D.omega_min : -1.0f;
+    const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);          // largest cell index
@@ -978,7 +989,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float sg4 = D.hwp ? -1.0f : 1.0f;
     const float wV = (float)D.wv;
 
-    Acc<float> acc0, acc1, acc2, accn;
+    AccWide acc0, acc1, acc2, accn;
     int32_t npairs = 0;
 
     const int32_t nring = 4 * N - 1;
@@ -1063,12 +1074,21 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     const PairCtx C{Fg, omax, omin, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes, sg4,
                                     (float)(n - 1)};
                     const float *vr = has_v ? vrec : nullptr;
-                    if (clip)
-                        consume_records<MODE, BEAM, PS, HWP, true>(L.rec, vr, m_end, C, beam, vbeam, acc0, acc1, acc2,
-                                                                    accn);
-                    else
-                        consume_records<MODE, BEAM, PS, HWP, false>(L.rec, vr, m_end, C, beam, vbeam, acc0, acc1,
-                                                                     acc2, accn);
+                    if (clip) {
+                        if (inner)
+                            consume_records<MODE, BEAM, PS, HWP, true, true>(L.rec, vr, m_end, C, beam, vbeam, acc0,
+                                                                             acc1, acc2, accn);
+                        else
+                            consume_records<MODE, BEAM, PS, HWP, true, false>(L.rec, vr, m_end, C, beam, vbeam, acc0,
+                                                                              acc1, acc2, accn);
+                    } else {
+                        if (inner)
+                            consume_records<MODE, BEAM, PS, HWP, false, true>(L.rec, vr, m_end, C, beam, vbeam, acc0,
+                                                                              acc1, acc2, accn);
+                        else
+                            consume_records<MODE, BEAM, PS, HWP, false, false>(L.rec, vr, m_end, C, beam, vbeam, acc0,
+                                                                               acc1, acc2, accn);
+                    }
                 }
             }
             wave_sync();
