@@ -261,6 +261,21 @@ typedef struct {
     double coherence;
 } pisco_launch;
 pisco_status pisco_set_launch(pisco_ctx *ctx, const pisco_launch *launch);
+/*
+ * Processing order of each detector's samples (the output is always in the
+ * caller's order).  Tiles group 64 consecutive samples of the processing
+ * order; a stream whose consecutive samples are far apart on the sky (random
+ * pointings, pixel-centre patterns like the paper's benchmark) gives tiles
+ * too spread for the tile path.  PISCO_ORDER_SPATIAL processes every
+ * detector's samples sorted along a Hilbert curve over (phi, cos theta) (a
+ * device sort at plan time, redone when the pointing changes);
+ * PISCO_ORDER_AUTO (the default) does so, on the FP32 tile paths, for a
+ * detector whose given order leaves more than half of its 64-sample groups
+ * incoherent; PISCO_ORDER_GIVEN keeps the given order.  Results depend on the
+ * order only through which samples share a tile (rounding).
+ */
+enum { PISCO_ORDER_GIVEN = 0, PISCO_ORDER_AUTO = 1, PISCO_ORDER_SPATIAL = 2 };
+pisco_status pisco_set_ordering(pisco_ctx *ctx, int32_t mode);
 pisco_status pisco_get_launch(const pisco_ctx *ctx, pisco_launch *launch);
 
 /*

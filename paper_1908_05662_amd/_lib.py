@@ -55,6 +55,7 @@ SIGNATURES = [
     ("pisco_convolve", ctypes.c_int, [_vp, _i32, ctypes.c_int, _vp, ctypes.c_int, _vp]),
     ("pisco_output_samples", _i64, [_vp, _i32]),
     ("pisco_set_launch", ctypes.c_int, [_vp, ctypes.c_void_p]),
+    ("pisco_set_ordering", ctypes.c_int, [_vp, _i32]),
     ("pisco_get_launch", ctypes.c_int, [_vp, ctypes.c_void_p]),
     ("pisco_set_timing", ctypes.c_int, [_vp, ctypes.c_int]),
     ("pisco_kernel_time", ctypes.c_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_i64), ctypes.c_int]),

@@ -233,6 +233,12 @@ class Convolver:
         self._check(self._lib.pisco_set_launch(self._h, ctypes.byref(l)))
         return self.get_launch()
 
+    def set_ordering(self, mode: str = "auto"):
+        """Processing order of each detector's samples: "given", "auto" (spatial
+        order for streams whose given order is incoherent) or "spatial"."""
+        code = {"given": 0, "auto": 1, "spatial": 2}[mode]
+        self._check(self._lib.pisco_set_ordering(self._h, code))
+
     def get_launch(self) -> dict:
         l = L.Launch()
         self._check(self._lib.pisco_get_launch(self._h, ctypes.byref(l)))

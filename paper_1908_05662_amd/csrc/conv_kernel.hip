@@ -44,6 +44,11 @@ struct RingGeom {
     int32_t first, n;
 };
 
+// The caller's index of the sample at position t of a detector's processing
+// order (the library may process an incoherent stream in spatial order; the
+// pointing is read and the output written at the caller's index).
+__device__ inline int64_t sample_at(const DetDesc &D, int64_t t) { return D.order ? (int64_t)D.order[t] : t; }
+
 __device__ inline RingGeom ring_geom(int32_t N, int32_t r) {
     RingGeom g;
     const double NN = (double)N;
@@ -259,7 +264,8 @@ __device__ inline BeamVals<T> beam_lookup(const void *beam, int32_t n, int32_t i
 // Pixel-parallel path: one sample at a time, lanes over its disc pixels
 // ----------------------------------------------------------------------
 template <typename T, int MODE, int BEAM>
-__device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t t, WaveLds<T> &L, int lane) {
+__device__ void convolve_sample(const ConvArgs &A, const DetDesc &D, int64_t pos, WaveLds<T> &L, int lane) {
+    const int64_t t = sample_at(D, pos);
     using R4 = typename Rec4<T>::type;
     const R4 *__restrict__ sky = reinterpret_cast<const R4 *>(A.sky);
     const int32_t N = (int32_t)A.nside;
@@ -947,7 +953,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
     const int32_t N = (int32_t)A.nside;
     const bool valid = lane < cnt;
-    const int64_t t = begin + (valid ? lane : 0);
+    const int64_t t = sample_at(D, begin + (valid ? lane : 0));
 
     const TileFrame T = tile_setup(D, t, valid, &L.lane[lane]);
     const LaneFrame F = L.lane[lane];
@@ -1174,7 +1180,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
     const int32_t N = (int32_t)A.nside;
     const bool valid = lane < cnt;
-    const int64_t t = begin + (valid ? lane : 0);
+    const int64_t t = sample_at(D, begin + (valid ? lane : 0));
 
     const TileFrame T = tile_setup(D, t, valid, &L.lane[lane]);
     const double thc = uniform(T.thc), phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
@@ -1400,7 +1406,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
             float v = L.acc[jb][0][lane];
             v += __shfl_xor(v, 16, WAVE);
             v += __shfl_xor(v, 32, WAVE);
-            if (k4 == 0 && smp < cnt) out[D.out_offset + begin + smp] = v;
+            if (k4 == 0 && smp < cnt) out[D.out_offset + sample_at(D, begin + smp)] = v;
             continue;
         }
         Acc<float> a0, a1s, a2s, an;
@@ -1426,7 +1432,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
             const double snm = an.value() * (BEAM == BEAM_SCALAR ? D.w[3] : 1.0);
             Nrm = (snm != 0.0) ? D.norm_scale / snm : 0.0;
         }
-        const int64_t o = D.out_offset + begin + smp;
+        const int64_t o = D.out_offset + sample_at(D, begin + smp);
         if (MODE == MODE_TOD) {
             out[o] = (float)(a0.value() * Nrm);
         } else {
@@ -1442,7 +1448,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
 // its samples lie within `frac` disc radii of their mean direction.
 __device__ inline bool tile_is_coherent(const DetDesc &D, int64_t begin, int32_t cnt, int lane, double frac) {
     const bool valid = lane < cnt;
-    const int64_t t = begin + (valid ? lane : 0);
+    const int64_t t = sample_at(D, begin + (valid ? lane : 0));
     double st, ct, sf, cf;
     sincos(D.theta[t], &st, &ct);
     sincos(D.phi[t], &sf, &cf);

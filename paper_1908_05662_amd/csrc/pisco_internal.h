@@ -30,6 +30,7 @@ struct DetDesc {
     double w[4];           // scalar beam weights (wI, wQ, wU, wT); unused for full beams
     const void *beam_v;    // full beams with a V column: (n-1)^2 cell polynomials of bV, else null
     const double *hwp;     // per-sample half-wave-plate angle, or null (no plate)
+    const int32_t *order;  // processing order: position t holds the caller's sample order[t]; null = given order
     double wv;             // scalar beam V weight
     int32_t n;             // grid nodes per side
     int32_t norm_mode;     // 0 fixed, 1 per sample
@@ -78,6 +79,9 @@ struct HpxGridArgs {
     void *out[4];
 };
 hipError_t launch_healpix_grid(const HpxGridArgs &a, bool f64, hipStream_t s);
+// Spatial processing order (order_kernel.hip): order[t] = the sample at position t when the n samples
+// are sorted along a Hilbert curve over (phi, cos theta); synchronises on `s`.
+hipError_t spatial_order(const double *theta, const double *phi, int64_t n, int32_t *order, hipStream_t s);
 hipError_t launch_classify(const DetDesc *dets, const Tile *groups, int32_t n_groups, double frac, int32_t *flag,
                            hipStream_t s);
 hipError_t launch_check_pointing(const double *theta, const double *phi, const double *psi, int64_t n,

@@ -39,6 +39,8 @@ struct DetState {
     int64_t nsamp = 0;
     const double *th = nullptr, *ph = nullptr, *ps = nullptr;
     double *owned_pointing = nullptr;  // one allocation holding th, ph, ps when copied
+    int32_t *order = nullptr;          // spatial processing order of the pointing (plan-time), owned
+    size_t order_cap = 0;
 };
 
 struct TimedLaunch {
@@ -100,6 +102,7 @@ struct pisco_ctx {
     int32_t spt = 64, wpg = 4, gpc = 4, xq = 1;
     int32_t algo = PISCO_ALGO_TILE, chunk = 64;
     double coherence = 0.5;
+    int32_t ordering = PISCO_ORDER_AUTO;   // processing order of the samples
 
     Plan plans[2];            // [0] batched (det = -1), [1] single detector
     int32_t *d_flag = nullptr;
@@ -172,6 +175,9 @@ void release_hwp(DetState &d) {
 void release_pointing(DetState &d) {
     if (d.owned_pointing) (void)hipFree(d.owned_pointing);
     d.owned_pointing = nullptr;
+    if (d.order) (void)hipFree(d.order);
+    d.order = nullptr;
+    d.order_cap = 0;
     d.th = d.ph = d.ps = nullptr;
     d.nsamp = 0;
     d.has_pointing = false;
@@ -275,6 +281,7 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         p.coherence == c->coherence)
         return PISCO_OK;
     std::vector<DetDesc> descs;
+    std::vector<int32_t> det_of;   // detector index of each descriptor
     int64_t out_off = 0;
     p.per_sample = 0;
     p.hwp = 0;
@@ -312,7 +319,9 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         x.n = d.n;
         x.norm_mode = d.norm_mode;
         x.has_inner = d.rho_min > 0.0 ? 1 : 0;
+        x.order = nullptr;
         descs.push_back(x);
+        det_of.push_back(k);
         out_off += d.nsamp;
         p.beam_kind = d.beam_kind;
         if (d.norm_mode == PISCO_NORM_PER_SAMPLE) p.per_sample = 1;
@@ -323,10 +332,27 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         return fail(c, PISCO_ENOMEM, "plan allocation failed");
     if (!grow(c, &p.d_dets, &p.d_dets_cap, std::max<size_t>(descs.size(), 1)))
         return fail(c, PISCO_ENOMEM, "plan allocation failed");
+    // the spatial processing order of a descriptor's detector (device sort)
+    auto set_order = [&](size_t i) -> pisco_status {
+        DetState &d = c->dets[det_of[i]];
+        if (!grow(c, &d.order, &d.order_cap, std::max<size_t>((size_t)d.nsamp, 1)))
+            return fail(c, PISCO_ENOMEM, "order allocation failed");
+        const hipError_t eo = pisco::spatial_order(d.th, d.ph, d.nsamp, d.order, nullptr);
+        if (eo != hipSuccess) return fail(c, PISCO_EDEVICE, "spatial ordering failed: %s", hipGetErrorString(eo));
+        descs[i].order = d.order;
+        return PISCO_OK;
+    };
+    if (c->ordering == PISCO_ORDER_SPATIAL)
+        for (size_t i = 0; i < descs.size(); ++i)
+            if (descs[i].n_samples > 64) {
+                const pisco_status so = set_order(i);
+                if (so != PISCO_OK) return so;
+            }
     if (!descs.empty()) HIP_TRY(c, hipMemcpy(p.d_dets, descs.data(), descs.size() * sizeof(DetDesc), hipMemcpyHostToDevice));
 
-    // groups of up to 64 consecutive samples; on the tile path each group is
-    // classified on the device as coherent (tile kernel) or not (pixel kernel)
+    // groups of up to 64 consecutive samples (in processing order); on the tile
+    // path each group is classified on the device as coherent (tile kernel) or
+    // not (pixel kernel)
     std::vector<Tile> groups;
     for (size_t i = 0; i < descs.size(); ++i)
         for (int64_t b = 0; b < descs[i].n_samples; b += 64) {
@@ -338,7 +364,8 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         }
     std::vector<int32_t> flag(groups.size(), 0);
     const bool tile_path = (c->algo == PISCO_ALGO_TILE || c->algo == PISCO_ALGO_TILE_MX) && (c->sky_dtype == PISCO_F32);
-    if (tile_path && !groups.empty()) {
+    auto classify = [&]() -> pisco_status {
+        if (!tile_path || groups.empty()) return PISCO_OK;
         const size_t need = groups.size() * (sizeof(Tile) + sizeof(int32_t));
         if (p.scratch_cap < need) {
             if (p.d_scratch) (void)hipFree(p.d_scratch);
@@ -352,6 +379,29 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         HIP_TRY(c, hipMemcpy(dg, groups.data(), groups.size() * sizeof(Tile), hipMemcpyHostToDevice));
         HIP_TRY(c, pisco::launch_classify(p.d_dets, dg, (int32_t)groups.size(), c->coherence, df, nullptr));
         HIP_TRY(c, hipMemcpy(flag.data(), df, groups.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        return PISCO_OK;
+    };
+    pisco_status cs = classify();
+    if (cs != PISCO_OK) return cs;
+    if (c->ordering == PISCO_ORDER_AUTO && tile_path) {
+        // detectors whose given order leaves most groups incoherent are processed in spatial order
+        std::vector<int64_t> coherent(descs.size(), 0), total(descs.size(), 0);
+        for (size_t g = 0; g < groups.size(); ++g) {
+            ++total[groups[g].det];
+            coherent[groups[g].det] += flag[g] ? 1 : 0;
+        }
+        bool any = false;
+        for (size_t i = 0; i < descs.size(); ++i)
+            if (total[i] >= 2 && 2 * coherent[i] < total[i]) {
+                const pisco_status so = set_order(i);
+                if (so != PISCO_OK) return so;
+                any = true;
+            }
+        if (any) {
+            HIP_TRY(c, hipMemcpy(p.d_dets, descs.data(), descs.size() * sizeof(DetDesc), hipMemcpyHostToDevice));
+            cs = classify();
+            if (cs != PISCO_OK) return cs;
+        }
     }
     std::vector<Tile> ttiles, ptiles;
     for (size_t g = 0; g < groups.size(); ++g) {
@@ -965,6 +1015,18 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
         e = hipMemcpy(out, dout, el_bytes(c->sky_dtype) * (size_t)nout, hipMemcpyDeviceToHost);
         (void)hipFree(dout);
         if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "output copy failed: %s", hipGetErrorString(e));
+    }
+    return PISCO_OK;
+}
+
+pisco_status pisco_set_ordering(pisco_ctx *c, int32_t mode) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (mode != PISCO_ORDER_GIVEN && mode != PISCO_ORDER_AUTO && mode != PISCO_ORDER_SPATIAL)
+        return fail(c, PISCO_EINVAL, "bad ordering mode %d", mode);
+    if (mode != c->ordering) {
+        c->ordering = mode;
+        ++c->generation;
     }
     return PISCO_OK;
 }
