@@ -375,6 +375,53 @@ pisco_status pisco_map_accumulate(pisco_ctx *ctx, int64_t nside_map, int64_t n, 
 pisco_status pisco_map_solve(pisco_ctx *ctx, int64_t nside_map, const double *accum, double rcond_min, double *maps,
                              double *rcond, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Angular power spectra of I, Q, U maps: the spectrum estimation the
+ * validation maps go through (Sec. 6.2), with the beam-corrected spectra
+ * compared with those of the input maps.  FP64 throughout.
+ *
+ * Definitions.  Y_lm(theta, phi) = lambda_lm(theta) e^{i m phi}, orthonormal,
+ * Condon-Shortley phase; _{+-2}Y_lm = (W_lm +- X_lm) e^{i m phi}, the spin-2
+ * harmonics of Goldberg et al. (1967).  With w = 4 pi / (12 nside^2) per pixel
+ * (one pass of pixel quadrature):
+ *   a^T_lm = w sum_p T_p Y*_lm(p),  a^{+-2}_lm = w sum_p (Q +- iU)_p _{+-2}Y*_lm(p),
+ *   a^E = -(a^2 + a^-2) / 2,  a^B = i (a^2 - a^-2) / 2
+ * (Zaldarriaga & Seljak 1997; the HEALPix sign convention), and
+ *   C^XY_l = (2l + 1)^-1 [Re(a^X_l0 a^Y*_l0) + 2 sum_{m=1..l} Re(a^X_lm a^Y*_lm)].
+ *
+ * a_lm arrays: device float64, complex interleaved (re, im), m-major packing:
+ * index(l, m) = m (2 lmax + 1 - m) / 2 + l for 0 <= m <= l <= lmax,
+ * pisco_alm_size(lmax) = (lmax + 1)(lmax + 2) / 2 complex values.
+ *
+ * pisco_map2alm: T, Q, U are device float64 RING maps of 12 nside^2 pixels
+ * (Q and U both null: temperature only; alm_E and alm_B are then not
+ * written and may be null).  `workspace` is caller-owned device memory of at
+ * least pisco_map2alm_workspace_bytes(nside, lmax, pol) bytes (the ring
+ * Fourier sums of every field); it must not be shared by calls in flight.
+ * mmax = lmax.
+ *
+ * pisco_alm2cl: cl[l] = C^XY_l for l = 0..lmax (device float64, lmax + 1).
+ *
+ * pisco_anafast: pisco_map2alm into the caller's alm arrays, then the six
+ * spectra TT, EE, BB, TE, EB, TB into cl [6][lmax + 1] (TT only, cl [1][lmax + 1],
+ * without Q and U).
+ *
+ * All return PISCO_EINVAL for nside not a power of two in [1, 1024], lmax
+ * outside [0, 4 nside], a null array that is needed, or a workspace smaller
+ * than required; launches are asynchronous on `stream` (hipStream_t, NULL =
+ * default) and every array must stay valid until the work there is done.
+ * ------------------------------------------------------------------------ */
+int64_t pisco_alm_size(int32_t lmax);
+int64_t pisco_map2alm_workspace_bytes(int64_t nside, int32_t lmax, int32_t pol);
+pisco_status pisco_map2alm(pisco_ctx *ctx, int64_t nside, int32_t lmax, const double *T, const double *Q,
+                           const double *U, double *alm_T, double *alm_E, double *alm_B, void *workspace,
+                           int64_t workspace_bytes, void *stream);
+pisco_status pisco_alm2cl(pisco_ctx *ctx, int32_t lmax, const double *alm_x, const double *alm_y, double *cl,
+                          void *stream);
+pisco_status pisco_anafast(pisco_ctx *ctx, int64_t nside, int32_t lmax, const double *T, const double *Q,
+                           const double *U, double *alm_T, double *alm_E, double *alm_B, void *workspace,
+                           int64_t workspace_bytes, double *cl, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

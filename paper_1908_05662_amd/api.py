@@ -404,3 +404,87 @@ class MapMaker:
 
     def hits(self):
         return self.accum.view(self.npix, 10)[:, 9]
+
+class Spectra:
+    """Spherical-harmonic analysis of HEALPix maps and their angular power
+    spectra on the convolver's device (``pisco_map2alm``, ``pisco_alm2cl``,
+    ``pisco_anafast``), FP64.  a_lm are complex128 device tensors in the
+    m-major packing index(l, m) = m (2 lmax + 1 - m) / 2 + l; spectra come in the
+    order TT, EE, BB, TE, EB, TB."""
+
+    NAMES = ("TT", "EE", "BB", "TE", "EB", "TB")
+
+    def __init__(self, conv: Convolver, nside: int, lmax: int | None = None, pol: bool = True):
+        torch = _torch()
+        self.conv, self.nside = conv, int(nside)
+        self.lmax = 3 * self.nside - 1 if lmax is None else int(lmax)
+        self.pol = bool(pol)
+        self._lib = conv._lib
+        nbytes = self._lib.pisco_map2alm_workspace_bytes(self.nside, self.lmax, int(self.pol))
+        if nbytes < 0:
+            raise ValueError("nside must be a power of two in [1, 1024] and lmax in [0, 4 nside]")
+        dev = conv.torch_device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        n = int(self._lib.pisco_alm_size(self.lmax))
+        self.alm = [torch.empty(n, dtype=torch.complex128, device=dev) for _ in range(3 if self.pol else 1)]
+
+    def _stream(self, stream):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.conv.torch_device)
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _maps(self, T, Q, U):
+        torch = _torch()
+        dev = self.conv.torch_device
+        npix = 12 * self.nside * self.nside
+        ms = [self.conv._as_tensor(x, torch.float64).to(dev).contiguous() for x in (T, Q, U) if x is not None]
+        if (Q is None) != (U is None) or (Q is not None and not self.pol) or any(m.numel() != npix for m in ms):
+            raise ValueError(f"expected T (and Q, U if polarised) RING maps of {npix} pixels")
+        return ms + [None] * (3 - len(ms))
+
+    def _ptrs(self, maps):
+        pol = maps[1] is not None
+        mp = [None if m is None else m.data_ptr() for m in maps]
+        ap = [self.alm[0].data_ptr()] + ([a.data_ptr() for a in self.alm[1:]] if pol else [None, None])
+        return mp, ap
+
+    def map2alm(self, T, Q=None, U=None, stream=None):
+        """(a^T, a^E, a^B) complex128 device tensors (a^E, a^B None without Q, U); the
+        tensors are this object's buffers, overwritten by the next call."""
+        maps = self._maps(T, Q, U)
+        mp, ap = self._ptrs(maps)
+        self.conv._check(self._lib.pisco_map2alm(self.conv._h, self.nside, self.lmax, *mp, *ap,
+                                                 self.workspace.data_ptr(), self.workspace.numel(),
+                                                 self._stream(stream)))
+        if stream is not None:
+            stream.synchronize()
+        return tuple(self.alm) if maps[1] is not None else (self.alm[0], None, None)
+
+    def anafast(self, T, Q=None, U=None, stream=None):
+        """[6, lmax + 1] float64 device tensor (TT, EE, BB, TE, EB, TB), or [1, lmax + 1] for T only."""
+        torch = _torch()
+        maps = self._maps(T, Q, U)
+        mp, ap = self._ptrs(maps)
+        cl = torch.empty((6 if maps[1] is not None else 1, self.lmax + 1), dtype=torch.float64,
+                         device=self.conv.torch_device)
+        self.conv._check(self._lib.pisco_anafast(self.conv._h, self.nside, self.lmax, *mp, *ap,
+                                                 self.workspace.data_ptr(), self.workspace.numel(), cl.data_ptr(),
+                                                 self._stream(stream)))
+        if stream is not None:
+            stream.synchronize()
+        return cl
+
+    def alm2cl(self, x, y=None, stream=None):
+        """C_l of two a_lm tensors of this object's lmax (y = x for an auto-spectrum)."""
+        torch = _torch()
+        y = x if y is None else y
+        n = int(self._lib.pisco_alm_size(self.lmax))
+        if x.dtype != torch.complex128 or y.dtype != torch.complex128 or x.numel() != n or y.numel() != n \
+                or not x.is_cuda or not y.is_cuda:
+            raise ValueError(f"a_lm must be complex128 device tensors of {n} values")
+        cl = torch.empty(self.lmax + 1, dtype=torch.float64, device=self.conv.torch_device)
+        self.conv._check(self._lib.pisco_alm2cl(self.conv._h, self.lmax, x.contiguous().data_ptr(),
+                                                y.contiguous().data_ptr(), cl.data_ptr(), self._stream(stream)))
+        if stream is not None:
+            stream.synchronize()
+        return cl

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpisco.so")
-SOURCES = ["conv_kernel.hip", "mlp_kernels.hip", "map_kernel.hip", "order_kernel.hip", "runtime.cpp", "mlp_runtime.cpp",
+SOURCES = ["conv_kernel.hip", "mlp_kernels.hip", "map_kernel.hip", "order_kernel.hip", "sht_kernel.hip", "runtime.cpp",
+           "mlp_runtime.cpp", "sht_runtime.cpp",
            "map_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

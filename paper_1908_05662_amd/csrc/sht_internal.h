@@ -1,0 +1,31 @@
+// Kernel arguments and launch helpers of the harmonic analysis (sht_kernel.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pisco {
+
+constexpr int SHT_MAX_NSIDE = 1024;        // ring FFT buffers (2 x 4N complex) fit one CU's LDS
+constexpr int SHT_PAIRS_PER_LANE = 4;      // 512 lanes x 4 ring pairs = 2N pairs at the largest nside
+
+struct ShtArgs {
+    int nside, lmax, mmax, nfields;        // nfields: 1 (T) or 3 (T, Q, U)
+    int nrings;                            // 4 nside - 1
+    const double *map[3];                  // RING order, 12 nside^2 each
+    double2 *F;                            // [nfields][mmax + 1][nrings]: weighted ring Fourier sums
+    double *alm[3];                        // complex interleaved, m-major: T, E, B
+};
+
+struct ClArgs {
+    int lmax, nspec;                       // up to 6 spectra
+    const double *x[6], *y[6];             // complex interleaved a_lm of each pair
+    double *cl;                            // [nspec][lmax + 1]
+};
+
+hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s);
+hipError_t launch_alm(const ShtArgs &a, hipStream_t s);
+hipError_t launch_alm2cl(const ClArgs &a, hipStream_t s);
+
+}  // namespace pisco

@@ -1,0 +1,380 @@
+// Spherical-harmonic analysis of HEALPix I, Q, U maps and their angular power
+// spectra, in FP64: the spectrum estimator the paper applies to maps made from
+// the TOD (Sec. 6.2).  Definitions (orthonormal Y_lm with the Condon-Shortley
+// phase; spin-2 harmonics of Goldberg et al. 1967; E and B as in Zaldarriaga &
+// Seljak 1997 with the HEALPix sign convention) are stated in include/pisco.h.
+//
+// Three kernels:
+//   ring_fourier_kernel  one workgroup per ring: F_r(m) = w sum_j x_j e^{-i m phi_j}
+//                        for every field, by an FFT in LDS (direct DFT over the
+//                        odd factor of the ring length, then radix-2 Stockham
+//                        passes over its power-of-two factor), read at m mod n;
+//   alm_kernel           one workgroup per m: lanes own north/south ring pairs,
+//                        run the recurrence for lambda_lm in l (mantissa plus a
+//                        carried power-of-two exponent, so sin^m theta cannot
+//                        underflow), form W_lm and X_lm from lambda_l and
+//                        lambda_{l-1}, and accumulate the symmetric and
+//                        antisymmetric ring-pair sums; every four l the
+//                        workgroup sums its lanes through LDS;
+//   alm2cl_kernel        one thread per l: C_l of up to six a_lm pairs.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sht_internal.h"
+
+namespace pisco {
+namespace {
+
+constexpr int SCALE = 256;               // exponent step of the carried recurrence
+constexpr int ALM_THREADS = 512;
+constexpr int ALM_WAVES = ALM_THREADS / 64;
+constexpr int LBLOCK = 4;                // l values per LDS reduction
+constexpr int NCOMP = 6;                 // a^T, a^E, a^B (re, im)
+constexpr int LCHUNK = 64;               // l values per coefficient table
+
+struct RingGeom {
+    int64_t first;
+    int n;
+    double z, s, phi0_over_pi;
+};
+
+// Ring i = r + 1 of the RING scheme (Gorski et al. 2005, Sec. 4): colatitude
+// from exact integer ratios, first pixel and its longitude / pi.
+__device__ inline RingGeom sht_ring(int N, int r) {
+    const int i = r + 1;
+    RingGeom g;
+    const double n3 = 3.0 * (double)N * (double)N;
+    if (i < N || i > 3 * N) {
+        const int k = i < N ? i : 4 * N - i;
+        const double t = (double)k * (double)k / n3;      // 1 - |z|
+        g.n = 4 * k;
+        g.first = i < N ? 2LL * k * (k - 1) : 12LL * N * N - 2LL * k * (k + 1);
+        g.z = i < N ? 1.0 - t : t - 1.0;
+        g.s = sqrt(t * (2.0 - t));
+        g.phi0_over_pi = 0.25 / (double)k;
+    } else {
+        g.n = 4 * N;
+        g.first = 2LL * N * (N - 1) + (int64_t)(i - N) * 4 * N;
+        g.z = (double)(4 * N - 2 * i) / (3.0 * N);
+        g.s = sqrt((double)(2 * i - N) * (double)(7 * N - 2 * i)) / (3.0 * N);
+        g.phi0_over_pi = ((i - N) & 1) == 0 ? 0.25 / (double)N : 0.0;
+    }
+    return g;
+}
+
+__global__ void __launch_bounds__(256) ring_fourier_kernel(ShtArgs a) {
+    extern __shared__ double2 sh_ring[];
+    const int r = blockIdx.x;
+    const RingGeom g = sht_ring(a.nside, r);
+    const int n = g.n;
+    const int P = n & -n;                // power-of-two factor
+    const int q = n / P;                 // odd factor
+    double2 *bufA = sh_ring;
+    double2 *bufB = sh_ring + n;
+    double *xs = reinterpret_cast<double *>(bufB);
+    const double w = 4.0 * M_PI / (12.0 * (double)a.nside * (double)a.nside);
+    for (int f = 0; f < a.nfields; ++f) {
+        const double *x = a.map[f] + g.first;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) xs[j] = x[j];
+        __syncthreads();
+        // P DFTs of length q over the stride-P subsequences x[P j2 + j1]
+        for (int it = threadIdx.x; it < n; it += blockDim.x) {
+            const int j1 = it / q, k2 = it - j1 * q;
+            double re = 0.0, im = 0.0;
+            if (q == 1) {
+                re = xs[j1];
+            } else {
+                double ss, cs;
+                sincospi(2.0 * (double)k2 / (double)q, &ss, &cs);   // step e^{-2 pi i k2 / q}
+                double wr = 1.0, wi = 0.0;
+                int idx = 0;                                          // j2 k2 mod q
+                for (int j2 = 0; j2 < q; ++j2) {
+                    if ((j2 & 15) == 0) {                             // exact twiddle every 16 steps
+                        double s0, c0;
+                        sincospi(2.0 * (double)idx / (double)q, &s0, &c0);
+                        wr = c0;
+                        wi = -s0;
+                    }
+                    const double xv = xs[P * j2 + j1];
+                    re = fma(xv, wr, re);
+                    im = fma(xv, wi, im);
+                    const double nr = fma(wr, cs, wi * ss);
+                    const double ni = fma(wi, cs, -wr * ss);
+                    wr = nr;
+                    wi = ni;
+                    idx += k2;
+                    if (idx >= q) idx -= q;
+                }
+            }
+            bufA[it] = make_double2(re, im);
+        }
+        __syncthreads();
+        // radix-2 passes: sequences c and c + Ps/2 (offsets of stride Ps) merge into
+        // sequence c of stride Ps/2 and twice the length
+        double2 *src = bufA, *dst = bufB;
+        int L = q;
+        for (int Ps = P; Ps > 1; Ps >>= 1) {
+            const int half = Ps >> 1;
+            for (int it = threadIdx.x; it < half * L; it += blockDim.x) {
+                const int c = it / L, k = it - c * L;
+                const double2 E = src[c * L + k];
+                const double2 O = src[(c + half) * L + k];
+                double sn, cs;
+                sincospi((double)k / (double)L, &sn, &cs);          // e^{-i pi k / L}
+                const double tr = fma(O.x, cs, O.y * sn);
+                const double ti = fma(O.y, cs, -O.x * sn);
+                dst[c * 2 * L + k] = make_double2(E.x + tr, E.y + ti);
+                dst[c * 2 * L + k + L] = make_double2(E.x - tr, E.y - ti);
+            }
+            __syncthreads();
+            double2 *t = src;
+            src = dst;
+            dst = t;
+            L <<= 1;
+        }
+        double2 *out = a.F + (size_t)f * (a.mmax + 1) * a.nrings + r;
+        for (int m = threadIdx.x; m <= a.mmax; m += blockDim.x) {
+            const double2 X = src[m % n];
+            double sn, cs;
+            sincospi((double)m * g.phi0_over_pi, &sn, &cs);        // e^{-i m phi0}
+            out[(size_t)m * a.nrings] = make_double2(w * fma(X.x, cs, X.y * sn), w * fma(X.y, cs, -X.x * sn));
+        }
+        __syncthreads();
+    }
+}
+
+struct Coef {
+    double ra, rb;           // lambda_l = ra (z lambda_{l-1} - rb lambda_{l-2})
+    double A, B, C, D;       // n_l (l - m^2), n_l l (l - 1) / 2, n_l (l + m) c_lm, n_l (l - 1)
+};
+
+__device__ inline Coef make_coef(int l, int m) {
+    Coef c{};
+    const double dl = l, dm = m;
+    if (l == m + 1) c.ra = sqrt(2.0 * dm + 3.0);
+    if (l >= m + 2) {
+        c.ra = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
+        c.rb = sqrt(((dl - 1.0) * (dl - 1.0) - dm * dm) / (4.0 * (dl - 1.0) * (dl - 1.0) - 1.0));
+    }
+    if (l >= 2) {
+        const double nl = 2.0 / sqrt((dl - 1.0) * dl * (dl + 1.0) * (dl + 2.0));
+        const double clm = l > m ? sqrt((2.0 * dl + 1.0) * (dl - dm) / ((2.0 * dl - 1.0) * (dl + dm))) : 0.0;
+        c.A = nl * (dl - dm * dm);
+        c.B = nl * dl * (dl - 1.0) * 0.5;
+        c.C = nl * (dl + dm) * clm;
+        c.D = nl * (dl - 1.0);
+    }
+    return c;
+}
+
+struct PairState {
+    double2 Tp, Tm, Qp, Qm, Up, Um;   // F_north +- F_south
+    double z, inv_s2, z_s2, m_s2;
+    double v, vp;                      // lambda_l, lambda_{l-1} in units of 2^(SCALE e)
+    int e;
+};
+
+// lambda_mm = (-1)^m c_m s^m, split into a mantissa and a multiple of SCALE in the exponent
+__device__ inline void start_value(double s, int m, double cm, double *v, int *e) {
+    int es;
+    const double fs = frexp(s, &es);
+    double base = fs, res = 1.0;
+    long long be = 0, re = 0;
+    for (int k = m; k; k >>= 1) {
+        int t;
+        if (k & 1) {
+            res = frexp(res * base, &t);
+            re += be + t;
+        }
+        base = frexp(base * base, &t);
+        be = 2 * be + t;
+    }
+    const long long E = re + (long long)es * m;
+    long long q = E / SCALE;
+    if (q * SCALE > E) --q;                       // floor
+    *e = (int)q;
+    *v = ((m & 1) ? -cm : cm) * ldexp(res, (int)(E - q * SCALE));
+}
+
+template <int P, bool POL>
+__device__ inline void pair_terms(PairState &p, const Coef &c, int m, double *acc) {
+    const double f = p.e == 0 ? 1.0 : (p.e == -1 ? 0x1p-256 : 0.0);
+    const double L = f * p.v;
+    const double2 FT = P ? p.Tm : p.Tp;
+    acc[0] = fma(L, FT.x, acc[0]);
+    acc[1] = fma(L, FT.y, acc[1]);
+    if (POL) {
+        const double Lp = f * p.vp;
+        // W = -(A / s^2 + B) lambda_l + C (z / s^2) lambda_{l-1};  X = (m / s^2)(C lambda_{l-1} - D z lambda_l)
+        const double W = fma(-fma(c.A, p.inv_s2, c.B), L, c.C * p.z_s2 * Lp);
+        const double X = p.m_s2 * fma(c.C, Lp, -c.D * p.z * L);
+        const double2 Qa = P ? p.Qm : p.Qp, Ua = P ? p.Um : p.Up;    // parity of lambda and W
+        const double2 Qb = P ? p.Qp : p.Qm, Ub = P ? p.Up : p.Um;    // parity of X
+        acc[2] -= fma(W, Qa.x, -X * Ub.y);
+        acc[3] -= fma(W, Qa.y, X * Ub.x);
+        acc[4] -= fma(W, Ua.x, X * Qb.y);
+        acc[5] -= fma(W, Ua.y, -X * Qb.x);
+    }
+}
+
+__device__ inline void advance(PairState &p, const Coef &c) {
+    const double vn = c.ra * fma(p.z, p.v, -c.rb * p.vp);
+    p.vp = p.v;
+    p.v = vn;
+    if (fabs(vn) > 0x1p256) {
+        p.v *= 0x1p-256;
+        p.vp *= 0x1p-256;
+        p.e += 1;
+    }
+}
+
+template <bool POL>
+__global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
+    extern __shared__ double sh_alm[];
+    double *red = sh_alm;                                            // [waves][LBLOCK * NCOMP][64]
+    Coef *coef = reinterpret_cast<Coef *>(sh_alm + ALM_WAVES * LBLOCK * NCOMP * 64);   // [LCHUNK]
+    const int m = blockIdx.x;
+    const int N = a.nside, lmax = a.lmax;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int npairs = 2 * N;
+    const int kcount = (npairs + ALM_THREADS - 1) / ALM_THREADS;
+
+    // c_m = sqrt((4 pi)^-1 prod_{k=1..m} (2k + 1) / (2k)): partial products per lane, then across the wave
+    double pr = 1.0;
+    for (int k = lane + 1; k <= m; k += 64) pr *= (2.0 * k + 1.0) / (2.0 * k);
+    for (int o = 32; o; o >>= 1) pr *= __shfl_xor(pr, o, 64);
+    const double cm = sqrt(pr / (4.0 * M_PI));
+
+    PairState ps[SHT_PAIRS_PER_LANE];
+#pragma unroll
+    for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
+        PairState &p = ps[k];
+        const int pi = tid + k * ALM_THREADS;
+        const bool ok = k < kcount && pi < npairs;
+        const int rn = ok ? pi : 0;
+        const int rs = a.nrings - 1 - rn;                            // mirror ring; rs == rn on the equator
+        const RingGeom g = sht_ring(N, rn);
+        double2 fn[3] = {}, fs[3] = {};
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (ok && f < a.nfields) {
+                const double2 *F = a.F + ((size_t)f * (a.mmax + 1) + m) * a.nrings;
+                fn[f] = F[rn];
+                if (rs != rn) fs[f] = F[rs];
+            }
+        }
+        p.Tp = make_double2(fn[0].x + fs[0].x, fn[0].y + fs[0].y);
+        p.Tm = make_double2(fn[0].x - fs[0].x, fn[0].y - fs[0].y);
+        p.Qp = make_double2(fn[1].x + fs[1].x, fn[1].y + fs[1].y);
+        p.Qm = make_double2(fn[1].x - fs[1].x, fn[1].y - fs[1].y);
+        p.Up = make_double2(fn[2].x + fs[2].x, fn[2].y + fs[2].y);
+        p.Um = make_double2(fn[2].x - fs[2].x, fn[2].y - fs[2].y);
+        p.z = g.z;
+        p.inv_s2 = 1.0 / (g.s * g.s);
+        p.z_s2 = g.z * p.inv_s2;
+        p.m_s2 = (double)m * p.inv_s2;
+        start_value(g.s, m, cm, &p.v, &p.e);
+        p.vp = 0.0;
+        if (!ok) p.e = -1000000;                                     // never contributes
+    }
+
+    const int nl = lmax - m + 1;
+    for (int c0 = 0; c0 < nl; c0 += LCHUNK) {
+        __syncthreads();
+        if (tid < LCHUNK && c0 + tid < nl) coef[tid] = make_coef(m + c0 + tid, m);
+        __syncthreads();
+        const int cend = min(nl, c0 + LCHUNK);
+        for (int b0 = c0; b0 < cend; b0 += LBLOCK) {
+            double acc[LBLOCK][NCOMP];
+#pragma unroll
+            for (int j = 0; j < LBLOCK; ++j) {
+#pragma unroll
+                for (int t = 0; t < NCOMP; ++t) acc[j][t] = 0.0;
+                const int li = b0 + j;                               // l - m; even = same parity as m
+                if (li < cend) {
+                    const Coef c = coef[li - c0];
+#pragma unroll
+                    for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
+                        if (k >= kcount) continue;
+                        if (li > 0) advance(ps[k], c);
+                        if (__ballot(ps[k].e >= -1) == 0) continue;   // whole wave below 2^-256
+                        if (j & 1)
+                            pair_terms<1, POL>(ps[k], c, m, acc[j]);
+                        else
+                            pair_terms<0, POL>(ps[k], c, m, acc[j]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < LBLOCK; ++j)
+#pragma unroll
+                for (int t = 0; t < NCOMP; ++t) red[((wave * LBLOCK + j) * NCOMP + t) * 64 + lane] = acc[j][t];
+            __syncthreads();
+            // 24 sums over 8 waves x 64 lanes: 16 threads per sum, 32 entries each, then a shuffle tree
+            if (tid < LBLOCK * NCOMP * 16) {
+                const int o = tid >> 4, g = tid & 15;
+                double s = 0.0;
+#pragma unroll
+                for (int w = 0; w < ALM_WAVES; ++w)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) s += red[((w * LBLOCK * NCOMP) + o) * 64 + g * 4 + u];
+                for (int x = 8; x; x >>= 1) s += __shfl_xor(s, x, 16);
+                const int j = o / NCOMP, t = o - j * NCOMP;
+                const int l = m + b0 + j;
+                if (g == 0 && b0 + j < cend) {
+                    const int64_t idx = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
+                    double *dst = a.alm[t >> 1];
+                    if (dst) dst[2 * idx + (t & 1)] = s;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) alm2cl_kernel(ClArgs a) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l > a.lmax) return;
+    for (int sp = 0; sp < a.nspec; ++sp) {
+        double acc = 0.0;
+        for (int m = 0; m <= l; ++m) {
+            const int64_t idx = (int64_t)m * (2 * a.lmax + 1 - m) / 2 + l;
+            const double2 x = reinterpret_cast<const double2 *>(a.x[sp])[idx];
+            const double2 y = reinterpret_cast<const double2 *>(a.y[sp])[idx];
+            const double p = fma(x.x, y.x, x.y * y.y);
+            acc += m == 0 ? p : 2.0 * p;
+        }
+        a.cl[(size_t)sp * (a.lmax + 1) + l] = acc / (2.0 * l + 1.0);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) {
+    const size_t lds = 2 * (size_t)(4 * a.nside) * sizeof(double2);
+    hipError_t e = hipFuncSetAttribute((const void *)ring_fourier_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ring_fourier_kernel, dim3(a.nrings), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_alm(const ShtArgs &a, hipStream_t s) {
+    const size_t lds = (size_t)ALM_WAVES * LBLOCK * NCOMP * 64 * sizeof(double) + LCHUNK * sizeof(Coef);
+    const void *k = a.nfields == 3 ? (const void *)alm_kernel<true> : (const void *)alm_kernel<false>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.nfields == 3)
+        hipLaunchKernelGGL(alm_kernel<true>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
+    else
+        hipLaunchKernelGGL(alm_kernel<false>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_alm2cl(const ClArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(alm2cl_kernel, dim3((a.lmax + 256) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace pisco

@@ -63,3 +63,18 @@ def test_no_cpu_fallback_in_product_path():
     for p in glob.glob(os.path.join(ROOT, "paper_1908_05662_amd", "**", "*.py"), recursive=True):
         src = open(p).read()
         assert "import oracle" not in src and "from oracle" not in src, p
+
+
+def test_spectra_host_logic():
+    from paper_1908_05662_amd import _lib
+
+    lib = _lib.load()
+    assert lib.pisco_alm_size(10) == 66 and lib.pisco_alm_size(0) == 1 and lib.pisco_alm_size(-1) == 0
+    assert lib.pisco_map2alm_workspace_bytes(64, 191, 1) == 3 * 192 * 255 * 16
+    assert lib.pisco_map2alm_workspace_bytes(64, 191, 0) == 192 * 255 * 16
+    assert lib.pisco_map2alm_workspace_bytes(48, 10, 1) == -1       # not a power of two
+    assert lib.pisco_map2alm_workspace_bytes(2048, 10, 1) == -1     # above the largest nside
+    assert lib.pisco_map2alm_workspace_bytes(8, 33, 1) == -1        # lmax above 4 nside
+    assert lib.pisco_map2alm(None, 8, 10, None, None, None, None, None, None, None, 0, None) == _lib.EINVAL
+    assert lib.pisco_anafast(None, 8, 10, None, None, None, None, None, None, None, 0, None, None) == _lib.EINVAL
+    assert lib.pisco_alm2cl(None, 10, None, None, None, None) == _lib.EINVAL
