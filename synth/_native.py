@@ -27,5 +27,7 @@ def lib():
         dp = ctypes.POINTER(ctypes.c_double)
         h.synth_ring_coeffs.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, dp, dp, dp, dp, dp, dp]
         h.synth_ring_coeffs.restype = None
+        h.synth_ring_coeffs_spin2.argtypes = [ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp, dp] + [dp] * 8
+        h.synth_ring_coeffs_spin2.restype = None
         _handle = h
     return _handle

@@ -90,3 +90,78 @@ void synth_ring_coeffs(int lmax, const double *alm_re, const double *alm_im,
     }
     free(A); free(B);
 }
+
+/*
+ * Spin-2 counterpart for the Q and U maps of an (E, B) expansion, in the
+ * convention of Zaldarriaga & Seljak (1997) with the HEALPix signs: with the
+ * spin-2 harmonics of Goldberg et al. (1967) written _{+-2}Y_lm =
+ * (W_lm +- X_lm) e^{i m phi},
+ *     Q = -sum_{l,m} (aE_lm W_lm + i aB_lm X_lm) e^{i m phi},
+ *     U = -sum_{l,m} (aB_lm W_lm - i aE_lm X_lm) e^{i m phi}.
+ * W and X follow from lambda_lm and lambda_{l-1,m} (Kamionkowski, Kosowsky &
+ * Stebbins 1997):
+ *     W = n_l [-((l - m^2)/s^2 + l(l-1)/2) lambda_l + (l+m) c_lm (z/s^2) lambda_{l-1}]
+ *     X = n_l (m/s^2) [-(l-1) z lambda_l + (l+m) c_lm lambda_{l-1}]
+ * with n_l = 2 / sqrt((l-1) l (l+1) (l+2)), c_lm = sqrt((2l+1)(l-m)/((2l-1)(l+m))).
+ * Under z -> -z, W has the parity (-1)^(l+m) of lambda_lm and X the opposite.
+ * Outputs as in synth_ring_coeffs, for Q and U.
+ */
+void synth_ring_coeffs_spin2(int lmax, const double *e_re, const double *e_im, const double *b_re,
+                             const double *b_im, int npair, const double *z, const double *sth,
+                             double *QN_re, double *QN_im, double *UN_re, double *UN_im,
+                             double *QS_re, double *QS_im, double *US_re, double *US_im) {
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int r = 0; r < npair; ++r) {
+        const double x = z[r], s = sth[r];
+        const double is2 = 1.0 / (s * s);
+        double vmm = 1.0 / sqrt(4.0 * M_PI);
+        int emm = 0;
+        for (int m = 0; m <= lmax; ++m) {
+            if (m > 0) {
+                vmm *= -sqrt((2.0 * m + 1.0) / (2.0 * m)) * s;
+                while (fabs(vmm) < SC_SMALL && vmm != 0.0) { vmm *= SC_BIG; emm -= 1; }
+            }
+            /* [0] = (l+m) even, [1] = odd; W-terms and X-terms kept apart for the mirror ring */
+            double qw_r[2] = {0, 0}, qw_i[2] = {0, 0}, qx_r[2] = {0, 0}, qx_i[2] = {0, 0};
+            double uw_r[2] = {0, 0}, uw_i[2] = {0, 0}, ux_r[2] = {0, 0}, ux_i[2] = {0, 0};
+            double lam_prev = 0.0, lam = vmm;
+            int e = emm;
+            for (int l = m; l <= lmax; ++l) {
+                if (l == m + 1) {
+                    lam_prev = lam;
+                    lam = sqrt(2.0 * m + 3.0) * x * lam;
+                } else if (l > m + 1) {
+                    const double a = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+                    const double b = sqrt(((l - 1.0) * (l - 1.0) - (double)m * m) / (4.0 * (l - 1.0) * (l - 1.0) - 1.0));
+                    const double nxt = a * (x * lam - b * lam_prev);
+                    lam_prev = lam;
+                    lam = nxt;
+                }
+                if (e < 0 && fabs(lam) > SC_BIG) { lam *= SC_SMALL; lam_prev *= SC_SMALL; e += 1; }
+                if (l < 2 || e < -1) continue;
+                const double f = (e == 0) ? 1.0 : SC_SMALL;
+                const double L = lam * f, Lp = lam_prev * f;
+                const double c = (l > m) ? sqrt((2.0 * l + 1.0) * (l - m) / ((2.0 * l - 1.0) * (l + m))) : 0.0;
+                const double nl = 2.0 / sqrt((l - 1.0) * l * (l + 1.0) * (l + 2.0));
+                const double W = nl * (-((l - (double)m * m) * is2 + 0.5 * l * (l - 1.0)) * L + (l + m) * c * x * is2 * Lp);
+                const double X = nl * m * is2 * (-(l - 1.0) * x * L + (l + m) * c * Lp);
+                const int64_t k = alm_index(lmax, l, m);
+                const int par = (l + m) & 1;
+                qw_r[par] += e_re[k] * W;  qw_i[par] += e_im[k] * W;     /* aE W    */
+                qx_r[par] -= b_im[k] * X;  qx_i[par] += b_re[k] * X;     /* i aB X  */
+                uw_r[par] += b_re[k] * W;  uw_i[par] += b_im[k] * W;     /* aB W    */
+                ux_r[par] += e_im[k] * X;  ux_i[par] -= e_re[k] * X;     /* -i aE X */
+            }
+            const int64_t o = (int64_t)r * (lmax + 1) + m;
+            /* north: all terms; south: W-terms with (-1)^(l+m), X-terms with -(-1)^(l+m) */
+            QN_re[o] = -(qw_r[0] + qw_r[1] + qx_r[0] + qx_r[1]);
+            QN_im[o] = -(qw_i[0] + qw_i[1] + qx_i[0] + qx_i[1]);
+            UN_re[o] = -(uw_r[0] + uw_r[1] + ux_r[0] + ux_r[1]);
+            UN_im[o] = -(uw_i[0] + uw_i[1] + ux_i[0] + ux_i[1]);
+            QS_re[o] = -(qw_r[0] - qw_r[1] - qx_r[0] + qx_r[1]);
+            QS_im[o] = -(qw_i[0] - qw_i[1] - qx_i[0] + qx_i[1]);
+            US_re[o] = -(uw_r[0] - uw_r[1] - ux_r[0] + ux_r[1]);
+            US_im[o] = -(uw_i[0] - uw_i[1] - ux_i[0] + ux_i[1]);
+        }
+    }
+}
