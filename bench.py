@@ -345,10 +345,52 @@ def map_leg(w, keep, out, stream, torch, nside_map=1024, reps=3):
     good = int((rc >= 1e-3).sum().item())
     nbytes = 28.0 * n + 80.0 * npix + 160.0 * hit + 80.0 * npix + 32.0 * npix
     log(f"maps: {t * 1e3:.2f} ms for {n} samples into nside {nside_map} ({hit} pixels hit, {good} solved for I, Q, U)")
+    keep["maps"] = maps
     return {"workload": f"the benchmark TOD ({len(w.detectors)} detectors) binned into nside-{nside_map} I, Q, U maps",
             "ms": t * 1e3, "samples_per_s": n / t, "pixels_hit": hit, "pixels_iqu": good,
             "hbm_bytes": nbytes, "achieved_gbs": nbytes / t / 1e9, "peak_gbs": HBM_PEAK_GBS,
             "frac": nbytes / t / 1e9 / HBM_PEAK_GBS}
+
+
+SHT_FLOPS_PER_ITEM = 33   # per (l, m, ring pair): recurrence 4; lambda scaling 2; T 4; W 6, X 5; E 6, B 6
+
+
+def spectra_leg(conv, maps, torch, lmax=3071, reps=5):
+    """Spectra of the map leg's nside-1024 I, Q, U maps (the validation step the
+    maps go through): harmonic analysis to lmax 3071 and the six spectra, FP64,
+    HIP events on the current stream.  `dense_tflops` counts 33 flops for every
+    (l, m, ring pair) of the triangle, including the polar pairs the kernel skips
+    while lambda_lm is below 2^-256 (so it is an equivalent rate, not the
+    executed one); the executed FP64 rate is in the kernel profile."""
+    from paper_1908_05662_amd.api import Spectra
+
+    nside = int(round(np.sqrt(maps.shape[1] / 12)))
+    sp = Spectra(conv, nside, lmax)
+    T, Q, U = maps[0], maps[1], maps[2]
+    sp.anafast(T, Q, U)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps / 1e3
+
+    t_alm = timed(lambda: sp.map2alm(T, Q, U))
+    t_all = timed(lambda: sp.anafast(T, Q, U))
+    cl = sp.anafast(T, Q, U).cpu().numpy()
+    items = sum((lmax - m + 1) * 2 * nside for m in range(lmax + 1))
+    dense = SHT_FLOPS_PER_ITEM * items / t_alm / 1e12
+    log(f"spectra: nside {nside} lmax {lmax}: map2alm {t_alm * 1e3:.2f} ms, anafast {t_all * 1e3:.2f} ms "
+        f"({dense:.1f} TFLOP/s dense-equivalent)")
+    return {"workload": f"the map leg's nside-{nside} I, Q, U maps: harmonic analysis to lmax {lmax} and the six "
+                        "spectra TT, EE, BB, TE, EB, TB (FP64)",
+            "ms_map2alm": t_alm * 1e3, "ms_anafast": t_all * 1e3, "items": items,
+            "flops_per_item": SHT_FLOPS_PER_ITEM, "dense_tflops": dense, "peak_tflops_fp64": ALU_PEAK_TFLOPS,
+            "dense_frac": dense / ALU_PEAK_TFLOPS, "finite": bool(np.all(np.isfinite(cl)))}
 
 
 def full_scale_leg(epochs, n_train, width, hidden, lr):
@@ -516,7 +558,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the far-sidelobe surrogate leg")
     ap.add_argument("--no-paper-shape", action="store_true", help="skip the paper's benchmark-pattern leg")
     ap.add_argument("--no-plate", action="store_true", help="skip the half-wave-plate leg")
-    ap.add_argument("--no-maps", action="store_true", help="skip the map-making leg")
+    ap.add_argument("--no-maps", action="store_true", help="skip the map-making leg (and the spectra leg)")
+    ap.add_argument("--no-spectra", action="store_true", help="skip the power-spectrum leg")
     ap.add_argument("--full-scale", action="store_true",
                     help="also run the nside-2048, 1e8-sample surrogate-vs-exact leg (about 3 minutes)")
     ap.add_argument("--full-scale-train", type=int, default=6_000_000)
@@ -614,12 +657,16 @@ def main():
     plate = None
     if not args.no_plate:
         plate = plate_leg(conv, w, stream, out, args.steps, args.warmup, k_ms, torch)
-    maps = None
+    maps = spectra = None
     if not args.no_maps:
         with torch.cuda.stream(stream):
             conv.convolve(-1, OUT_TOD, out=out, stream=stream)
         stream.synchronize()
-        maps = map_leg(w, {"conv": conv, "pointing": keep}, out, stream, torch)
+        mk = {"conv": conv, "pointing": keep}
+        maps = map_leg(w, mk, out, stream, torch)
+        if not args.no_spectra:
+            spectra = spectra_leg(conv, mk["maps"], torch)
+        del mk
 
     rec = {
         "metric": "TOD samples/s + beam-pixel MACs/s at nside 1024; surrogate vs exact at fixed error",
@@ -649,6 +696,7 @@ def main():
         "parity_max_rel_err": parity,
         "plate": plate,
         "maps": maps,
+        "spectra": spectra,
     }
     conv.close()
     del keep, out

@@ -63,9 +63,16 @@ __device__ inline RingGeom sht_ring(int N, int r) {
     return g;
 }
 
-__global__ void __launch_bounds__(256) ring_fourier_kernel(ShtArgs a) {
+// Rings [r0, r1) and [r2, r3): one launch per ring-length class, so that the
+// LDS each workgroup reserves matches the longest ring of its class.
+struct RingRange {
+    int r0, r1, r2, r3;
+};
+
+__global__ void __launch_bounds__(256) ring_fourier_kernel(ShtArgs a, RingRange rr) {
     extern __shared__ double2 sh_ring[];
-    const int r = blockIdx.x;
+    const int b = blockIdx.x;
+    const int r = b < rr.r1 - rr.r0 ? rr.r0 + b : rr.r2 + (b - (rr.r1 - rr.r0));
     const RingGeom g = sht_ring(a.nside, r);
     const int n = g.n;
     const int P = n & -n;                // power-of-two factor
@@ -78,36 +85,54 @@ __global__ void __launch_bounds__(256) ring_fourier_kernel(ShtArgs a) {
         const double *x = a.map[f] + g.first;
         for (int j = threadIdx.x; j < n; j += blockDim.x) xs[j] = x[j];
         __syncthreads();
-        // P DFTs of length q over the stride-P subsequences x[P j2 + j1]
-        for (int it = threadIdx.x; it < n; it += blockDim.x) {
-            const int j1 = it / q, k2 = it - j1 * q;
+        // P DFTs of length q over the stride-P subsequences x[P j2 + j1]; the input is
+        // real, so Y[q - k2] = conj Y[k2] and only k2 <= (q - 1) / 2 is summed
+        const int h = (q + 1) / 2;
+        for (int it = threadIdx.x; it < P * h; it += blockDim.x) {
+            const int j1 = it / h, k2 = it - j1 * h;
             double re = 0.0, im = 0.0;
             if (q == 1) {
                 re = xs[j1];
             } else {
+                // four interleaved chains (j2 = c mod 4), each turning its twiddle by
+                // e^{-2 pi i 4 k2 / q} and re-seeded exactly every 16 of its steps
+                int k4 = (4 * k2) % q;
                 double ss, cs;
-                sincospi(2.0 * (double)k2 / (double)q, &ss, &cs);   // step e^{-2 pi i k2 / q}
-                double wr = 1.0, wi = 0.0;
-                int idx = 0;                                          // j2 k2 mod q
-                for (int j2 = 0; j2 < q; ++j2) {
-                    if ((j2 & 15) == 0) {                             // exact twiddle every 16 steps
-                        double s0, c0;
-                        sincospi(2.0 * (double)idx / (double)q, &s0, &c0);
-                        wr = c0;
-                        wi = -s0;
+                sincospi(2.0 * (double)k4 / (double)q, &ss, &cs);
+                double wr[4], wi[4], ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+                int idx[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) idx[c] = (c * k2) % q;
+                for (int j0 = 0; j0 < q; j0 += 4) {
+                    if ((j0 & 63) == 0) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            double s0, c0;
+                            sincospi(2.0 * (double)idx[c] / (double)q, &s0, &c0);
+                            wr[c] = c0;
+                            wi[c] = -s0;
+                        }
                     }
-                    const double xv = xs[P * j2 + j1];
-                    re = fma(xv, wr, re);
-                    im = fma(xv, wi, im);
-                    const double nr = fma(wr, cs, wi * ss);
-                    const double ni = fma(wi, cs, -wr * ss);
-                    wr = nr;
-                    wi = ni;
-                    idx += k2;
-                    if (idx >= q) idx -= q;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (j0 + c < q) {
+                            const double xv = xs[P * (j0 + c) + j1];
+                            ar[c] = fma(xv, wr[c], ar[c]);
+                            ai[c] = fma(xv, wi[c], ai[c]);
+                        }
+                        const double nr = fma(wr[c], cs, wi[c] * ss);
+                        const double ni = fma(wi[c], cs, -wr[c] * ss);
+                        wr[c] = nr;
+                        wi[c] = ni;
+                        idx[c] += k4;
+                        if (idx[c] >= q) idx[c] -= q;
+                    }
                 }
+                re = (ar[0] + ar[1]) + (ar[2] + ar[3]);
+                im = (ai[0] + ai[1]) + (ai[2] + ai[3]);
             }
-            bufA[it] = make_double2(re, im);
+            bufA[j1 * q + k2] = make_double2(re, im);
+            if (k2 > 0) bufA[j1 * q + q - k2] = make_double2(re, -im);
         }
         __syncthreads();
         // radix-2 passes: sequences c and c + Ps/2 (offsets of stride Ps) merge into
@@ -197,32 +222,39 @@ __device__ inline void start_value(double s, int m, double cm, double *v, int *e
     *v = ((m & 1) ? -cm : cm) * ldexp(res, (int)(E - q * SCALE));
 }
 
-template <int P, bool POL>
-__device__ inline void pair_terms(PairState &p, const Coef &c, int m, double *acc) {
-    const double f = p.e == 0 ? 1.0 : (p.e == -1 ? 0x1p-256 : 0.0);
-    const double L = f * p.v;
+// Adds lambda_l F_T, W F_Q + i X F_U and W F_U - i X F_Q (the last two are
+// -a^E and -a^B; the sign is applied when the sums are stored).  SCALED: the
+// lane's values may still carry a power-of-two exponent (e < 0).
+template <int P, bool POL, bool SCALED>
+__device__ inline void pair_terms(const PairState &p, const Coef &c, double *acc) {
+    double L = p.v, Lp = p.vp;
+    if (SCALED) {
+        const double f = p.e == 0 ? 1.0 : (p.e == -1 ? 0x1p-256 : 0.0);
+        L *= f;
+        Lp *= f;
+    }
     const double2 FT = P ? p.Tm : p.Tp;
     acc[0] = fma(L, FT.x, acc[0]);
     acc[1] = fma(L, FT.y, acc[1]);
     if (POL) {
-        const double Lp = f * p.vp;
         // W = -(A / s^2 + B) lambda_l + C (z / s^2) lambda_{l-1};  X = (m / s^2)(C lambda_{l-1} - D z lambda_l)
         const double W = fma(-fma(c.A, p.inv_s2, c.B), L, c.C * p.z_s2 * Lp);
         const double X = p.m_s2 * fma(c.C, Lp, -c.D * p.z * L);
         const double2 Qa = P ? p.Qm : p.Qp, Ua = P ? p.Um : p.Up;    // parity of lambda and W
         const double2 Qb = P ? p.Qp : p.Qm, Ub = P ? p.Up : p.Um;    // parity of X
-        acc[2] -= fma(W, Qa.x, -X * Ub.y);
-        acc[3] -= fma(W, Qa.y, X * Ub.x);
-        acc[4] -= fma(W, Ua.x, X * Qb.y);
-        acc[5] -= fma(W, Ua.y, -X * Qb.x);
+        acc[2] += fma(W, Qa.x, -X * Ub.y);          // one dependent add per pair on each sum
+        acc[3] += fma(W, Qa.y, X * Ub.x);
+        acc[4] += fma(W, Ua.x, X * Qb.y);
+        acc[5] += fma(W, Ua.y, -X * Qb.x);
     }
 }
 
+template <bool SCALED>
 __device__ inline void advance(PairState &p, const Coef &c) {
     const double vn = c.ra * fma(p.z, p.v, -c.rb * p.vp);
     p.vp = p.v;
     p.v = vn;
-    if (fabs(vn) > 0x1p256) {
+    if (SCALED && fabs(vn) > 0x1p256) {
         p.v *= 0x1p-256;
         p.vp *= 0x1p-256;
         p.e += 1;
@@ -297,12 +329,22 @@ __global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
 #pragma unroll
                     for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
                         if (k >= kcount) continue;
-                        if (li > 0) advance(ps[k], c);
-                        if (__ballot(ps[k].e >= -1) == 0) continue;   // whole wave below 2^-256
-                        if (j & 1)
-                            pair_terms<1, POL>(ps[k], c, m, acc[j]);
-                        else
-                            pair_terms<0, POL>(ps[k], c, m, acc[j]);
+                        // once no lane of this band carries an exponent, its values stay
+                        // O(1) and the checks and scale factors drop out (wave-uniform)
+                        if (__ballot(ps[k].e != 0) == 0) {
+                            if (li > 0) advance<false>(ps[k], c);
+                            if (j & 1)
+                                pair_terms<1, POL, false>(ps[k], c, acc[j]);
+                            else
+                                pair_terms<0, POL, false>(ps[k], c, acc[j]);
+                        } else {
+                            if (li > 0) advance<true>(ps[k], c);
+                            if (__ballot(ps[k].e >= -1) == 0) continue;   // whole band below 2^-256
+                            if (j & 1)
+                                pair_terms<1, POL, true>(ps[k], c, acc[j]);
+                            else
+                                pair_terms<0, POL, true>(ps[k], c, acc[j]);
+                        }
                     }
                 }
             }
@@ -325,7 +367,7 @@ __global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
                 if (g == 0 && b0 + j < cend) {
                     const int64_t idx = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
                     double *dst = a.alm[t >> 1];
-                    if (dst) dst[2 * idx + (t & 1)] = s;
+                    if (dst) dst[2 * idx + (t & 1)] = t < 2 ? s : -s;
                 }
             }
             __syncthreads();
@@ -333,31 +375,55 @@ __global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
     }
 }
 
-__global__ void __launch_bounds__(256) alm2cl_kernel(ClArgs a) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l > a.lmax) return;
+// One wave per l: lanes take m = lane, lane + 64, ...; then a shuffle tree.
+__global__ void __launch_bounds__(64) alm2cl_kernel(ClArgs a) {
+    const int l = blockIdx.x;
+    const int lane = threadIdx.x;
     for (int sp = 0; sp < a.nspec; ++sp) {
         double acc = 0.0;
-        for (int m = 0; m <= l; ++m) {
+        for (int m = lane; m <= l; m += 64) {
             const int64_t idx = (int64_t)m * (2 * a.lmax + 1 - m) / 2 + l;
             const double2 x = reinterpret_cast<const double2 *>(a.x[sp])[idx];
             const double2 y = reinterpret_cast<const double2 *>(a.y[sp])[idx];
             const double p = fma(x.x, y.x, x.y * y.y);
             acc += m == 0 ? p : 2.0 * p;
         }
-        a.cl[(size_t)sp * (a.lmax + 1) + l] = acc / (2.0 * l + 1.0);
+        for (int o = 32; o; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) a.cl[(size_t)sp * (a.lmax + 1) + l] = acc / (2.0 * l + 1.0);
     }
 }
 
 }  // namespace
 
 hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) {
-    const size_t lds = 2 * (size_t)(4 * a.nside) * sizeof(double2);
+    const int N = a.nside;
     hipError_t e = hipFuncSetAttribute((const void *)ring_fourier_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
+                                       (int)(2 * (size_t)(4 * N) * sizeof(double2)));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(ring_fourier_kernel, dim3(a.nrings), dim3(256), lds, s, a);
-    return hipGetLastError();
+    // classes by cap ring index k (ring length 4k): k <= N/4, N/4 < k <= N/2, the rest
+    // (longer polar rings and the equatorial belt, length 4N)
+    const int c1 = N / 4, c2 = N / 2;
+    const int bounds[3] = {c1, c2, N};
+    int lo = 0;
+    for (int c = 0; c < 3; ++c) {
+        const int hi = bounds[c];
+        RingRange rr{};
+        if (c < 2) {       // north rings k = lo+1..hi and their southern mirrors
+            rr = RingRange{lo, hi, a.nrings - hi, a.nrings - lo};
+        } else {           // everything between
+            rr = RingRange{lo, a.nrings - lo, 0, 0};
+        }
+        const int nblocks = (rr.r1 - rr.r0) + (rr.r3 - rr.r2);
+        const int nmax = c < 2 ? 4 * hi : 4 * N;
+        if (nblocks > 0) {
+            hipLaunchKernelGGL(ring_fourier_kernel, dim3(nblocks), dim3(256), 2 * (size_t)nmax * sizeof(double2), s, a,
+                               rr);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        lo = hi;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_alm(const ShtArgs &a, hipStream_t s) {
@@ -373,7 +439,7 @@ hipError_t launch_alm(const ShtArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_alm2cl(const ClArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL(alm2cl_kernel, dim3((a.lmax + 256) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(alm2cl_kernel, dim3(a.lmax + 1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
