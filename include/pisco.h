@@ -397,7 +397,8 @@ pisco_status pisco_map_solve(pisco_ctx *ctx, int64_t nside_map, const double *ac
  * (Q and U both null: temperature only; alm_E and alm_B are then not
  * written and may be null).  `workspace` is caller-owned device memory of at
  * least pisco_map2alm_workspace_bytes(nside, lmax, pol) bytes (the ring
- * Fourier sums of every field); it must not be shared by calls in flight.
+ * Fourier sums of every field and partial sums of the a_lm, about 2.4 GB at
+ * nside 1024, lmax 3071); it must not be shared by calls in flight.
  * mmax = lmax.
  *
  * pisco_alm2cl: cl[l] = C^XY_l for l = 0..lmax (device float64, lmax + 1).

@@ -16,7 +16,10 @@ struct ShtArgs {
     const double *map[3];                  // RING order, 12 nside^2 each
     double2 *F;                            // [nfields][mmax + 1][nrings]: weighted ring Fourier sums
     double *alm[3];                        // complex interleaved, m-major: T, E, B
+    double *partial;                       // [SHT_WAVES][alm size][6]: per-wave partial sums
 };
+
+constexpr int SHT_WAVES = 8;               // waves per a_lm workgroup (one workgroup per m)
 
 struct ClArgs {
     int lmax, nspec;                       // up to 6 spectra

@@ -29,6 +29,7 @@ namespace {
 constexpr int SCALE = 256;               // exponent step of the carried recurrence
 constexpr int ALM_THREADS = 512;
 constexpr int ALM_WAVES = ALM_THREADS / 64;
+static_assert(ALM_WAVES == SHT_WAVES, "partial-sum layout");
 constexpr int LBLOCK = 4;                // l values per LDS reduction
 constexpr int NCOMP = 6;                 // a^T, a^E, a^B (re, im)
 constexpr int LCHUNK = 64;               // l values per coefficient table
@@ -261,16 +262,28 @@ __device__ inline void advance(PairState &p, const Coef &c) {
     }
 }
 
+// Orders this wave's LDS writes before its later LDS reads (lanes exchange
+// values inside one wave; no other wave touches the region).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int RED_STRIDE = LBLOCK * NCOMP + 1;   // padded row of one lane's sums (doubles)
+
 template <bool POL>
 __global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
     extern __shared__ double sh_alm[];
-    double *red = sh_alm;                                            // [waves][LBLOCK * NCOMP][64]
-    Coef *coef = reinterpret_cast<Coef *>(sh_alm + ALM_WAVES * LBLOCK * NCOMP * 64);   // [LCHUNK]
     const int m = blockIdx.x;
     const int N = a.nside, lmax = a.lmax;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // per-wave regions: [64][RED_STRIDE] lane sums, then LCHUNK coefficient records
+    double *red = sh_alm + wave * (64 * RED_STRIDE + LCHUNK * (int)(sizeof(Coef) / sizeof(double)));
+    Coef *coef = reinterpret_cast<Coef *>(red + 64 * RED_STRIDE);
     const int npairs = 2 * N;
     const int kcount = (npairs + ALM_THREADS - 1) / ALM_THREADS;
+    const int64_t nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
 
     // c_m = sqrt((4 pi)^-1 prod_{k=1..m} (2k + 1) / (2k)): partial products per lane, then across the wave
     double pr = 1.0;
@@ -313,9 +326,8 @@ __global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
 
     const int nl = lmax - m + 1;
     for (int c0 = 0; c0 < nl; c0 += LCHUNK) {
-        __syncthreads();
-        if (tid < LCHUNK && c0 + tid < nl) coef[tid] = make_coef(m + c0 + tid, m);
-        __syncthreads();
+        if (c0 + lane < nl) coef[lane] = make_coef(m + c0 + lane, m);
+        wave_sync();
         const int cend = min(nl, c0 + LCHUNK);
         for (int b0 = c0; b0 < cend; b0 += LBLOCK) {
             double acc[LBLOCK][NCOMP];
@@ -351,28 +363,38 @@ __global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
 #pragma unroll
             for (int j = 0; j < LBLOCK; ++j)
 #pragma unroll
-                for (int t = 0; t < NCOMP; ++t) red[((wave * LBLOCK + j) * NCOMP + t) * 64 + lane] = acc[j][t];
-            __syncthreads();
-            // 24 sums over 8 waves x 64 lanes: 16 threads per sum, 32 entries each, then a shuffle tree
-            if (tid < LBLOCK * NCOMP * 16) {
-                const int o = tid >> 4, g = tid & 15;
-                double s = 0.0;
-#pragma unroll
-                for (int w = 0; w < ALM_WAVES; ++w)
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) s += red[((w * LBLOCK * NCOMP) + o) * 64 + g * 4 + u];
-                for (int x = 8; x; x >>= 1) s += __shfl_xor(s, x, 16);
-                const int j = o / NCOMP, t = o - j * NCOMP;
-                const int l = m + b0 + j;
-                if (g == 0 && b0 + j < cend) {
-                    const int64_t idx = (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
-                    double *dst = a.alm[t >> 1];
-                    if (dst) dst[2 * idx + (t & 1)] = t < 2 ? s : -s;
-                }
+                for (int t = 0; t < NCOMP; ++t) red[lane * RED_STRIDE + j * NCOMP + t] = acc[j][t];
+            wave_sync();
+            // lanes 0..47: sum o = lane / 2 over the half of the wave's lanes given by lane & 1
+            double sum = 0.0;
+            const int o = lane >> 1, half = lane & 1;
+            if (lane < 2 * LBLOCK * NCOMP) {
+#pragma unroll 8
+                for (int u = 0; u < 32; ++u) sum += red[(half * 32 + u) * RED_STRIDE + o];
             }
-            __syncthreads();
+            sum += __shfl_xor(sum, 1, 64);
+            const int j = o / NCOMP, t = o - j * NCOMP;
+            if (lane < 2 * LBLOCK * NCOMP && half == 0 && b0 + j < cend) {
+                const int64_t idx = (int64_t)m * (2 * lmax + 1 - m) / 2 + m + b0 + j;
+                a.partial[((int64_t)wave * nalm + idx) * NCOMP + t] = sum;
+            }
+            wave_sync();
         }
     }
+}
+
+// a_lm = sum of the waves' partial sums; E and B take the sign of their definitions.
+__global__ void __launch_bounds__(256) alm_reduce_kernel(ShtArgs a) {
+    const int64_t nalm = (int64_t)(a.lmax + 1) * (a.lmax + 2) / 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nalm * NCOMP) return;
+    const int t = (int)(i % NCOMP);
+    double *dst = a.alm[t >> 1];
+    if (!dst) return;
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < ALM_WAVES; ++w) s += a.partial[(int64_t)w * nalm * NCOMP + i];
+    dst[2 * (i / NCOMP) + (t & 1)] = t < 2 ? s : -s;
 }
 
 // One wave per l: lanes take m = lane, lane + 64, ...; then a shuffle tree.
@@ -427,7 +449,7 @@ hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_alm(const ShtArgs &a, hipStream_t s) {
-    const size_t lds = (size_t)ALM_WAVES * LBLOCK * NCOMP * 64 * sizeof(double) + LCHUNK * sizeof(Coef);
+    const size_t lds = (size_t)ALM_WAVES * (64 * RED_STRIDE * sizeof(double) + LCHUNK * sizeof(Coef));
     const void *k = a.nfields == 3 ? (const void *)alm_kernel<true> : (const void *)alm_kernel<false>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -435,6 +457,10 @@ hipError_t launch_alm(const ShtArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(alm_kernel<true>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
     else
         hipLaunchKernelGGL(alm_kernel<false>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)(a.lmax + 1) * (a.lmax + 2) / 2 * NCOMP;
+    hipLaunchKernelGGL(alm_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

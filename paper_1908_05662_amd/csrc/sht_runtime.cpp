@@ -24,8 +24,13 @@ pisco_status launched(pisco_ctx *c, hipError_t e) {
 bool nside_ok(int64_t n) { return n >= 1 && n <= pisco::SHT_MAX_NSIDE && (n & (n - 1)) == 0; }
 bool lmax_ok(int64_t nside, int64_t lmax) { return lmax >= 0 && lmax <= 4 * nside; }
 
-int64_t workspace_bytes(int64_t nside, int64_t lmax, bool pol) {
+int64_t fourier_bytes(int64_t nside, int64_t lmax, bool pol) {
     return (pol ? 3 : 1) * (lmax + 1) * (4 * nside - 1) * (int64_t)sizeof(double2);
+}
+
+// ring Fourier sums, then the a_lm workgroups' per-wave partial sums
+int64_t workspace_bytes(int64_t nside, int64_t lmax, bool pol) {
+    return fourier_bytes(nside, lmax, pol) + (int64_t)pisco::SHT_WAVES * (lmax + 1) * (lmax + 2) / 2 * 6 * 8;
 }
 
 pisco_status map2alm(pisco_ctx *ctx, int64_t nside, int32_t lmax, const double *T, const double *Q, const double *U,
@@ -49,6 +54,7 @@ pisco_status map2alm(pisco_ctx *ctx, int64_t nside, int32_t lmax, const double *
     a.map[1] = Q;
     a.map[2] = U;
     a.F = static_cast<double2 *>(ws);
+    a.partial = reinterpret_cast<double *>(static_cast<char *>(ws) + fourier_bytes(nside, lmax, pol));
     a.alm[0] = aT;
     a.alm[1] = pol ? aE : nullptr;
     a.alm[2] = pol ? aB : nullptr;
