@@ -55,10 +55,10 @@ def setup(torch):
     conv.close()
 
 
-def _observe(conv, torch, sky, th, ph, psi):
+def _observe(conv, torch, sky, th, ph, psi, nside_sky=NSIDE_SKY):
     from paper_1908_05662_amd.api import MapMaker, Spectra
 
-    conv.set_sky(NSIDE_SKY, *(torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in sky), dtype=torch.float64)
+    conv.set_sky(nside_sky, *(torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in sky), dtype=torch.float64)
     conv.set_pointing(0, *(torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (th, ph, psi)))
     tod = conv.convolve(0)
     maps, rc = MapMaker(conv, NSIDE_MAP).add(th, ph, psi, tod, 0.0, 0.0, 1.0).solve()
@@ -144,3 +144,35 @@ def test_random_versus_symmetric_offsets(setup, torch):
         f"random BB / EE_in {bb_r / ee:.2e}")
     assert bb_r > 1e-6 * ee                         # a spurious B appears with random offsets
     assert bb_s < 1e-2 * bb_r                       # symmetric offsets suppress it
+
+
+def test_ideal_cmb_paper_configuration(torch):
+    """The same pixel-centre run in the paper's own configuration: sky at nside 512
+    and the 1.5 deg Gaussian given as an nside-2048 HEALPix beam map (resampled by
+    the library onto a 201^2 grid over +-5 deg)."""
+    from paper_1908_05662_amd.api import Convolver, Spectra
+
+    say("case: ideal CMB, paper configuration (sky nside 512, beam map nside 2048)")
+    nside_sky, lmax_sky = 512, 1535
+    conv = Convolver(0)
+    try:
+        cl = SK.cmb_like_cl(lmax_sky)
+        sky, _ = SK.make_teb_sky(nside_sky, lmax_sky, cl, seed=W.SEED_BASE + 63)
+        conv.set_sky(nside_sky, *(torch.from_numpy(m).cuda() for m in sky), dtype=torch.float64)
+        bmap = B.healpix_beam_map(2048, FWHM, rho_max_rad=6.0 * D2R)
+        conv.set_beam_healpix_scalar(0, 2048, 201, np.tan(5.0 * D2R), bmap, 0.5, 0.5, 0.0, 1.0, dtype=torch.float64)
+        conv.set_detector(0, 0.0, 0.0, 5.0 * D2R, W.NORM_PER_SAMPLE, 1.0)
+        cl_in = Spectra(conv, nside_sky, LMAX).anafast(*(torch.from_numpy(m).cuda() for m in sky)).cpu().numpy()
+        th, ph, psi = SC.pixel_centre_scan(NSIDE_MAP)
+        out = _beam_corrected(_observe(conv, torch, sky, th, ph, psi, nside_sky=nside_sky))
+    finally:
+        torch.cuda.synchronize()
+        conv.close()
+    ls = slice(L_LO, L_HI + 1)
+    rt = np.abs(out[0, ls] / cl_in[0, ls] - 1.0)
+    re = np.abs(out[1, ls] / cl_in[1, ls] - 1.0)
+    leak = out[2, ls] / cl_in[1, ls]
+    say(f"  TT residual median {np.median(rt):.2e} max {rt.max():.2e}; EE median {np.median(re):.2e} "
+        f"max {re.max():.2e}; BB / EE_in max {leak.max():.2e}")
+    assert np.median(rt) < 1e-2 and np.median(re) < 1e-2
+    assert leak.max() < 1e-4
