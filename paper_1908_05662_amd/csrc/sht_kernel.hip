@@ -80,8 +80,16 @@ __global__ void __launch_bounds__(256) ring_fourier_kernel(ShtArgs a, RingRange 
     const int q = n / P;                 // odd factor
     double2 *bufA = sh_ring;
     double2 *bufB = sh_ring + n;
+    double2 *tab = sh_ring + 2 * n;          // e^{-2 pi i t / q}, t < q (q <= n / 4 when q > 1)
     double *xs = reinterpret_cast<double *>(bufB);
     const double w = 4.0 * M_PI / (12.0 * (double)a.nside * (double)a.nside);
+    if (q > 1) {
+        for (int t = threadIdx.x; t < q; t += blockDim.x) {
+            double st, ct;
+            sincospi(2.0 * (double)t / (double)q, &st, &ct);
+            tab[t] = make_double2(ct, -st);
+        }
+    }
     for (int f = 0; f < a.nfields; ++f) {
         const double *x = a.map[f] + g.first;
         for (int j = threadIdx.x; j < n; j += blockDim.x) xs[j] = x[j];
@@ -95,39 +103,29 @@ __global__ void __launch_bounds__(256) ring_fourier_kernel(ShtArgs a, RingRange 
             if (q == 1) {
                 re = xs[j1];
             } else {
-                // four interleaved chains (j2 = c mod 4), each turning its twiddle by
-                // e^{-2 pi i 4 k2 / q} and re-seeded exactly every 16 of its steps
-                int k4 = (4 * k2) % q;
-                double ss, cs;
-                sincospi(2.0 * (double)k4 / (double)q, &ss, &cs);
-                double wr[4], wi[4], ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-                int idx[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) idx[c] = (c * k2) % q;
-                for (int j0 = 0; j0 < q; j0 += 4) {
-                    if ((j0 & 63) == 0) {
-#pragma unroll
-                        for (int c = 0; c < 4; ++c) {
-                            double s0, c0;
-                            sincospi(2.0 * (double)idx[c] / (double)q, &s0, &c0);
-                            wr[c] = c0;
-                            wi[c] = -s0;
-                        }
-                    }
+                // twiddles e^{-2 pi i j2 k2 / q} from the ring's table (index j2 k2 mod q),
+                // four interleaved accumulators (j2 = c mod 4)
+                double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
+                int idx = 0;
+                int j2 = 0;
+                for (; j2 + 3 < q; j2 += 4) {
 #pragma unroll
                     for (int c = 0; c < 4; ++c) {
-                        if (j0 + c < q) {
-                            const double xv = xs[P * (j0 + c) + j1];
-                            ar[c] = fma(xv, wr[c], ar[c]);
-                            ai[c] = fma(xv, wi[c], ai[c]);
-                        }
-                        const double nr = fma(wr[c], cs, wi[c] * ss);
-                        const double ni = fma(wi[c], cs, -wr[c] * ss);
-                        wr[c] = nr;
-                        wi[c] = ni;
-                        idx[c] += k4;
-                        if (idx[c] >= q) idx[c] -= q;
+                        const double2 tw = tab[idx];
+                        const double xv = xs[P * (j2 + c) + j1];
+                        ar[c] = fma(xv, tw.x, ar[c]);
+                        ai[c] = fma(xv, tw.y, ai[c]);
+                        idx += k2;
+                        idx = idx >= q ? idx - q : idx;
                     }
+                }
+                for (; j2 < q; ++j2) {
+                    const double2 tw = tab[idx];
+                    const double xv = xs[P * j2 + j1];
+                    ar[0] = fma(xv, tw.x, ar[0]);
+                    ai[0] = fma(xv, tw.y, ai[0]);
+                    idx += k2;
+                    idx = idx >= q ? idx - q : idx;
                 }
                 re = (ar[0] + ar[1]) + (ar[2] + ar[3]);
                 im = (ai[0] + ai[1]) + (ai[2] + ai[3]);
@@ -419,8 +417,10 @@ __global__ void __launch_bounds__(64) alm2cl_kernel(ClArgs a) {
 
 hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) {
     const int N = a.nside;
+    // LDS: two ring buffers and the odd-factor twiddle table (q <= length / 4)
+    auto lds_for = [](int nmax) { return (2 * (size_t)nmax + (size_t)nmax / 4 + 1) * sizeof(double2); };
     hipError_t e = hipFuncSetAttribute((const void *)ring_fourier_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(2 * (size_t)(4 * N) * sizeof(double2)));
+                                       (int)lds_for(4 * N));
     if (e != hipSuccess) return e;
     // classes by cap ring index k (ring length 4k): k <= N/4, N/4 < k <= N/2, the rest
     // (longer polar rings and the equatorial belt, length 4N)
@@ -438,8 +438,7 @@ hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) {
         const int nblocks = (rr.r1 - rr.r0) + (rr.r3 - rr.r2);
         const int nmax = c < 2 ? 4 * hi : 4 * N;
         if (nblocks > 0) {
-            hipLaunchKernelGGL(ring_fourier_kernel, dim3(nblocks), dim3(256), 2 * (size_t)nmax * sizeof(double2), s, a,
-                               rr);
+            hipLaunchKernelGGL(ring_fourier_kernel, dim3(nblocks), dim3(256), lds_for(nmax), s, a, rr);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
