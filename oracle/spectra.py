@@ -19,9 +19,10 @@ that estimator, written from the standard definitions:
   C^XY_l = (2l + 1)^-1 sum_{m=-l..l} a^X_lm a^Y*_lm (real part),
       using a_{l,-m} = (-1)^m a*_lm for real maps.
 
-w_p is the quadrature weight of pixel p: 4 pi / Npix on the HEALPix grid
-(one pass of pixel quadrature, no iterative refinement), Gauss-Legendre
-weights on the grids the pins use.
+w_p is the quadrature weight of pixel p: 4 pi / Npix on the HEALPix grid,
+Gauss-Legendre weights on the grids the pins use.  `map2alm` is one pass of
+that quadrature; `map2alm_iter` refines it by Jacobi steps through the
+synthesis `alm2map` (the scheme of HEALPix's anafast with iterations).
 
 Steps, in the order the sums are written: the Fourier sum along each
 iso-latitude ring (a library FFT, then the ring's phase offset), then the sum
@@ -181,6 +182,62 @@ def map2alm(T, Q, U, rings: dict, lmax: int, mmax: int | None = None, ms=None):
     return aT, aE, aB
 
 
+def alm2map(aT, aE, aB, rings: dict, lmax: int, mmax: int | None = None):
+    """Maps at the ring pixels from a^T (and a^E, a^B): the sums the analysis
+    inverts, written out,
+
+      T = sum_{l, m=-l..l} a^T_lm Y_lm,
+      Q + iU = -sum_{l, m=-l..l} (a^E + i a^B)_lm _2Y_lm,
+
+    i.e. with a_{l,-m} = (-1)^m a*_lm, per ring x(phi) = G_0 + 2 Re sum_{m>0} G_m e^{i m phi},
+      G^T_m = sum_l a^T_lm lambda_lm,  G^Q_m = -sum_l (a^E W + i a^B X)_lm,
+      G^U_m = -sum_l (a^B W - i a^E X)_lm.
+    Returns (T, Q, U) (Q, U None without a^E)."""
+    mmax = lmax if mmax is None else mmax
+    pol = aE is not None
+    nr = len(rings["z"])
+    GT = np.zeros((nr, mmax + 1), dtype=np.complex128)
+    GQ = np.zeros_like(GT) if pol else None
+    GU = np.zeros_like(GT) if pol else None
+    for m in range(mmax + 1):
+        lam = lambda_block(m, lmax, rings["z"], rings["s"])
+        k = alm_index(lmax, np.arange(m, lmax + 1), m)
+        GT[:, m] = aT[k] @ lam
+        if pol:
+            W, X = spin2_block(m, lmax, rings["z"], rings["s"], lam)
+            GQ[:, m] = -(aE[k] @ W + 1j * (aB[k] @ X))
+            GU[:, m] = -(aB[k] @ W - 1j * (aE[k] @ X))
+    npix = int(rings["count"].sum())
+    outs = []
+    for G in (GT, GQ, GU):
+        if G is None:
+            outs.append(None)
+            continue
+        x = np.empty(npix)
+        m = np.arange(mmax + 1)
+        c = np.where(m == 0, 1.0, 2.0)
+        for r in range(nr):
+            n, f = int(rings["count"][r]), int(rings["first"][r])
+            phi = rings["phi0"][r] + 2.0 * np.pi * np.arange(n) / n
+            x[f:f + n] = ((c * G[r]) @ np.exp(1j * np.outer(m, phi))).real
+        outs.append(x)
+    return tuple(outs)
+
+
+def map2alm_iter(T, Q, U, rings: dict, lmax: int, iterations: int):
+    """Pixel quadrature refined by `iterations` Jacobi steps:
+    a <- map2alm(m), then a <- a + map2alm(m - alm2map(a)) (the scheme of
+    HEALPix's anafast with iter > 0)."""
+    a = list(map2alm(T, Q, U, rings, lmax))
+    maps = [T, Q, U]
+    for _ in range(iterations):
+        syn = alm2map(*a, rings, lmax)
+        res = [None if m is None else m - s for m, s in zip(maps, syn)]
+        d = map2alm(*res, rings, lmax)
+        a = [None if x is None else x + y for x, y in zip(a, d)]
+    return tuple(a)
+
+
 def alm2cl(a, b, lmax: int) -> np.ndarray:
     """C_l = (2l + 1)^-1 [Re(a_l0 b*_l0) + 2 sum_{m>0} Re(a_lm b*_lm)]."""
     cl = np.zeros(lmax + 1)
@@ -191,9 +248,9 @@ def alm2cl(a, b, lmax: int) -> np.ndarray:
     return cl
 
 
-def anafast(nside: int, lmax: int, T, Q, U) -> np.ndarray:
+def anafast(nside: int, lmax: int, T, Q, U, iterations: int = 0) -> np.ndarray:
     """(6, lmax + 1) spectra TT, EE, BB, TE, EB, TB of RING maps."""
-    aT, aE, aB = map2alm(T, Q, U, healpix_rings(nside), lmax)
+    aT, aE, aB = map2alm_iter(T, Q, U, healpix_rings(nside), lmax, iterations)
     pairs = ((aT, aT), (aE, aE), (aB, aB), (aT, aE), (aE, aB), (aT, aB))
     return np.stack([alm2cl(a, b, lmax) for a, b in pairs])
 
