@@ -395,11 +395,18 @@ pisco_status pisco_map_solve(pisco_ctx *ctx, int64_t nside_map, const double *ac
  *
  * pisco_map2alm: T, Q, U are device float64 RING maps of 12 nside^2 pixels
  * (Q and U both null: temperature only; alm_E and alm_B are then not
- * written and may be null).  `workspace` is caller-owned device memory of at
- * least pisco_map2alm_workspace_bytes(nside, lmax, pol) bytes (the ring
- * Fourier sums of every field and partial sums of the a_lm, about 2.4 GB at
- * nside 1024, lmax 3071); it must not be shared by calls in flight.
- * mmax = lmax.
+ * written and may be null).  iterations (0..16) Jacobi steps refine the pixel
+ * quadrature: a <- a + map2alm(m - alm2map(a)) (each step costs one synthesis
+ * and one analysis; 0 = one pass of quadrature).  `workspace` is caller-owned
+ * device memory of at least pisco_map2alm_workspace_bytes(nside, lmax, pol)
+ * bytes (ring Fourier sums, partial sums of the a_lm, and a residual map and
+ * a_lm correction per field for the iterations: about 2.9 GB at nside 1024,
+ * lmax 3071); it must not be shared by calls in flight.  mmax = lmax.
+ *
+ * pisco_alm2map: the synthesis T = sum a^T_lm Y_lm, Q + iU = -sum (a^E + i a^B)_lm
+ * _2Y_lm over m = -l..l (a_{l,-m} = (-1)^m a*_lm) at every RING pixel centre,
+ * into device float64 maps (alm_E, alm_B, Q, U all null: T only).  Same
+ * workspace as pisco_map2alm.
  *
  * pisco_alm2cl: cl[l] = C^XY_l for l = 0..lmax (device float64, lmax + 1).
  *
@@ -408,20 +415,24 @@ pisco_status pisco_map_solve(pisco_ctx *ctx, int64_t nside_map, const double *ac
  * without Q and U).
  *
  * All return PISCO_EINVAL for nside not a power of two in [1, 1024], lmax
- * outside [0, 4 nside], a null array that is needed, or a workspace smaller
- * than required; launches are asynchronous on `stream` (hipStream_t, NULL =
- * default) and every array must stay valid until the work there is done.
+ * outside [0, 4 nside], iterations outside [0, 16], a null array that is
+ * needed, or a workspace smaller than required; launches are asynchronous on
+ * `stream` (hipStream_t, NULL = default) and every array must stay valid until
+ * the work there is done.
  * ------------------------------------------------------------------------ */
 int64_t pisco_alm_size(int32_t lmax);
 int64_t pisco_map2alm_workspace_bytes(int64_t nside, int32_t lmax, int32_t pol);
-pisco_status pisco_map2alm(pisco_ctx *ctx, int64_t nside, int32_t lmax, const double *T, const double *Q,
-                           const double *U, double *alm_T, double *alm_E, double *alm_B, void *workspace,
+pisco_status pisco_map2alm(pisco_ctx *ctx, int64_t nside, int32_t lmax, int32_t iterations, const double *T,
+                           const double *Q, const double *U, double *alm_T, double *alm_E, double *alm_B,
+                           void *workspace, int64_t workspace_bytes, void *stream);
+pisco_status pisco_alm2map(pisco_ctx *ctx, int64_t nside, int32_t lmax, const double *alm_T, const double *alm_E,
+                           const double *alm_B, double *T, double *Q, double *U, void *workspace,
                            int64_t workspace_bytes, void *stream);
 pisco_status pisco_alm2cl(pisco_ctx *ctx, int32_t lmax, const double *alm_x, const double *alm_y, double *cl,
                           void *stream);
-pisco_status pisco_anafast(pisco_ctx *ctx, int64_t nside, int32_t lmax, const double *T, const double *Q,
-                           const double *U, double *alm_T, double *alm_E, double *alm_B, void *workspace,
-                           int64_t workspace_bytes, double *cl, void *stream);
+pisco_status pisco_anafast(pisco_ctx *ctx, int64_t nside, int32_t lmax, int32_t iterations, const double *T,
+                           const double *Q, const double *U, double *alm_T, double *alm_E, double *alm_B,
+                           void *workspace, int64_t workspace_bytes, double *cl, void *stream);
 
 #ifdef __cplusplus
 }

@@ -77,9 +77,10 @@ SIGNATURES = [
     ("pisco_map_solve", ctypes.c_int, [_vp, _i64, _vp, _dbl, _vp, _vp, _vp]),
     ("pisco_alm_size", _i64, [_i32]),
     ("pisco_map2alm_workspace_bytes", _i64, [_i64, _i32, _i32]),
-    ("pisco_map2alm", ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    ("pisco_map2alm", ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    ("pisco_alm2map", ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     ("pisco_alm2cl", ctypes.c_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
-    ("pisco_anafast", ctypes.c_int, [_vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    ("pisco_anafast", ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
 ]
 
 _lib = None

@@ -448,26 +448,49 @@ class Spectra:
         ap = [self.alm[0].data_ptr()] + ([a.data_ptr() for a in self.alm[1:]] if pol else [None, None])
         return mp, ap
 
-    def map2alm(self, T, Q=None, U=None, stream=None):
+    def map2alm(self, T, Q=None, U=None, iterations: int = 0, stream=None):
         """(a^T, a^E, a^B) complex128 device tensors (a^E, a^B None without Q, U); the
-        tensors are this object's buffers, overwritten by the next call."""
+        tensors are this object's buffers, overwritten by the next call.
+        `iterations` Jacobi steps refine the pixel quadrature."""
         maps = self._maps(T, Q, U)
         mp, ap = self._ptrs(maps)
-        self.conv._check(self._lib.pisco_map2alm(self.conv._h, self.nside, self.lmax, *mp, *ap,
+        self.conv._check(self._lib.pisco_map2alm(self.conv._h, self.nside, self.lmax, int(iterations), *mp, *ap,
                                                  self.workspace.data_ptr(), self.workspace.numel(),
                                                  self._stream(stream)))
         if stream is not None:
             stream.synchronize()
         return tuple(self.alm) if maps[1] is not None else (self.alm[0], None, None)
 
-    def anafast(self, T, Q=None, U=None, stream=None):
+    def alm2map(self, aT, aE=None, aB=None, stream=None):
+        """(T, Q, U) float64 device maps from complex128 a_lm tensors of this
+        object's lmax (Q, U None without a^E, a^B)."""
+        torch = _torch()
+        n = int(self._lib.pisco_alm_size(self.lmax))
+        al = [aT, aE, aB]
+        if (aE is None) != (aB is None) or (aE is not None and not self.pol) or any(
+                a is not None and (a.dtype != torch.complex128 or a.numel() != n or not a.is_cuda) for a in al):
+            raise ValueError(f"a_lm must be complex128 device tensors of {n} values (a^E and a^B together)")
+        pol = aE is not None
+        npix = 12 * self.nside * self.nside
+        maps = [torch.empty(npix, dtype=torch.float64, device=self.conv.torch_device) for _ in range(3 if pol else 1)]
+        al = [a.contiguous() for a in al if a is not None]
+        ap = [a.data_ptr() for a in al] + [None] * (3 - len(al))
+        mp = [m.data_ptr() for m in maps] + [None] * (3 - len(maps))
+        self.conv._check(self._lib.pisco_alm2map(self.conv._h, self.nside, self.lmax, *ap, *mp,
+                                                 self.workspace.data_ptr(), self.workspace.numel(),
+                                                 self._stream(stream)))
+        if stream is not None:
+            stream.synchronize()
+        return tuple(maps) if pol else (maps[0], None, None)
+
+    def anafast(self, T, Q=None, U=None, iterations: int = 0, stream=None):
         """[6, lmax + 1] float64 device tensor (TT, EE, BB, TE, EB, TB), or [1, lmax + 1] for T only."""
         torch = _torch()
         maps = self._maps(T, Q, U)
         mp, ap = self._ptrs(maps)
         cl = torch.empty((6 if maps[1] is not None else 1, self.lmax + 1), dtype=torch.float64,
                          device=self.conv.torch_device)
-        self.conv._check(self._lib.pisco_anafast(self.conv._h, self.nside, self.lmax, *mp, *ap,
+        self.conv._check(self._lib.pisco_anafast(self.conv._h, self.nside, self.lmax, int(iterations), *mp, *ap,
                                                  self.workspace.data_ptr(), self.workspace.numel(), cl.data_ptr(),
                                                  self._stream(stream)))
         if stream is not None:

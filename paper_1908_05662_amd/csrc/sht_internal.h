@@ -17,6 +17,8 @@ struct ShtArgs {
     double2 *F;                            // [nfields][mmax + 1][nrings]: weighted ring Fourier sums
     double *alm[3];                        // complex interleaved, m-major: T, E, B
     double *partial;                       // [SHT_WAVES][alm size][6]: per-wave partial sums
+    const double *alm_in[3];               // synthesis input (complex interleaved)
+    double *map_out[3];                    // synthesis output (RING order)
 };
 
 constexpr int SHT_WAVES = 8;               // waves per a_lm workgroup (one workgroup per m)
@@ -29,6 +31,8 @@ struct ClArgs {
 
 hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s);
 hipError_t launch_alm(const ShtArgs &a, hipStream_t s);
+hipError_t launch_alm2map(const ShtArgs &a, hipStream_t s);          // alm_in -> F (as G) -> map_out
+hipError_t launch_axpy(double *y, const double *x, double alpha, int64_t n, bool reverse, hipStream_t s);
 hipError_t launch_alm2cl(const ClArgs &a, hipStream_t s);
 
 }  // namespace pisco

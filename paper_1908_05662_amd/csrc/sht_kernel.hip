@@ -16,7 +16,11 @@
 //                        lambda_{l-1}, and accumulate the symmetric and
 //                        antisymmetric ring-pair sums; every four l the
 //                        workgroup sums its lanes through LDS;
-//   alm2cl_kernel        one thread per l: C_l of up to six a_lm pairs.
+//   alm2cl_kernel        one wave per l: C_l of up to six a_lm pairs;
+//   alm2ring_kernel      the synthesis: one workgroup per m, lanes own ring pairs
+//                        and sum over l in registers (no cross-lane sums);
+//   ring_synth_kernel    one workgroup per ring: the m sums folded onto the ring
+//                        length, then the same LDS FFT as the analysis.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -395,6 +399,238 @@ __global__ void __launch_bounds__(256) alm_reduce_kernel(ShtArgs a) {
     dst[2 * (i / NCOMP) + (t & 1)] = t < 2 ? s : -s;
 }
 
+struct SynPair {
+    double z, inv_s2, z_s2, m_s2;
+    double v, vp;
+    int e;
+    double2 acc[3][2];                 // [field][class]: north-ring sums split by their south sign
+};
+
+// Adds one l to the pair's sums: lambda and W terms go to class P = (l + m) & 1
+// (south value (-1)^(l+m) times the north one), X terms to class 1 - P.
+template <int P, bool POL, bool SCALED>
+__device__ inline void syn_terms(SynPair &p, const Coef &c, const double *al) {
+    double L = p.v, Lp = p.vp;
+    if (SCALED) {
+        const double f = p.e == 0 ? 1.0 : (p.e == -1 ? 0x1p-256 : 0.0);
+        L *= f;
+        Lp *= f;
+    }
+    const double2 aT = make_double2(al[0], al[1]);
+    p.acc[0][P].x = fma(L, aT.x, p.acc[0][P].x);
+    p.acc[0][P].y = fma(L, aT.y, p.acc[0][P].y);
+    if (POL) {
+        const double2 aE = make_double2(al[2], al[3]), aB = make_double2(al[4], al[5]);
+        const double W = fma(-fma(c.A, p.inv_s2, c.B), L, c.C * p.z_s2 * Lp);
+        const double X = p.m_s2 * fma(c.C, Lp, -c.D * p.z * L);
+        // Q: -(aE W + i aB X);  U: -(aB W - i aE X)
+        p.acc[1][P].x = fma(-W, aE.x, p.acc[1][P].x);
+        p.acc[1][P].y = fma(-W, aE.y, p.acc[1][P].y);
+        p.acc[1][1 - P].x = fma(X, aB.y, p.acc[1][1 - P].x);
+        p.acc[1][1 - P].y = fma(-X, aB.x, p.acc[1][1 - P].y);
+        p.acc[2][P].x = fma(-W, aB.x, p.acc[2][P].x);
+        p.acc[2][P].y = fma(-W, aB.y, p.acc[2][P].y);
+        p.acc[2][1 - P].x = fma(-X, aE.y, p.acc[2][1 - P].x);
+        p.acc[2][1 - P].y = fma(X, aE.x, p.acc[2][1 - P].y);
+    }
+}
+
+template <bool SCALED>
+__device__ inline void syn_advance(SynPair &p, const Coef &c) {
+    const double vn = c.ra * fma(p.z, p.v, -c.rb * p.vp);
+    p.vp = p.v;
+    p.v = vn;
+    if (SCALED && fabs(vn) > 0x1p256) {
+        p.v *= 0x1p-256;
+        p.vp *= 0x1p-256;
+        p.e += 1;
+    }
+}
+
+template <bool POL>
+__global__ void __launch_bounds__(ALM_THREADS) alm2ring_kernel(ShtArgs a) {
+    extern __shared__ double sh_syn[];
+    const int m = blockIdx.x;
+    const int N = a.nside, lmax = a.lmax;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr int CW = (int)(sizeof(Coef) / sizeof(double));
+    double *al = sh_syn + wave * LCHUNK * (CW + NCOMP);             // per wave: [LCHUNK][6] a_lm values
+    Coef *coef = reinterpret_cast<Coef *>(al + LCHUNK * NCOMP);     // then [LCHUNK] coefficient records
+    const int npairs = 2 * N;
+    const int kcount = (npairs + ALM_THREADS - 1) / ALM_THREADS;
+
+    double pr = 1.0;
+    for (int k = lane + 1; k <= m; k += 64) pr *= (2.0 * k + 1.0) / (2.0 * k);
+    for (int o = 32; o; o >>= 1) pr *= __shfl_xor(pr, o, 64);
+    const double cm = sqrt(pr / (4.0 * M_PI));
+
+    SynPair ps[SHT_PAIRS_PER_LANE];
+#pragma unroll
+    for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
+        SynPair &p = ps[k];
+        const int pi = tid + k * ALM_THREADS;
+        const bool ok = k < kcount && pi < npairs;
+        const RingGeom g = sht_ring(N, ok ? pi : 0);
+        p.z = g.z;
+        p.inv_s2 = 1.0 / (g.s * g.s);
+        p.z_s2 = g.z * p.inv_s2;
+        p.m_s2 = (double)m * p.inv_s2;
+        start_value(g.s, m, cm, &p.v, &p.e);
+        p.vp = 0.0;
+        if (!ok) p.e = -1000000;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) p.acc[f][0] = p.acc[f][1] = make_double2(0.0, 0.0);
+    }
+
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;        // index of (l = 0, m) minus 0: + l
+    const int nl = lmax - m + 1;
+    for (int c0 = 0; c0 < nl; c0 += LCHUNK) {
+        if (c0 + lane < nl) {
+            const int l = m + c0 + lane;
+            coef[lane] = make_coef(l, m);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                const double *src = a.alm_in[f];
+                const bool use = src && (f == 0 || POL);
+                al[lane * NCOMP + 2 * f] = use ? src[2 * (base + l)] : 0.0;
+                al[lane * NCOMP + 2 * f + 1] = use ? src[2 * (base + l) + 1] : 0.0;
+            }
+        }
+        wave_sync();
+        const int cend = min(nl, c0 + LCHUNK);
+        for (int b0 = c0; b0 < cend; b0 += 2) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int li = b0 + j;                                // l - m; even = class 0
+                if (li >= cend) break;
+                const Coef c = coef[li - c0];
+                const double *A = al + (li - c0) * NCOMP;
+#pragma unroll
+                for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
+                    if (k >= kcount) continue;
+                    if (__ballot(ps[k].e != 0) == 0) {
+                        if (li > 0) syn_advance<false>(ps[k], c);
+                        if (j)
+                            syn_terms<1, POL, false>(ps[k], c, A);
+                        else
+                            syn_terms<0, POL, false>(ps[k], c, A);
+                    } else {
+                        if (li > 0) syn_advance<true>(ps[k], c);
+                        if (__ballot(ps[k].e >= -1) == 0) continue;
+                        if (j)
+                            syn_terms<1, POL, true>(ps[k], c, A);
+                        else
+                            syn_terms<0, POL, true>(ps[k], c, A);
+                    }
+                }
+            }
+        }
+        wave_sync();
+    }
+#pragma unroll
+    for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
+        const int pi = tid + k * ALM_THREADS;
+        if (k >= kcount || pi >= npairs) continue;
+        const int rn = pi, rs = a.nrings - 1 - pi;
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (f >= a.nfields) break;
+            const double2 s0 = ps[k].acc[f][0], s1 = ps[k].acc[f][1];
+            double2 *G = a.F + ((size_t)f * (a.mmax + 1) + m) * a.nrings;
+            G[rn] = make_double2(s0.x + s1.x, s0.y + s1.y);
+            if (rs != rn) G[rs] = make_double2(s0.x - s1.x, s0.y - s1.y);
+        }
+    }
+}
+
+// x_j = Re sum_{m=0..mmax} c_m G_m e^{i m (phi0 + 2 pi j / n)}, c_0 = 1, c_m = 2:
+// the m sums folded onto k = m mod n give H; x = Re DFT(conj H).
+__global__ void __launch_bounds__(256) ring_synth_kernel(ShtArgs a, RingRange rr) {
+    extern __shared__ double2 sh_ring[];
+    const int b = blockIdx.x;
+    const int r = b < rr.r1 - rr.r0 ? rr.r0 + b : rr.r2 + (b - (rr.r1 - rr.r0));
+    const RingGeom g = sht_ring(a.nside, r);
+    const int n = g.n;
+    const int P = n & -n;
+    const int q = n / P;
+    double2 *bufA = sh_ring;
+    double2 *bufB = sh_ring + n;
+    double2 *tab = sh_ring + 2 * n;
+    if (q > 1) {
+        for (int t = threadIdx.x; t < q; t += blockDim.x) {
+            double st, ct;
+            sincospi(2.0 * (double)t / (double)q, &st, &ct);
+            tab[t] = make_double2(ct, -st);
+        }
+    }
+    for (int f = 0; f < a.nfields; ++f) {
+        const double2 *G = a.F + (size_t)f * (a.mmax + 1) * a.nrings + r;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            double hr = 0.0, hi = 0.0;
+            for (int m = k; m <= a.mmax; m += n) {
+                const double2 v = G[(size_t)m * a.nrings];
+                double sn, cs;
+                sincospi((double)m * g.phi0_over_pi, &sn, &cs);       // e^{+i m phi0}
+                const double c = m == 0 ? 1.0 : 2.0;
+                hr = fma(c, fma(v.x, cs, -v.y * sn), hr);
+                hi = fma(c, fma(v.x, sn, v.y * cs), hi);
+            }
+            bufA[k] = make_double2(hr, -hi);
+        }
+        __syncthreads();
+        double2 *src = bufA, *dst = bufB;
+        if (q > 1) {
+            // complex input: all k2 < q
+            for (int it = threadIdx.x; it < n; it += blockDim.x) {
+                const int j1 = it / q, k2 = it - j1 * q;
+                double ar = 0.0, ai = 0.0;
+                int idx = 0;
+                for (int j2 = 0; j2 < q; ++j2) {
+                    const double2 tw = tab[idx];
+                    const double2 xv = bufA[P * j2 + j1];
+                    ar = fma(xv.x, tw.x, fma(-xv.y, tw.y, ar));
+                    ai = fma(xv.x, tw.y, fma(xv.y, tw.x, ai));
+                    idx += k2;
+                    idx = idx >= q ? idx - q : idx;
+                }
+                bufB[j1 * q + k2] = make_double2(ar, ai);
+            }
+            __syncthreads();
+            src = bufB;
+            dst = bufA;
+        }
+        int L = q;
+        for (int Ps = P; Ps > 1; Ps >>= 1) {
+            const int half = Ps >> 1;
+            for (int it = threadIdx.x; it < half * L; it += blockDim.x) {
+                const int c = it / L, k = it - c * L;
+                const double2 E = src[c * L + k];
+                const double2 O = src[(c + half) * L + k];
+                double sn, cs;
+                sincospi((double)k / (double)L, &sn, &cs);
+                const double tr = fma(O.x, cs, O.y * sn);
+                const double ti = fma(O.y, cs, -O.x * sn);
+                dst[c * 2 * L + k] = make_double2(E.x + tr, E.y + ti);
+                dst[c * 2 * L + k + L] = make_double2(E.x - tr, E.y - ti);
+            }
+            __syncthreads();
+            double2 *t = src;
+            src = dst;
+            dst = t;
+            L <<= 1;
+        }
+        double *out = a.map_out[f] + g.first;
+        for (int j = threadIdx.x; j < n; j += blockDim.x) out[j] = src[j].x;
+        __syncthreads();
+    }
+}
+
+// y <- x + alpha y (reverse) or y <- y + alpha x
+__global__ void __launch_bounds__(256) axpy_kernel(double *y, const double *x, double alpha, int64_t n, bool reverse) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = reverse ? fma(alpha, y[i], x[i]) : fma(alpha, x[i], y[i]);
+}
+
 // One wave per l: lanes take m = lane, lane + 64, ...; then a shuffle tree.
 __global__ void __launch_bounds__(64) alm2cl_kernel(ClArgs a) {
     const int l = blockIdx.x;
@@ -415,12 +651,13 @@ __global__ void __launch_bounds__(64) alm2cl_kernel(ClArgs a) {
 
 }  // namespace
 
-hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) {
+template <bool SYN>
+hipError_t launch_rings(const ShtArgs &a, hipStream_t s) {
     const int N = a.nside;
+    const void *kern = SYN ? (const void *)ring_synth_kernel : (const void *)ring_fourier_kernel;
     // LDS: two ring buffers and the odd-factor twiddle table (q <= length / 4)
     auto lds_for = [](int nmax) { return (2 * (size_t)nmax + (size_t)nmax / 4 + 1) * sizeof(double2); };
-    hipError_t e = hipFuncSetAttribute((const void *)ring_fourier_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds_for(4 * N));
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_for(4 * N));
     if (e != hipSuccess) return e;
     // classes by cap ring index k (ring length 4k): k <= N/4, N/4 < k <= N/2, the rest
     // (longer polar rings and the equatorial belt, length 4N)
@@ -438,13 +675,38 @@ hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) {
         const int nblocks = (rr.r1 - rr.r0) + (rr.r3 - rr.r2);
         const int nmax = c < 2 ? 4 * hi : 4 * N;
         if (nblocks > 0) {
-            hipLaunchKernelGGL(ring_fourier_kernel, dim3(nblocks), dim3(256), lds_for(nmax), s, a, rr);
+            if (SYN)
+                hipLaunchKernelGGL(ring_synth_kernel, dim3(nblocks), dim3(256), lds_for(nmax), s, a, rr);
+            else
+                hipLaunchKernelGGL(ring_fourier_kernel, dim3(nblocks), dim3(256), lds_for(nmax), s, a, rr);
             e = hipGetLastError();
             if (e != hipSuccess) return e;
         }
         lo = hi;
     }
     return hipSuccess;
+}
+
+hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) { return launch_rings<false>(a, s); }
+
+hipError_t launch_alm2map(const ShtArgs &a, hipStream_t s) {
+    const size_t lds = (size_t)ALM_WAVES * LCHUNK * (sizeof(Coef) + NCOMP * sizeof(double));
+    const void *k = a.nfields == 3 ? (const void *)alm2ring_kernel<true> : (const void *)alm2ring_kernel<false>;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.nfields == 3)
+        hipLaunchKernelGGL(alm2ring_kernel<true>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
+    else
+        hipLaunchKernelGGL(alm2ring_kernel<false>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_rings<true>(a, s);
+}
+
+hipError_t launch_axpy(double *y, const double *x, double alpha, int64_t n, bool reverse, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, y, x, alpha, n, reverse);
+    return hipGetLastError();
 }
 
 hipError_t launch_alm(const ShtArgs &a, hipStream_t s) {

@@ -70,12 +70,15 @@ def test_spectra_host_logic():
 
     lib = _lib.load()
     assert lib.pisco_alm_size(10) == 66 and lib.pisco_alm_size(0) == 1 and lib.pisco_alm_size(-1) == 0
-    partial = 8 * (192 * 193 // 2) * 6 * 8           # per-wave partial sums of the a_lm
-    assert lib.pisco_map2alm_workspace_bytes(64, 191, 1) == 3 * 192 * 255 * 16 + partial
-    assert lib.pisco_map2alm_workspace_bytes(64, 191, 0) == 192 * 255 * 16 + partial
+    nalm = 192 * 193 // 2
+    partial = 8 * nalm * 6 * 8                        # per-wave partial sums of the a_lm
+    it = 12 * 64 * 64 * 8 + nalm * 16                 # per field: residual map and a_lm correction
+    assert lib.pisco_map2alm_workspace_bytes(64, 191, 1) == 3 * 192 * 255 * 16 + partial + 3 * it
+    assert lib.pisco_map2alm_workspace_bytes(64, 191, 0) == 192 * 255 * 16 + partial + it
     assert lib.pisco_map2alm_workspace_bytes(48, 10, 1) == -1       # not a power of two
     assert lib.pisco_map2alm_workspace_bytes(2048, 10, 1) == -1     # above the largest nside
     assert lib.pisco_map2alm_workspace_bytes(8, 33, 1) == -1        # lmax above 4 nside
-    assert lib.pisco_map2alm(None, 8, 10, None, None, None, None, None, None, None, 0, None) == _lib.EINVAL
-    assert lib.pisco_anafast(None, 8, 10, None, None, None, None, None, None, None, 0, None, None) == _lib.EINVAL
+    assert lib.pisco_map2alm(None, 8, 10, 0, None, None, None, None, None, None, None, 0, None) == _lib.EINVAL
+    assert lib.pisco_alm2map(None, 8, 10, None, None, None, None, None, None, None, 0, None) == _lib.EINVAL
+    assert lib.pisco_anafast(None, 8, 10, 0, None, None, None, None, None, None, None, 0, None, None) == _lib.EINVAL
     assert lib.pisco_alm2cl(None, 10, None, None, None, None) == _lib.EINVAL
