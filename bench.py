@@ -358,7 +358,8 @@ SHT_FLOPS_PER_ITEM = 33   # per (l, m, ring pair): recurrence 4; lambda scaling 
 def spectra_leg(conv, maps, torch, lmax=3071, reps=5):
     """Spectra of the map leg's nside-1024 I, Q, U maps (the validation step the
     maps go through): harmonic analysis to lmax 3071 and the six spectra, FP64,
-    HIP events on the current stream.  `dense_tflops` counts 33 flops for every
+    HIP events on the current stream; also the synthesis (alm2map) and the
+    analysis refined by three Jacobi steps.  `dense_tflops` counts 33 flops for every
     (l, m, ring pair) of the triangle, including the polar pairs the kernel skips
     while lambda_lm is below 2^-256 (so it is an equivalent rate, not the
     executed one); the executed FP64 rate is in the kernel profile."""
@@ -381,14 +382,19 @@ def spectra_leg(conv, maps, torch, lmax=3071, reps=5):
 
     t_alm = timed(lambda: sp.map2alm(T, Q, U))
     t_all = timed(lambda: sp.anafast(T, Q, U))
+    aT, aE, aB = (x.clone() for x in sp.map2alm(T, Q, U))
+    t_syn = timed(lambda: sp.alm2map(aT, aE, aB))
+    t_it3 = timed(lambda: sp.anafast(T, Q, U, iterations=3))
     cl = sp.anafast(T, Q, U).cpu().numpy()
     items = sum((lmax - m + 1) * 2 * nside for m in range(lmax + 1))
     dense = SHT_FLOPS_PER_ITEM * items / t_alm / 1e12
     log(f"spectra: nside {nside} lmax {lmax}: map2alm {t_alm * 1e3:.2f} ms, anafast {t_all * 1e3:.2f} ms "
-        f"({dense:.1f} TFLOP/s dense-equivalent)")
+        f"({dense:.1f} TFLOP/s dense-equivalent), alm2map {t_syn * 1e3:.2f} ms, anafast with 3 iterations "
+        f"{t_it3 * 1e3:.2f} ms")
     return {"workload": f"the map leg's nside-{nside} I, Q, U maps: harmonic analysis to lmax {lmax} and the six "
                         "spectra TT, EE, BB, TE, EB, TB (FP64)",
-            "ms_map2alm": t_alm * 1e3, "ms_anafast": t_all * 1e3, "items": items,
+            "ms_map2alm": t_alm * 1e3, "ms_anafast": t_all * 1e3, "ms_alm2map": t_syn * 1e3,
+            "ms_anafast_3_iterations": t_it3 * 1e3, "items": items,
             "flops_per_item": SHT_FLOPS_PER_ITEM, "dense_tflops": dense, "peak_tflops_fp64": ALU_PEAK_TFLOPS,
             "dense_frac": dense / ALU_PEAK_TFLOPS, "finite": bool(np.all(np.isfinite(cl)))}
 

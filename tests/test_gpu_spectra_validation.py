@@ -26,6 +26,7 @@ NSIDE_SKY, LMAX_SKY = 256, 767
 NSIDE_MAP, LMAX = 128, 383
 FWHM = 1.5 * D2R
 L_LO, L_HI = 2, 200
+ITER = 3                      # Jacobi steps of the spectrum estimator (the usual anafast default)
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +50,7 @@ def setup(torch):
     conv.set_beamsor(0, bs.dense(), bs.half_span_tan, 0.0, 1.0, dtype=torch.float64)
     conv.set_detector(0, 0.0, 0.0, 5.0 * D2R, W.NORM_PER_SAMPLE, 1.0)
     sp_in = Spectra(conv, NSIDE_SKY, LMAX)
-    cl_in = sp_in.anafast(*(torch.from_numpy(m).cuda() for m in (I, Q, U))).cpu().numpy()
+    cl_in = sp_in.anafast(*(torch.from_numpy(m).cuda() for m in (I, Q, U)), iterations=ITER).cpu().numpy()
     yield conv, (I, Q, U), cl_in
     torch.cuda.synchronize()
     conv.close()
@@ -63,7 +64,7 @@ def _observe(conv, torch, sky, th, ph, psi, nside_sky=NSIDE_SKY):
     tod = conv.convolve(0)
     maps, rc = MapMaker(conv, NSIDE_MAP).add(th, ph, psi, tod, 0.0, 0.0, 1.0).solve()
     assert float(rc.min()) > 0.1                    # every pixel seen at three angles
-    return Spectra(conv, NSIDE_MAP, LMAX).anafast(maps[0], maps[1], maps[2]).cpu().numpy()
+    return Spectra(conv, NSIDE_MAP, LMAX).anafast(maps[0], maps[1], maps[2], iterations=ITER).cpu().numpy()
 
 
 def _beam_corrected(cl):
@@ -162,7 +163,8 @@ def test_ideal_cmb_paper_configuration(torch):
         bmap = B.healpix_beam_map(2048, FWHM, rho_max_rad=6.0 * D2R)
         conv.set_beam_healpix_scalar(0, 2048, 201, np.tan(5.0 * D2R), bmap, 0.5, 0.5, 0.0, 1.0, dtype=torch.float64)
         conv.set_detector(0, 0.0, 0.0, 5.0 * D2R, W.NORM_PER_SAMPLE, 1.0)
-        cl_in = Spectra(conv, nside_sky, LMAX).anafast(*(torch.from_numpy(m).cuda() for m in sky)).cpu().numpy()
+        cl_in = Spectra(conv, nside_sky, LMAX).anafast(*(torch.from_numpy(m).cuda() for m in sky),
+                                                       iterations=ITER).cpu().numpy()
         th, ph, psi = SC.pixel_centre_scan(NSIDE_MAP)
         out = _beam_corrected(_observe(conv, torch, sky, th, ph, psi, nside_sky=nside_sky))
     finally:
