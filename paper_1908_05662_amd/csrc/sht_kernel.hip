@@ -580,20 +580,32 @@ __global__ void __launch_bounds__(256) ring_synth_kernel(ShtArgs a, RingRange rr
         __syncthreads();
         double2 *src = bufA, *dst = bufB;
         if (q > 1) {
-            // complex input: all k2 < q
+            // complex input: all k2 < q; four interleaved accumulators (j2 = c mod 4)
             for (int it = threadIdx.x; it < n; it += blockDim.x) {
                 const int j1 = it / q, k2 = it - j1 * q;
-                double ar = 0.0, ai = 0.0;
+                double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
                 int idx = 0;
-                for (int j2 = 0; j2 < q; ++j2) {
+                int j2 = 0;
+                for (; j2 + 3 < q; j2 += 4) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const double2 tw = tab[idx];
+                        const double2 xv = bufA[P * (j2 + c) + j1];
+                        ar[c] = fma(xv.x, tw.x, fma(-xv.y, tw.y, ar[c]));
+                        ai[c] = fma(xv.x, tw.y, fma(xv.y, tw.x, ai[c]));
+                        idx += k2;
+                        idx = idx >= q ? idx - q : idx;
+                    }
+                }
+                for (; j2 < q; ++j2) {
                     const double2 tw = tab[idx];
                     const double2 xv = bufA[P * j2 + j1];
-                    ar = fma(xv.x, tw.x, fma(-xv.y, tw.y, ar));
-                    ai = fma(xv.x, tw.y, fma(xv.y, tw.x, ai));
+                    ar[0] = fma(xv.x, tw.x, fma(-xv.y, tw.y, ar[0]));
+                    ai[0] = fma(xv.x, tw.y, fma(xv.y, tw.x, ai[0]));
                     idx += k2;
                     idx = idx >= q ? idx - q : idx;
                 }
-                bufB[j1 * q + k2] = make_double2(ar, ai);
+                bufB[j1 * q + k2] = make_double2((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
             }
             __syncthreads();
             src = bufB;
