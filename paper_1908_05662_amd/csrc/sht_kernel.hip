@@ -447,8 +447,14 @@ __device__ inline void syn_advance(SynPair &p, const Coef &c) {
     }
 }
 
+// Synthesis workgroups: 12 waves of up to three ring pairs per lane (2304 >= 2N
+// at the largest nside), three waves per SIMD.
+constexpr int SYN_THREADS = 768;
+constexpr int SYN_PAIRS = 3;
+static_assert(SYN_THREADS * SYN_PAIRS >= 2 * SHT_MAX_NSIDE, "ring pairs per workgroup");
+
 template <bool POL>
-__global__ void __launch_bounds__(ALM_THREADS) alm2ring_kernel(ShtArgs a) {
+__global__ void __launch_bounds__(SYN_THREADS) alm2ring_kernel(ShtArgs a) {
     extern __shared__ double sh_syn[];
     const int m = blockIdx.x;
     const int N = a.nside, lmax = a.lmax;
@@ -457,18 +463,18 @@ __global__ void __launch_bounds__(ALM_THREADS) alm2ring_kernel(ShtArgs a) {
     double *al = sh_syn + wave * LCHUNK * (CW + NCOMP);             // per wave: [LCHUNK][6] a_lm values
     Coef *coef = reinterpret_cast<Coef *>(al + LCHUNK * NCOMP);     // then [LCHUNK] coefficient records
     const int npairs = 2 * N;
-    const int kcount = (npairs + ALM_THREADS - 1) / ALM_THREADS;
+    const int kcount = (npairs + SYN_THREADS - 1) / SYN_THREADS;
 
     double pr = 1.0;
     for (int k = lane + 1; k <= m; k += 64) pr *= (2.0 * k + 1.0) / (2.0 * k);
     for (int o = 32; o; o >>= 1) pr *= __shfl_xor(pr, o, 64);
     const double cm = sqrt(pr / (4.0 * M_PI));
 
-    SynPair ps[SHT_PAIRS_PER_LANE];
+    SynPair ps[SYN_PAIRS];
 #pragma unroll
-    for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
+    for (int k = 0; k < SYN_PAIRS; ++k) {
         SynPair &p = ps[k];
-        const int pi = tid + k * ALM_THREADS;
+        const int pi = tid + k * SYN_THREADS;
         const bool ok = k < kcount && pi < npairs;
         const RingGeom g = sht_ring(N, ok ? pi : 0);
         p.z = g.z;
@@ -506,7 +512,7 @@ __global__ void __launch_bounds__(ALM_THREADS) alm2ring_kernel(ShtArgs a) {
                 const Coef c = coef[li - c0];
                 const double *A = al + (li - c0) * NCOMP;
 #pragma unroll
-                for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
+                for (int k = 0; k < SYN_PAIRS; ++k) {
                     if (k >= kcount) continue;
                     if (__ballot(ps[k].e != 0) == 0) {
                         if (li > 0) syn_advance<false>(ps[k], c);
@@ -528,8 +534,8 @@ __global__ void __launch_bounds__(ALM_THREADS) alm2ring_kernel(ShtArgs a) {
         wave_sync();
     }
 #pragma unroll
-    for (int k = 0; k < SHT_PAIRS_PER_LANE; ++k) {
-        const int pi = tid + k * ALM_THREADS;
+    for (int k = 0; k < SYN_PAIRS; ++k) {
+        const int pi = tid + k * SYN_THREADS;
         if (k >= kcount || pi >= npairs) continue;
         const int rn = pi, rs = a.nrings - 1 - pi;
 #pragma unroll
@@ -702,14 +708,14 @@ hipError_t launch_rings(const ShtArgs &a, hipStream_t s) {
 hipError_t launch_ring_fourier(const ShtArgs &a, hipStream_t s) { return launch_rings<false>(a, s); }
 
 hipError_t launch_alm2map(const ShtArgs &a, hipStream_t s) {
-    const size_t lds = (size_t)ALM_WAVES * LCHUNK * (sizeof(Coef) + NCOMP * sizeof(double));
+    const size_t lds = (size_t)(SYN_THREADS / 64) * LCHUNK * (sizeof(Coef) + NCOMP * sizeof(double));
     const void *k = a.nfields == 3 ? (const void *)alm2ring_kernel<true> : (const void *)alm2ring_kernel<false>;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (a.nfields == 3)
-        hipLaunchKernelGGL(alm2ring_kernel<true>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
+        hipLaunchKernelGGL(alm2ring_kernel<true>, dim3(a.mmax + 1), dim3(SYN_THREADS), lds, s, a);
     else
-        hipLaunchKernelGGL(alm2ring_kernel<false>, dim3(a.mmax + 1), dim3(ALM_THREADS), lds, s, a);
+        hipLaunchKernelGGL(alm2ring_kernel<false>, dim3(a.mmax + 1), dim3(SYN_THREADS), lds, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_rings<true>(a, s);
