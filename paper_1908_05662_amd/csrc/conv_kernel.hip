@@ -252,8 +252,10 @@ __device__ inline BeamVals<T> beam_lookup(const void *beam, int32_t n, int32_t i
         o.bU = lerp(lerp(q00.z, q10.z, fu), lerp(q01.z, q11.z, fu), fv);
         o.bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
     } else {
-        // cell record (b00, b10 - b00, b01 - b00, b11 - b10 - b01 + b00)
-        const R4 c = g[iv * (n - 1) + iu];
+        // cell record (b00, b10 - b00, b01 - b00, b11 - b10 - b01 + b00); the
+        // records carry a ring of extrapolated cells, so cell (iv, iu) is record
+        // (iv + 1, iu + 1) of rows of n + 1
+        const R4 c = g[(iv + 1) * (n + 1) + iu + 1];
         o.bT = fma(fv, fma(fu, c.w, c.z), fma(fu, c.y, c.x));
         o.bI = o.bQ = o.bU = o.bT;
     }
@@ -769,6 +771,7 @@ struct PairCtx {
     int32_t row_bytes;
     float sg4;            // -1 with a half-wave plate: U-row and V terms change sign
     float rowc;           // cells per grid row (bV cell polynomials)
+    float kbase;          // record index of cell (0, 0): row + 1 for one-grid beams (extrapolated ring)
 };
 
 // Masked contributions of NP consecutive (pixel record, sample) pairs,
@@ -815,12 +818,18 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         const float tu = fmaf(xp[k], rzh[k], C.c0);
         const float tv = fmaf(yp[k], rzh[k], C.c0);
         if (CLIP) in[k] = in[k] & (tu >= 0.0f) & (tu <= C.tmax) & (tv >= 0.0f) & (tv <= C.tmax);
-        // cell indices (clamped: pairs outside the disc are masked below)
-        const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
-        const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
+        // cell indices.  One-grid beams: no clamp -- a pair inside the disc (and,
+        // with CLIP, inside the grid) has t in [0, n - 1] up to rounding, so
+        // floor(t) is a cell or one of the extrapolated cells around them, which
+        // continue the edge cells' bilinear polynomials (the value the clamped
+        // lookup extrapolates to); other pairs are masked, and the buffer
+        // resource turns any offset past the records into a zero read.
+        // Four-channel beams: clamped node indices.
+        const float ku = BEAM == BEAM_SCALAR ? floorf(tu) : floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
+        const float kv = BEAM == BEAM_SCALAR ? floorf(tv) : floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
         fu[k] = tu - ku;   // exact; carries the rounding of tu (half an ulp)
         fv[k] = tv - kv;
-        off[k] = (uint32_t)fmaf(kv, C.row, ku) << 4;  // exact: row^2 < 2^24
+        off[k] = (uint32_t)fmaf(kv, C.row, ku + C.kbase) << 4;  // exact: row^2 < 2^24
     }
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
 #pragma unroll
@@ -981,11 +990,12 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);          // largest cell index
-    const float row = (float)(BEAM == BEAM_SCALAR ? n - 1 : n);
+    const float row = (float)(BEAM == BEAM_SCALAR ? n + 1 : n);
+    const float kbase = BEAM == BEAM_SCALAR ? row + 1.0f : 0.0f;
     const float pp3 = F.p3 + 1.0f;
     // beam records through a buffer resource: 32-bit byte offsets, reads past
     // the end return zero
-    const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n - 1) * (n - 1) : n * n);
+    const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n + 1) * (n + 1) : n * n);
     const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
     const int32_t row_bytes = (int32_t)(16 * n);
     // full beams with a V column: bV cell polynomials, and the V of each staged pixel
@@ -1078,7 +1088,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     // and the pair enters the compensated sums (halves the
                     // compensation work; each pre-sum rounds once)
                     const PairCtx C{Fg, omax, omin, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes, sg4,
-                                    (float)(n - 1)};
+                                    (float)(n - 1), kbase};
                     const float *vr = has_v ? vrec : nullptr;
                     if (clip) {
                         if (inner)
@@ -1202,8 +1212,9 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const bool clip = D.needs_clip != 0;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);
-    const float row = (float)(BEAM == BEAM_SCALAR ? n - 1 : n);
-    const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n - 1) * (n - 1) : n * n);
+    const float row = (float)(BEAM == BEAM_SCALAR ? n + 1 : n);
+    const float kbase = BEAM == BEAM_SCALAR ? row + 1.0f : 0.0f;   // cell (0, 0) past the extrapolated ring
+    const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n + 1) * (n + 1) : n * n);
     const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
     const int32_t row_bytes = (int32_t)(16 * n);
     const int k4 = lane >> 4, c16 = lane & 15;
@@ -1343,7 +1354,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
                         const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, cmax));
                         const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, cmax));
                         const float fu = fmaf(su, inv_h, c0 - ku), fv = fmaf(sv, inv_h, c0 - kv);
-                        const uint32_t off = (uint32_t)fmaf(kv, row, ku) << 4;
+                        const uint32_t off = (uint32_t)fmaf(kv, row, ku + kbase) << 4;
                         float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
                         if (BEAM == BEAM_SCALAR) {
                             const float4 cl = beam_ld(beam, off, 0);
@@ -1653,19 +1664,34 @@ __global__ void __launch_bounds__(256) healpix_grid_kernel(HpxGridArgs a) {
     }
 }
 
+// Cell polynomials (b00, b10 - b00, b01 - b00, b11 - b10 - b01 + b00) of the
+// (n - 1)^2 grid cells; with `padded`, (n + 1)^2 records: a ring of cells one
+// step outside the grid whose polynomials continue those of the nearest edge
+// cell (P(x + du, y + dv) with du, dv in {-1, 0, 1}), the interior unchanged.
 template <typename T>
-__global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::type *out) {
+__global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::type *out, bool padded) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t m = (int64_t)(n - 1) * (n - 1);
+    const int32_t side = padded ? n + 1 : n - 1;
+    const int64_t m = (int64_t)side * side;
     if (i >= m) return;
-    const int32_t iv = (int32_t)(i / (n - 1)), iu = (int32_t)(i % (n - 1));
-    const int64_t k = (int64_t)iv * n + iu;
+    const int32_t iv = (int32_t)(i / side) - (padded ? 1 : 0), iu = (int32_t)(i % side) - (padded ? 1 : 0);
+    const int32_t cv = min(max(iv, 0), n - 2), cu = min(max(iu, 0), n - 2);
+    const int64_t k = (int64_t)cv * n + cu;
     const double b00 = b[k], b10 = b[k + 1], b01 = b[k + n], b11 = b[k + n + 1];
+    const double c00 = b00, c10 = b10 - b00, c01 = b01 - b00, c11 = (b11 - b10) - (b01 - b00);
     typename Rec4<T>::type r;
-    r.x = (T)b00;
-    r.y = (T)(b10 - b00);
-    r.z = (T)(b01 - b00);
-    r.w = (T)((b11 - b10) - (b01 - b00));
+    if (iu == cu && iv == cv) {
+        r.x = (T)c00;
+        r.y = (T)c10;
+        r.z = (T)c01;
+        r.w = (T)c11;
+    } else {
+        const double du = (double)(iu - cu), dv = (double)(iv - cv);
+        r.x = (T)(c00 + c10 * du + c01 * dv + c11 * du * dv);
+        r.y = (T)(c10 + c11 * dv);
+        r.z = (T)(c01 + c11 * du);
+        r.w = (T)c11;
+    }
     out[i] = r;
 }
 
@@ -1808,17 +1834,18 @@ hipError_t launch_healpix_grid(const HpxGridArgs &a, bool f64, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, hipStream_t s) {
+hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, bool padded, hipStream_t s) {
     const int bs = 256;
-    const int64_t m = (int64_t)(n - 1) * (n - 1);
+    const int64_t side = padded ? n + 1 : n - 1;
+    const int64_t m = side * side;
     const int64_t g = (m + bs - 1) / bs;
     if (g == 0) return hipSuccess;
     if (f64)
         hipLaunchKernelGGL(repack_cells_kernel<double>, dim3((unsigned)g), dim3(bs), 0, s, (const double *)b, n,
-                           (double4 *)out);
+                           (double4 *)out, padded);
     else
         hipLaunchKernelGGL(repack_cells_kernel<float>, dim3((unsigned)g), dim3(bs), 0, s, (const float *)b, n,
-                           (float4 *)out);
+                           (float4 *)out, padded);
     return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ enum { ALGO_PIXEL = 0, ALGO_TILE = 1, ALGO_TILE_MX = 2 };
 
 // Per-detector description, read by the kernel from device memory.
 struct DetDesc {
-    const void *beam;      // full: n*n node records (bI, bQ, bU, bT); scalar: (n-1)^2 cell polynomials
+    const void *beam;      // full: n*n node records (bI, bQ, bU, bT); scalar: (n+1)^2 cell polynomials
+                           // (the (n-1)^2 grid cells inside a ring of extrapolated ones)
     const double *theta;   // pointing, SoA
     const double *phi;
     const double *psi;
@@ -70,7 +71,7 @@ hipError_t launch_zero_counters(int32_t *counters, int n, hipStream_t s);
 hipError_t launch_conv(const ConvArgs &a, bool f64, int waves_per_group, int groups, hipStream_t s);
 hipError_t launch_repack4(const void *a, const void *b, const void *c, const void *d, void *out, int64_t n,
                           bool f64, hipStream_t s);
-hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, hipStream_t s);
+hipError_t launch_repack_cells(const void *b, int32_t n, void *out, bool f64, bool padded, hipStream_t s);
 // HEALPix beam maps (nside, nch channels) resampled onto an n x n node grid over [-T, T]^2.
 struct HpxGridArgs {
     int32_t nside, n, nch;

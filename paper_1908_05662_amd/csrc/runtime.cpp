@@ -696,7 +696,7 @@ pisco_status pisco_set_beam_scalar(pisco_ctx *c, int32_t det, int32_t n, double 
     if (mem != PISCO_HOST && mem != PISCO_DEVICE) return fail(c, PISCO_EINVAL, "bad mem %d", mem);
     if (!b) return fail(c, PISCO_EINVAL, "null beam");
     HIP_TRY(c, hipSetDevice(c->device));
-    const size_t nodes = (size_t)n * n, cells = (size_t)(n - 1) * (n - 1);
+    const size_t nodes = (size_t)n * n, cells = (size_t)(n + 1) * (n + 1);   // grid cells + extrapolated ring
     void *src = nullptr;
     pisco_status st = PISCO_OK;
     if (mem == PISCO_DEVICE) src = const_cast<void *>(b);
@@ -707,7 +707,7 @@ pisco_status pisco_set_beam_scalar(pisco_ctx *c, int32_t det, int32_t n, double 
         if (mem == PISCO_HOST) (void)hipFree(src);
         return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * cells);
     }
-    hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, nullptr);
+    hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, true, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (mem == PISCO_HOST) (void)hipFree(src);
     if (e != hipSuccess) {
@@ -772,7 +772,7 @@ pisco_status pisco_set_beam_v(pisco_ctx *c, int32_t det, int32_t n, double T, co
         if (mem == PISCO_HOST) (void)hipFree(src);
         return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * cells);
     }
-    hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, nullptr);
+    hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, false, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (mem == PISCO_HOST) (void)hipFree(src);
     if (e != hipSuccess) {
