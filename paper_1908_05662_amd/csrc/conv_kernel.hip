@@ -771,7 +771,7 @@ struct PairCtx {
     int32_t row_bytes;
     float sg4;            // -1 with a half-wave plate: U-row and V terms change sign
     float rowc;           // cells per grid row (bV cell polynomials)
-    float kbase;          // record index of cell (0, 0): row + 1 for one-grid beams (extrapolated ring)
+    float tmin;           // lower grid bound of t: 1 for one-grid beams (their t counts the extrapolated ring), else 0
 };
 
 // Masked contributions of NP consecutive (pixel record, sample) pairs,
@@ -817,11 +817,12 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         rq[k] = rr * zp;             // 1 / (1 + z')
         const float tu = fmaf(xp[k], rzh[k], C.c0);
         const float tv = fmaf(yp[k], rzh[k], C.c0);
-        if (CLIP) in[k] = in[k] & (tu >= 0.0f) & (tu <= C.tmax) & (tv >= 0.0f) & (tv <= C.tmax);
-        // cell indices.  One-grid beams: no clamp -- a pair inside the disc (and,
-        // with CLIP, inside the grid) has t in [0, n - 1] up to rounding, so
-        // floor(t) is a cell or one of the extrapolated cells around them, which
-        // continue the edge cells' bilinear polynomials (the value the clamped
+        if (CLIP) in[k] = in[k] & (tu >= C.tmin) & (tu <= C.tmax) & (tv >= C.tmin) & (tv <= C.tmax);
+        // cell indices.  One-grid beams: t counts from the extrapolated ring
+        // (C.c0 is one larger), and there is no clamp -- a pair inside the disc
+        // (and, with CLIP, inside the grid) has t in [1, n] up to rounding, so
+        // floor(t) is a record of the grid's cells or of the ring around them,
+        // whose polynomials continue the edge cells' (the value the clamped
         // lookup extrapolates to); other pairs are masked, and the buffer
         // resource turns any offset past the records into a zero read.
         // Four-channel beams: clamped node indices.
@@ -829,7 +830,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         const float kv = BEAM == BEAM_SCALAR ? floorf(tv) : floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
         fu[k] = tu - ku;   // exact; carries the rounding of tu (half an ulp)
         fv[k] = tv - kv;
-        off[k] = (uint32_t)fmaf(kv, C.row, ku + C.kbase) << 4;  // exact: row^2 < 2^24
+        off[k] = (uint32_t)fmaf(kv, C.row, ku) << 4;  // exact: row^2 < 2^24
     }
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
 #pragma unroll
@@ -991,7 +992,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);          // largest cell index
     const float row = (float)(BEAM == BEAM_SCALAR ? n + 1 : n);
-    const float kbase = BEAM == BEAM_SCALAR ? row + 1.0f : 0.0f;
+    const float ringoff = BEAM == BEAM_SCALAR ? 1.0f : 0.0f;   // one-grid t counts from the extrapolated ring
     const float pp3 = F.p3 + 1.0f;
     // beam records through a buffer resource: 32-bit byte offsets, reads past
     // the end return zero
@@ -1087,8 +1088,8 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     // two records per step: their masked terms are added in FP32
                     // and the pair enters the compensated sums (halves the
                     // compensation work; each pre-sum rounds once)
-                    const PairCtx C{Fg, omax, omin, clip, inv_h, c0, tmax, cmax, row, pp3, row_bytes, sg4,
-                                    (float)(n - 1), kbase};
+                    const PairCtx C{Fg, omax, omin, clip, inv_h, c0 + ringoff, tmax + ringoff, cmax, row, pp3, row_bytes,
+                                    sg4, (float)(n - 1), ringoff};
                     const float *vr = has_v ? vrec : nullptr;
                     if (clip) {
                         if (inner)
