@@ -793,7 +793,14 @@ constexpr int tile_min_waves() {
     return (MODE == MODE_STOKES || (MODE == MODE_TOD && BEAM == BEAM_FULL)) ? 2 : 4;
 }
 
-template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER>
+// SC (small cap): every pair inside the disc has omega = 1 - n.p <= SC_OMEGA, so
+// 1 / z' = 1 / (1 - omega) and 1 / (1 + z') = (1/2) / (1 - omega / 2) are their
+// geometric series to the third power (truncation below omega^4 = 2.6e-10,
+// inside FP32's rounding) instead of a quarter-rate reciprocal; pairs outside
+// the disc are masked.
+constexpr double SC_OMEGA = 4e-3;
+
+template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER, bool SC = false>
 __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp, const PairCtx &C,
                                               const BeamRsrc &beam, const BeamRsrc &vbeam) {
     const LaneFrame &F = C.F;
@@ -810,11 +817,17 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         // n . theta'_0 and n . phi'_0 in grid units (the lane's rows carry 1 / h)
         xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));
         yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));
-        // one reciprocal for both divisions of the pair: 1 / (z' (1 + z')), z' = n.p
-        const float zp = 1.0f - omg[k], zq = 2.0f - omg[k];
-        const float rr = rcp(zp * zq);
-        rzh[k] = rr * zq;            // gnomonic scale 1 / z'
-        rq[k] = rr * zp;             // 1 / (1 + z')
+        if (SC) {
+            const float w = omg[k];
+            rzh[k] = fmaf(w, fmaf(w, w + 1.0f, 1.0f), 1.0f);                   // 1 / z'
+            rq[k] = fmaf(w, fmaf(w, fmaf(w, 0.0625f, 0.125f), 0.25f), 0.5f);    // 1 / (1 + z')
+        } else {
+            // one reciprocal for both divisions of the pair: 1 / (z' (1 + z')), z' = n.p
+            const float zp = 1.0f - omg[k], zq = 2.0f - omg[k];
+            const float rr = rcp(zp * zq);
+            rzh[k] = rr * zq;            // gnomonic scale 1 / z'
+            rq[k] = rr * zp;             // 1 / (1 + z')
+        }
         const float tu = fmaf(xp[k], rzh[k], C.c0);
         const float tv = fmaf(yp[k], rzh[k], C.c0);
         if (CLIP) in[k] = in[k] & (tu >= C.tmin) & (tu <= C.tmax) & (tv >= C.tmin) & (tv <= C.tmax);
@@ -917,16 +930,16 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
 // per step, then the remainder one by one.  CLIP (the disc-versus-grid test)
 // and INNER (the inner-disc test of an annulus) are uniform per detector and
 // template switches, so the common case runs a loop without either.
-template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER>
+template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER, bool SC = false>
 __device__ __forceinline__ void consume_records(const PixRec *rec, const float *vrec, int32_t m_end, const PairCtx &C,
                                                 const BeamRsrc &beam, const BeamRsrc &vbeam, AccWide &acc0,
                                                 AccWide &acc1, AccWide &acc2, AccWide &accn) {
     int32_t m = 0;
     // two groups per compensated add: eight masked terms summed in FP32
     for (; m + 2 * TILE_NP - 1 < m_end; m += 2 * TILE_NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER>(&rec[m], vrec ? &vrec[m] : nullptr, C,
-                                                                                beam, vbeam);
-        const PairOut b = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER>(
+        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER, SC>(
+            &rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
+        const PairOut b = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER, SC>(
             &rec[m + TILE_NP], vrec ? &vrec[m + TILE_NP] : nullptr, C, beam, vbeam);
         acc0.add(a.v0 + b.v0);
         if (MODE == MODE_STOKES) {
@@ -936,8 +949,8 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
         if (PS) accn.add(a.vn + b.vn);
     }
     for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER>(&rec[m], vrec ? &vrec[m] : nullptr, C,
-                                                                                beam, vbeam);
+        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER, SC>(
+            &rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
         acc0.add(a.v0);
         if (MODE == MODE_STOKES) {
             acc1.add(a.v1);
@@ -946,8 +959,8 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
         if (PS) accn.add(a.vn);
     }
     for (; m < m_end; ++m) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP, CLIP, INNER>(&rec[m], vrec ? &vrec[m] : nullptr, C, beam,
-                                                                          vbeam);
+        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP, CLIP, INNER, SC>(&rec[m], vrec ? &vrec[m] : nullptr, C,
+                                                                              beam, vbeam);
         acc0.add(a.v0);
         if (MODE == MODE_STOKES) {
             acc1.add(a.v1);
@@ -989,6 +1002,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float omax = (float)D.omega_max, omin = D.has_inner ? (float)D.omega_min : -1.0f;
     const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
+    const bool small_cap = D.omega_max <= SC_OMEGA;    // reciprocal-free pair geometry (see tile_pairs)
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);          // largest cell index
     const float row = (float)(BEAM == BEAM_SCALAR ? n + 1 : n);
@@ -1102,6 +1116,9 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         if (inner)
                             consume_records<MODE, BEAM, PS, HWP, false, true>(L.rec, vr, m_end, C, beam, vbeam, acc0,
                                                                               acc1, acc2, accn);
+                        else if (small_cap)
+                            consume_records<MODE, BEAM, PS, HWP, false, false, true>(L.rec, vr, m_end, C, beam, vbeam,
+                                                                                     acc0, acc1, acc2, accn);
                         else
                             consume_records<MODE, BEAM, PS, HWP, false, false>(L.rec, vr, m_end, C, beam, vbeam, acc0,
                                                                                acc1, acc2, accn);
