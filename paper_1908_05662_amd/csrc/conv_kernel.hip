@@ -844,6 +844,9 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         fu[k] = tu - ku;   // exact; carries the rounding of tu (half an ulp)
         fv[k] = tv - kv;
         off[k] = (uint32_t)fmaf(kv, C.row, ku) << 4;  // exact: row^2 < 2^24
+        // wide discs: a masked pair's unclamped cell can be anywhere in a large
+        // record array, so its load is sent to record 0 (kept in cache)
+        if (BEAM == BEAM_SCALAR && !SC) off[k] = in[k] ? off[k] : 0u;
     }
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
 #pragma unroll
