@@ -371,8 +371,13 @@ __global__ void __launch_bounds__(ALM_THREADS) alm_kernel(ShtArgs a) {
             double sum = 0.0;
             const int o = lane >> 1, half = lane & 1;
             if (lane < 2 * LBLOCK * NCOMP) {
-#pragma unroll 8
-                for (int u = 0; u < 32; ++u) sum += red[(half * 32 + u) * RED_STRIDE + o];
+                // four partial sums: short dependency chains (fixed order)
+                double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < 32; u += 4)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) s4[c] += red[(half * 32 + u + c) * RED_STRIDE + o];
+                sum = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             }
             sum += __shfl_xor(sum, 1, 64);
             const int j = o / NCOMP, t = o - j * NCOMP;
