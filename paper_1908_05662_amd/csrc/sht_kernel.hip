@@ -555,7 +555,11 @@ __global__ void __launch_bounds__(SYN_THREADS) alm2ring_kernel(ShtArgs a) {
 }
 
 // x_j = Re sum_{m=0..mmax} c_m G_m e^{i m (phi0 + 2 pi j / n)}, c_0 = 1, c_m = 2:
-// the m sums folded onto k = m mod n give H; x = Re DFT(conj H).
+// the m sums folded onto k = m mod n give H, and x = Re DFT(conj H) = DFT(conj Hs)
+// with Hs[k] = (H[k] + conj H[n - k]) / 2 Hermitian.  Then the stride-P
+// subsequences of conj Hs pair up: their q-point DFTs obey
+// Y_{P-j1}[k] = e^{2 pi i k / q} conj Y_{j1}[k] (1 <= j1 < P), so only
+// j1 = 0..P/2 are summed.
 __global__ void __launch_bounds__(256) ring_synth_kernel(ShtArgs a, RingRange rr) {
     extern __shared__ double2 sh_ring[];
     const int b = blockIdx.x;
@@ -586,13 +590,24 @@ __global__ void __launch_bounds__(256) ring_synth_kernel(ShtArgs a, RingRange rr
                 hr = fma(c, fma(v.x, cs, -v.y * sn), hr);
                 hi = fma(c, fma(v.x, sn, v.y * cs), hi);
             }
-            bufA[k] = make_double2(hr, -hi);
+            bufA[k] = make_double2(hr, hi);
+        }
+        __syncthreads();
+        // bufA <- conj Hs
+        for (int k = threadIdx.x; 2 * k <= n; k += blockDim.x) {
+            const int k2 = k == 0 ? 0 : n - k;
+            const double2 u = bufA[k], v = bufA[k2];
+            const double2 hs = make_double2(0.5 * (u.x + v.x), 0.5 * (u.y - v.y));   // (H[k] + conj H[n-k]) / 2
+            bufA[k] = make_double2(hs.x, -hs.y);
+            bufA[k2] = hs;                                                        // conj of Hs[n-k] = conj conj Hs[k]
         }
         __syncthreads();
         double2 *src = bufA, *dst = bufB;
         if (q > 1) {
-            // complex input: all k2 < q; four interleaved accumulators (j2 = c mod 4)
-            for (int it = threadIdx.x; it < n; it += blockDim.x) {
+            // complex input: all k2 < q for j1 = 0..P/2 (P >= 4 on every ring with q > 1);
+            // four interleaved accumulators (j2 = c mod 4)
+            const int jhalf = P >= 4 ? P / 2 : P - 1;
+            for (int it = threadIdx.x; it < (jhalf + 1) * q; it += blockDim.x) {
                 const int j1 = it / q, k2 = it - j1 * q;
                 double ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
                 int idx = 0;
@@ -617,6 +632,15 @@ __global__ void __launch_bounds__(256) ring_synth_kernel(ShtArgs a, RingRange rr
                     idx = idx >= q ? idx - q : idx;
                 }
                 bufB[j1 * q + k2] = make_double2((ar[0] + ar[1]) + (ar[2] + ar[3]), (ai[0] + ai[1]) + (ai[2] + ai[3]));
+            }
+            __syncthreads();
+            // the rest by the pairing: Y_{j1}[k] = e^{2 pi i k / q} conj Y_{P - j1}[k]
+            for (int it = threadIdx.x; it < (P - 1 - jhalf) * q; it += blockDim.x) {
+                const int j1 = jhalf + 1 + it / q, k2 = it % q;
+                const double2 y = bufB[(P - j1) * q + k2];
+                const double2 t = tab[k2];                                          // e^{-2 pi i k / q}
+                // conj(t) * conj(y) = conj(t * y)
+                bufB[j1 * q + k2] = make_double2(t.x * y.x - t.y * y.y, -(t.x * y.y + t.y * y.x));
             }
             __syncthreads();
             src = bufB;
