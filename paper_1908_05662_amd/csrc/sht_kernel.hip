@@ -245,10 +245,10 @@ __device__ inline void pair_terms(const PairState &p, const Coef &c, double *acc
         const double X = p.m_s2 * fma(c.C, Lp, -c.D * p.z * L);
         const double2 Qa = P ? p.Qm : p.Qp, Ua = P ? p.Um : p.Up;    // parity of lambda and W
         const double2 Qb = P ? p.Qp : p.Qm, Ub = P ? p.Up : p.Um;    // parity of X
-        acc[2] += fma(W, Qa.x, -X * Ub.y);          // one dependent add per pair on each sum
-        acc[3] += fma(W, Qa.y, X * Ub.x);
-        acc[4] += fma(W, Ua.x, X * Qb.y);
-        acc[5] += fma(W, Ua.y, -X * Qb.x);
+        acc[2] = fma(-X, Ub.y, fma(W, Qa.x, acc[2]));
+        acc[3] = fma(X, Ub.x, fma(W, Qa.y, acc[3]));
+        acc[4] = fma(X, Qb.y, fma(W, Ua.x, acc[4]));
+        acc[5] = fma(-X, Qb.x, fma(W, Ua.y, acc[5]));
     }
 }
 
