@@ -227,7 +227,8 @@ void orc_healpix_to_grid(int64_t N, const double *map, double T, int n, double *
  *   beta  = angle with sin ~ sin th0 sin dphi, cos ~ cos th0 sin th - sin th0 cos th cos dphi
  *   chi   = beta + zeta - sigma
  * The arctangents of Appendix A are taken as two-argument arctangents of the
- * printed sine and cosine numerators (their common 1/sin(rho) is positive).
+ * printed sine and cosine numerators (their common 1/sin(rho) is positive);
+ * rho is computed as the angle with that cosine and sine |n0 x n|.
  */
 static void appA(double z0, double s0, double phi0, double psi0, double zeta,
                  double z, double s, double phi,
@@ -238,7 +239,12 @@ static void appA(double z0, double s0, double phi0, double psi0, double zeta,
     if (c > 1.0) c = 1.0;
     if (c < -1.0) c = -1.0;
     *cosrho = c;
-    *rho = acos(c);
+    /* rho from its sine and cosine together: the cross product of the two unit
+     * vectors, in the frame turned by phi0, has components (s sd z0,
+     * z s0 - s z0 cd, s s0 sd).  An arccosine of a cosine near 1 keeps only
+     * about half the digits of a small rho; the arctangent keeps them all. */
+    const double x1 = s * sd * z0, x2 = z * s0 - s * z0 * cd, x3 = s * s0 * sd;
+    *rho = atan2(sqrt(x1 * x1 + x2 * x2 + x3 * x3), c);
     const double alpha = atan2(s * sd, z * s0 - s * z0 * cd);
     *sigma = M_PI - psi0 - alpha;
     const double beta = atan2(s0 * sd, z0 * s - s0 * z * cd);

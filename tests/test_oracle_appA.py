@@ -31,8 +31,22 @@ def test_rho_sigma_match_vector_route():
     for t0, f0, psi, zeta, t, f in _random_pairs(rng, 300, np.deg2rad(25)):
         rho, sig, chi = oracle.appA(t0, f0, psi, zeta, t, f)
         r2, s2, *_ = brute.antenna_coords(t0, f0, psi, np.array(t), np.array(f))
-        assert abs(rho - r2) < 1e-11
+        assert abs(rho - r2) < 1e-14
         assert abs(_wrap(sig - s2)) < 1e-9
+
+
+def test_rho_full_precision_at_small_separations():
+    """rho of a direction placed at a known distance r from the pointing, for r
+    from 1e-7 rad to 1 deg: absolute error a few units of 1e-16, where an
+    arccosine of the cosine would be off by ~1e-16 / r."""
+    rng = np.random.default_rng(7)
+    for r in 10.0 ** np.arange(-7.0, -1.7, 0.5):
+        t0, f0, a = rng.uniform(0.6, 2.5), rng.uniform(0, 2 * np.pi), rng.uniform(0, 2 * np.pi)
+        p, th, ph = brute.sky_basis(t0, f0)
+        d = np.cos(r) * p + np.sin(r) * (np.cos(a) * th + np.sin(a) * ph)
+        t, f = np.arctan2(np.hypot(d[0], d[1]), d[2]), np.arctan2(d[1], d[0])
+        rho, _, _ = oracle.appA(t0, f0, 0.3, 0.0, t, f)
+        assert abs(rho - r) < 2e-15, (r, rho - r)
 
 
 def test_chi_matches_ludwig3_vector_route():
