@@ -767,7 +767,7 @@ struct PairCtx {
     LaneFrame F;
     float omax, omin;
     bool clip;
-    float inv_h, c0, tmax, cmax, row, pp3;
+    float inv_h, c0, tmax, cmax, row;
     int32_t row_bytes;
     float sg4;            // -1 with a half-wave plate: U-row and V terms change sign
     float rowc;           // cells per grid row (bV cell polynomials)
@@ -872,12 +872,14 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
     PairOut o{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        // co-polar vector carried from the boresight to the pixel along the great circle
+        // co-polar vector carried from the boresight to the pixel along the great
+        // circle, e = g - q (p + n) with q = g.n / (1 + n.p); the pixel's
+        // theta_hat and phi_hat are normal to n, so their projections take g - q p
         const float gn = fmaf(-R[k].W, F.g3, fmaf(F.g2, R[k].Y, fmaf(F.g1, R[k].X, F.g3)));
         const float q = gn * rq[k];
-        const float ex = fmaf(-q, F.p1 + R[k].X, F.g1);
-        const float ey = fmaf(-q, F.p2 + R[k].Y, F.g2);
-        const float ez = fmaf(-q, C.pp3 - R[k].W, F.g3);
+        const float ex = fmaf(-q, F.p1, F.g1);
+        const float ey = fmaf(-q, F.p2, F.g2);
+        const float ez = fmaf(-q, F.p3, F.g3);
         const float cc = fmaf(ex, R[k].t1, fmaf(ey, R[k].t2, ez * R[k].t3));
         const float ss = fmaf(ex, R[k].f1, fmaf(ey, R[k].f2, ez * R[k].f3));
         float c2 = fmaf(cc, cc, -ss * ss);   // cos 2chi, then cos(2chi + 4phi) with a plate
@@ -1010,7 +1012,6 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const float cmax = (float)(n - 2);          // largest cell index
     const float row = (float)(BEAM == BEAM_SCALAR ? n + 1 : n);
     const float ringoff = BEAM == BEAM_SCALAR ? 1.0f : 0.0f;   // one-grid t counts from the extrapolated ring
-    const float pp3 = F.p3 + 1.0f;
     // beam records through a buffer resource: 32-bit byte offsets, reads past
     // the end return zero
     const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n + 1) * (n + 1) : n * n);
@@ -1105,7 +1106,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     // two records per step: their masked terms are added in FP32
                     // and the pair enters the compensated sums (halves the
                     // compensation work; each pre-sum rounds once)
-                    const PairCtx C{Fg, omax, omin, clip, inv_h, c0 + ringoff, tmax + ringoff, cmax, row, pp3, row_bytes,
+                    const PairCtx C{Fg, omax, omin, clip, inv_h, c0 + ringoff, tmax + ringoff, cmax, row, row_bytes,
                                     sg4, (float)(n - 1), ringoff};
                     const float *vr = has_v ? vrec : nullptr;
                     if (clip) {
