@@ -772,6 +772,7 @@ struct PairCtx {
     float sg4;            // -1 with a half-wave plate: U-row and V terms change sign
     float rowc;           // cells per grid row (bV cell polynomials)
     float tmin;           // lower grid bound of t: 1 for one-grid beams (their t counts the extrapolated ring), else 0
+    uint32_t irow;        // records per row, as an integer
 };
 
 // Masked contributions of NP consecutive (pixel record, sample) pairs,
@@ -839,11 +840,23 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         // lookup extrapolates to); other pairs are masked, and the buffer
         // resource turns any offset past the records into a zero read.
         // Four-channel beams: clamped node indices.
-        const float ku = BEAM == BEAM_SCALAR ? floorf(tu) : floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
-        const float kv = BEAM == BEAM_SCALAR ? floorf(tv) : floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
-        fu[k] = tu - ku;   // exact; carries the rounding of tu (half an ulp)
-        fv[k] = tv - kv;
-        off[k] = (uint32_t)fmaf(kv, C.row, ku) << 4;  // exact: row^2 < 2^24
+        if (BEAM == BEAM_SCALAR) {
+            // truncation is the floor there (t >= 0 up to rounding; a masked pair's
+            // index only picks some record or a zero read, and wide discs send it
+            // to record 0 below), fract gives t - floor(t) exactly, and the record
+            // offset takes one 24-bit multiply-add (row < 4097)
+            const uint32_t iu = (uint32_t)(int32_t)tu, iv = (uint32_t)(int32_t)tv;
+            fu[k] = __builtin_amdgcn_fractf(tu);
+            fv[k] = __builtin_amdgcn_fractf(tv);
+            off[k] = (uint32_t)__umul24(iv, C.irow) + iu;
+            off[k] <<= 4;
+        } else {
+            const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
+            const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
+            fu[k] = tu - ku;   // exact; carries the rounding of tu (half an ulp)
+            fv[k] = tv - kv;
+            off[k] = (uint32_t)fmaf(kv, C.row, ku) << 4;  // exact: row^2 < 2^24
+        }
         // wide discs: a masked pair's unclamped cell can be anywhere in a large
         // record array, so its load is sent to record 0 (kept in cache)
         if (BEAM == BEAM_SCALAR && !SC) off[k] = in[k] ? off[k] : 0u;
@@ -1107,7 +1120,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     // and the pair enters the compensated sums (halves the
                     // compensation work; each pre-sum rounds once)
                     const PairCtx C{Fg, omax, omin, clip, inv_h, c0 + ringoff, tmax + ringoff, cmax, row, row_bytes,
-                                    sg4, (float)(n - 1), ringoff};
+                                    sg4, (float)(n - 1), ringoff, (uint32_t)row};
                     const float *vr = has_v ? vrec : nullptr;
                     if (clip) {
                         if (inner)
