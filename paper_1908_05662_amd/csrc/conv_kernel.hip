@@ -796,12 +796,14 @@ constexpr int tile_min_waves() {
 
 // SC (small cap): every pair inside the disc has omega = 1 - n.p <= SC_OMEGA, so
 // 1 / z' = 1 / (1 - omega) and 1 / (1 + z') = (1/2) / (1 - omega / 2) are their
-// geometric series to the third power (truncation below omega^4 = 2.6e-10,
-// inside FP32's rounding) instead of a quarter-rate reciprocal; pairs outside
-// the disc are masked.
+// geometric series instead of a quarter-rate reciprocal; pairs outside the disc
+// are masked.  SC = 1: to the third power (truncation below omega^4 = 2.6e-10,
+// inside FP32's rounding); SC = 2, for omega <= SC2_OMEGA: to the second power
+// (truncation below omega^3 = 1e-9), two instructions fewer.
 constexpr double SC_OMEGA = 4e-3;
+constexpr double SC2_OMEGA = 1e-3;
 
-template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER, bool SC = false>
+template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER, int SC = 0>
 __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp, const PairCtx &C,
                                               const BeamRsrc &beam, const BeamRsrc &vbeam) {
     const LaneFrame &F = C.F;
@@ -818,7 +820,11 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         // n . theta'_0 and n . phi'_0 in grid units (the lane's rows carry 1 / h)
         xp[k] = fmaf(-R[k].W, F.a3, fmaf(R[k].Y, F.a2, fmaf(R[k].X, F.a1, F.a3)));
         yp[k] = fmaf(-R[k].W, F.b3, fmaf(R[k].Y, F.b2, fmaf(R[k].X, F.b1, F.b3)));
-        if (SC) {
+        if (SC == 2) {
+            const float w = omg[k];
+            rzh[k] = fmaf(w, w + 1.0f, 1.0f);                                  // 1 / z'
+            rq[k] = fmaf(w, fmaf(w, 0.125f, 0.25f), 0.5f);                      // 1 / (1 + z')
+        } else if (SC == 1) {
             const float w = omg[k];
             rzh[k] = fmaf(w, fmaf(w, w + 1.0f, 1.0f), 1.0f);                   // 1 / z'
             rq[k] = fmaf(w, fmaf(w, fmaf(w, 0.0625f, 0.125f), 0.25f), 0.5f);    // 1 / (1 + z')
@@ -859,7 +865,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         }
         // wide discs: a masked pair's unclamped cell can be anywhere in a large
         // record array, so its load is sent to record 0 (kept in cache)
-        if (BEAM == BEAM_SCALAR && !SC) off[k] = in[k] ? off[k] : 0u;
+        if (BEAM == BEAM_SCALAR && SC == 0) off[k] = in[k] ? off[k] : 0u;
     }
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
 #pragma unroll
@@ -948,7 +954,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
 // per step, then the remainder one by one.  CLIP (the disc-versus-grid test)
 // and INNER (the inner-disc test of an annulus) are uniform per detector and
 // template switches, so the common case runs a loop without either.
-template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER, bool SC = false>
+template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER, int SC = 0>
 __device__ __forceinline__ void consume_records(const PixRec *rec, const float *vrec, int32_t m_end, const PairCtx &C,
                                                 const BeamRsrc &beam, const BeamRsrc &vbeam, AccWide &acc0,
                                                 AccWide &acc1, AccWide &acc2, AccWide &accn) {
@@ -1021,6 +1027,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const bool inner = D.has_inner != 0;
     const bool clip = D.needs_clip != 0;
     const bool small_cap = D.omega_max <= SC_OMEGA;    // reciprocal-free pair geometry (see tile_pairs)
+    const bool tiny_cap = D.omega_max <= SC2_OMEGA;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);          // largest cell index
     const float row = (float)(BEAM == BEAM_SCALAR ? n + 1 : n);
@@ -1133,9 +1140,12 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                         if (inner)
                             consume_records<MODE, BEAM, PS, HWP, false, true>(L.rec, vr, m_end, C, beam, vbeam, acc0,
                                                                               acc1, acc2, accn);
+                        else if (tiny_cap)
+                            consume_records<MODE, BEAM, PS, HWP, false, false, 2>(L.rec, vr, m_end, C, beam, vbeam,
+                                                                                  acc0, acc1, acc2, accn);
                         else if (small_cap)
-                            consume_records<MODE, BEAM, PS, HWP, false, false, true>(L.rec, vr, m_end, C, beam, vbeam,
-                                                                                     acc0, acc1, acc2, accn);
+                            consume_records<MODE, BEAM, PS, HWP, false, false, 1>(L.rec, vr, m_end, C, beam, vbeam,
+                                                                                  acc0, acc1, acc2, accn);
                         else
                             consume_records<MODE, BEAM, PS, HWP, false, false>(L.rec, vr, m_end, C, beam, vbeam, acc0,
                                                                                acc1, acc2, accn);
