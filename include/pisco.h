@@ -338,6 +338,92 @@ pisco_status pisco_sidelobe_apply(pisco_ctx *ctx, pisco_mlp *mlp, int32_t det, c
                                   const double *coef, float *tod, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Far-sidelobe surrogate of a detector, trained and used by the library.
+ *
+ * For a detector with a one-grid (scalar) beam b and FIXED normalisation,
+ * the TOD over its disc rho <= rho_max splits exactly into the main disc
+ * rho <= r_main and the annulus r_main < rho <= rho_max (Sec. 4.2: the
+ * pixelated sum is additive over disjoint pixel sets).  The annulus term is
+ *   sum_c coef[c] P[c],  coef = (wI, wQ cos2z - wU sin2z, wQ sin2z + wU cos2z) / wT
+ * with P the annulus' Stokes pickup (OUT_STOKES) of the same beam at
+ * zeta = 0 and z = zeta (the pixel angle chi grows by zeta, Appendix A).
+ * P depends on the pointing only, so a network can stand in for it.
+ *
+ * pisco_sidelobe_train(ctx, det, r_main_rad, n_train, seed, epochs):
+ *   draws n_train pointings (direction uniform on the sphere, psi uniform in
+ *   [0, 2 pi), SplitMix64 outputs 3i .. 3i+2 of `seed` for pointing i),
+ *   computes their exact annulus pickups P with the convolution kernels,
+ *   standardises each channel (mean, sample standard deviation), and trains
+ *   a network 5 -> [width, SiLU] x hidden_layers -> 3 (the network
+ *   section above) on the standardised targets: `epochs` passes, each over
+ *   floor(n_train / batch) * batch rows in a fresh pseudo-random order (a
+ *   Feistel bijection keyed by the seed and the epoch), one Adam step per
+ *   batch, the learning rate decaying from lr to lr_end along a cosine over
+ *   all steps.  Runs synchronously; the detector's previous network, if any,
+ *   is replaced.  Needs: a scalar beam without V weight, no plate, FIXED
+ *   normalisation, wT != 0, 0 < r_main_rad < rho_max, n_train >= batch,
+ *   epochs >= 1 (EINVAL otherwise; ESTATE without sky, beam or parameters).
+ *   The pointing of `det` is not used (it may be unset).  Changing the
+ *   detector's beam or parameters later drops the network.
+ * pisco_sidelobe_enable(ctx, det, on): with on != 0 (ESTATE if untrained),
+ *   OUT_TOD convolves of `det` (alone or batched) evaluate the exact sum over
+ *   rho <= r_main only and add sum_c coef[c] (mean[c] + std[c] y[c]) with y the
+ *   network's output for the sample's pointing (one fused launch per
+ *   detector, queued after the convolution on the same stream and captured
+ *   in the same graph).  OUT_STOKES and OUT_COUNT stay exact over the whole
+ *   disc.  on = 0 restores the exact TOD.
+ * pisco_sidelobe_share(ctx, det, src): detector `det` uses the network
+ *   trained for `src` (kept alive while any detector uses it): once enabled,
+ *   its OUT_TOD is the exact sum over rho <= min(its rho_max, r_main of src)
+ *   with its own beam, plus the network's annulus pickup (of src's beam)
+ *   weighted by its own (wI, wQ, wU) turned by its zeta, times
+ *   N_det / (N_src wT_src) -- e.g. many detectors with their own main beams
+ *   sharing one far-sidelobe grid.  det needs what training needs (scalar
+ *   beam without V, no plate, FIXED normalisation); ESTATE if src is
+ *   untrained.  Enabling stays per detector.
+ * pisco_sidelobe_history: copies up to `cap` per-epoch mean training losses
+ *   of the last run into `loss` (may be NULL) and returns the epoch count (0
+ *   if untrained, -1 for a bad detector).
+ * pisco_sidelobe_set_options: network and optimiser of later training runs
+ *   (width a multiple of 64 in [64, 512], hidden_layers in [1, 16], batch a
+ *   multiple of 64 in [64, 4194304], 0 < lr_end <= lr, 0 <= beta < 1,
+ *   eps > 0).  Defaults: {256, 4, 8192, 2e-3, 2e-5, 0.9, 0.999, 1e-8}.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t width;
+    int32_t hidden_layers;
+    int32_t batch;
+    float lr, lr_end;
+    float beta1, beta2, eps;
+} pisco_sidelobe_opts;
+pisco_status pisco_sidelobe_set_options(pisco_ctx *ctx, const pisco_sidelobe_opts *opts);
+pisco_status pisco_sidelobe_train(pisco_ctx *ctx, int32_t det, double r_main_rad, int64_t n_train, uint64_t seed,
+                                  int32_t epochs);
+pisco_status pisco_sidelobe_enable(pisco_ctx *ctx, int32_t det, int on);
+pisco_status pisco_sidelobe_share(pisco_ctx *ctx, int32_t det, int32_t src);
+int32_t pisco_sidelobe_history(const pisco_ctx *ctx, int32_t det, double *loss, int32_t cap);
+
+/* ------------------------------------------------------------------------
+ * Device-memory budget (the paper runs discs that overflow device memory in
+ * serial blocks, Sec. 5.3).  pisco_set_memory_budget caps the device memory
+ * this context allocates for its sky, beams, pointing and plate copies, work
+ * queues and output staging at `bytes` (0: no cap beyond the device's).
+ * When a host pointing or plate-angle stream would exceed the budget (or its
+ * allocation fails), the context keeps the host copy instead; convolve then
+ * streams such detectors -- and every call whose queues or output staging do
+ * not fit -- through device buffers sized to the remaining budget, in blocks
+ * of consecutive samples (multiples of 64, so every block starts a tile of
+ * the given order and the results equal those of the resident path for
+ * PISCO_ORDER_GIVEN), block after block on the call's stream, synchronously.
+ * PISCO_ENOMEM is returned only when not even a 64-sample block fits.
+ * Lowering the budget below what is already allocated is allowed; it applies
+ * to later allocations.  pisco_memory_in_use reports the bytes counted
+ * against the budget now.
+ * ------------------------------------------------------------------------ */
+pisco_status pisco_set_memory_budget(pisco_ctx *ctx, int64_t bytes);
+int64_t pisco_memory_in_use(const pisco_ctx *ctx);
+
+/* ------------------------------------------------------------------------
  * Binned maps from TOD: the map-making step the TOD are handed to (Sec. 5.1)
  * and from which the validation maps are made (Sec. 6).
  *

@@ -24,6 +24,13 @@ class Launch(ctypes.Structure):
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
+class SidelobeOpts(ctypes.Structure):
+    """Mirror of pisco_sidelobe_opts."""
+    _fields_ = [("width", ctypes.c_int32), ("hidden_layers", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("lr_end", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 _STATUS = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ESTATE: "ESTATE",
            EUNSUPPORTED: "EUNSUPPORTED"}
 
@@ -72,6 +79,13 @@ SIGNATURES = [
     ("pisco_sidelobe_features", ctypes.c_int, [_vp, _i32, _vp, _vp]),
     ("pisco_sidelobe_apply", ctypes.c_int, [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_float),
                                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_dbl), _vp, _vp]),
+    ("pisco_sidelobe_set_options", ctypes.c_int, [_vp, ctypes.c_void_p]),
+    ("pisco_sidelobe_train", ctypes.c_int, [_vp, _i32, _dbl, _i64, ctypes.c_uint64, _i32]),
+    ("pisco_sidelobe_enable", ctypes.c_int, [_vp, _i32, ctypes.c_int]),
+    ("pisco_sidelobe_share", ctypes.c_int, [_vp, _i32, _i32]),
+    ("pisco_sidelobe_history", _i32, [_vp, _i32, ctypes.POINTER(_dbl), _i32]),
+    ("pisco_set_memory_budget", ctypes.c_int, [_vp, _i64]),
+    ("pisco_memory_in_use", _i64, [_vp]),
     ("pisco_map_accumulate", ctypes.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _dbl, _dbl, _dbl,
                                             _vp, _vp]),
     ("pisco_map_solve", ctypes.c_int, [_vp, _i64, _vp, _dbl, _vp, _vp, _vp]),

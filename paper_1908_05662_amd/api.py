@@ -218,8 +218,13 @@ class Convolver:
         shape = (n, 3) if out_mode == L.OUT_STOKES else (n,)
         if out is None:
             out = torch.empty(shape, dtype=self.dtype, device=self.torch_device)
-        if tuple(out.shape) != shape or out.dtype != self.dtype or not out.is_cuda or not out.is_contiguous():
-            raise ValueError(f"out must be a contiguous {self.dtype} device tensor of shape {shape}")
+        if tuple(out.shape) != shape or out.dtype != self.dtype or not out.is_contiguous() or \
+                (out.is_cuda and out.device != self.torch_device):
+            raise ValueError(f"out must be a contiguous {self.dtype} tensor of shape {shape} on the host or "
+                             f"{self.torch_device}")
+        if not out.is_cuda:   # host output: the library synchronises and copies
+            self._check(self._lib.pisco_convolve(self._h, int(det), int(out_mode), out.data_ptr(), L.HOST, None))
+            return out
         s = stream if stream is not None else torch.cuda.current_stream(self.torch_device)
         self._check(self._lib.pisco_convolve(self._h, int(det), int(out_mode), out.data_ptr(), L.DEVICE,
                                              ctypes.c_void_p(s.cuda_stream)))
@@ -243,6 +248,45 @@ class Convolver:
         l = L.Launch()
         self._check(self._lib.pisco_get_launch(self._h, ctypes.byref(l)))
         return l.as_dict()
+
+    def set_memory_budget(self, nbytes: int):
+        """Cap the device memory this context allocates (0: no cap); streams that do
+        not fit are convolved in blocks of samples (``pisco_set_memory_budget``)."""
+        self._check(self._lib.pisco_set_memory_budget(self._h, int(nbytes)))
+
+    def memory_in_use(self) -> int:
+        return int(self._lib.pisco_memory_in_use(self._h))
+
+    def sidelobe_options(self, width: int = 256, hidden_layers: int = 4, batch: int = 8192, lr: float = 2e-3,
+                         lr_end: float = 2e-5, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        """Network and optimiser of later ``sidelobe_train`` runs."""
+        o = L.SidelobeOpts(int(width), int(hidden_layers), int(batch), float(lr), float(lr_end), float(beta1),
+                           float(beta2), float(eps))
+        self._check(self._lib.pisco_sidelobe_set_options(self._h, ctypes.byref(o)))
+
+    def sidelobe_train(self, det: int, r_main: float, n_train: int, seed: int = 1, epochs: int = 40):
+        """Train detector `det`'s far-sidelobe network on exact annulus pickups
+        (r_main, rho_max] of n_train library-drawn pointings; returns the per-epoch
+        mean training losses."""
+        self._check(self._lib.pisco_sidelobe_train(self._h, int(det), float(r_main), int(n_train),
+                                                   ctypes.c_uint64(seed), int(epochs)))
+        return self.sidelobe_history(det)
+
+    def sidelobe_enable(self, det: int, on: bool = True):
+        """TOD of `det` = exact main disc + the trained network (on) or the exact disc (off)."""
+        self._check(self._lib.pisco_sidelobe_enable(self._h, int(det), int(bool(on))))
+
+    def sidelobe_share(self, det: int, src: int):
+        """Detector `det` uses the network trained for `src` (its own beam, weights and zeta)."""
+        self._check(self._lib.pisco_sidelobe_share(self._h, int(det), int(src)))
+
+    def sidelobe_history(self, det: int):
+        n = int(self._lib.pisco_sidelobe_history(self._h, int(det), None, 0))
+        if n <= 0:
+            return []
+        buf = (ctypes.c_double * n)()
+        self._lib.pisco_sidelobe_history(self._h, int(det), buf, n)
+        return list(buf)
 
     def set_timing(self, on: bool = True):
         self._check(self._lib.pisco_set_timing(self._h, int(bool(on))))
@@ -306,25 +350,45 @@ class Mlp:
             raise ValueError("wrong parameter count")
         self.conv._check(self._lib.pisco_mlp_set_params(self._h, t.data_ptr(), self.conv._mem(t)))
 
+    def _rows(self, x, cols, name, batch=False):
+        """A contiguous float32 device copy (or view) of x with shape (n, cols); with
+        batch, n must be a multiple of 64 in [64, max_batch].  The caller keeps
+        the returned tensor alive until the library call has been queued."""
+        torch = _torch()
+        if not torch.is_tensor(x) or x.dtype != torch.float32 or x.device != self.conv.torch_device \
+                or x.dim() != 2 or x.shape[1] != cols:
+            raise ValueError(f"{name} must be a float32 tensor of shape (n, {cols}) on {self.conv.torch_device}")
+        n = x.shape[0]
+        if batch and (n < 64 or n > self.max_batch or n % 64):
+            raise ValueError(f"{name}: batch of {n} rows must be a multiple of 64 in [64, {self.max_batch}]")
+        return x.contiguous()
+
     def forward(self, x, stream=None):
         torch = _torch()
-        x = x.contiguous()
-        y = torch.empty((x.shape[0], 3), dtype=torch.float32, device=x.device)
-        self.conv._check(self._lib.pisco_mlp_forward(self._h, x.data_ptr(), x.shape[0], y.data_ptr(),
+        xc = self._rows(x, 5, "x")
+        y = torch.empty((xc.shape[0], 3), dtype=torch.float32, device=xc.device)
+        self.conv._check(self._lib.pisco_mlp_forward(self._h, xc.data_ptr(), xc.shape[0], y.data_ptr(),
                                                      self._stream(stream)))
         return y
 
     def gradient(self, x, t, stream=None):
         torch = _torch()
-        g = torch.empty(self.n_params, dtype=torch.float32, device=x.device)
-        self.conv._check(self._lib.pisco_mlp_gradient(self._h, x.contiguous().data_ptr(), t.contiguous().data_ptr(),
-                                                      x.shape[0], g.data_ptr(), self._loss.data_ptr(),
-                                                      self._stream(stream)))
+        xc = self._rows(x, 5, "x", batch=True)
+        tc = self._rows(t, 3, "targets", batch=True)
+        if tc.shape[0] != xc.shape[0]:
+            raise ValueError("x and targets must have the same number of rows")
+        g = torch.empty(self.n_params, dtype=torch.float32, device=xc.device)
+        self.conv._check(self._lib.pisco_mlp_gradient(self._h, xc.data_ptr(), tc.data_ptr(), xc.shape[0],
+                                                      g.data_ptr(), self._loss.data_ptr(), self._stream(stream)))
         return self._loss.clone(), g
 
     def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         """One Adam step; returns the (device) loss tensor of the batch before the update."""
-        self.conv._check(self._lib.pisco_mlp_train_step(self._h, x.data_ptr(), t.data_ptr(), x.shape[0],
+        xc = self._rows(x, 5, "x", batch=True)
+        tc = self._rows(t, 3, "targets", batch=True)
+        if tc.shape[0] != xc.shape[0]:
+            raise ValueError("x and targets must have the same number of rows")
+        self.conv._check(self._lib.pisco_mlp_train_step(self._h, xc.data_ptr(), tc.data_ptr(), xc.shape[0],
                                                         float(lr), float(beta1), float(beta2), float(eps),
                                                         self._loss.data_ptr(), self._stream(stream)))
         return self._loss

@@ -9,9 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpisco.so")
-SOURCES = ["conv_kernel.hip", "mlp_kernels.hip", "map_kernel.hip", "order_kernel.hip", "sht_kernel.hip", "runtime.cpp",
-           "mlp_runtime.cpp", "sht_runtime.cpp",
-           "map_runtime.cpp"]
+SOURCES = ["conv_kernel.hip", "mlp_kernels.hip", "map_kernel.hip", "order_kernel.hip", "sht_kernel.hip",
+           "sidelobe_kernel.hip", "runtime.cpp", "mlp_runtime.cpp", "sht_runtime.cpp", "map_runtime.cpp",
+           "sidelobe_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Every HIP translation unit: gfx950 only, -O3, and no packed FP32 instructions.
@@ -24,15 +24,25 @@ def sources():
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    """Compile every translation unit (in parallel) and link libpisco.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
+    jobs = []
     for src in sources():
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
-        cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o", obj]
+        jobs.append((obj, [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-c", src, "-o", obj]))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+
+    def compile_one(job):
+        obj, cmd = job
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
-        objs.append(obj)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        objs = list(ex.map(compile_one, jobs))
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)

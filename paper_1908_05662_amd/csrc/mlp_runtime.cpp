@@ -12,6 +12,7 @@
 #include "mlp_internal.h"
 #include "pisco.h"
 #include "pisco_internal.h"
+#include "sidelobe_internal.h"
 
 struct pisco_mlp {
     pisco_ctx *ctx = nullptr;
@@ -110,6 +111,35 @@ pisco_status run(pisco_mlp *m, const float *x, const float *tgt, int32_t n, floa
 }
 
 }  // namespace
+
+namespace pisco {
+// one fused launch over the whole stream (features, every layer and the
+// epilogue on chip); equal bit for bit to features + forward + apply
+hipError_t mlp_apply_pointing(const pisco_mlp *m, const double *th, const double *ph, const double *ps, int64_t n,
+                              const float mean[3], const float stdv[3], const double coef[3], float *tod,
+                              hipStream_t s) {
+    MlpInferArgs a{};
+    a.th = th;
+    a.ph = ph;
+    a.ps = ps;
+    a.n = n;
+    a.H = m->H;
+    a.L = m->L;
+    a.wb = m->wb;
+    a.w = m->w;
+    for (int l = 0; l <= m->L; ++l) {
+        a.off_w[l] = m->off_w[l];
+        a.off_b[l] = m->off_b[l];
+    }
+    for (int c = 0; c < MLP_OUT; ++c) {
+        a.mean[c] = mean[c];
+        a.stdv[c] = stdv[c];
+        a.coef[c] = coef[c];
+    }
+    a.tod = tod;
+    return mlp_infer_apply(a, s);
+}
+}  // namespace pisco
 
 extern "C" {
 
@@ -293,28 +323,7 @@ pisco_status pisco_sidelobe_apply(pisco_ctx *ctx, pisco_mlp *m, int32_t det, con
         pisco::set_error(ctx, "detector has no pointing");
         return PISCO_ESTATE;
     }
-    // one fused launch over the whole stream (features, every layer and the
-    // epilogue on chip); equal bit for bit to features + forward + apply
-    pisco::MlpInferArgs a{};
-    a.th = th;
-    a.ph = ph;
-    a.ps = ps;
-    a.n = n;
-    a.H = m->H;
-    a.L = m->L;
-    a.wb = m->wb;
-    a.w = m->w;
-    for (int l = 0; l <= m->L; ++l) {
-        a.off_w[l] = m->off_w[l];
-        a.off_b[l] = m->off_b[l];
-    }
-    for (int c = 0; c < MLP_OUT; ++c) {
-        a.mean[c] = mean[c];
-        a.stdv[c] = stdv[c];
-        a.coef[c] = coef[c];
-    }
-    a.tod = tod;
-    MLP_TRY(m, pisco::mlp_infer_apply(a, static_cast<hipStream_t>(stream)));
+    MLP_TRY(m, pisco::mlp_apply_pointing(m, th, ph, ps, n, mean, stdv, coef, tod, static_cast<hipStream_t>(stream)));
     return PISCO_OK;
 }
 

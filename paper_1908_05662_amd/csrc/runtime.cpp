@@ -8,17 +8,37 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "pisco.h"
 #include "pisco_internal.h"
+#include "sidelobe_internal.h"
 
 using pisco::ConvArgs;
 using pisco::DetDesc;
 using pisco::Tile;
 
 namespace {
+
+// A trained far-sidelobe network and what its outputs mean: the annulus
+// (r_main, R] pickups of the training detector's beam at zeta = 0, which
+// include that detector's wT and normalisation.  Shared by every detector that
+// uses it; released with the last one.
+struct SlNet {
+    pisco_mlp *net = nullptr;
+    float mean[3] = {0.0f, 0.0f, 0.0f}, stdv[3] = {1.0f, 1.0f, 1.0f};
+    double r_main = 0.0, wT = 1.0, norm = 1.0;
+    std::vector<double> hist;
+    SlNet() = default;
+    SlNet(const SlNet &) = delete;
+    SlNet &operator=(const SlNet &) = delete;
+    ~SlNet() {
+        if (net) pisco_mlp_destroy(net);
+    }
+};
 
 struct DetState {
     bool has_beam = false, has_params = false, has_pointing = false;
@@ -41,6 +61,11 @@ struct DetState {
     double *owned_pointing = nullptr;  // one allocation holding th, ph, ps when copied
     int32_t *order = nullptr;          // spatial processing order of the pointing (plan-time), owned
     size_t order_cap = 0;
+    std::vector<double> host_pointing;  // pointing kept on the host (memory budget): theta | phi | psi
+    std::vector<double> host_hwp;       // plate angles kept on the host (memory budget)
+    // far-sidelobe surrogate: a network standing in for the annulus beyond its r_main
+    std::shared_ptr<SlNet> sl;
+    bool sl_on = false;
 };
 
 struct TimedLaunch {
@@ -56,6 +81,15 @@ struct Queues {
     size_t cap = 0;
     int32_t per = 1, nq = 1;
     int64_t ntiles = 0;
+};
+
+// The fused network epilogue of one surrogate-substituted detector in a launch.
+struct SlApply {
+    const pisco_mlp *net;
+    const double *th, *ph, *ps;
+    int64_t n, out_offset;
+    float mean[3], stdv[3];
+    double coef[3];
 };
 
 // A device-side launch plan: detector descriptors, the tile-path and
@@ -79,6 +113,8 @@ struct Plan {
     int32_t vbeam = 0;       // some detector of the plan has a full beam with a V column
     int32_t hwp = 0;         // some detector of the plan has a half-wave plate
     int32_t extended = 0;    // some detector has a plate or V terms (not on the matrix-core path)
+    int32_t sub = -1;        // TOD plans: surrogate-enabled detectors run their main disc + network
+    std::vector<SlApply> sl; // their epilogues
     // captured launch
     hipGraphExec_t gexec = nullptr;
     uint64_t g_gen = 0;
@@ -104,8 +140,14 @@ struct pisco_ctx {
     double coherence = 0.5;
     int32_t ordering = PISCO_ORDER_AUTO;   // processing order of the samples
 
-    Plan plans[2];            // [0] batched (det = -1), [1] single detector
+    Plan plans[3];            // [0] batched (det = -1), [1] single detector, [2] blocks of the budgeted path
     int32_t *d_flag = nullptr;
+
+    // device memory counted against the budget (0: none)
+    int64_t budget = 0, in_use = 0;
+    std::unordered_map<void *, size_t> dsize;
+    bool sky_owned = true;     // false: the sky records are borrowed from another context
+    pisco_sidelobe_opts sl_opts = {256, 4, 8192, 2e-3f, 2e-5f, 0.9f, 0.999f, 1e-8f};
 
     bool timing = false;
     std::vector<TimedLaunch> pending;
@@ -137,6 +179,30 @@ bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 size_t rec_bytes(int dtype) { return dtype == PISCO_F64 ? 32 : 16; }
 size_t el_bytes(int dtype) { return dtype == PISCO_F64 ? 8 : 4; }
 
+// Device allocations of a context, counted against its memory budget.
+bool dmalloc(pisco_ctx *c, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 1;
+    if (c->budget > 0 && c->in_use + (int64_t)bytes > c->budget) return false;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return false;
+    }
+    c->dsize[*p] = bytes;
+    c->in_use += (int64_t)bytes;
+    return true;
+}
+
+void dfree(pisco_ctx *c, void *p) {
+    if (!p) return;
+    auto it = c->dsize.find(p);
+    if (it != c->dsize.end()) {
+        c->in_use -= (int64_t)it->second;
+        c->dsize.erase(it);
+    }
+    (void)hipFree(p);
+}
+
 DetState *det_slot(pisco_ctx *c, int32_t det) {
     if (det < 0 || det >= PISCO_MAX_DETECTORS) return nullptr;
     if ((size_t)det >= c->dets.size()) c->dets.resize(det + 1);
@@ -144,6 +210,13 @@ DetState *det_slot(pisco_ctx *c, int32_t det) {
 }
 
 bool det_ready(const DetState &d) { return d.has_beam && d.has_params && d.has_pointing; }
+
+// The trained far-sidelobe network of a detector no longer matches once its
+// beam or disc changes.
+void release_sidelobe(DetState &d) {
+    d.sl.reset();
+    d.sl_on = false;
+}
 
 void release_beam(pisco_ctx *c, int32_t det) {
     DetState &d = c->dets[det];
@@ -154,28 +227,32 @@ void release_beam(pisco_ctx *c, int32_t det) {
                 c->dets[k].beam = nullptr;
                 c->dets[k].beam_v = nullptr;
                 c->dets[k].has_beam = false;
+                release_sidelobe(c->dets[k]);
             }
-        (void)hipFree(d.beam);
-        if (d.beam_v) (void)hipFree(d.beam_v);
+        dfree(c, d.beam);
+        dfree(c, d.beam_v);
     }
     d.beam = nullptr;
     d.beam_v = nullptr;
     d.wv = 0.0;
     d.beam_owned = false;
     d.has_beam = false;
+    release_sidelobe(d);
 }
 
-void release_hwp(DetState &d) {
-    if (d.owned_hwp) (void)hipFree(d.owned_hwp);
+void release_hwp(pisco_ctx *c, DetState &d) {
+    dfree(c, d.owned_hwp);
     d.owned_hwp = nullptr;
     d.hwp = nullptr;
     d.hwp_n = 0;
+    std::vector<double>().swap(d.host_hwp);
 }
 
-void release_pointing(DetState &d) {
-    if (d.owned_pointing) (void)hipFree(d.owned_pointing);
+void release_pointing(pisco_ctx *c, DetState &d) {
+    dfree(c, d.owned_pointing);
     d.owned_pointing = nullptr;
-    if (d.order) (void)hipFree(d.order);
+    dfree(c, d.order);
+    std::vector<double>().swap(d.host_pointing);
     d.order = nullptr;
     d.order_cap = 0;
     d.th = d.ph = d.ps = nullptr;
@@ -188,13 +265,13 @@ void drop_graph(Plan &p) {
     p.gexec = nullptr;
 }
 
-void free_plan(Plan &p) {
+void free_plan(pisco_ctx *c, Plan &p) {
     drop_graph(p);
-    if (p.d_dets) (void)hipFree(p.d_dets);
-    if (p.tq.d_tiles) (void)hipFree(p.tq.d_tiles);
-    if (p.pq.d_tiles) (void)hipFree(p.pq.d_tiles);
-    if (p.d_ctrl) (void)hipFree(p.d_ctrl);
-    if (p.d_scratch) (void)hipFree(p.d_scratch);
+    dfree(c, p.d_dets);
+    dfree(c, p.tq.d_tiles);
+    dfree(c, p.pq.d_tiles);
+    dfree(c, p.d_ctrl);
+    dfree(c, p.d_scratch);
     p = Plan();
 }
 
@@ -205,10 +282,10 @@ pisco_status to_device(pisco_ctx *c, const void *src, size_t bytes, int mem, voi
         *out = nullptr;
         return PISCO_OK;
     }
-    if (hipMalloc(&p, bytes) != hipSuccess) return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    if (!dmalloc(c, &p, bytes)) return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", bytes);
     const hipError_t e = hipMemcpy(p, src, bytes, mem == PISCO_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(p);
+        dfree(c, p);
         return fail(c, PISCO_EDEVICE, "copy to device failed: %s", hipGetErrorString(e));
     }
     *out = p;
@@ -220,7 +297,7 @@ pisco_status interleave(pisco_ctx *c, const void *a, const void *b, const void *
                         int dtype, int mem, void **out) {
     const size_t eb = el_bytes(dtype);
     void *rec = nullptr;
-    if (hipMalloc(&rec, rec_bytes(dtype) * (size_t)n) != hipSuccess)
+    if (!dmalloc(c, &rec, rec_bytes(dtype) * (size_t)n))
         return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * (size_t)n);
     const void *src[4] = {a, b, cc, d};
     void *tmp[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -240,9 +317,9 @@ pisco_status interleave(pisco_ctx *c, const void *a, const void *b, const void *
     }
     if (mem == PISCO_HOST)
         for (int k = 0; k < 4; ++k)
-            if (tmp[k]) (void)hipFree(tmp[k]);
+            dfree(c, tmp[k]);
     if (st != PISCO_OK) {
-        (void)hipFree(rec);
+        dfree(c, rec);
         return st;
     }
     *out = rec;
@@ -254,11 +331,10 @@ bool grow(pisco_ctx *c, T **p, size_t *cap, size_t need) {
     if (*cap >= need) return true;
     size_t nc = std::max(need, *cap * 2 + 16);
     void *q = nullptr;
-    if (hipMalloc(&q, nc * sizeof(T)) != hipSuccess) return false;
-    if (*p) (void)hipFree(*p);
+    if (!dmalloc(c, &q, nc * sizeof(T)) && !(nc > need && dmalloc(c, &q, (nc = need) * sizeof(T)))) return false;
+    dfree(c, *p);
     *p = static_cast<T *>(q);
     *cap = nc;
-    (void)c;
     return true;
 }
 
@@ -275,60 +351,71 @@ void fill_queues(const std::vector<Tile> &tiles, int nq, std::vector<Tile> &qt, 
     }
 }
 
-// Build and upload the tile plan for `det` (-1 = all ready detectors).
-pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
-    if (p.gen == c->generation && p.det == det && p.spt == c->spt && p.xq == c->xq && p.algo == c->algo &&
-        p.coherence == c->coherence)
-        return PISCO_OK;
-    std::vector<DetDesc> descs;
-    std::vector<int32_t> det_of;   // detector index of each descriptor
-    int64_t out_off = 0;
+// Weights of the annulus pickup (P_I, P_Q, P_U at zeta = 0) in the TOD of a
+// scalar-beam detector at angle zeta: the pixel angle chi grows by zeta, which
+// turns the Q, U pickups by 2 zeta.
+// The pickups of a network trained on another detector's beam carry that
+// detector's wT and normalisation instead of this one's.
+void sidelobe_coef(const DetState &d, double coef[3]) {
+    const double c2 = std::cos(2.0 * d.zeta), s2 = std::sin(2.0 * d.zeta);
+    const double f = d.norm_scale / (d.sl->norm * d.sl->wT);
+    coef[0] = f * d.w[0];
+    coef[1] = f * (d.w[1] * c2 - d.w[2] * s2);
+    coef[2] = f * (d.w[1] * s2 + d.w[2] * c2);
+}
+
+// The kernels' description of a detector (pointing and output offset left to
+// the caller).  sub: the detector's trained surrogate stands in for the
+// annulus, so the exact disc ends at its main radius.
+DetDesc make_desc(const DetState &d, bool sub) {
+    DetDesc x{};
+    const double rho_max = sub ? std::min(d.rho_max, d.sl->r_main) : d.rho_max;
+    x.beam = d.beam;
+    x.n_samples = d.nsamp;
+    x.zeta = d.zeta;
+    x.cos_rho_max = std::cos(rho_max);
+    x.cos_rho_min = std::cos(d.rho_min);
+    x.rho_max = rho_max;
+    x.norm_scale = d.norm_scale;
+    x.half_span_tan = d.T;
+    x.inv_h = (double)(d.n - 1) / (2.0 * d.T);
+    x.omega_max = 2.0 * std::sin(0.5 * rho_max) * std::sin(0.5 * rho_max);
+    x.omega_min = 2.0 * std::sin(0.5 * d.rho_min) * std::sin(0.5 * d.rho_min);
+    for (int i = 0; i < 4; ++i) x.w[i] = d.w[i];
+    x.beam_v = d.beam_v;
+    x.wv = d.wv;
+    x.hwp = d.hwp;
+    // a disc inside the grid's square maps every member into the grid (|u|, |v| <= tan rho)
+    x.needs_clip = (std::tan(rho_max) <= d.T * (1.0 + 1e-12)) ? 0 : 1;
+    x.n = d.n;
+    x.norm_mode = d.norm_mode;
+    x.has_inner = d.rho_min > 0.0 ? 1 : 0;
+    x.order = nullptr;
+    return x;
+}
+
+// Upload descriptors, classify their 64-sample groups (tile paths) and fill the
+// work queues of plan p.  det_of[i] names the detector of descs[i] (for its
+// spatial processing order, taken when may_reorder).
+pisco_status build_plan(pisco_ctx *c, Plan &p, std::vector<DetDesc> &descs, const std::vector<int32_t> &det_of,
+                        bool may_reorder) {
     p.per_sample = 0;
     p.hwp = 0;
     p.vbeam = 0;
     p.extended = 0;
-    const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
-    for (int32_t k = lo; k <= hi; ++k) {
-        const DetState &d = c->dets[k];
-        if (!det_ready(d)) continue;
-        DetDesc x{};
-        x.beam = d.beam;
-        x.theta = d.th;
-        x.phi = d.ph;
-        x.psi = d.ps;
-        x.n_samples = d.nsamp;
-        x.out_offset = out_off;
-        x.zeta = d.zeta;
-        x.cos_rho_max = std::cos(d.rho_max);
-        x.cos_rho_min = std::cos(d.rho_min);
-        x.rho_max = d.rho_max;
-        x.norm_scale = d.norm_scale;
-        x.half_span_tan = d.T;
-        x.inv_h = (double)(d.n - 1) / (2.0 * d.T);
-        x.omega_max = 2.0 * std::sin(0.5 * d.rho_max) * std::sin(0.5 * d.rho_max);
-        x.omega_min = 2.0 * std::sin(0.5 * d.rho_min) * std::sin(0.5 * d.rho_min);
-        for (int i = 0; i < 4; ++i) x.w[i] = d.w[i];
-        x.beam_v = d.beam_v;
-        x.wv = d.wv;
-        x.hwp = d.hwp;
-        if (d.hwp) p.hwp = 1;
-        if (d.beam_v) p.vbeam = 1;
-        if (d.beam_v || d.wv != 0.0 || d.hwp) p.extended = 1;
-        // a disc inside the grid's square maps every member into the grid (|u|, |v| <= tan rho)
-        x.needs_clip = (std::tan(d.rho_max) <= d.T * (1.0 + 1e-12)) ? 0 : 1;
-        x.n = d.n;
-        x.norm_mode = d.norm_mode;
-        x.has_inner = d.rho_min > 0.0 ? 1 : 0;
-        x.order = nullptr;
-        descs.push_back(x);
-        det_of.push_back(k);
-        out_off += d.nsamp;
-        p.beam_kind = d.beam_kind;
-        if (d.norm_mode == PISCO_NORM_PER_SAMPLE) p.per_sample = 1;
+    int64_t out_end = 0;
+    for (const DetDesc &x : descs) {
+        if (x.hwp) p.hwp = 1;
+        if (x.beam_v) p.vbeam = 1;
+        if (x.beam_v || x.wv != 0.0 || x.hwp) p.extended = 1;
+        if (x.norm_mode == PISCO_NORM_PER_SAMPLE) p.per_sample = 1;
+        out_end = std::max(out_end, x.out_offset + x.n_samples);
     }
     hipError_t e = hipDeviceSynchronize();  // no launch may still read the old plan
     if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "synchronise failed: %s", hipGetErrorString(e));
-    if (!p.d_ctrl && hipMalloc(&p.d_ctrl, 32 * sizeof(int32_t)) != hipSuccess)
+    p.gen = 0;  // the plan is incomplete until the end of this function
+    drop_graph(p);
+    if (!p.d_ctrl && !dmalloc(c, reinterpret_cast<void **>(&p.d_ctrl), 32 * sizeof(int32_t)))
         return fail(c, PISCO_ENOMEM, "plan allocation failed");
     if (!grow(c, &p.d_dets, &p.d_dets_cap, std::max<size_t>(descs.size(), 1)))
         return fail(c, PISCO_ENOMEM, "plan allocation failed");
@@ -342,7 +429,7 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         descs[i].order = d.order;
         return PISCO_OK;
     };
-    if (c->ordering == PISCO_ORDER_SPATIAL)
+    if (may_reorder && c->ordering == PISCO_ORDER_SPATIAL)
         for (size_t i = 0; i < descs.size(); ++i)
             if (descs[i].n_samples > 64) {
                 const pisco_status so = set_order(i);
@@ -368,10 +455,11 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
         if (!tile_path || groups.empty()) return PISCO_OK;
         const size_t need = groups.size() * (sizeof(Tile) + sizeof(int32_t));
         if (p.scratch_cap < need) {
-            if (p.d_scratch) (void)hipFree(p.d_scratch);
+            dfree(c, p.d_scratch);
             p.d_scratch = nullptr;
             p.scratch_cap = 0;
-            if (hipMalloc(&p.d_scratch, need) != hipSuccess) return fail(c, PISCO_ENOMEM, "plan scratch allocation failed");
+            if (!dmalloc(c, reinterpret_cast<void **>(&p.d_scratch), need))
+                return fail(c, PISCO_ENOMEM, "plan scratch allocation failed");
             p.scratch_cap = need;
         }
         Tile *dg = reinterpret_cast<Tile *>(p.d_scratch);
@@ -383,7 +471,7 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
     };
     pisco_status cs = classify();
     if (cs != PISCO_OK) return cs;
-    if (c->ordering == PISCO_ORDER_AUTO && tile_path) {
+    if (may_reorder && c->ordering == PISCO_ORDER_AUTO && tile_path) {
         // detectors whose given order leaves most groups incoherent are processed in spatial order
         std::vector<int64_t> coherent(descs.size(), 0), total(descs.size(), 0);
         for (size_t g = 0; g < groups.size(); ++g) {
@@ -440,14 +528,62 @@ pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det) {
     p.tq.nq = p.pq.nq = nq;
     p.tq.ntiles = (int64_t)ttiles.size();
     p.pq.ntiles = (int64_t)ptiles.size();
+    p.out_samples = out_end;
+    return PISCO_OK;
+}
+
+// The surrogate epilogue of detector state d writing from output sample `off`.
+SlApply sl_apply_of(const DetState &d, const double *th, const double *ph, const double *ps, int64_t n, int64_t off) {
+    SlApply a{};
+    a.net = d.sl->net;
+    a.th = th;
+    a.ph = ph;
+    a.ps = ps;
+    a.n = n;
+    a.out_offset = off;
+    for (int k = 0; k < 3; ++k) {
+        a.mean[k] = d.sl->mean[k];
+        a.stdv[k] = d.sl->stdv[k];
+    }
+    sidelobe_coef(d, a.coef);
+    return a;
+}
+
+// Build and upload the plan for `det` (-1 = all ready detectors) and output mode.
+pisco_status prepare_plan(pisco_ctx *c, Plan &p, int32_t det, int out_mode) {
+    const int32_t sub = out_mode == PISCO_OUT_TOD ? 1 : 0;
+    if (p.gen == c->generation && p.det == det && p.spt == c->spt && p.xq == c->xq && p.algo == c->algo &&
+        p.coherence == c->coherence && p.sub == sub)
+        return PISCO_OK;
+    std::vector<DetDesc> descs;
+    std::vector<int32_t> det_of;   // detector index of each descriptor
+    p.sl.clear();
+    int64_t out_off = 0;
+    const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
+    for (int32_t k = lo; k <= hi; ++k) {
+        const DetState &d = c->dets[k];
+        if (!det_ready(d)) continue;
+        const bool sl = sub && d.sl_on && d.sl;
+        DetDesc x = make_desc(d, sl);
+        x.theta = d.th;
+        x.phi = d.ph;
+        x.psi = d.ps;
+        x.out_offset = out_off;
+        if (sl) p.sl.push_back(sl_apply_of(d, d.th, d.ph, d.ps, d.nsamp, out_off));
+        descs.push_back(x);
+        det_of.push_back(k);
+        out_off += d.nsamp;
+        p.beam_kind = d.beam_kind;
+    }
+    const pisco_status st = build_plan(c, p, descs, det_of, true);
+    if (st != PISCO_OK) return st;
     p.gen = c->generation;
     p.det = det;
     p.spt = c->spt;
     p.xq = c->xq;
     p.algo = c->algo;
     p.coherence = c->coherence;
-    p.out_samples = out_off;
-    drop_graph(p);
+    p.sub = sub;
     return PISCO_OK;
 }
 
@@ -483,7 +619,16 @@ hipError_t enqueue(pisco_ctx *c, const Plan &p, void *out, int out_mode, hipStre
         e = pisco::launch_conv(make_args(c, p, out, out_mode, true), f64, c->wpg, c->gpc * c->num_cu, s);
         if (e != hipSuccess) return e;
     }
-    if (p.pq.ntiles > 0) e = pisco::launch_conv(make_args(c, p, out, out_mode, false), f64, c->wpg, c->gpc * c->num_cu, s);
+    if (p.pq.ntiles > 0) {
+        e = pisco::launch_conv(make_args(c, p, out, out_mode, false), f64, c->wpg, c->gpc * c->num_cu, s);
+        if (e != hipSuccess) return e;
+    }
+    // far-sidelobe network of surrogate-enabled detectors, added to their TOD
+    for (const SlApply &a : p.sl) {
+        e = pisco::mlp_apply_pointing(a.net, a.th, a.ph, a.ps, a.n, a.mean, a.stdv, a.coef,
+                                      static_cast<float *>(out) + a.out_offset, s);
+        if (e != hipSuccess) return e;
+    }
     return e;
 }
 
@@ -499,6 +644,7 @@ bool ctx_pointing(const pisco_ctx *c, int32_t det, const double **th, const doub
                   int64_t *n) {
     if (det < 0 || (size_t)det >= c->dets.size() || !c->dets[det].has_pointing) return false;
     const DetState &d = c->dets[det];
+    if (d.nsamp > 0 && !d.th) return false;  // kept on the host (memory budget)
     *th = d.th;
     *ph = d.ph;
     *ps = d.ps;
@@ -523,7 +669,7 @@ pisco_status pisco_create(int device, pisco_ctx **out) {
     pisco_ctx *c = new pisco_ctx();
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
-    if (hipMalloc(&c->d_flag, sizeof(int32_t)) != hipSuccess) {
+    if (!dmalloc(c, reinterpret_cast<void **>(&c->d_flag), sizeof(int32_t))) {
         delete c;
         return PISCO_ENOMEM;
     }
@@ -535,18 +681,19 @@ void pisco_destroy(pisco_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
-    for (auto &p : c->plans) free_plan(p);
+    for (auto &p : c->plans) free_plan(c, p);
     for (auto &t : c->pending) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }
     for (size_t k = 0; k < c->dets.size(); ++k) {
         release_beam(c, (int32_t)k);
-        release_pointing(c->dets[k]);
-        release_hwp(c->dets[k]);
+        release_pointing(c, c->dets[k]);
+        release_hwp(c, c->dets[k]);
+        release_sidelobe(c->dets[k]);
     }
-    if (c->sky) (void)hipFree(c->sky);
-    if (c->d_flag) (void)hipFree(c->d_flag);
+    if (c->sky && c->sky_owned) dfree(c, c->sky);
+    dfree(c, c->d_flag);
     delete c;
 }
 
@@ -570,8 +717,9 @@ pisco_status pisco_set_sky_iquv(pisco_ctx *c, int64_t nside, const void *I, cons
     const pisco_status st = interleave(c, I, Q, U, V, 12 * nside * nside, dtype, mem, &rec);
     if (st != PISCO_OK) return st;
     HIP_TRY(c, hipDeviceSynchronize());
-    if (c->sky) (void)hipFree(c->sky);
+    if (c->sky && c->sky_owned) dfree(c, c->sky);
     c->sky = rec;
+    c->sky_owned = true;
     c->nside = nside;
     c->sky_dtype = dtype;
     ++c->generation;
@@ -634,7 +782,7 @@ static pisco_status healpix_nodes(pisco_ctx *c, int64_t nside_b, const void *con
         nodes[k] = nullptr;
         if (mem == PISCO_HOST) st = to_device(c, maps[k], mbytes, PISCO_HOST, &staged[k]);
         a.map[k] = mem == PISCO_HOST ? staged[k] : maps[k];
-        if (st == PISCO_OK && hipMalloc(&nodes[k], nbytes) != hipSuccess)
+        if (st == PISCO_OK && !dmalloc(c, &nodes[k], nbytes))
             st = fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", nbytes);
         a.out[k] = nodes[k];
     }
@@ -644,11 +792,11 @@ static pisco_status healpix_nodes(pisco_ctx *c, int64_t nside_b, const void *con
         if (e != hipSuccess) st = fail(c, PISCO_EDEVICE, "beam map resampling failed: %s", hipGetErrorString(e));
     }
     for (int k = 0; k < nch; ++k)
-        if (staged[k]) (void)hipFree(staged[k]);
+        dfree(c, staged[k]);
     if (st != PISCO_OK)
         for (int k = 0; k < nch; ++k)
             if (nodes[k]) {
-                (void)hipFree(nodes[k]);
+                dfree(c, nodes[k]);
                 nodes[k] = nullptr;
             }
     return st;
@@ -664,7 +812,7 @@ pisco_status pisco_set_beam_healpix(pisco_ctx *c, int32_t det, int64_t nside_bea
     pisco_status st = healpix_nodes(c, nside_beam, maps, 4, n, T, dtype, mem, nodes);
     if (st != PISCO_OK) return st;
     st = pisco_set_beam(c, det, n, T, nodes[0], nodes[1], nodes[2], nodes[3], dtype, PISCO_DEVICE);
-    for (int k = 0; k < 4; ++k) (void)hipFree(nodes[k]);
+    for (int k = 0; k < 4; ++k) dfree(c, nodes[k]);
     return st;
 }
 
@@ -678,7 +826,7 @@ pisco_status pisco_set_beam_healpix_scalar(pisco_ctx *c, int32_t det, int64_t ns
     pisco_status st = healpix_nodes(c, nside_beam, maps, 1, n, T, dtype, mem, nodes);
     if (st != PISCO_OK) return st;
     st = pisco_set_beam_scalar(c, det, n, T, nodes[0], wI, wQ, wU, wT, dtype, PISCO_DEVICE);
-    (void)hipFree(nodes[0]);
+    dfree(c, nodes[0]);
     return st;
 }
 
@@ -703,15 +851,15 @@ pisco_status pisco_set_beam_scalar(pisco_ctx *c, int32_t det, int32_t n, double 
     else st = to_device(c, b, el_bytes(dtype) * nodes, PISCO_HOST, &src);
     if (st != PISCO_OK) return st;
     void *rec = nullptr;
-    if (hipMalloc(&rec, rec_bytes(dtype) * cells) != hipSuccess) {
-        if (mem == PISCO_HOST) (void)hipFree(src);
+    if (!dmalloc(c, &rec, rec_bytes(dtype) * cells)) {
+        if (mem == PISCO_HOST) dfree(c, src);
         return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * cells);
     }
     hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, true, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (mem == PISCO_HOST) (void)hipFree(src);
+    if (mem == PISCO_HOST) dfree(c, src);
     if (e != hipSuccess) {
-        (void)hipFree(rec);
+        dfree(c, rec);
         return fail(c, PISCO_EDEVICE, "beam repack failed: %s", hipGetErrorString(e));
     }
     release_beam(c, det);
@@ -768,15 +916,15 @@ pisco_status pisco_set_beam_v(pisco_ctx *c, int32_t det, int32_t n, double T, co
     if (mem == PISCO_DEVICE) src = const_cast<void *>(bV);
     else if ((st = to_device(c, bV, el_bytes(dtype) * nodes, PISCO_HOST, &src)) != PISCO_OK) return st;
     void *rec = nullptr;
-    if (hipMalloc(&rec, rec_bytes(dtype) * cells) != hipSuccess) {
-        if (mem == PISCO_HOST) (void)hipFree(src);
+    if (!dmalloc(c, &rec, rec_bytes(dtype) * cells)) {
+        if (mem == PISCO_HOST) dfree(c, src);
         return fail(c, PISCO_ENOMEM, "device allocation of %zu bytes failed", rec_bytes(dtype) * cells);
     }
     hipError_t e = pisco::launch_repack_cells(src, n, rec, dtype == PISCO_F64, false, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (mem == PISCO_HOST) (void)hipFree(src);
+    if (mem == PISCO_HOST) dfree(c, src);
     if (e != hipSuccess) {
-        (void)hipFree(rec);
+        dfree(c, rec);
         return fail(c, PISCO_EDEVICE, "beam repack failed: %s", hipGetErrorString(e));
     }
     c->dets[det].beam_v = rec;
@@ -805,26 +953,29 @@ pisco_status pisco_set_hwp(pisco_ctx *c, int32_t det, int64_t n, const double *a
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipDeviceSynchronize());
     if (!angle || n == 0) {
-        release_hwp(*d);
+        release_hwp(c, *d);
         ++c->generation;
         return PISCO_OK;
     }
     if (mem == PISCO_HOST) {
         for (int64_t i = 0; i < n; ++i)
             if (!std::isfinite(angle[i])) return fail(c, PISCO_EINVAL, "plate angle %lld is not finite", (long long)i);
-        double *buf = nullptr;
-        if (hipMalloc(&buf, sizeof(double) * (size_t)n) != hipSuccess)
-            return fail(c, PISCO_ENOMEM, "plate-angle allocation failed");
-        const hipError_t e = hipMemcpy(buf, angle, sizeof(double) * (size_t)n, hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(buf);
-            return fail(c, PISCO_EDEVICE, "plate-angle copy failed: %s", hipGetErrorString(e));
+        release_hwp(c, *d);
+        void *buf = nullptr;
+        if (dmalloc(c, &buf, sizeof(double) * (size_t)n)) {
+            const hipError_t e = hipMemcpy(buf, angle, sizeof(double) * (size_t)n, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                dfree(c, buf);
+                return fail(c, PISCO_EDEVICE, "plate-angle copy failed: %s", hipGetErrorString(e));
+            }
+            d->owned_hwp = static_cast<double *>(buf);
+            d->hwp = d->owned_hwp;
+        } else {
+            // over the memory budget: keep the angles on the host, streamed in blocks by convolve
+            d->host_hwp.assign(angle, angle + n);
         }
-        release_hwp(*d);
-        d->owned_hwp = buf;
-        d->hwp = buf;
     } else {
-        release_hwp(*d);
+        release_hwp(c, *d);
         d->hwp = angle;
     }
     d->hwp_n = n;
@@ -849,6 +1000,7 @@ pisco_status pisco_set_detector(pisco_ctx *c, int32_t det, double zeta, double r
     d->norm_mode = norm_mode;
     d->norm_scale = norm_scale;
     d->has_params = true;
+    release_sidelobe(*d);
     ++c->generation;
     return PISCO_OK;
 }
@@ -869,25 +1021,33 @@ pisco_status pisco_set_pointing(pisco_ctx *c, int32_t det, int64_t n, const doub
             if (!std::isfinite(t) || t < 0.0 || t > M_PI || !std::isfinite(phi[i]) || !std::isfinite(psi[i]))
                 return fail(c, PISCO_EINVAL, "pointing sample %lld is non-finite or has theta outside [0, pi]", (long long)i);
         }
-        double *buf = nullptr;
-        if (n > 0) {
-            if (hipMalloc(&buf, 3 * sizeof(double) * (size_t)n) != hipSuccess)
-                return fail(c, PISCO_ENOMEM, "pointing allocation failed");
+        HIP_TRY(c, hipDeviceSynchronize());
+        release_pointing(c, *d);
+        void *vb = nullptr;
+        if (n > 0 && dmalloc(c, &vb, 3 * sizeof(double) * (size_t)n)) {
+            double *buf = static_cast<double *>(vb);
             const size_t b = sizeof(double) * (size_t)n;
             hipError_t e = hipMemcpy(buf, theta, b, hipMemcpyHostToDevice);
             if (e == hipSuccess) e = hipMemcpy(buf + n, phi, b, hipMemcpyHostToDevice);
             if (e == hipSuccess) e = hipMemcpy(buf + 2 * n, psi, b, hipMemcpyHostToDevice);
             if (e != hipSuccess) {
-                (void)hipFree(buf);
+                dfree(c, buf);
+                d->has_pointing = false;
+                d->nsamp = 0;
+                ++c->generation;
                 return fail(c, PISCO_EDEVICE, "pointing copy failed: %s", hipGetErrorString(e));
             }
+            d->owned_pointing = buf;
+            d->th = buf;
+            d->ph = buf + n;
+            d->ps = buf + 2 * n;
+        } else if (n > 0) {
+            // over the memory budget: keep the pointing on the host, streamed in blocks by convolve
+            d->host_pointing.resize(3 * (size_t)n);
+            std::memcpy(d->host_pointing.data(), theta, sizeof(double) * (size_t)n);
+            std::memcpy(d->host_pointing.data() + n, phi, sizeof(double) * (size_t)n);
+            std::memcpy(d->host_pointing.data() + 2 * n, psi, sizeof(double) * (size_t)n);
         }
-        HIP_TRY(c, hipDeviceSynchronize());
-        release_pointing(*d);
-        d->owned_pointing = buf;
-        d->th = buf;
-        d->ph = buf ? buf + n : nullptr;
-        d->ps = buf ? buf + 2 * n : nullptr;
     } else {
         if (n > 0) {
             HIP_TRY(c, hipMemset(c->d_flag, 0, sizeof(int32_t)));
@@ -897,7 +1057,7 @@ pisco_status pisco_set_pointing(pisco_ctx *c, int32_t det, int64_t n, const doub
             if (bad) return fail(c, PISCO_EINVAL, "pointing holds non-finite values or theta outside [0, pi]");
         }
         HIP_TRY(c, hipDeviceSynchronize());
-        release_pointing(*d);
+        release_pointing(c, *d);
         d->th = theta;
         d->ph = phi;
         d->ps = psi;
@@ -917,6 +1077,120 @@ int64_t pisco_output_samples(const pisco_ctx *c, int32_t det) {
     return s;
 }
 
+}  // extern "C"
+
+namespace {
+
+// The budgeted path: every ready detector of [lo, hi] streamed in blocks of
+// consecutive samples (multiples of 64) through device buffers that fit the
+// remaining budget, block after block on stream s.
+pisco_status convolve_blocks(pisco_ctx *c, int32_t det, int out_mode, void *out, int mem, hipStream_t s) {
+    const size_t el = el_bytes(c->sky_dtype) * (out_mode == PISCO_OUT_STOKES ? 3 : 1);  // bytes per output sample
+    const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
+    // the resident plans' buffers make room for the blocks
+    for (int i = 0; i < 2; ++i) free_plan(c, c->plans[i]);
+    Plan &p = c->plans[2];
+    const bool sub = out_mode == PISCO_OUT_TOD;
+    int64_t out_base = 0;
+    for (int32_t k = lo; k <= hi; ++k) {
+        const DetState &d = c->dets[k];
+        if (!det_ready(d)) continue;
+        const int64_t n = d.nsamp;
+        const bool hp = !d.host_pointing.empty(), hh = !d.host_hwp.empty();
+        const bool sl = sub && d.sl_on && d.sl;
+        // device bytes per sample of a block: staged pointing, plate angles and
+        // output, and the queues (tile entries and classification flags of its
+        // 64-sample groups); a fixed part for the descriptor and control block
+        const int64_t per = (hp ? 24 : 0) + (hh ? 8 : 0) + (mem == PISCO_HOST ? (int64_t)el : 0) + 2;
+        const int64_t fixed = 8192;
+        const int64_t room = c->budget > 0 ? c->budget - c->in_use - fixed : ((int64_t)1 << 50);
+        int64_t C = room > 0 ? room / per : 0;
+        C = std::min<int64_t>(C, ((n + 63) / 64) * 64);
+        C = (C / 64) * 64;
+        void *bp = nullptr, *bh = nullptr, *bo = nullptr;
+        for (;;) {
+            if (C < 64) {
+                free_plan(c, p);
+                return fail(c, PISCO_ENOMEM, "detector %d: the device memory budget (%lld bytes, %lld in use) leaves "
+                            "no room for a 64-sample block", k, (long long)c->budget, (long long)c->in_use);
+            }
+            const bool ok = (!hp || dmalloc(c, &bp, 24 * (size_t)C)) && (!hh || dmalloc(c, &bh, 8 * (size_t)C)) &&
+                            (mem != PISCO_HOST || dmalloc(c, &bo, el * (size_t)C));
+            if (ok) break;
+            dfree(c, bp);
+            dfree(c, bh);
+            dfree(c, bo);
+            bp = bh = bo = nullptr;
+            C = ((C / 2) / 64) * 64;
+        }
+        auto release = [&]() {
+            dfree(c, bp);
+            dfree(c, bh);
+            dfree(c, bo);
+        };
+        for (int64_t b = 0; b < n; b += C) {
+            const int64_t m = std::min(C, n - b);
+            const double *th = d.th ? d.th + b : nullptr, *ph = d.ph ? d.ph + b : nullptr,
+                         *ps = d.ps ? d.ps + b : nullptr, *hw = d.hwp ? d.hwp + b : nullptr;
+            hipError_t e = hipSuccess;
+            if (hp) {
+                double *q = static_cast<double *>(bp);
+                const size_t bytes = sizeof(double) * (size_t)m;
+                e = hipMemcpy(q, d.host_pointing.data() + b, bytes, hipMemcpyHostToDevice);
+                if (e == hipSuccess) e = hipMemcpy(q + C, d.host_pointing.data() + n + b, bytes, hipMemcpyHostToDevice);
+                if (e == hipSuccess)
+                    e = hipMemcpy(q + 2 * C, d.host_pointing.data() + 2 * n + b, bytes, hipMemcpyHostToDevice);
+                th = q;
+                ph = q + C;
+                ps = q + 2 * C;
+            }
+            if (hh && e == hipSuccess) {
+                e = hipMemcpy(bh, d.host_hwp.data() + b, sizeof(double) * (size_t)m, hipMemcpyHostToDevice);
+                hw = static_cast<const double *>(bh);
+            }
+            if (e != hipSuccess) {
+                release();
+                return fail(c, PISCO_EDEVICE, "block upload failed: %s", hipGetErrorString(e));
+            }
+            DetDesc x = make_desc(d, sl);
+            x.theta = th;
+            x.phi = ph;
+            x.psi = ps;
+            x.hwp = hw;
+            x.n_samples = m;
+            x.out_offset = 0;
+            std::vector<DetDesc> descs{x};
+            const std::vector<int32_t> det_of{k};
+            p.beam_kind = d.beam_kind;
+            p.sl.clear();
+            if (sl) p.sl.push_back(sl_apply_of(d, th, ph, ps, m, 0));
+            const pisco_status st = build_plan(c, p, descs, det_of, false);
+            if (st != PISCO_OK) {
+                release();
+                return st;
+            }
+            void *o = mem == PISCO_HOST ? bo : static_cast<void *>(static_cast<char *>(out) + (out_base + b) * el);
+            e = enqueue(c, p, o, out_mode, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);   // the staging buffers are reused by the next block
+            if (e == hipSuccess && mem == PISCO_HOST)
+                e = hipMemcpy(static_cast<char *>(out) + (out_base + b) * el, bo, el * (size_t)m,
+                              hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                release();
+                return fail(c, PISCO_EDEVICE, "block convolution failed: %s", hipGetErrorString(e));
+            }
+        }
+        release();
+        out_base += n;
+    }
+    free_plan(c, p);
+    return PISCO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, int mem, void *stream) {
     if (!c) return PISCO_EINVAL;
     c->err.clear();
@@ -929,16 +1203,18 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
         if ((size_t)det >= c->dets.size() || !det_ready(c->dets[det]))
             return fail(c, PISCO_ESTATE, "detector %d lacks a beam, parameters or pointing", det);
     }
-    bool any = false;
+    bool any = false, host_resident = false;
     int first_kind = -1;
+    int64_t nall = 0;
     const int32_t lo = det < 0 ? 0 : det, hi = det < 0 ? (int32_t)c->dets.size() - 1 : det;
     for (int32_t k = lo; k <= hi; ++k) {
         const DetState &d = c->dets[k];
         if (!det_ready(d)) continue;
         any = true;
+        nall += d.nsamp;
         if (d.beam_dtype != c->sky_dtype)
             return fail(c, PISCO_EINVAL, "detector %d beam dtype differs from the sky dtype", k);
-        if (d.hwp && d.hwp_n != d.nsamp)
+        if ((d.hwp || !d.host_hwp.empty()) && d.hwp_n != d.nsamp)
             return fail(c, PISCO_EINVAL, "detector %d has %lld plate angles for %lld samples", k, (long long)d.hwp_n,
                         (long long)d.nsamp);
         // a V column adds 4 bytes of LDS per staged record and wave on the tile path
@@ -947,30 +1223,56 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
                 160 * 1024)
             return fail(c, PISCO_EINVAL, "detector %d: a V-column beam needs more LDS than chunk %d with %d waves "
                         "per group leaves; use a smaller chunk or fewer waves", k, c->chunk, c->wpg);
+        if (d.sl_on && out_mode == PISCO_OUT_TOD && c->sky_dtype != PISCO_F32)
+            return fail(c, PISCO_EINVAL, "detector %d: the sidelobe network runs on the FP32 path only", k);
         if (first_kind < 0) first_kind = d.beam_kind;
         if (d.beam_kind != first_kind)
             return fail(c, PISCO_EINVAL, "detectors in one launch must all have full or all scalar beams");
+        if (!d.host_pointing.empty() || !d.host_hwp.empty()) host_resident = true;
     }
     if (!any) return fail(c, PISCO_ESTATE, "no detector is ready");
+    if (nall > 0 && !out) return fail(c, PISCO_EINVAL, "null output");
     HIP_TRY(c, hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (mem == PISCO_HOST) s = nullptr;
+    TimedLaunch tl{};
+    auto timing_start = [&]() -> pisco_status {
+        if (c->timing) {
+            HIP_TRY(c, hipEventCreate(&tl.a));
+            HIP_TRY(c, hipEventCreate(&tl.b));
+            HIP_TRY(c, hipEventRecord(tl.a, s));
+        }
+        return PISCO_OK;
+    };
+    auto timing_end = [&]() -> pisco_status {
+        if (c->timing) {
+            HIP_TRY(c, hipEventRecord(tl.b, s));
+            c->pending.push_back(tl);
+        }
+        return PISCO_OK;
+    };
+    auto blocks = [&]() -> pisco_status {
+        pisco_status st = timing_start();
+        if (st == PISCO_OK) st = convolve_blocks(c, det, out_mode, out, mem, s);
+        if (st == PISCO_OK) st = timing_end();
+        return st;
+    };
+    if (host_resident) return blocks();
     Plan &p = c->plans[det < 0 ? 0 : 1];
-    pisco_status st = prepare_plan(c, p, det);
+    pisco_status st = prepare_plan(c, p, det, out_mode);
+    if (st == PISCO_ENOMEM) {  // the work queues do not fit: run in blocks
+        c->err.clear();
+        return blocks();
+    }
     if (st != PISCO_OK) return st;
     const int64_t nout = p.out_samples * (out_mode == PISCO_OUT_STOKES ? 3 : 1);
     if (nout == 0) return PISCO_OK;
-    if (!out) return fail(c, PISCO_EINVAL, "null output");
-    hipStream_t s = static_cast<hipStream_t>(stream);
     void *dout = out;
-    if (mem == PISCO_HOST) {
-        s = nullptr;
-        if (hipMalloc(&dout, el_bytes(c->sky_dtype) * (size_t)nout) != hipSuccess)
-            return fail(c, PISCO_ENOMEM, "output staging allocation failed");
-    }
-    TimedLaunch tl{};
-    if (c->timing) {
-        HIP_TRY(c, hipEventCreate(&tl.a));
-        HIP_TRY(c, hipEventCreate(&tl.b));
-        HIP_TRY(c, hipEventRecord(tl.a, s));
+    if (mem == PISCO_HOST && !dmalloc(c, &dout, el_bytes(c->sky_dtype) * (size_t)nout)) return blocks();
+    st = timing_start();
+    if (st != PISCO_OK) {
+        if (mem == PISCO_HOST) dfree(c, dout);
+        return st;
     }
     hipError_t e = hipSuccess;
     const bool use_graph = (det < 0) && (s != nullptr);
@@ -1004,19 +1306,16 @@ pisco_status pisco_convolve(pisco_ctx *c, int32_t det, int out_mode, void *out, 
         e = enqueue(c, p, dout, out_mode, s);
     }
     if (e != hipSuccess) {
-        if (mem == PISCO_HOST) (void)hipFree(dout);
+        if (mem == PISCO_HOST) dfree(c, dout);
         return fail(c, PISCO_EDEVICE, "convolution launch failed: %s", hipGetErrorString(e));
     }
-    if (c->timing) {
-        HIP_TRY(c, hipEventRecord(tl.b, s));
-        c->pending.push_back(tl);
-    }
+    st = timing_end();
     if (mem == PISCO_HOST) {
         e = hipMemcpy(out, dout, el_bytes(c->sky_dtype) * (size_t)nout, hipMemcpyDeviceToHost);
-        (void)hipFree(dout);
+        dfree(c, dout);
         if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "output copy failed: %s", hipGetErrorString(e));
     }
-    return PISCO_OK;
+    return st;
 }
 
 pisco_status pisco_set_ordering(pisco_ctx *c, int32_t mode) {
@@ -1101,6 +1400,167 @@ pisco_status pisco_kernel_time(pisco_ctx *c, double *total_ms, int64_t *launches
         c->launches = 0;
     }
     return PISCO_OK;
+}
+
+pisco_status pisco_set_memory_budget(pisco_ctx *c, int64_t bytes) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (bytes < 0) return fail(c, PISCO_EINVAL, "memory budget must be >= 0");
+    c->budget = bytes;
+    return PISCO_OK;
+}
+
+int64_t pisco_memory_in_use(const pisco_ctx *c) { return c ? c->in_use : -1; }
+
+pisco_status pisco_sidelobe_set_options(pisco_ctx *c, const pisco_sidelobe_opts *o) {
+    if (!c || !o) return PISCO_EINVAL;
+    c->err.clear();
+    if (o->width < 64 || o->width > 512 || o->width % 64)
+        return fail(c, PISCO_EINVAL, "width must be a multiple of 64 in [64, 512]");
+    if (o->hidden_layers < 1 || o->hidden_layers > 16) return fail(c, PISCO_EINVAL, "hidden_layers must be in [1, 16]");
+    if (o->batch < 64 || o->batch > (1 << 22) || o->batch % 64)
+        return fail(c, PISCO_EINVAL, "batch must be a multiple of 64 in [64, 4194304]");
+    if (!(o->lr_end > 0.0f) || !(o->lr >= o->lr_end) || !std::isfinite(o->lr))
+        return fail(c, PISCO_EINVAL, "need 0 < lr_end <= lr");
+    if (!(o->beta1 >= 0.0f && o->beta1 < 1.0f) || !(o->beta2 >= 0.0f && o->beta2 < 1.0f) || !(o->eps > 0.0f))
+        return fail(c, PISCO_EINVAL, "bad Adam hyper-parameters");
+    c->sl_opts = *o;
+    return PISCO_OK;
+}
+
+static pisco_status sidelobe_capable(pisco_ctx *c, int32_t det, const DetState &d);
+
+pisco_status pisco_sidelobe_train(pisco_ctx *c, int32_t det, double r_main, int64_t n_train, uint64_t seed,
+                                  int32_t epochs) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (det < 0 || det >= PISCO_MAX_DETECTORS) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    if (!c->sky) return fail(c, PISCO_ESTATE, "no sky set");
+    if ((size_t)det >= c->dets.size() || !c->dets[det].has_beam || !c->dets[det].has_params)
+        return fail(c, PISCO_ESTATE, "detector %d lacks a beam or parameters", det);
+    DetState &d = c->dets[det];
+    {
+        const pisco_status cs = sidelobe_capable(c, det, d);
+        if (cs != PISCO_OK) return cs;
+    }
+    if (!(r_main > d.rho_min) || !(r_main < d.rho_max))
+        return fail(c, PISCO_EINVAL, "need rho_min < r_main < rho_max (got %g, disc %g..%g)", r_main, d.rho_min,
+                    d.rho_max);
+    if (n_train < c->sl_opts.batch || n_train > ((int64_t)1 << 31))
+        return fail(c, PISCO_EINVAL, "n_train must be in [batch = %d, 2^31]", c->sl_opts.batch);
+    if (epochs < 1) return fail(c, PISCO_EINVAL, "epochs must be >= 1");
+    HIP_TRY(c, hipSetDevice(c->device));
+    // the annulus (r_main, rho_max] at zeta = 0 on a context that borrows the sky and the beam
+    pisco_ctx *t = nullptr;
+    pisco_status st = pisco_create(c->device, &t);
+    if (st != PISCO_OK) return fail(c, st, "target context creation failed");
+    t->sky = c->sky;
+    t->sky_owned = false;
+    t->nside = c->nside;
+    t->sky_dtype = c->sky_dtype;
+    t->dets.resize(1);
+    DetState &td = t->dets[0];
+    td.beam = d.beam;
+    td.beam_owned = false;
+    td.n = d.n;
+    td.T = d.T;
+    td.beam_dtype = d.beam_dtype;
+    td.beam_kind = d.beam_kind;
+    for (int i = 0; i < 4; ++i) td.w[i] = d.w[i];
+    td.has_beam = true;
+    t->algo = c->algo;
+    t->spt = c->spt;
+    t->wpg = c->wpg;
+    t->gpc = c->gpc;
+    t->xq = c->xq;
+    t->chunk = c->chunk;
+    t->coherence = c->coherence;
+    t->ordering = PISCO_ORDER_SPATIAL;  // isotropic pointings: tiles of spatially sorted samples
+    st = pisco_set_detector(t, 0, 0.0, r_main, d.rho_max, PISCO_NORM_FIXED, d.norm_scale);
+    pisco_mlp *net = nullptr;
+    float mean[3], stdv[3];
+    std::vector<double> hist;
+    if (st == PISCO_OK) {
+        pisco::SidelobeRun r{c, t, n_train, seed, epochs, c->sl_opts};
+        st = pisco::sidelobe_train_run(r, &net, mean, stdv, hist);
+    } else {
+        fail(c, st, "annulus set-up failed: %s", pisco_last_error(t));
+    }
+    pisco_destroy(t);
+    if (st != PISCO_OK) return st;
+    auto sl = std::make_shared<SlNet>();
+    sl->net = net;
+    for (int k = 0; k < 3; ++k) {
+        sl->mean[k] = mean[k];
+        sl->stdv[k] = stdv[k];
+    }
+    sl->r_main = r_main;
+    sl->wT = d.w[3];
+    sl->norm = d.norm_scale;
+    sl->hist = hist;
+    d.sl = sl;
+    ++c->generation;
+    return PISCO_OK;
+}
+
+// Whether detector d can take a far-sidelobe network (the split of its TOD into
+// disc + annulus pickups holds): a one-grid beam without V terms, no plate,
+// FIXED normalisation, wT != 0, FP32 sky.
+static pisco_status sidelobe_capable(pisco_ctx *c, int32_t det, const DetState &d) {
+    if (c->sky && c->sky_dtype != PISCO_F32)
+        return fail(c, PISCO_EINVAL, "the sidelobe network runs on the FP32 path only");
+    if (d.beam_kind != pisco::BEAM_SCALAR || d.beam_v || d.wv != 0.0)
+        return fail(c, PISCO_EINVAL, "detector %d: the sidelobe split needs a one-grid beam without V terms", det);
+    if (d.hwp || !d.host_hwp.empty()) return fail(c, PISCO_EINVAL, "detector %d has a half-wave plate", det);
+    if (d.norm_mode != PISCO_NORM_FIXED)
+        return fail(c, PISCO_EINVAL, "detector %d: the sidelobe split needs FIXED normalisation", det);
+    if (d.w[3] == 0.0) return fail(c, PISCO_EINVAL, "detector %d: wT is zero", det);
+    return PISCO_OK;
+}
+
+pisco_status pisco_sidelobe_share(pisco_ctx *c, int32_t det, int32_t src) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (det < 0 || det >= PISCO_MAX_DETECTORS || src < 0 || src >= PISCO_MAX_DETECTORS)
+        return fail(c, PISCO_EINVAL, "detector out of range");
+    if ((size_t)src >= c->dets.size() || !c->dets[src].sl)
+        return fail(c, PISCO_ESTATE, "detector %d has no trained sidelobe network", src);
+    if ((size_t)det >= c->dets.size() || !c->dets[det].has_beam || !c->dets[det].has_params)
+        return fail(c, PISCO_ESTATE, "detector %d lacks a beam or parameters", det);
+    DetState &d = c->dets[det];
+    const pisco_status st = sidelobe_capable(c, det, d);
+    if (st != PISCO_OK) return st;
+    if (det != src) {
+        d.sl = c->dets[src].sl;
+        ++c->generation;
+    }
+    return PISCO_OK;
+}
+
+pisco_status pisco_sidelobe_enable(pisco_ctx *c, int32_t det, int on) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (det < 0 || det >= PISCO_MAX_DETECTORS) return fail(c, PISCO_EINVAL, "detector %d out of range", det);
+    if (on && ((size_t)det >= c->dets.size() || !c->dets[det].sl))
+        return fail(c, PISCO_ESTATE, "detector %d has no trained sidelobe network", det);
+    if ((size_t)det >= c->dets.size()) return PISCO_OK;
+    DetState &d = c->dets[det];
+    if (d.sl_on != (on != 0)) {
+        d.sl_on = on != 0;
+        ++c->generation;
+    }
+    return PISCO_OK;
+}
+
+int32_t pisco_sidelobe_history(const pisco_ctx *c, int32_t det, double *loss, int32_t cap) {
+    if (!c || det < 0 || det >= PISCO_MAX_DETECTORS) return -1;
+    if ((size_t)det >= c->dets.size()) return 0;
+    const DetState &d = c->dets[det];
+    if (!d.sl) return 0;
+    const int32_t n = (int32_t)d.sl->hist.size();
+    if (loss)
+        for (int32_t i = 0; i < std::min(n, cap); ++i) loss[i] = d.sl->hist[i];
+    return n;
 }
 
 }  // extern "C"

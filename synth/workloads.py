@@ -26,6 +26,7 @@ float64 on the host; callers cast to the precision they run in.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -77,6 +78,16 @@ def _deg(x):
     return np.deg2rad(x)
 
 
+def _per_detector(make, n_det: int) -> list:
+    """[make(k) for k in range(n_det)] on a thread pool: every detector is built
+    from its own index alone, so the arrays equal a plain loop's (numpy releases
+    the interpreter lock in its array kernels)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(make, range(n_det)))
+
+
 def sky_for(nside: int, lmax: int, power: float, idx: int):
     return tuple(make_sky(nside, lmax, power, seed=SEED_BASE + idx))
 
@@ -120,8 +131,7 @@ def c3(count_scale: float = 1.0, n_det: int = 64, sky=None, max_per_det=None) ->
     orient = rng.uniform(0.0, np.pi, size=64)
     sites = S.hex_focal_plane(32, _deg(0.7))
     T, u, v, rho, sig = B.tangent_grid(201, _deg(2.0))
-    dets = []
-    for k in range(n_det):
+    def one(k):
         pair = k // 2
         zeta = _deg(0.0 if pair % 2 == 0 else 45.0) - (_deg(90.0) if k % 2 else 0.0)
         n = max(1, int(round(counts[k] * count_scale)))
@@ -131,8 +141,10 @@ def c3(count_scale: float = 1.0, n_det: int = 64, sky=None, max_per_det=None) ->
         dx, dy = sites[pair]
         th, ph, ps = S.offset_pointing(th, ph, ps, dx, dy)
         g = B.elliptical_gaussian(rho, sig, _deg(fwhm[k]), ell[k], orient[k])
-        dets.append(Detector(B.ideal_beamsor(g, T), B.DetectorParams(zeta, 1e-3, 1.0), 0.0, _deg(2.0),
-                             NORM_PER_SAMPLE, 1.0, th, ph, ps))
+        return Detector(B.ideal_beamsor(g, T), B.DetectorParams(zeta, 1e-3, 1.0), 0.0, _deg(2.0),
+                        NORM_PER_SAMPLE, 1.0, th, ph, ps)
+
+    dets = _per_detector(one, n_det)
     return Workload("c3", nside, sky, dets, {"precision": "f32", "lmax": lmax, "lat": lat})
 
 
@@ -181,16 +193,17 @@ def c5(n_det: int = 256, per_det: int = 390_625, sky=None) -> Workload:
     T, u, v, rho, sig = B.tangent_grid(151, _deg(1.5))
     dOm = 4.0 * np.pi / (12 * nside * nside)
     norm = dOm / analytic_solid_angle(0.25)
-    dets = []
-    for k in range(n_det):
+    def one(k):
         pair = k // 2
         zeta = _deg(0.0 if pair % 2 == 0 else 45.0) - (_deg(90.0) if k % 2 else 0.0)
         th, ph, ps = S.ces(per_det, lat, start=int(starts[k]), boresight_deg=np.arange(-45, 46, 15), lst0=lst0)
         dx, dy = sites[pair]
         th, ph, ps = S.offset_pointing(th, ph, ps, dx, dy)
         g = B.elliptical_gaussian(rho, sig, _deg(0.25), ell[k], orient[k])
-        dets.append(Detector(B.ideal_beamsor(g, T), B.DetectorParams(zeta, 0.0, 1.0), 0.0, _deg(1.5),
-                             NORM_FIXED, norm, th, ph, ps))
+        return Detector(B.ideal_beamsor(g, T), B.DetectorParams(zeta, 0.0, 1.0), 0.0, _deg(1.5),
+                        NORM_FIXED, norm, th, ph, ps)
+
+    dets = _per_detector(one, n_det)
     return Workload("c5", nside, sky, dets, {"precision": "f32", "lmax": lmax, "lat": lat,
                                               "ring_grid": (401, 20.0), "r_main": _deg(1.5)})
 

@@ -51,3 +51,38 @@ def rel_err(got, want):
 
 def say(msg):
     print(msg, flush=True)
+
+
+_WORKLOADS = {}
+
+
+def cached_workload(name, **kw):
+    """A synthetic workload built once per test process (the nside-1024 recipe takes
+    about half a minute to synthesise); callers must not modify what they get."""
+    from synth import workloads as W
+
+    key = (name, tuple(sorted(kw.items())))
+    if key not in _WORKLOADS:
+        _WORKLOADS[key] = getattr(W, name)(**kw)
+    return _WORKLOADS[key]
+
+
+def coherence_chords(d, frac, group=64):
+    """Per group of `group` consecutive samples: the largest chord from the
+    group's normalised mean direction, and the limit frac * rho_max below which
+    the tile path takes the group (FP64 on the host).  Returns (chord, limit)."""
+    st = np.sin(d.theta)
+    p = np.stack([st * np.cos(d.phi), st * np.sin(d.phi), np.cos(d.theta)], 1)
+    nfull = d.n // group
+    chords = []
+    if nfull:
+        q = p[:nfull * group].reshape(nfull, group, 3)
+        c = q.sum(1)
+        c /= np.linalg.norm(c, axis=1, keepdims=True)
+        chords.append(np.linalg.norm(q - c[:, None, :], axis=2).max(1))
+    if d.n % group:
+        q = p[nfull * group:]
+        c = q.sum(0)
+        c /= np.linalg.norm(c)
+        chords.append(np.array([np.linalg.norm(q - c, axis=1).max()]))
+    return np.concatenate(chords), frac * d.rho_max

@@ -12,7 +12,7 @@ from oracle import maps as OM
 from synth import beams as B
 from synth import workloads as W
 
-from gpu_helpers import load_workload, rel_err, say
+from gpu_helpers import cached_workload, load_workload, rel_err, say
 
 pytestmark = pytest.mark.gpu
 D2R = np.pi / 180
@@ -196,7 +196,9 @@ def test_benchmark_detectors_binned_at_nside_1024(conv, torch):
     from paper_1908_05662_amd.api import MapMaker
 
     say("case: 8 detectors of the nside-1024 workload binned at nside 1024")
-    w = W.c3()
+    import copy
+
+    w = copy.copy(cached_workload("c3"))
     w.detectors = w.detectors[:8]
     load_workload(conv, w, np.float32)
     tod = conv.convolve(-1).cpu().numpy()

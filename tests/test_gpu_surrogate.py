@@ -60,24 +60,23 @@ def test_annulus_targets_match_oracle(conv, torch, algo):
 
 
 def test_surrogate_gain_and_speed(conv, torch):
-    """Trained on 1e6 exact pickups (GPU forward/backward/Adam kernels), the
-    network brings the held-out sidelobe error of the main-beam-only TOD below
-    1e-3 of the main-beam RMS, and main beam + network is faster than the
-    exact 20 deg disc."""
+    """The library trains the network (pisco_sidelobe_train: 1e6 exact pickups of
+    pointings it draws, GPU forward/backward/Adam kernels, 40 epochs); enabled
+    (pisco_sidelobe_enable), it brings the held-out sidelobe error of the
+    main-beam TOD below 1e-3 of the main-beam RMS, and main beam + network is
+    faster than the exact 20 deg disc."""
     from paper_1908_05662_amd import surrogate as SG
 
-    say("case: surrogate train 1e6 / held-out 1e6, 40 epochs")
-    wtr = _sorted(W.c4(1_000_000, stream=1))
-    wte = _sorted(W.c4(1_000_000, stream=2, sky=wtr.sky))
-    d = wtr.detectors[0]
+    say("case: library-trained surrogate, 1e6 drawn training pointings / 1e6 held-out, 40 epochs")
+    wte = _sorted(W.c4(1_000_000, stream=2))
+    d = wte.detectors[0]
     T, g = W.sidelobe_beam(401, 20.0, 1.0)
-    pts = [(x.detectors[0].theta, x.detectors[0].phi, x.detectors[0].psi) for x in (wtr, wte)]
-    r = SG.experiment(conv, wtr.nside, wtr.sky, g, T, (d.det.zeta, d.det.eps, d.det.s), d.norm_scale,
-                      wtr.meta["r_main"], d.rho_max, pts[0], pts[1], epochs=40)
+    test = (d.theta, d.phi, d.psi)
+    r = SG.experiment(conv, wte.nside, wte.sky, g, T, (d.det.zeta, d.det.eps, d.det.s), d.norm_scale,
+                      wte.meta["r_main"], d.rho_max, test, n_train=1_000_000, epochs=40)
     for k, v in r.items():
         say(f"  {k}: {v}")
     assert r["split_identity_error"] < 1e-6       # d_full = d_main + sum_c coef_c P_c (exact decomposition)
-    assert r["apply_vs_predict"] < 1e-6           # fused TOD epilogue = forward + host combination
     assert r["sidelobe_error"] <= 1e-3
     assert r["main_only_error"] > 5 * r["sidelobe_error"]
     assert r["speedup"] > 2.0
