@@ -23,30 +23,51 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work per (sample, disc pixel) pair, counted from each path's pair
-# arithmetic, as (vector ALU flops, matrix-core flops) (FMA = 2; reciprocals,
-# clamps, floors and single ops count 1; compares, selects and address
-# arithmetic are not counted):
-#  tile path, one-grid beam, TOD: membership 1 - n.p 6, rotation into the
-#  antenna frame 12, gnomonic projection (1 - z', reciprocal, two products) 4,
-#  grid coordinates, clamps and fractions 14, bilinear cell polynomial 6,
-#  position angle (co-polar vector carried along the great circle, projected
-#  on the pixel basis, doubled angle) 32, contraction 5, compensated
-#  accumulation 4 -> 83.
-#  tile path on the matrix cores, one-grid beam, TOD: eight 16x16x4 FP32 MFMAs
-#  per 16 pixels x 16 samples give 1 - n.p, the antenna-frame coordinates, g.n
-#  and the four co-polar projections (64 matrix flops per pair); on the vector
-#  ALU: projection 4, grid 14, bilinear 6, q = g.n / (2 - 1 + n.p) 3, carried
-#  projections 4, doubled angle 4, contraction 5, accumulation 4 -> 44.
-#  Four-channel beams: bilinear 36 and the Stokes rotation 11 instead -> 81.
-#  pixel path, four-channel beam, TOD: longitude offset 3, half-angle sin/cos
-#  polynomials 29, h and sin(dphi) 4, offsets from the boresight 5, rotation 6,
-#  projection 3, grid 12, position angle 34, bilinear x4 channels 36, Stokes
-#  rotation 6, contraction 5, accumulations 12 -> 155 (one-grid beam: 125).
-FLOPS_PER_PAIR = {(1, "scalar"): (83, 0), (1, "full"): (113, 0), (2, "scalar"): (44, 64), (2, "full"): (81, 64),
-                  (0, "scalar"): (125, 0), (0, "full"): (155, 0)}
-# vector ALU peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 (FMA)
-ALU_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# Algorithmic work per (sample, disc pixel) pair of each tile-path loop variant,
+# counted from its source (FMA = 2; add, multiply, fract, floor and reciprocal 1;
+# compares, selects, conversions to integers and address arithmetic 0):
+#  membership 1 - n.p 6; n.theta'_0 and n.phi'_0 12; 1/z' and 1/(1+z') as
+#  second-order series in omega 7 (third order: 11; one reciprocal of
+#  z'(1+z') and the two products: 6); grid coordinates 4; cell fractions 2;
+#  g.n 6 and q 1; carried co-polar vector 6; its projections on the pixel's
+#  theta/phi 10; cos 2chi and sin 2chi 4; one-grid bilinear cell polynomial 6;
+#  contraction with the staged sky terms 5 and the per-step sum 1; the sum of
+#  eight terms added in FP64 0.25 per sum -> 70.25, plus the normaliser of a
+#  per-sample-normalised launch (its masked add 1 + 0.25) -> 71.5.
+#  Four-channel beams: floors and fractions 4 instead of 2, four bilinear
+#  channels 36 instead of 6, the contraction with the Stokes rotation 12
+#  instead of 5 -> 110.5 with the normaliser.
+#  Matrix-core variant (algorithm 2): eight 16x16x4 FP32 MFMAs per 16 pixels x
+#  16 samples give the pixel-linear quantities (64 matrix flops per pair);
+#  vector ALU 44 (one-grid) / 81 (four-channel).
+#  Pixel path (FP32 incoherent groups), four-channel beam: 155; one-grid: 125.
+FLOPS_PER_PAIR = {(1, "scalar", 2, True): (71.5, 0), (1, "scalar", 2, False): (70.25, 0),
+                  (1, "scalar", 1, True): (75.5, 0), (1, "scalar", 1, False): (74.25, 0),
+                  (1, "scalar", 0, True): (70.5, 0), (1, "scalar", 0, False): (69.25, 0),
+                  (1, "full", 2, True): (110.5, 0), (1, "full", 2, False): (109.25, 0),
+                  (1, "full", 1, True): (114.5, 0), (1, "full", 0, True): (109.5, 0),
+                  (2, "scalar"): (44, 64), (2, "full"): (81, 64), (0, "scalar"): (125, 0), (0, "full"): (155, 0)}
+
+
+def flops_per_pair(algorithm, kind, rho_max, per_sample):
+    """(vector, matrix) flops per pair of the loop a launch runs: the series
+    order follows the disc (omega = 1 - cos rho_max <= 1e-3: second order, <= 4e-3:
+    third, else the reciprocal)."""
+    if algorithm != 1:
+        return FLOPS_PER_PAIR[(algorithm, kind)]
+    om = 2.0 * np.sin(0.5 * rho_max) ** 2
+    sc = 2 if om <= 1e-3 else (1 if om <= 4e-3 else 0)
+    return FLOPS_PER_PAIR.get((1, kind, sc, per_sample), FLOPS_PER_PAIR[(1, kind, sc, True)])
+
+
+# FP32 vector peak of one MI355X (published): 256 CUs x 4 SIMDs x 32 FMA per
+# SIMD per clock x 2 flops x 2.4 GHz = 157.3 TFLOP/s.  The build never emits
+# packed FP32, but gfx950 issues plain v_fma_f32, v_add_f32 and v_mul_f32 faster
+# than one wave64 instruction per four clocks (a probe of independent chains:
+# 1.27x, 1.54x and 1.54x that rate), so the published figure is the ceiling of
+# this loop too.  FP64 vector: 78.6 TFLOP/s (16 FMA per SIMD per clock).
+ALU_PEAK_TFLOPS = 256 * 4 * 32 * 2.4e9 * 2 / 1e12
+FP64_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 # HBM3E bandwidth of one MI355X (published)
 HBM_PEAK_GBS = 8000.0
 
@@ -124,33 +145,202 @@ def cpu_baseline(w, got, seconds):
     return n, dt, err, per_det
 
 
+def host_info():
+    """Logical CPUs and model name of this host (nproc, lscpu)."""
+    import subprocess
+
+    info = {"nproc": os.cpu_count()}
+    try:
+        info["nproc"] = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def load_any(conv, w, dtype, torch, dets=None):
+    """Sky, beams (one-grid form when the folded channels allow it), detector
+    parameters and device pointing of workload w in precision dtype."""
+    tdt = torch.float64 if dtype == np.float64 else torch.float32
+    conv.set_sky(w.nside, *(torch.from_numpy(np.asarray(m, dtype=dtype)).cuda() for m in w.sky), dtype=tdt)
+    keep = []
+    for k in (range(len(w.detectors)) if dets is None else dets):
+        d = w.detectors[k]
+        conv.set_beamsor(k, d.beam.dense(), d.beam.half_span_tan, d.det.eps, d.det.s, dtype=tdt)
+        conv.set_detector(k, d.det.zeta, d.rho_min, d.rho_max, d.norm_mode, d.norm_scale)
+        arrs = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (d.theta, d.phi, d.psi)]
+        conv.set_pointing(k, *arrs)
+        keep.append(arrs)
+    return keep
+
+
+def oracle_samples(w, k, idx, dtype, out_mode=0, rho_min=None, rho_max=None, beam=None, zeta=None):
+    """The FP64 oracle on detector k's samples idx, the sky and beam rounded as the GPU holds them."""
+    import oracle
+
+    d = w.detectors[k]
+    sky = [np.asarray(m, dtype=dtype).astype(np.float64) for m in w.sky]
+    M = d.beam.dense() if beam is None else beam
+    M = np.asarray(M, dtype=dtype).astype(np.float64)
+    return oracle.tod(w.nside, *sky, M, d.beam.half_span_tan, d.det.zeta if zeta is None else zeta, d.det.eps,
+                      d.det.s, d.rho_min if rho_min is None else rho_min, d.rho_max if rho_max is None else rho_max,
+                      d.norm_mode, d.norm_scale, d.theta[idx], d.phi[idx], d.psi[idx], out_mode)
+
+
+def rel_inf(got, want):
+    got, want = np.asarray(got, dtype=np.float64), np.asarray(want, dtype=np.float64)
+    return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+
+
+def parity_leg():
+    """Relative TOD error of the GPU against the FP64 oracle, per workload recipe,
+    ||d_gpu - d_oracle||_inf / ||d_oracle||_inf over the compared samples (the
+    nside-1024 batched recipe is checked inside the headline run, the nside-2048
+    one inside the full-scale leg)."""
+    import torch
+
+    from paper_1908_05662_amd import OUT_STOKES
+    from paper_1908_05662_amd.api import Convolver
+    from paper_1908_05662_amd.surrogate import spatial_order
+    from synth import workloads as W
+
+    res = {}
+    t0 = time.perf_counter()
+    # nside 64, FP64 kernel, the whole 1e5-sample stream
+    w = W.c1()
+    conv = Convolver(0)
+    keep = load_any(conv, w, np.float64, torch)
+    got = conv.convolve(0).cpu().numpy()
+    conv.close()
+    res["c1_nside64_fp64"] = {"max_rel_err": rel_inf(got, oracle_samples(w, 0, slice(None), np.float64)),
+                              "samples": int(got.size), "of": int(got.size), "tolerance": 1e-12,
+                              "path": "FP64 pixel path"}
+    # nside 512, FP32 tile path, the whole 1e7-sample stream; 10,000 samples spread over it
+    w = W.c2()
+    d = w.detectors[0]
+    conv = Convolver(0)
+    keep = load_any(conv, w, np.float32, torch)
+    got = conv.convolve(0).cpu().numpy()
+    conv.close()
+    idx = np.unique(np.concatenate([np.linspace(0, d.n - 1, 10_001).astype(np.int64), [63, 64, d.n - 1]]))
+    res["c2_nside512_fp32"] = {"max_rel_err": rel_inf(got[idx], oracle_samples(w, 0, idx, np.float32)),
+                               "samples": int(idx.size), "of": int(d.n), "tolerance": 1e-6,
+                               "path": "FP32 tile path (pixel path for incoherent groups)"}
+    # nside 256 far-sidelobe recipe, 1e6 held-out isotropic pointings in spatial order:
+    # the 20 deg disc, the 5 deg main disc and the (5, 20] deg annulus pickups
+    w = W.c4(1_000_000, stream=2)
+    d = w.detectors[0]
+    o = spatial_order(d.theta, d.phi)
+    d.theta, d.phi, d.psi = d.theta[o], d.phi[o], d.psi[o]
+    r_main = w.meta["r_main"]
+    conv = Convolver(0)
+    keep = load_any(conv, w, np.float32, torch)
+    idx = np.unique(np.concatenate([np.linspace(0, d.n - 1, 40).astype(np.int64), [63, 64]]))
+    full = conv.convolve(0).cpu().numpy()[idx]
+    conv.set_detector(0, d.det.zeta, 0.0, r_main, d.norm_mode, d.norm_scale)
+    main = conv.convolve(0).cpu().numpy()[idx]
+    conv.set_detector(0, 0.0, r_main, d.rho_max, d.norm_mode, d.norm_scale)
+    ann = conv.convolve(0, out_mode=OUT_STOKES).cpu().numpy()[idx]
+    conv.close()
+    del keep
+    e_full = rel_inf(full, oracle_samples(w, 0, idx, np.float32))
+    e_main = rel_inf(main, oracle_samples(w, 0, idx, np.float32, rho_max=r_main))
+    e_ann = rel_inf(ann, oracle_samples(w, 0, idx, np.float32, out_mode=OUT_STOKES, rho_min=r_main, zeta=0.0))
+    res["c4_nside256_fp32"] = {"max_rel_err": max(e_full, e_main, e_ann), "full_disc": e_full, "main_disc": e_main,
+                               "annulus_stokes": e_ann, "samples": int(idx.size), "of": int(d.n),
+                               "tolerance": 1e-6, "path": "FP32 tile path"}
+    log(f"parity: " + ", ".join(f"{k} {v['max_rel_err']:.2e}" for k, v in res.items()) +
+        f" ({time.perf_counter() - t0:.1f}s)")
+    return res
+
+
+def full_beam_leg(conv, w, stream, out, steps, warmup, torch, pairs):
+    """The benchmark workload with four-channel beams: every beamsor gains a
+    four-lobed cross-polar leakage B_QU = B_UQ = 0.01 b cos 2 sigma, so the folded
+    channels are no longer multiples of one grid and each pair reads the four
+    bilinear channels.  Timed like the headline; the one-grid beams return after."""
+    from paper_1908_05662_amd import OUT_TOD
+    from synth import beams as B
+
+    T, u, v, rho, sig = B.tangent_grid(w.detectors[0].beam.n, np.deg2rad(2.0))
+    lobes = np.cos(2.0 * sig)
+    for k, d in enumerate(w.detectors):
+        g = d.beam.get(0, 0)
+        el = dict(d.beam.elements)
+        el[(1, 2)] = 0.01 * g * lobes
+        el[(2, 1)] = 0.01 * g * lobes
+        kind = conv.set_beamsor(k, B.Beamsor(d.beam.n, d.beam.half_span_tan, el).dense(), d.beam.half_span_tan,
+                                d.det.eps, d.det.s, dtype=torch.float32)
+        assert kind == "full"
+    conv.set_timing(True)
+    for _ in range(max(warmup, 1)):
+        with torch.cuda.stream(stream):
+            conv.convolve(-1, OUT_TOD, out=out, stream=stream)
+    stream.synchronize()
+    conv.kernel_time(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        with torch.cuda.stream(stream):
+            conv.convolve(-1, OUT_TOD, out=out, stream=stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    kms, launches = conv.kernel_time(reset=True)
+    k_ms = kms / max(launches, 1)
+    got = out.cpu().numpy()
+    # sampled parity of the four-channel path
+    offs = np.cumsum([0] + [d.n for d in w.detectors])
+    errs = []
+    for k in range(0, len(w.detectors), 8):
+        d = w.detectors[k]
+        el = dict(d.beam.elements)
+        el[(1, 2)] = 0.01 * d.beam.get(0, 0) * lobes
+        el[(2, 1)] = 0.01 * d.beam.get(0, 0) * lobes
+        idx = np.array([0, 63, 64, d.n // 2, d.n - 1])
+        want = oracle_samples(w, k, idx, np.float32, beam=B.Beamsor(d.beam.n, d.beam.half_span_tan, el).dense())
+        errs.append(rel_inf(got[offs[k] + idx], want))
+    for k, d in enumerate(w.detectors):   # back to the one-grid beams
+        conv.set_beamsor(k, d.beam.dense(), d.beam.half_span_tan, d.det.eps, d.det.s, dtype=torch.float32)
+    fpp, _ = flops_per_pair(1, "full", w.detectors[0].rho_max, True)
+    achieved = fpp * pairs / (k_ms / 1e3) / 1e12
+    n = conv.output_samples(-1)
+    log(f"four-channel beams: {wall * 1e3 / steps:.2f} ms/step, kernel {k_ms:.2f} ms, frac {achieved / ALU_PEAK_TFLOPS:.3f}")
+    return {"workload": "the benchmark workload with four-channel beams (cross-polar leakage 0.01 b cos 2 sigma "
+                        "in B_QU and B_UQ)", "ms_per_step": wall * 1e3 / steps, "kernel_ms": k_ms,
+            "samples_per_s": n / (wall / steps), "macs_per_s": pairs / (wall / steps),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / ALU_PEAK_TFLOPS, "flops_per_pair": fpp},
+            "parity_max_rel_err": max(errs), "parity_samples": 5 * len(errs)}
+
+
 def surrogate_leg(epochs):
-    """Exact main beam + trained far-sidelobe network against the exact 20 deg
-    disc on the nside-256 far-sidelobe workload: 1e6 training and 1e6 held-out
-    pointings uniform on the sphere (put in spatial order), error judged by the
-    exact annulus convolution."""
+    """Exact main beam + the library-trained far-sidelobe network against the
+    exact 20 deg disc on the nside-256 far-sidelobe workload: the library draws
+    1e6 training pointings uniform on the sphere and trains on their exact
+    annulus pickups; 1e6 held-out pointings (put in spatial order) judge it
+    against the exact annulus convolution."""
     from paper_1908_05662_amd import surrogate as SG
     from paper_1908_05662_amd.api import Convolver
     from synth import workloads as W
 
-    def ordered(w):
-        d = w.detectors[0]
-        o = SG.spatial_order(d.theta, d.phi)
-        return d.theta[o], d.phi[o], d.psi[o]
-
-    wtr = W.c4(1_000_000, stream=1)
-    wte = W.c4(1_000_000, stream=2, sky=wtr.sky)
-    d = wtr.detectors[0]
+    wte = W.c4(1_000_000, stream=2)
+    d = wte.detectors[0]
+    o = SG.spatial_order(d.theta, d.phi)
     T, g = W.sidelobe_beam(401, 20.0, 1.0)
     conv = Convolver(0)
-    r = SG.experiment(conv, wtr.nside, wtr.sky, g, T, (d.det.zeta, d.det.eps, d.det.s), d.norm_scale,
-                      wtr.meta["r_main"], d.rho_max, ordered(wtr), ordered(wte), epochs=epochs)
+    r = SG.experiment(conv, wte.nside, wte.sky, g, T, (d.det.zeta, d.det.eps, d.det.s), d.norm_scale,
+                      wte.meta["r_main"], d.rho_max, (d.theta[o], d.phi[o], d.psi[o]), n_train=1_000_000,
+                      epochs=epochs)
     conv.close()
     r["workload"] = ("nside-256 smooth sky, 401^2 beam over +-20 deg (1 deg Gaussian + -40 dB ring at 10 deg), "
-                     "main disc 5 deg, annulus (5, 20] deg; network 5 -> 4 x 256 SiLU -> 3, BF16 weights")
+                     "main disc 5 deg, annulus (5, 20] deg; network 5 -> 4 x 256 SiLU -> 3, BF16 weights, trained "
+                     "by the library (pisco_sidelobe_train) on 1e6 drawn pointings")
     r["error_unit"] = "RMS(d_sl_hat - d_sl) / RMS(d_main) on held-out samples"
     log(f"surrogate: sidelobe error {r['sidelobe_error']:.3e} (main only {r['main_only_error']:.3e}), "
-        f"{r['samples_per_s_surrogate']:.4g} vs exact {r['samples_per_s_exact']:.4g} samples/s")
+        f"{r['samples_per_s_surrogate']:.4g} vs exact {r['samples_per_s_exact']:.4g} samples/s, "
+        f"training {r['train_s']:.1f}s")
     return r
 
 
@@ -416,10 +606,13 @@ def spectra_leg(conv, maps, torch, lmax=3071, reps=5):
     """Spectra of the map leg's nside-1024 I, Q, U maps (the validation step the
     maps go through): harmonic analysis to lmax 3071 and the six spectra, FP64,
     HIP events on the current stream; also the synthesis (alm2map) and the
-    analysis refined by three Jacobi steps.  `dense_tflops` counts 33 flops for every
-    (l, m, ring pair) of the triangle, including the polar pairs the kernel skips
-    while lambda_lm is below 2^-256 (so it is an equivalent rate, not the
-    executed one); the executed FP64 rate is in the kernel profile."""
+    analysis refined by three Jacobi steps.  The roofline of the analysis
+    (`roofline`) counts the work the a_lm kernel executes: its VALU wave
+    instructions per analysis from the committed counter run (valid while the
+    kernel source is the one counted), against one FP64 wave64 instruction per
+    four clocks per SIMD.  `dense_equivalent_tflops` (33 flops for every
+    (l, m, ring pair) of the triangle, skipped polar pairs included) is a rate
+    for comparison only."""
     from paper_1908_05662_amd.api import Spectra
 
     nside = int(round(np.sqrt(maps.shape[1] / 12)))
@@ -445,6 +638,13 @@ def spectra_leg(conv, maps, torch, lmax=3071, reps=5):
     cl = sp.anafast(T, Q, U).cpu().numpy()
     items = sum((lmax - m + 1) * 2 * nside for m in range(lmax + 1))
     dense = SHT_FLOPS_PER_ITEM * items / t_alm / 1e12
+    roof = None
+    rec = counted_instructions("spectra_counters.json")
+    if rec is not None and rec.get("nside") == nside and rec.get("lmax") == lmax:
+        issue = rec["alm_kernel_valu_wave_instructions"] / (rec["alm_kernel_ms"] * 1e-3)
+        roof = {"bound": "alu (fp64)", "achieved": issue, "unit": "wave64 VALU instructions/s",
+                "peak": FP64_ISSUE_PEAK, "frac": issue / FP64_ISSUE_PEAK,
+                "counted_ms": rec["alm_kernel_ms"], "instructions": rec["alm_kernel_valu_wave_instructions"]}
     log(f"spectra: nside {nside} lmax {lmax}: map2alm {t_alm * 1e3:.2f} ms, anafast {t_all * 1e3:.2f} ms "
         f"({dense:.1f} TFLOP/s dense-equivalent), alm2map {t_syn * 1e3:.2f} ms, anafast with 3 iterations "
         f"{t_it3 * 1e3:.2f} ms")
@@ -452,25 +652,42 @@ def spectra_leg(conv, maps, torch, lmax=3071, reps=5):
                         "spectra TT, EE, BB, TE, EB, TB (FP64)",
             "ms_map2alm": t_alm * 1e3, "ms_anafast": t_all * 1e3, "ms_alm2map": t_syn * 1e3,
             "ms_anafast_3_iterations": t_it3 * 1e3, "items": items,
-            "flops_per_item": SHT_FLOPS_PER_ITEM, "dense_tflops": dense, "peak_tflops_fp64": ALU_PEAK_TFLOPS,
-            "dense_frac": dense / ALU_PEAK_TFLOPS, "finite": bool(np.all(np.isfinite(cl)))}
+            "dense_equivalent_tflops": dense, "roofline": roof, "finite": bool(np.all(np.isfinite(cl)))}
+
+
+def counted_instructions(name):
+    """A committed counter record from profiles/ if the kernel source it names is
+    unchanged since the counters were taken, else None."""
+    import hashlib
+
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+        sha = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec if sha == rec.get("source_sha256") else None
+
+
+# FP64 VALU issue peak: one wave64 instruction per four clocks per SIMD at 2.4 GHz
+FP64_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
 
 def full_scale_leg(epochs, n_train, width, hidden, lr):
     """The nside-2048 full-scale workload on one GPU: 256 detectors x 390,625 CES
-    samples (1e8), each with its own 151^2 elliptical main beam (disc 1.5 deg),
-    plus the shared -40 dB ring at 10 deg on a 401^2 grid over +-20 deg for the
-    annulus (1.5, 20] deg.  Exact main beam + network against the exact main
-    beam + exact annulus.  The exact annulus is timed on 1024 samples of every
-    detector (four runs of 256 consecutive samples, 262,144 in all, also the
-    held-out set) and its rate extrapolated to the whole job; everything else
-    runs on the whole job."""
+    samples (1e8), each its own 151^2 elliptical main beam (disc 1.5 deg), plus
+    the shared -40 dB ring at 10 deg on a 401^2 grid over +-20 deg for the
+    annulus (1.5, 20] deg.  The library trains one network on the ring grid's
+    annulus (pisco_sidelobe_train on a slot without pointing) and every detector
+    uses it (pisco_sidelobe_share / pisco_sidelobe_enable): one batched graph
+    launch runs the exact main beams and adds the network.  Against the exact
+    form (exact main beams + exact annulus): the annulus is timed on 1024 samples
+    of every detector (four runs of 256 consecutive samples, 262,144 in all, also
+    the held-out set) and its rate extrapolated to the whole job."""
     import torch
 
     from paper_1908_05662_amd import OUT_STOKES, OUT_TOD
     from paper_1908_05662_amd import surrogate as SG
     from paper_1908_05662_amd.api import Convolver
-    from synth import scans as S
     from synth import workloads as W
 
     t0 = time.perf_counter()
@@ -481,34 +698,49 @@ def full_scale_leg(epochs, n_train, width, hidden, lr):
     d0 = w.detectors[0]
     norm = d0.norm_scale
     stream = torch.cuda.Stream()
-
-    # main beams, exact, whole job: one batched graph launch
     cm = Convolver(0)
-    keep_m, kind = load(cm, w, torch)
+    keep, kind = load(cm, w, torch)
     out = torch.empty(n, dtype=torch.float32, device="cuda")
-    with torch.cuda.stream(stream):
-        cm.convolve(-1, OUT_TOD, out=out, stream=stream)
-    stream.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(stream):
-        a.record(stream)
-        cm.convolve(-1, OUT_TOD, out=out, stream=stream)
-        b.record(stream)
-    b.synchronize()
-    t_main = a.elapsed_time(b) / 1e3
+
+    def timed_launch():
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            cm.convolve(-1, OUT_TOD, out=out, stream=stream)     # capture or warm-up
+        stream.synchronize()
+        with torch.cuda.stream(stream):
+            a.record(stream)
+            cm.convolve(-1, OUT_TOD, out=out, stream=stream)
+            b.record(stream)
+        b.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    # exact main beams over the whole job
+    t_main = timed_launch()
     d_main_all = out.clone()
     log(f"main exact: {t_main:.3f} s for {n} samples")
 
-    # annulus context: the ring grid, training pointings and the held-out runs
+    # one network for the shared ring grid's annulus, trained by the library
+    R = len(w.detectors)
     T, g = W.sidelobe_beam(401, 20.0, 0.25)
-    cs = Convolver(0)
-    cs.set_sky(w.nside, *(torch.from_numpy(m.astype(np.float32)).cuda() for m in w.sky), dtype=torch.float32)
-    cs.set_beam_scalar(0, 401, T, torch.from_numpy(g.astype(np.float32)).cuda(), 0.5, 0.5, 0.0, 1.0,
+    cm.set_beam_scalar(R, 401, T, torch.from_numpy(g.astype(np.float32)).cuda(), 0.5, 0.5, 0.0, 1.0,
                        dtype=torch.float32)
-    rng = np.random.Generator(np.random.PCG64([W.SEED_BASE + 5, 7]))
-    th, ph, ps = S.uniform_sphere(n_train, rng)
-    o = SG.spatial_order(th, ph)
-    train = [torch.from_numpy(np.ascontiguousarray(x[o])).cuda() for x in (th, ph, ps)]
+    cm.set_detector(R, 0.0, 0.0, np.deg2rad(20.0), W.NORM_FIXED, norm)
+    cm.sidelobe_options(width=width, hidden_layers=hidden, batch=8192, lr=lr, lr_end=2e-5)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = cm.sidelobe_train(R, r_main, n_train, 1, epochs)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    log(f"library training (targets included): {n_train} samples, {epochs} epochs in {t_train:.1f} s, "
+        f"loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    for k in range(R):
+        cm.sidelobe_share(k, R)
+        cm.sidelobe_enable(k, True)
+    # surrogate form over the whole job: exact main beams + the network, one graph launch
+    t_sur = timed_launch()
+    d_sur_all = out.clone()
+
+    # held-out judgement: exact annulus pickups (zeta = 0) of 262,144 scan samples
     offs = np.cumsum([0] + [d.n for d in w.detectors])
     idx, det_of = [], []
     for k, d in enumerate(w.detectors):
@@ -522,62 +754,44 @@ def full_scale_leg(epochs, n_train, width, hidden, lr):
     all_ph = np.concatenate([d.phi for d in w.detectors])
     all_ps = np.concatenate([d.psi for d in w.detectors])
     held = [torch.from_numpy(np.ascontiguousarray(x[idx])).cuda() for x in (all_th, all_ph, all_ps)]
-    for k in (1, 2, 3):
-        cs.share_beam(k, 0)
-    cs.set_detector(0, 0.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm)
-    cs.set_detector(1, 0.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm)
-    cs.set_detector(2, 0.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm)
-    cs.set_pointing(0, *train)
-    cs.set_pointing(1, *held)
-    cs.set_pointing(2, *held)
-
-    t1 = time.perf_counter()
-    p_train = cs.convolve(0, OUT_STOKES)
-    model = SG.SidelobeModel(cs, width, hidden, 16384, 1)
-    x_train = model.features(0)
-    torch.cuda.synchronize()
-    t_targets = time.perf_counter() - t1
-    log(f"targets: {n_train} samples in {t_targets:.2f} s")
-    t1 = time.perf_counter()
-    hist = model.fit(x_train, p_train, epochs=epochs, batch=8192, lr=lr, seed=1)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t1
-    del x_train, p_train
-
-    # held-out judgement by the exact annulus
-    p_held = cs.convolve(1, OUT_STOKES).double()
+    A = R + 1
+    cm.share_beam(A, R)
+    cm.set_detector(A, 0.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm)
+    cm.set_pointing(A, *held)
+    p_held = cm.convolve(A, OUT_STOKES).double()
     coef = np.array([SG.detector_coef(d.det.zeta, d.det.eps, d.det.s) for d in w.detectors])
     cvec = torch.from_numpy(coef[det_of]).cuda()
     d_sl = (p_held * cvec).sum(1)
-    p_hat = model.predict(model.features(1)).double()
-    d_sl_hat = (p_hat * cvec).sum(1)
-    d_main = d_main_all[torch.from_numpy(idx).cuda()].double()
+    sel = torch.from_numpy(idx).cuda()
+    d_main = d_main_all[sel].double()
+    d_sl_hat = d_sur_all[sel].double() - d_main
     ref = SG.rms(d_main)
     err = SG.rms(d_sl_hat - d_sl) / ref
     err0 = SG.rms(d_sl) / ref
-
-    # exact annulus rate on the held-out runs (TOD of a zeta = 0 detector)
-    t_ann = SG.time_call(lambda: cs.convolve(2, OUT_TOD), reps=2)
+    # exact annulus rate on the held-out runs
+    ann_out = torch.empty(idx.size, dtype=torch.float32, device="cuda")
+    t_ann = SG.time_call(lambda: cm.convolve(A, OUT_TOD, out=ann_out), reps=2)
     per_sample_ann = t_ann / idx.size
-
-    # surrogate form over the whole job: main exact + the fused network per detector
-    def surrogate_pass():
-        with torch.cuda.stream(stream):
-            cm.convolve(-1, OUT_TOD, out=out, stream=stream)
-            for k, d in enumerate(w.detectors):
-                model.apply(k, coef[k], out[offs[k]:offs[k + 1]], stream=stream, conv=cm)
-
-    surrogate_pass()
-    stream.synchronize()
-    with torch.cuda.stream(stream):
-        a.record(stream)
-    surrogate_pass()
-    with torch.cuda.stream(stream):
-        b.record(stream)
-    b.synchronize()
-    t_sur = a.elapsed_time(b) / 1e3
-
     log(f"full scale: sidelobe error {err:.3e} (main only {err0:.3e})")
+
+    # sampled parity of this recipe against the oracle: main beams and annulus pickups
+    main_np = d_main_all.cpu().numpy()
+    e_main = 0.0
+    for k in range(0, R, 32):
+        d = w.detectors[k]
+        j = np.array([0, 63, 64, d.n - 1])
+        e_main = max(e_main, rel_inf(main_np[offs[k] + j], oracle_samples(w, k, j, np.float32)))
+    jj = np.arange(0, idx.size, idx.size // 8)[:8]
+    ring = B_ideal(g, T)
+    import oracle
+
+    sky = [np.asarray(m, dtype=np.float32).astype(np.float64) for m in w.sky]
+    want = oracle.tod(w.nside, *sky, ring, T, 0.0, 0.0, 1.0, r_main, np.deg2rad(20.0), W.NORM_FIXED, norm,
+                      all_th[idx[jj]], all_ph[idx[jj]], all_ps[idx[jj]], OUT_STOKES)
+    e_ann = rel_inf(p_held.cpu().numpy()[jj], want)
+    parity = {"max_rel_err": max(e_main, e_ann), "main_beams": e_main, "annulus_stokes": e_ann,
+              "samples": int(4 * ((R + 31) // 32) + jj.size), "of": int(n), "tolerance": 1e-6,
+              "path": "FP32 tile path"}
 
     t_exact = t_main + per_sample_ann * n
     res = {
@@ -596,16 +810,23 @@ def full_scale_leg(epochs, n_train, width, hidden, lr):
         "sidelobe_error": err,
         "main_only_error": err0,
         "error_unit": "RMS(d_sl_hat - d_sl) / RMS(d_main) on the 262,144 held-out scan samples",
-        "network": f"5 -> {hidden} x {width} SiLU -> 3, BF16 weights",
+        "network": f"5 -> {hidden} x {width} SiLU -> 3, BF16 weights, trained by the library on {n_train} drawn "
+                   f"pointings, {epochs} epochs",
         "network_flops_per_sample": SG.network_flops_per_sample(width, hidden),
-        "train_samples": n_train, "epochs": epochs, "lr": lr, "final_loss": hist[-1], "targets_s": t_targets,
-        "train_s": t_train,
+        "train_samples": n_train, "epochs": epochs, "lr": lr, "final_loss": hist[-1],
+        "train_s_with_targets": t_train,
+        "parity": parity,
     }
-    model.close()
-    cs.close()
     cm.close()
-    del keep_m
+    del keep, held
     return res
+
+
+def B_ideal(g, T):
+    """Dense ideal beamsor of a scalar grid, FP32-rounded like the device copy."""
+    from synth import beams as B
+
+    return B.ideal_beamsor(np.asarray(g, dtype=np.float32).astype(np.float64), T).dense()
 
 
 def main():
@@ -621,13 +842,15 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the far-sidelobe surrogate leg")
     ap.add_argument("--no-paper-shape", action="store_true", help="skip the paper's benchmark-pattern leg")
     ap.add_argument("--no-plate", action="store_true", help="skip the half-wave-plate leg")
+    ap.add_argument("--no-full-beam", action="store_true", help="skip the four-channel-beam leg")
     ap.add_argument("--no-maps", action="store_true", help="skip the map-making leg (and the spectra leg)")
     ap.add_argument("--no-spectra", action="store_true", help="skip the power-spectrum leg")
     ap.add_argument("--no-ideal-cmb", action="store_true", help="skip the paper's whole-sky ideal CMB run")
-    ap.add_argument("--full-scale", action="store_true",
-                    help="also run the nside-2048, 1e8-sample surrogate-vs-exact leg (about 3 minutes)")
-    ap.add_argument("--full-scale-train", type=int, default=6_000_000)
-    ap.add_argument("--full-scale-epochs", type=int, default=120)
+    ap.add_argument("--no-parity", action="store_true", help="skip the per-recipe parity leg")
+    ap.add_argument("--no-full-scale", action="store_true",
+                    help="skip the nside-2048, 1e8-sample surrogate-vs-exact leg")
+    ap.add_argument("--full-scale-train", type=int, default=2_000_000)
+    ap.add_argument("--full-scale-epochs", type=int, default=60)
     ap.add_argument("--full-scale-net", type=str, default="512x10",
                     help="network width x hidden layers for the full-scale leg")
     ap.add_argument("--full-scale-lr", type=float, default=7e-4)
@@ -664,7 +887,8 @@ def main():
         kv = dict(x.split("=") for x in args.launch.split(","))
         conv.set_launch(**{k: (float(v) if k == "coherence" else int(v)) for k, v in kv.items()})
     launch = conv.get_launch()
-    flops_per_pair, mfma_per_pair = FLOPS_PER_PAIR[(launch["algorithm"], kind)]
+    per_sample = any(d.norm_mode == W.NORM_PER_SAMPLE for d in w.detectors)
+    fpp, mfma_per_pair = flops_per_pair(launch["algorithm"], kind, w.detectors[0].rho_max, per_sample)
     n = conv.output_samples(-1)
     stream = torch.cuda.Stream()
     out = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -700,12 +924,13 @@ def main():
     ms_step = wall * 1e3 / args.steps
     k_ms = kms / max(launches, 1)
     value = n / (ms_step / 1e3)
-    achieved = flops_per_pair * pairs / (k_ms / 1e3) / 1e12
+    achieved = fpp * pairs / (k_ms / 1e3) / 1e12
     got = out.cpu().numpy()
-    log(f"{ms_step:.2f} ms/step, kernel {k_ms:.2f} ms, {value:.4g} samples/s, {pairs / (k_ms / 1e3):.4g} pairs/s")
+    log(f"{ms_step:.2f} ms/step, kernel {k_ms:.2f} ms, {value:.4g} samples/s, {pairs / (k_ms / 1e3):.4g} pairs/s, "
+        f"roofline frac {achieved / ALU_PEAK_TFLOPS:.3f} ({fpp} flops/pair)")
 
     cpu = None
-    parity = None
+    parity = {}
     if not args.no_cpu_baseline:
         import oracle
 
@@ -714,13 +939,33 @@ def main():
         cpu = {"value": ns / dt, "unit": "samples/s", "cores": oracle.max_threads(), "kind": "oracle",
                "sample": f"{per_det} evenly spaced samples per detector x {len(w.detectors)} detectors "
                          f"({ns} samples, {frac * pairs:.3g} pairs est.) of the same workload, FP64, {dt:.1f}s",
-               "macs_per_s": frac * pairs / dt}
-        parity = err
+               "macs_per_s": frac * pairs / dt, "threads": oracle.max_threads(), **host_info()}
+        parity["c3_nside1024_fp32"] = {"max_rel_err": err, "samples": int(ns), "of": int(n), "tolerance": 1e-6,
+                                       "path": "FP32 tile path + pixel path, the timed batched launch"}
         log(f"cpu oracle {ns / dt:.4g} samples/s on {oracle.max_threads()} threads; parity max rel err {err:.3e}")
+
+    # the same job with the pointing handed over as host arrays: upload, plan and convolution
+    t = time.perf_counter()
+    for k, d in enumerate(w.detectors):
+        conv.set_pointing(k, *(np.ascontiguousarray(x) for x in (d.theta, d.phi, d.psi)))
+    t_up = time.perf_counter() - t
+    with torch.cuda.stream(stream):
+        conv.convolve(-1, OUT_TOD, out=out, stream=stream)
+    stream.synchronize()
+    t_all = time.perf_counter() - t
+    pcie = {"workload": "the benchmark job with the pointing given as host arrays (pageable): upload of "
+                        f"{24 * n / 1e9:.2f} GB, plan, one convolution", "ms": t_all * 1e3, "upload_ms": t_up * 1e3,
+            "samples_per_s": n / t_all}
+    log(f"pointing upload included: {t_all * 1e3:.1f} ms ({t_up * 1e3:.1f} ms upload)")
+    for k, d in enumerate(w.detectors):   # the resident device pointing again
+        conv.set_pointing(k, *keep[k])
 
     plate = None
     if not args.no_plate:
         plate = plate_leg(conv, w, stream, out, args.steps, args.warmup, k_ms, torch)
+    full_beam = None
+    if not args.no_full_beam:
+        full_beam = full_beam_leg(conv, w, stream, out, args.steps, args.warmup, torch, pairs)
     maps = spectra = None
     if not args.no_maps:
         with torch.cuda.stream(stream):
@@ -752,19 +997,23 @@ def main():
         "kernel_ms": k_ms,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(launch),
-                     "flops_per_pair": flops_per_pair,
+                     "flops_per_pair": fpp,
                      "matrix_tflops": mfma_per_pair * pairs / (k_ms / 1e3) / 1e12},
         "cpu_baseline": cpu,
         "autotune": None if tuned is None else {k: tuned[k] for k in ("launch", "ms", "default_ms", "speedup",
                                                                         "cached", "seconds", "subsample")},
-        "parity_max_rel_err": parity,
+        "pointing_upload_included": pcie,
+        "parity": parity,
         "plate": plate,
+        "full_beam": full_beam,
         "maps": maps,
         "spectra": spectra,
     }
     conv.close()
     del keep, out
     torch.cuda.empty_cache()
+    if not args.no_parity:
+        parity.update(parity_leg())
     if not args.no_surrogate:
         rec["surrogate"] = surrogate_leg(args.surrogate_epochs)
     if not args.no_paper_shape:
@@ -773,11 +1022,14 @@ def main():
     if not args.no_ideal_cmb:
         torch.cuda.empty_cache()
         rec["ideal_cmb"] = ideal_cmb_leg()
-    if args.full_scale:
+    if not args.no_full_scale:
         torch.cuda.empty_cache()
         width, hidden = (int(v) for v in args.full_scale_net.split("x"))
         rec["full_scale"] = full_scale_leg(args.full_scale_epochs, args.full_scale_train, width, hidden,
                                            args.full_scale_lr)
+        parity["c5_nside2048_fp32"] = rec["full_scale"]["parity"]
+    if parity:
+        parity["metric"] = "max |d_gpu - d_oracle| / max |d_oracle| over the compared samples (FP64 oracle)"
     print(json.dumps(rec), flush=True)
 
 
