@@ -161,6 +161,20 @@ def host_info():
     return info
 
 
+def valu_probe():
+    """Issue rates of the vector ALU on this device from the probe program built
+    beside the library (wave64 instructions/s and their ratio to one per four
+    clocks per SIMD), or None without it."""
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_1908_05662_amd", "valu_probe")
+    try:
+        out = subprocess.run([exe], capture_output=True, text=True, timeout=120).stdout
+        return json.loads(out.strip().splitlines()[-1])
+    except (OSError, ValueError, IndexError, subprocess.SubprocessError):
+        return None
+
+
 def load_any(conv, w, dtype, torch, dets=None):
     """Sky, beams (one-grid form when the folded channels allow it), detector
     parameters and device pointing of workload w in precision dtype."""
@@ -869,6 +883,10 @@ def main():
     from paper_1908_05662_amd.api import Convolver
     from synth import workloads as W
 
+    probe = valu_probe()
+    if probe:
+        log("vector ALU issue (x one wave64 instruction per 4 clocks per SIMD): " +
+            ", ".join(f"{k} {v[1]:.2f}" for k, v in probe.items() if isinstance(v, list)))
     t0 = time.perf_counter()
     w = W.c3()
     log(f"workload c3: {len(w.detectors)} detectors, {w.n_samples} samples, setup {time.perf_counter() - t0:.1f}s")
@@ -998,7 +1016,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(launch),
                      "flops_per_pair": fpp,
-                     "matrix_tflops": mfma_per_pair * pairs / (k_ms / 1e3) / 1e12},
+                     "matrix_tflops": mfma_per_pair * pairs / (k_ms / 1e3) / 1e12,
+                     "valu_issue_probe": probe},
         "cpu_baseline": cpu,
         "autotune": None if tuned is None else {k: tuned[k] for k in ("launch", "ms", "default_ms", "speedup",
                                                                         "cached", "seconds", "subsample")},

@@ -9,6 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpisco.so")
+# translation units of libpisco.so (valu_probe.hip is a separate program)
 SOURCES = ["conv_kernel.hip", "mlp_kernels.hip", "map_kernel.hip", "order_kernel.hip", "sht_kernel.hip",
            "sidelobe_kernel.hip", "runtime.cpp", "mlp_runtime.cpp", "sht_runtime.cpp", "map_runtime.cpp",
            "sidelobe_runtime.cpp"]
@@ -46,6 +47,11 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
+    # the vector-ALU issue-rate probe the benchmark runs beside the roofline
+    probe = os.path.join(HERE, "valu_probe")
+    subprocess.check_call([HIPCC, *[f for f in FLAGS if f != "-fPIC"], os.path.join(CSRC, "valu_probe.hip"), "-o",
+                           probe + ".tmp"])
+    os.replace(probe + ".tmp", probe)
     return LIB
 
 

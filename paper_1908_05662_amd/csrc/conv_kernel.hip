@@ -958,13 +958,17 @@ template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER, int SC =
 __device__ __forceinline__ void consume_records(const PixRec *rec, const float *vrec, int32_t m_end, const PairCtx &C,
                                                 const BeamRsrc &beam, const BeamRsrc &vbeam, AccWide &acc0,
                                                 AccWide &acc1, AccWide &acc2, AccWide &accn) {
+    // pairs whose beam loads are in flight together: four for one-grid beams (one
+    // 16-byte cell record each), two for four-channel beams (four node records
+    // each), so that a step's loaded records stay in registers
+    constexpr int NP = BEAM == BEAM_SCALAR ? TILE_NP : 2;
     int32_t m = 0;
-    // two groups per compensated add: eight masked terms summed in FP32
-    for (; m + 2 * TILE_NP - 1 < m_end; m += 2 * TILE_NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER, SC>(
+    // two groups per compensated add: 2 NP masked terms summed in FP32
+    for (; m + 2 * NP - 1 < m_end; m += 2 * NP) {
+        const PairOut a = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC>(
             &rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
-        const PairOut b = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER, SC>(
-            &rec[m + TILE_NP], vrec ? &vrec[m + TILE_NP] : nullptr, C, beam, vbeam);
+        const PairOut b = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC>(
+            &rec[m + NP], vrec ? &vrec[m + NP] : nullptr, C, beam, vbeam);
         acc0.add(a.v0 + b.v0);
         if (MODE == MODE_STOKES) {
             acc1.add(a.v1 + b.v1);
@@ -972,8 +976,8 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
         }
         if (PS) accn.add(a.vn + b.vn);
     }
-    for (; m + TILE_NP - 1 < m_end; m += TILE_NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, TILE_NP, HWP, CLIP, INNER, SC>(
+    for (; m + NP - 1 < m_end; m += NP) {
+        const PairOut a = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC>(
             &rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
         acc0.add(a.v0);
         if (MODE == MODE_STOKES) {

@@ -27,9 +27,27 @@ struct MlpInferArgs {
 
 hipError_t mlp_in_fwd(const float *x, const __bf16 *w0, const float *b0, int32_t n, int32_t H, float *z, __bf16 *a,
                       hipStream_t s);
-hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t asm_, int64_t ask, const __bf16 *b, int64_t bsk, int64_t bsn,
-                    int32_t M, int32_t N, int32_t K, int32_t k_slice, const float *bias, float *z_out, __bf16 *a_out,
-                    const float *z_prev, float *partial, hipStream_t s);
+// C = A B with A[m][k] at a[m*lda + k] and B(k, n) at b[n*ldb + k]; epilogues as
+// in mlp_kernels.hip (t_out, if not null, receives the transposed bf16 output).
+hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t lda, const __bf16 *b, int64_t ldb, int32_t M, int32_t N,
+                    int32_t K, int32_t k_slice, const float *bias, float *z_out, __bf16 *a_out, __bf16 *t_out,
+                    int64_t ldt, const float *z_prev, float *partial, hipStream_t s);
+// dst[c * ldd + r] = src[r * lds + c] (R, C multiples of 64), for `batch` matrices.
+hipError_t mlp_transpose(const __bf16 *src, int64_t lds, __bf16 *dst, int64_t ldd, int32_t R, int32_t C,
+                         int32_t batch, int64_t src_stride, int64_t dst_stride, hipStream_t s);
+// Fixed-order sums of several partial arrays in one launch.
+#define MLP_MAX_SEGS 40
+struct MlpReduceSeg {
+    const float *part;
+    float *out;
+    int64_t count;
+    int32_t slices;
+};
+struct MlpReduceList {
+    MlpReduceSeg seg[MLP_MAX_SEGS];
+    int32_t n;
+};
+hipError_t mlp_reduce_many(const MlpReduceList &l, hipStream_t s);
 hipError_t mlp_out(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n, int32_t H,
                    float *y, const float *tgt, float inv_count, __bf16 *dz, float *part_w, float *part_b,
                    float *part_loss, int32_t waves, int32_t rows_per_wave, hipStream_t s);

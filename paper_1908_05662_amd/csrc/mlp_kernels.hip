@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "mlp_internal.h"
 
 namespace pisco {
@@ -38,98 +40,155 @@ __device__ inline float silu_grad(float z) {
 }
 
 // ----------------------------------------------------------------------
-// GEMM: C[M x N] = A[M x K] B[K x N], element (m, k) of A at a[m*asm + k*ask],
-// element (k, n) of B at b[k*bsk + n*bsn]; M, N multiples of 64, K of 32.
-// Workgroup tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA 16x16x32 tiles).
+// GEMM: C[M x N] = A[M x K] B[K x N] with both operands k-contiguous: A[m][k]
+// at a[m*lda + k] and B given by rows n, B(k, n) at b[n*ldb + k] (so the
+// layers' backward passes read transposed copies the forward epilogues,
+// the output layer and Adam keep).  M, N multiples of the tile (64 or 128),
+// K of 32.  Workgroup: four waves as 2 x 2, each (BM/2) x (BN/2) of
+// v_mfma_f32_16x16x32_bf16 tiles; 32-wide k steps staged in LDS, double
+// buffered (the next step's tiles are fetched into registers while the
+// current step's MFMAs run).  Every output element is one MFMA chain over
+// k0 = 0, 32, 64, ... with lane l holding k0 + 8 (l / 16) .. + 7 of row
+// l % 16: the fragments and order of the fused inference kernel.
 // ----------------------------------------------------------------------
-constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;  // padded LDS rows
+constexpr int TK = 32, LDK = TK + 8;  // LDS rows padded by 16 bytes
 
 enum { EPI_FWD = MLP_EPI_FWD, EPI_BWD_D = MLP_EPI_BWD_D, EPI_BWD_W = MLP_EPI_BWD_W };
 
 struct GemmArgs {
     const __bf16 *a;
     const __bf16 *b;
-    int64_t asm_, ask, bsk, bsn;
+    int64_t lda, ldb;
     int32_t M, N, K;
     int32_t k_slice;       // split-K slice length (multiple of 32)
     const float *bias;     // FWD
     float *z_out;          // FWD: pre-activation (ldc = N)
-    __bf16 *a_out;         // FWD: SiLU(Z); BWD_D: dZ_prev
+    __bf16 *a_out;         // FWD: SiLU(Z); BWD_D: dZ_prev (ldc = N)
+    __bf16 *t_out;         // optional transposed copy of a_out: t_out[n * ldt + m]
+    int64_t ldt;
     const float *z_prev;   // BWD_D: pre-activation of the previous layer
     float *partial;        // BWD_W: [slice][M][N]
 };
 
-// Load a 64 x 32 tile of an operand into LDS as rows[r][k] (r = m or n), where
-// the tile's element (r, k) sits at p[r*sr + k*sk].
-__device__ inline void load_tile(const __bf16 *__restrict__ p, int64_t sr, int64_t sk, int r0, int k0,
-                                 __bf16 (*dst)[LDK], int tid) {
-    if (sk == 1) {
-        // 8 consecutive k per thread: one 16-byte load
-        const int r = tid >> 2, kk = (tid & 3) * 8;
-        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(p + (int64_t)(r0 + r) * sr + (k0 + kk));
+// Rows [r0, r0 + R) x k [k0, k0 + 32) of a k-contiguous operand: R * 4 chunks of
+// 16 bytes, CH per thread of 256.
+template <int R>
+struct TileRegs {
+    static constexpr int CH = R * 4 / 256;
+    bf16x8 v[CH];
+    __device__ inline void load(const __bf16 *__restrict__ p, int64_t ld, int r0, int k0, int tid) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) dst[r][kk + i] = v[i];
-    } else {
-        // rows contiguous (sr == 1): 8 consecutive r per thread for one k
-        const int kk = tid >> 3, r = (tid & 7) * 8;
-        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(p + (int64_t)(k0 + kk) * sk + (r0 + r));
-#pragma unroll
-        for (int i = 0; i < 8; ++i) dst[r + i][kk] = v[i];
+        for (int c = 0; c < CH; ++c) {
+            const int idx = tid + 256 * c, r = idx >> 2, kk = (idx & 3) * 8;
+            v[c] = *reinterpret_cast<const bf16x8 *>(p + (int64_t)(r0 + r) * ld + (k0 + kk));
+        }
     }
-}
+    __device__ inline void store(__bf16 (*dst)[LDK], int tid) const {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int idx = tid + 256 * c, r = idx >> 2, kk = (idx & 3) * 8;
+            *reinterpret_cast<bf16x8 *>(&dst[r][kk]) = v[c];
+        }
+    }
+};
 
-template <int EPI>
+template <int EPI, int BM, int BN>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-    __shared__ __align__(16) __bf16 As[TM][LDK];
-    __shared__ __align__(16) __bf16 Bs[TN][LDK];
+    constexpr int WM = BM / 2, WN = BN / 2, FI = WM / 16, FJ = WN / 16;
+    __shared__ __align__(16) __bf16 As[2][BM][LDK];
+    __shared__ __align__(16) __bf16 Bs[2][BN][LDK];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int kb = blockIdx.z * g.k_slice, ke = min(g.K, kb + g.k_slice);
-    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    f32x4 acc[2][2];
+    const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    f32x4 acc[FI][FJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < FJ; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
+    TileRegs<BM> ra;
+    TileRegs<BN> rb;
+    if (kb < ke) {
+        ra.load(g.a, g.lda, m0, kb, tid);
+        rb.load(g.b, g.ldb, n0, kb, tid);
+        ra.store(As[0], tid);
+        rb.store(Bs[0], tid);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int k0 = kb; k0 < ke; k0 += TK) {
-        load_tile(g.a, g.asm_, g.ask, m0, k0, As, tid);
-        load_tile(g.b, g.bsn, g.bsk, n0, k0, Bs, tid);
+        const bool more = k0 + TK < ke;
+        if (more) {
+            ra.load(g.a, g.lda, m0, k0 + TK, tid);
+            rb.load(g.b, g.ldb, n0, k0 + TK, tid);
+        }
+        bf16x8 af[FI], bfr[FJ];
+#pragma unroll
+        for (int i = 0; i < FI; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][wm + 16 * i + r][kq]);
+#pragma unroll
+        for (int j = 0; j < FJ; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][wn + 16 * j + r][kq]);
+#pragma unroll
+        for (int i = 0; i < FI; ++i)
+#pragma unroll
+            for (int j = 0; j < FJ; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        if (more) {
+            ra.store(As[cur ^ 1], tid);
+            rb.store(Bs[cur ^ 1], tid);
+        }
         __syncthreads();
-        const int r = lane & 15, kq = (lane >> 4) * 8;
-        bf16x8 af[2], bfr[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + r][kq]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * j + r][kq]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
+        cur ^= 1;
     }
 
     // epilogue: lane holds C[row0 + 4 (lane/16) + q][col0 + lane%16], q = 0..3
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < FI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FJ; ++j) {
+            const int rowb = m0 + wm + 16 * i + 4 * (lane >> 4);
+            const int col = n0 + wn + 16 * j + (lane & 15);
+            __bf16 t4[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int row = m0 + wm + 16 * i + 4 * (lane >> 4) + q;
-                const int col = n0 + wn + 16 * j + (lane & 15);
+                const int row = rowb + q;
                 const float v = acc[i][j][q];
                 const int64_t o = (int64_t)row * g.N + col;
                 if (EPI == EPI_FWD) {
                     const float z = v + g.bias[col];
                     g.z_out[o] = z;
-                    g.a_out[o] = (__bf16)silu(z);
+                    t4[q] = (__bf16)silu(z);
+                    g.a_out[o] = t4[q];
                 } else if (EPI == EPI_BWD_D) {
-                    g.a_out[o] = (__bf16)(v * silu_grad(g.z_prev[o]));
+                    t4[q] = (__bf16)(v * silu_grad(g.z_prev[o]));
+                    g.a_out[o] = t4[q];
                 } else {
                     g.partial[(int64_t)blockIdx.z * g.M * g.N + o] = v;
                 }
             }
+            // four consecutive rows of one column: one 8-byte store into the transposed copy
+            if (EPI != EPI_BWD_W && g.t_out) {
+                typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                *reinterpret_cast<bf16x4 *>(g.t_out + (int64_t)col * g.ldt + rowb) = bf16x4{t4[0], t4[1], t4[2], t4[3]};
+            }
+        }
+}
+
+// dst[c * ldd + r] = src[r * lds + c] for an R x C bf16 matrix (both multiples of
+// 64), 64 x 64 tiles through LDS; grid.z walks a batch of matrices (strides sz, dz).
+__global__ void __launch_bounds__(256) transpose_kernel(const __bf16 *src, int64_t lds, __bf16 *dst, int64_t ldd,
+                                                        int64_t sz, int64_t dz) {
+    __shared__ __bf16 t[64][66];
+    src += blockIdx.z * sz;
+    dst += blockIdx.z * dz;
+    const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t[ty * 16 + k][tx] = src[(int64_t)(r0 + ty * 16 + k) * lds + c0 + tx];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) dst[(int64_t)(c0 + ty * 16 + k) * ldd + r0 + tx] = t[tx][ty * 16 + k];
 }
 
 // ----------------------------------------------------------------------
@@ -243,6 +302,17 @@ __global__ void reduce_kernel(const float *part, int32_t slices, int64_t count, 
     float s = 0.0f;
     for (int k = 0; k < slices; ++k) s += part[(int64_t)k * count + i];
     out[i] = s;
+}
+
+// The same sums for a list of (partials, slices, count, out) segments in one
+// launch; blockIdx.y picks the segment.
+__global__ void reduce_many_kernel(MlpReduceList L) {
+    const MlpReduceSeg &g = L.seg[blockIdx.y];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.count; i += (int64_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int k = 0; k < g.slices; ++k) s += g.part[(int64_t)k * g.count + i];
+        g.out[i] = s;
+    }
 }
 
 // Adam on FP32 master weights (bias-corrected step size given), BF16 copy refreshed.
@@ -456,16 +526,25 @@ hipError_t mlp_in_fwd(const float *x, const __bf16 *w0, const float *b0, int32_t
     return hipGetLastError();
 }
 
-hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t asm_, int64_t ask, const __bf16 *b, int64_t bsk, int64_t bsn,
-                    int32_t M, int32_t N, int32_t K, int32_t k_slice, const float *bias, float *z_out, __bf16 *a_out,
-                    const float *z_prev, float *partial, hipStream_t s) {
+template <int EPI>
+static void gemm_launch(const GemmArgs &g, hipStream_t s) {
+    const int bm = g.M % 128 == 0 ? 128 : 64, bn = g.N % 128 == 0 ? 128 : 64;
+    const dim3 grid(g.N / bn, g.M / bm, (g.K + g.k_slice - 1) / g.k_slice);
+    if (bm == 128 && bn == 128) hipLaunchKernelGGL((gemm_kernel<EPI, 128, 128>), grid, dim3(256), 0, s, g);
+    else if (bm == 128) hipLaunchKernelGGL((gemm_kernel<EPI, 128, 64>), grid, dim3(256), 0, s, g);
+    else if (bn == 128) hipLaunchKernelGGL((gemm_kernel<EPI, 64, 128>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_kernel<EPI, 64, 64>), grid, dim3(256), 0, s, g);
+}
+
+hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t lda, const __bf16 *b, int64_t ldb, int32_t M, int32_t N,
+                    int32_t K, int32_t k_slice, const float *bias, float *z_out, __bf16 *a_out, __bf16 *t_out,
+                    int64_t ldt, const float *z_prev, float *partial, hipStream_t s) {
+    if (M % 64 || N % 64 || K % TK || k_slice % TK || k_slice <= 0) return hipErrorInvalidValue;
     GemmArgs g;
     g.a = a;
     g.b = b;
-    g.asm_ = asm_;
-    g.ask = ask;
-    g.bsk = bsk;
-    g.bsn = bsn;
+    g.lda = lda;
+    g.ldb = ldb;
     g.M = M;
     g.N = N;
     g.K = K;
@@ -473,12 +552,31 @@ hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t asm_, int64_t ask, const _
     g.bias = bias;
     g.z_out = z_out;
     g.a_out = a_out;
+    g.t_out = t_out;
+    g.ldt = ldt;
     g.z_prev = z_prev;
     g.partial = partial;
-    const dim3 grid(N / TN, M / TM, (K + k_slice - 1) / k_slice);
-    if (epi == EPI_FWD) hipLaunchKernelGGL(gemm_kernel<EPI_FWD>, grid, dim3(256), 0, s, g);
-    else if (epi == EPI_BWD_D) hipLaunchKernelGGL(gemm_kernel<EPI_BWD_D>, grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL(gemm_kernel<EPI_BWD_W>, grid, dim3(256), 0, s, g);
+    if (epi == EPI_FWD) gemm_launch<EPI_FWD>(g, s);
+    else if (epi == EPI_BWD_D) gemm_launch<EPI_BWD_D>(g, s);
+    else gemm_launch<EPI_BWD_W>(g, s);
+    return hipGetLastError();
+}
+
+hipError_t mlp_transpose(const __bf16 *src, int64_t lds, __bf16 *dst, int64_t ldd, int32_t R, int32_t C,
+                         int32_t batch, int64_t src_stride, int64_t dst_stride, hipStream_t s) {
+    if (R % 64 || C % 64) return hipErrorInvalidValue;
+    if (R == 0 || C == 0 || batch == 0) return hipSuccess;
+    hipLaunchKernelGGL(transpose_kernel, dim3(C / 64, R / 64, batch), dim3(256), 0, s, src, lds, dst, ldd,
+                       src_stride, dst_stride);
+    return hipGetLastError();
+}
+
+hipError_t mlp_reduce_many(const MlpReduceList &l, hipStream_t s) {
+    if (l.n <= 0) return hipSuccess;
+    int64_t mx = 0;
+    for (int i = 0; i < l.n; ++i) mx = std::max<int64_t>(mx, l.seg[i].count);
+    const unsigned bx = (unsigned)std::min<int64_t>(1024, (mx + 255) / 256);
+    hipLaunchKernelGGL(reduce_many_kernel, dim3(bx, l.n), dim3(256), 0, s, l);
     return hipGetLastError();
 }
 

@@ -23,11 +23,18 @@ struct pisco_mlp {
     int64_t step = 0;
     float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
     __bf16 *wb = nullptr;
-    std::vector<float *> z;          // L pre-activations [max_batch][H]
-    std::vector<__bf16 *> a;         // L activations [max_batch][H]
-    __bf16 *dz[2] = {nullptr, nullptr};
+    int32_t mbp = 0;                 // rows of the activation buffers: max_batch rounded up to 128
+    std::vector<float *> z;          // L pre-activations [mbp][H]
+    std::vector<__bf16 *> a;         // L activations [mbp][H]
+    std::vector<__bf16 *> aT;        // their transposes [H][mbp] (operands of the weight gradients)
+    __bf16 *dz[2] = {nullptr, nullptr};      // back-propagated dL/dz [mbp][H]
+    __bf16 *dzT[2] = {nullptr, nullptr};     // their transposes [H][mbp]
+    __bf16 *wbT = nullptr;           // transposes of the hidden maps' BF16 weights, [L-1][H][H]
     float *y = nullptr, *xbuf = nullptr, *ybuf = nullptr;
-    float *part = nullptr, *part_w = nullptr, *part_b = nullptr, *part_loss = nullptr;
+    float *part_w = nullptr, *part_b = nullptr, *part_loss = nullptr;
+    std::vector<float *> part_map;   // split-K partials of each hidden map's weight gradient
+    std::vector<float *> part_bias;  // per-block partial column sums of each hidden layer's dL/dz
+    float *part_in = nullptr;        // per-block partials of the input layer's weight gradient
     std::vector<void *> allocs;
 };
 
@@ -63,50 +70,85 @@ uint64_t splitmix(uint64_t &s) {
     return z ^ (z >> 31);
 }
 
-int32_t k_slice_for(int32_t n) {
-    // about 16 slices of the batch, each a multiple of 32 rows
-    int32_t ks = ((n / 16 + 31) / 32) * 32;
+// Split of the batch for a weight gradient of H x H: enough slices that the
+// output tiles times the slices make about 256 workgroups, each slice a
+// multiple of 32 rows.
+int32_t slices_for(int32_t H) {
+    const int32_t t = H % 128 == 0 ? 128 : 64;
+    const int32_t tiles = (H / t) * (H / t);
+    return std::max(1, std::min(256, (256 + tiles - 1) / tiles));
+}
+
+int32_t k_slice_for(int32_t n, int32_t H) {
+    const int32_t want = slices_for(H);
+    int32_t ks = ((n + want - 1) / want + 31) / 32 * 32;
     return std::max(32, ks);
 }
 
-// forward (+ loss and backward when tgt != nullptr) over one padded chunk of n rows
+int32_t round_up(int32_t n, int32_t q) { return (n + q - 1) / q * q; }
+
+// The BF16 transposes of the hidden maps' weights (operands of the backward pass).
+hipError_t refresh_wbT(pisco_mlp *m, hipStream_t s) {
+    if (m->L < 2) return hipSuccess;
+    const int64_t stride = m->off_w[2] - m->off_w[1];
+    return pisco::mlp_transpose(m->wb + m->off_w[1], m->H, m->wbT, m->H, m->H, m->H, m->L - 1, stride,
+                                (int64_t)m->H * m->H, s);
+}
+
+// forward (+ loss and backward when tgt != nullptr) over one chunk of n rows
+// (GEMM rows padded to 128; padding rows carry stale values, never read back)
 pisco_status run(pisco_mlp *m, const float *x, const float *tgt, int32_t n, float *y, float *grad, float *loss,
                  hipStream_t s) {
     const int32_t H = m->H, L = m->L;
-    const int32_t np = ((n + 63) / 64) * 64;  // GEMM rows (padding rows carry stale values, never read back)
+    const int32_t np = round_up(n, 128);
+    const int64_t ldt = m->mbp;
+    const bool train = tgt != nullptr;
     MLP_TRY(m, pisco::mlp_in_fwd(x, m->wb + m->off_w[0], m->w + m->off_b[0], n, H, m->z[0], m->a[0], s));
+    if (train && L > 1) MLP_TRY(m, pisco::mlp_transpose(m->a[0], H, m->aT[0], ldt, np, H, 1, 0, 0, s));
     for (int l = 1; l < L; ++l)
-        MLP_TRY(m, pisco::mlp_gemm(pisco::MLP_EPI_FWD, m->a[l - 1], H, 1, m->wb + m->off_w[l], 1, H, np, H, H, H,
-                                   m->w + m->off_b[l], m->z[l], m->a[l], nullptr, nullptr, s));
+        MLP_TRY(m, pisco::mlp_gemm(pisco::MLP_EPI_FWD, m->a[l - 1], H, m->wb + m->off_w[l], H, np, H, H, H,
+                                   m->w + m->off_b[l], m->z[l], m->a[l], (train && l < L - 1) ? m->aT[l] : nullptr,
+                                   ldt, nullptr, nullptr, s));
     const int32_t waves = (n + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
-    __bf16 *cur = m->dz[0];
+    int cur = 0;
     MLP_TRY(m, pisco::mlp_out(m->a[L - 1], m->z[L - 1], m->wb + m->off_w[L], m->w + m->off_b[L], n, H, y, tgt,
-                              1.0f / (float)(n * MLP_OUT), cur, m->part_w, m->part_b, m->part_loss, waves,
+                              1.0f / (float)(n * MLP_OUT), m->dz[cur], m->part_w, m->part_b, m->part_loss, waves,
                               ROWS_PER_WAVE, s));
-    if (!tgt) return PISCO_OK;
+    if (!train) return PISCO_OK;
     MLP_TRY(m, pisco::mlp_loss_sum(m->part_loss, waves, 1.0f / (float)(n * MLP_OUT), loss, s));
-    MLP_TRY(m, pisco::mlp_reduce(m->part_w, waves, (int64_t)MLP_OUT * H, grad + m->off_w[L], s));
-    MLP_TRY(m, pisco::mlp_reduce(m->part_b, waves, MLP_OUT, grad + m->off_b[L], s));
+    pisco::MlpReduceList R{};
+    auto seg = [&](const float *part, int32_t slices, int64_t count, float *out) {
+        pisco::MlpReduceSeg &g = R.seg[R.n++];
+        g.part = part;
+        g.slices = slices;
+        g.count = count;
+        g.out = out;
+    };
+    seg(m->part_w, waves, (int64_t)MLP_OUT * H, grad + m->off_w[L]);
+    seg(m->part_b, waves, MLP_OUT, grad + m->off_b[L]);
     const int32_t cblocks = (n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+    if (L > 1) MLP_TRY(m, pisco::mlp_transpose(m->dz[cur], H, m->dzT[cur], ldt, np, H, 1, 0, 0, s));
     for (int l = L - 1; l >= 1; --l) {
-        // weight gradient of map l: dZ_l^T A_{l-1}, split over the batch
-        const int32_t ks = k_slice_for(n);
+        // weight gradient of map l: dZ_l^T A_{l-1} over the batch, split into slices
+        const int32_t ks = k_slice_for(n, H);
         const int32_t slices = (n + ks - 1) / ks;
-        MLP_TRY(m, pisco::mlp_gemm(pisco::MLP_EPI_BWD_W, cur, 1, H, m->a[l - 1], H, 1, H, H, n, ks, nullptr, nullptr,
-                                   nullptr, nullptr, m->part, s));
-        MLP_TRY(m, pisco::mlp_reduce(m->part, slices, (int64_t)H * H, grad + m->off_w[l], s));
-        MLP_TRY(m, pisco::mlp_colsum(cur, n, H, ROWS_PER_BLOCK, cblocks, m->part, s));
-        MLP_TRY(m, pisco::mlp_reduce(m->part, cblocks, H, grad + m->off_b[l], s));
-        // gradient into the previous layer's pre-activation
-        __bf16 *nxt = (cur == m->dz[0]) ? m->dz[1] : m->dz[0];
-        MLP_TRY(m, pisco::mlp_gemm(pisco::MLP_EPI_BWD_D, cur, H, 1, m->wb + m->off_w[l], H, 1, np, H, H, H, nullptr,
-                                   nullptr, nxt, m->z[l - 1], nullptr, s));
+        MLP_TRY(m, pisco::mlp_gemm(pisco::MLP_EPI_BWD_W, m->dzT[cur], ldt, m->aT[l - 1], ldt, H, H, n, ks, nullptr,
+                                   nullptr, nullptr, nullptr, 0, nullptr, m->part_map[l], s));
+        seg(m->part_map[l], slices, (int64_t)H * H, grad + m->off_w[l]);
+        MLP_TRY(m, pisco::mlp_colsum(m->dz[cur], n, H, ROWS_PER_BLOCK, cblocks, m->part_bias[l], s));
+        seg(m->part_bias[l], cblocks, H, grad + m->off_b[l]);
+        // gradient into the previous layer's pre-activation (and its transpose unless it is layer 0)
+        const int nxt = cur ^ 1;
+        MLP_TRY(m, pisco::mlp_gemm(pisco::MLP_EPI_BWD_D, m->dz[cur], H, m->wbT + (int64_t)(l - 1) * H * H, H, np, H,
+                                   H, H, nullptr, nullptr, m->dz[nxt], l > 1 ? m->dzT[nxt] : nullptr, ldt,
+                                   m->z[l - 1], nullptr, s));
         cur = nxt;
     }
-    MLP_TRY(m, pisco::mlp_in_grad(cur, x, n, H, ROWS_PER_BLOCK, cblocks, m->part, s));
-    MLP_TRY(m, pisco::mlp_reduce(m->part, cblocks, (int64_t)H * MLP_IN, grad + m->off_w[0], s));
-    MLP_TRY(m, pisco::mlp_colsum(cur, n, H, ROWS_PER_BLOCK, cblocks, m->part, s));
-    MLP_TRY(m, pisco::mlp_reduce(m->part, cblocks, H, grad + m->off_b[0], s));
+    MLP_TRY(m, pisco::mlp_in_grad(m->dz[cur], x, n, H, ROWS_PER_BLOCK, cblocks, m->part_in, s));
+    seg(m->part_in, cblocks, (int64_t)H * MLP_IN, grad + m->off_w[0]);
+    MLP_TRY(m, pisco::mlp_colsum(m->dz[cur], n, H, ROWS_PER_BLOCK, cblocks, m->part_bias[0], s));
+    seg(m->part_bias[0], cblocks, H, grad + m->off_b[0]);
+    MLP_TRY(m, pisco::mlp_reduce_many(R, s));
     return PISCO_OK;
 }
 
@@ -176,23 +218,32 @@ pisco_status pisco_mlp_create(pisco_ctx *ctx, int32_t width, int32_t hidden_laye
         o += m->dim[l + 1];
     }
     m->nparam = o;
-    const size_t act = (size_t)max_batch * width;
-    const int32_t ks = k_slice_for(max_batch);
-    const size_t part_main = std::max({(size_t)((max_batch + ks - 1) / ks) * width * width,
-                                       (size_t)((max_batch + 63) / 64) * width * MLP_IN});
+    m->mbp = round_up(max_batch, 128);
+    const size_t act = (size_t)m->mbp * width;
     const int32_t waves = (max_batch + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
+    const int32_t cblocks = (max_batch + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+    const int32_t slices = std::max(slices_for(width), (max_batch + k_slice_for(max_batch, width) - 1) /
+                                                           k_slice_for(max_batch, width));
     bool ok = alloc(m, &m->w, o) && alloc(m, &m->m, o) && alloc(m, &m->v, o) && alloc(m, &m->g, o) &&
               alloc(m, &m->wb, o) && alloc(m, &m->dz[0], act) && alloc(m, &m->dz[1], act) &&
+              alloc(m, &m->dzT[0], act) && alloc(m, &m->dzT[1], act) &&
+              alloc(m, &m->wbT, (size_t)std::max(1, hidden_layers - 1) * width * width) &&
               alloc(m, &m->y, (size_t)max_batch * MLP_OUT) && alloc(m, &m->xbuf, (size_t)max_batch * MLP_IN) &&
-              alloc(m, &m->ybuf, (size_t)max_batch * MLP_OUT) && alloc(m, &m->part, part_main) &&
+              alloc(m, &m->ybuf, (size_t)max_batch * MLP_OUT) &&
               alloc(m, &m->part_w, (size_t)waves * MLP_OUT * width) &&
-              alloc(m, &m->part_b, (size_t)waves * MLP_OUT) && alloc(m, &m->part_loss, waves);
+              alloc(m, &m->part_b, (size_t)waves * MLP_OUT) && alloc(m, &m->part_loss, waves) &&
+              alloc(m, &m->part_in, (size_t)cblocks * width * MLP_IN);
+    m->part_map.assign(hidden_layers, nullptr);
+    m->part_bias.assign(hidden_layers, nullptr);
     for (int l = 0; l < hidden_layers && ok; ++l) {
         float *zz = nullptr;
-        __bf16 *aa = nullptr;
-        ok = alloc(m, &zz, act) && alloc(m, &aa, act);
+        __bf16 *aa = nullptr, *at = nullptr;
+        ok = alloc(m, &zz, act) && alloc(m, &aa, act) && alloc(m, &at, act) &&
+             alloc(m, &m->part_bias[l], (size_t)cblocks * width) &&
+             (l == 0 || alloc(m, &m->part_map[l], (size_t)slices * width * width));
         m->z.push_back(zz);
         m->a.push_back(aa);
+        m->aT.push_back(at);
     }
     if (!ok) {
         pisco_mlp_destroy(m);
@@ -245,6 +296,7 @@ pisco_status pisco_mlp_set_params(pisco_mlp *m, const float *params, int mem) {
     MLP_TRY(m, hipMemset(m->m, 0, b));
     MLP_TRY(m, hipMemset(m->v, 0, b));
     MLP_TRY(m, pisco::mlp_to_bf16(m->w, m->wb, m->nparam, nullptr));
+    MLP_TRY(m, refresh_wbT(m, nullptr));
     MLP_TRY(m, hipDeviceSynchronize());
     m->step = 0;
     return PISCO_OK;
@@ -295,6 +347,7 @@ pisco_status pisco_mlp_train_step(pisco_mlp *m, const float *x, const float *t, 
     const float lr_t = (float)(lr / bc1);
     const float inv = (float)(1.0 / std::sqrt(bc2));
     MLP_TRY(m, pisco::mlp_adam(m->w, m->m, m->v, m->g, m->wb, m->nparam, lr_t, beta1, beta2, eps, inv, s));
+    MLP_TRY(m, refresh_wbT(m, s));
     return PISCO_OK;
 }
 

@@ -52,11 +52,12 @@ def _rel(a, b):
 # within K_SIGMA sigma for every one of the ~10^4 compared entries (a tail of
 # 8 sigma has probability ~1e-15 per entry); FP32 accumulation adds at most
 # GAMMA_K = K u / (1 - K u) (u = 2^-24) of the sum of absolute products.  For
-# the gradients, sigma counts the rounding of the two stored factors of each
-# product directly; the errors they inherit from other layers (through the
-# residual and the chain rule) are of the same size and are covered by the
-# same K_SIGMA.  A wrong row or column moves an entry by about its own size,
-# 30 or more sigma here.
+# a weight gradient, a sum over the batch of (dL/dz) x (activation), both
+# factors carry the variance of everything that rounded before them: a stored
+# activation its own rounding plus that of the layers below it carried up by
+# the chain rule, dL/dz the output's forward variance carried down, plus each
+# hidden layer's rounding of its stored gradient.  A wrong row or column moves
+# an entry by about its own size, 30 or more sigma here.
 K_SIGMA = 8.0
 U32 = 2.0 ** -24
 
@@ -87,6 +88,18 @@ def _forward_bound(p, x):
     return y, tol + K_SIGMA * np.sqrt(var), var
 
 
+def _activation_variance(p, x):
+    """Rounding variance of every stored activation: its own BF16 rounding
+    plus the variance of its pre-activation, carried up from the layers
+    below (the input is exact)."""
+    _, (zs, acts, Ws) = ref.forward(p, x, WIDTH, HIDDEN)
+    var = [np.zeros_like(acts[0])]
+    for l in range(HIDDEN):
+        vz = var[l] @ (Ws[l] ** 2).T
+        var.append(ref.silu_grad(zs[l]) ** 2 * vz + _half_ulp_bf16(acts[l + 1]) ** 2 / 3.0)
+    return var
+
+
 def test_forward_matches_reference(net, torch):
     conv, m = net
     say("case: mlp forward element-wise vs the FP64 reference, n = 1000 and 3000 (several passes)")
@@ -104,11 +117,12 @@ def test_forward_matches_reference(net, torch):
 
 def test_gradient_matches_reference_and_is_deterministic(net, torch):
     """Weight and bias gradients entry by entry.  The variance of each entry
-    sums, over the batch, the rounding of the stored activation it multiplies
-    and the variance of the back-propagated gradient dL/dz it multiplies; the
-    latter starts from the output residual (which inherits the forward pass's
-    output variance) and is carried down the layers by the chain rule, each
-    hidden layer adding the rounding of its own stored gradient."""
+    sums, over the batch, the variance of the stored activation it multiplies
+    (its own rounding and what it inherits from the layers below) and the
+    variance of the back-propagated gradient dL/dz it multiplies; the latter
+    starts from the output residual (which inherits the forward pass's output
+    variance) and is carried down the layers by the chain rule, each hidden
+    layer adding the rounding of its own stored gradient."""
     conv, m = net
     say("case: mlp gradient element-wise vs the FP64 reference, n = 512")
     rng = np.random.default_rng(1)
@@ -125,6 +139,7 @@ def test_gradient_matches_reference_and_is_deterministic(net, torch):
     assert abs(loss.item() - lw) <= 1e-2 * lw
     y, (zs, acts, Ws) = ref.forward(p, x64, WIDTH, HIDDEN)
     _, _, var_y = _forward_bound(p, x64)
+    var_a = _activation_variance(p, x64)
     dz = 2.0 * (y - t64) / y.size            # dL/dy: FP32 on the device, not stored
     vdz = (2.0 / y.size) ** 2 * var_y        # inherited from the forward outputs
     g = g.cpu().numpy().astype(np.float64)
@@ -133,7 +148,7 @@ def test_gradient_matches_reference_and_is_deterministic(net, torch):
     for l in range(HIDDEN, -1, -1):
         wo, r, c, bo = lay[l]
         a = acts[l]
-        va = _half_ulp_bf16(a) ** 2 / 3.0 if l > 0 else np.zeros_like(a)   # map 0 multiplies the exact input
+        va = var_a[l]   # zero for map 0, which multiplies the exact input
         var_w = vdz.T @ (a * a) + (dz * dz).T @ va
         wt = _gamma(n) * (np.abs(dz).T @ np.abs(a)) + K_SIGMA * np.sqrt(var_w)
         bt = _gamma(n) * np.abs(dz).sum(0) + K_SIGMA * np.sqrt(vdz.sum(0))

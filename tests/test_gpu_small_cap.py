@@ -6,7 +6,9 @@ for omega_max <= 4e-3 to the third power, and uses a reciprocal above.  The
 truncation is largest at the edge of each range, so the discs here sit just
 below and just above both thresholds; every sample must match the FP64
 oracle to the FP32 tolerance on both tile variants, the one-grid and
-four-channel beams.
+four-channel beams.  The launch's coherence is set explicitly and every group
+of the scan is checked on the host to lie within it, so no group can pass by
+falling back to the pixel path.
 """
 import numpy as np
 import pytest
@@ -15,7 +17,7 @@ from synth import beams as B
 from synth import workloads as W
 from synth.workloads import Detector, Workload
 
-from gpu_helpers import load_workload, oracle_detector, rel_err, say
+from gpu_helpers import coherence_chords, load_workload, oracle_detector, rel_err, say
 
 pytestmark = pytest.mark.gpu
 F32_TOL = 1e-6
@@ -62,8 +64,12 @@ def _workload(leak):
 @pytest.mark.parametrize("beam", ["auto", "full"])
 def test_small_cap_boundaries(conv, torch, algo, beam):
     say(f"case: small-cap boundaries algo {algo} beam {beam}")
-    conv.set_launch(algorithm=algo)
+    coherence = 0.5
+    conv.set_launch(algorithm=algo, coherence=coherence)
     w = _workload(leak=(beam == "full"))
+    for d in w.detectors:
+        chord, lim = coherence_chords(d, coherence)
+        assert chord.max() < 0.9 * lim, "a group would leave the tile path"
     load_workload(conv, w, np.float32, beam=beam)
     for k, d in enumerate(w.detectors):
         got = conv.convolve(k).cpu().numpy()
