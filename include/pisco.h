@@ -219,6 +219,26 @@ pisco_status pisco_set_pointing(pisco_ctx *ctx, int32_t det, int64_t n, const do
  */
 pisco_status pisco_convolve(pisco_ctx *ctx, int32_t det, int out_mode, void *out, int mem, void *stream);
 
+/*
+ * Allocation-free convolve of one detector, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts that
+ * forbid allocation after start-up.  Same result as pisco_convolve(det, ...)
+ * under PISCO_ORDER_GIVEN (samples are processed in the given order), written
+ * to `out`, which must be device memory (sky dtype, one value per sample, three
+ * for STOKES); asynchronous on `stream`, no host synchronisation.  The call
+ * allocates nothing: its plan (descriptor, work counters and queues) is built
+ * on the device in one static array of the library, 2 MiB, which each GPU the
+ * library runs on holds until the process ends; it takes at most 4,194,304
+ * samples per call (EINVAL beyond).  Every call on a GPU shares that array:
+ * calls that overlap in time on one GPU (other streams, other contexts, other
+ * host threads) race and must be serialised by the caller.  Needs the
+ * detector's pointing and plate angles on the device (EINVAL when the memory
+ * budget kept them on the host); a surrogate-enabled detector adds its
+ * network as in pisco_convolve.  Kernel timing (pisco_set_timing) does not
+ * cover these calls.
+ */
+pisco_status pisco_convolve_static(pisco_ctx *ctx, int32_t det, int out_mode, void *out, void *stream);
+
 /* Number of output samples convolve(det) writes (det = -1: all detectors). */
 int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
 

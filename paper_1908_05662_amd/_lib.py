@@ -61,6 +61,7 @@ SIGNATURES = [
     ("pisco_set_pointing", ctypes.c_int, [_vp, _i32, _i64, _vp, _vp, _vp, ctypes.c_int]),
     ("pisco_convolve", ctypes.c_int, [_vp, _i32, ctypes.c_int, _vp, ctypes.c_int, _vp]),
     ("pisco_output_samples", _i64, [_vp, _i32]),
+    ("pisco_convolve_static", ctypes.c_int, [_vp, _i32, ctypes.c_int, _vp, _vp]),
     ("pisco_set_launch", ctypes.c_int, [_vp, ctypes.c_void_p]),
     ("pisco_set_ordering", ctypes.c_int, [_vp, _i32]),
     ("pisco_get_launch", ctypes.c_int, [_vp, ctypes.c_void_p]),

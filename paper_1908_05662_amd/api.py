@@ -230,6 +230,22 @@ class Convolver:
                                              ctypes.c_void_p(s.cuda_stream)))
         return out
 
+    def convolve_static(self, det: int, out_mode: int = L.OUT_TOD, out=None, stream=None):
+        """pisco_convolve_static: one detector, device output, no allocation by the
+        library (the output tensor is allocated here when not given)."""
+        torch = _torch()
+        n = self.output_samples(det)
+        shape = (n, 3) if out_mode == L.OUT_STOKES else (n,)
+        if out is None:
+            out = torch.empty(shape, dtype=self.dtype, device=self.torch_device)
+        if tuple(out.shape) != shape or out.dtype != self.dtype or not out.is_contiguous() or \
+                not out.is_cuda or out.device != self.torch_device:
+            raise ValueError(f"out must be a contiguous {self.dtype} tensor of shape {shape} on {self.torch_device}")
+        s = stream if stream is not None else torch.cuda.current_stream(self.torch_device)
+        self._check(self._lib.pisco_convolve_static(self._h, int(det), int(out_mode), out.data_ptr(),
+                                                    ctypes.c_void_p(s.cuda_stream)))
+        return out
+
     def set_launch(self, **kw):
         """Update fields of the launch shape (see pisco_launch); returns the new shape."""
         cur = self.get_launch()

@@ -29,6 +29,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <mutex>
+
 namespace pisco {
 namespace {
 
@@ -1914,6 +1917,108 @@ hipError_t launch_check_pointing(const double *theta, const double *phi, const d
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(check_pointing_kernel, dim3((unsigned)g), dim3(bs), 0, s, theta, phi, psi, n, bad);
     return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------
+// Allocation-free single-detector launches: the plan of one call (control
+// block, descriptor, both work queues) lives in the file-scope array below,
+// built on the device so that no host round trip is needed.
+// ----------------------------------------------------------------------
+namespace {
+
+// groups of 64 consecutive samples, classified as the plan builder does and
+// appended to the tile-path or pixel-path queue
+__global__ void static_plan_kernel(DetDesc D, int32_t n_groups, int32_t tile_path, double frac, unsigned char *base) {
+    int32_t *ctrl = reinterpret_cast<int32_t *>(base);
+    Tile *tq = reinterpret_cast<Tile *>(base + STATIC_TQ_OFF);
+    Tile *pq = reinterpret_cast<Tile *>(base + STATIC_PQ_OFF);
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *reinterpret_cast<DetDesc *>(base + STATIC_DESC_OFF) = D;
+    const int32_t g = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) / WAVE);
+    if (g >= n_groups) return;   // uniform per wave
+    Tile t;
+    t.det = 0;
+    t.begin = (int64_t)g * WAVE;
+    t.count = (int32_t)min((int64_t)WAVE, D.n_samples - t.begin);
+    const bool coherent = tile_path && tile_is_coherent(D, t.begin, t.count, lane, frac);
+    if (lane == 0) {
+        if (coherent) tq[atomicAdd(&ctrl[8], 1)] = t;
+        else pq[atomicAdd(&ctrl[24], 1)] = t;
+    }
+}
+
+__global__ void static_zero_kernel(int32_t *ctrl) {
+    if (threadIdx.x < 32) ctrl[threadIdx.x] = 0;
+}
+
+}  // namespace
+
+}  // namespace pisco
+
+static_assert(sizeof(pisco::DetDesc) <= pisco::STATIC_TQ_OFF - pisco::STATIC_DESC_OFF,
+              "the descriptor must fit between the control block and the queues");
+
+// The plan of allocation-free launches: one copy per GPU for the life of the
+// process.  Host code uses its address from hipGetSymbolAddress, never the name.
+static __device__ __align__(256) unsigned char scratch[pisco::STATIC_SCRATCH_BYTES];
+
+namespace pisco {
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+void *g_static_ptr[STATIC_MAX_DEVICES] = {};
+std::mutex g_static_mu;
+}  // namespace
+
+hipError_t static_scratch_init(int device) {
+    if (device < 0 || device >= STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_ptr[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_static_ptr[device] = p;
+    return hipSuccess;
+}
+
+void *static_scratch(int device) {
+    if (device < 0 || device >= STATIC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    return g_static_ptr[device];
+}
+
+hipError_t launch_static(ConvArgs tile, ConvArgs pix, const DetDesc &D, bool tile_path, bool f64, int waves,
+                         int groups, void *base, hipStream_t s) {
+    unsigned char *b = static_cast<unsigned char *>(base);
+    int32_t *ctrl = reinterpret_cast<int32_t *>(b);
+    const int64_t ng = (D.n_samples + WAVE - 1) / WAVE;
+    if (ng > STATIC_MAX_GROUPS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(static_zero_kernel, dim3(1), dim3(64), 0, s, ctrl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int per_block = 4;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, (ng + per_block - 1) / per_block);
+    hipLaunchKernelGGL(static_plan_kernel, dim3(blocks), dim3(WAVE * per_block), 0, s, D, (int32_t)ng,
+                       (int32_t)tile_path, tile.coherence, b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const DetDesc *dd = reinterpret_cast<const DetDesc *>(b + STATIC_DESC_OFF);
+    for (ConvArgs *a : {&tile, &pix}) {
+        a->dets = dd;
+        a->n_queues = 1;
+        a->tiles_per_queue = (int32_t)STATIC_MAX_GROUPS;
+    }
+    tile.tiles = reinterpret_cast<const Tile *>(b + STATIC_TQ_OFF);
+    tile.counters = ctrl;
+    tile.queue_len = ctrl + 8;
+    pix.tiles = reinterpret_cast<const Tile *>(b + STATIC_PQ_OFF);
+    pix.counters = ctrl + 16;
+    pix.queue_len = ctrl + 24;
+    if (tile_path) {
+        e = launch_conv(tile, f64, waves, groups, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_conv(pix, f64, waves, groups, s);
 }
 
 }  // namespace pisco

@@ -88,6 +88,26 @@ hipError_t launch_classify(const DetDesc *dets, const Tile *groups, int32_t n_gr
 hipError_t launch_check_pointing(const double *theta, const double *phi, const double *psi, int64_t n,
                                  int32_t *bad, hipStream_t s);
 
+// Allocation-free single-detector launches (pisco_convolve_static): the plan of
+// one call lives in a file-scope device array of conv_kernel.hip, one copy per
+// GPU.  Layout: int32 control block [32] at 0 (work counters and queue lengths as
+// in a Plan), the DetDesc at STATIC_DESC_OFF, the tile-path and pixel-path
+// queues of STATIC_MAX_GROUPS tiles each.
+constexpr int64_t STATIC_MAX_GROUPS = 1 << 16;
+constexpr size_t STATIC_DESC_OFF = 256;
+constexpr size_t STATIC_TQ_OFF = 1024;
+constexpr size_t STATIC_PQ_OFF = STATIC_TQ_OFF + sizeof(Tile) * STATIC_MAX_GROUPS;
+constexpr size_t STATIC_SCRATCH_BYTES = STATIC_PQ_OFF + sizeof(Tile) * STATIC_MAX_GROUPS;
+// Resolves the array's device address on the current device (once per device).
+hipError_t static_scratch_init(int device);
+// That address, or null before static_scratch_init succeeded on `device`.
+void *static_scratch(int device);
+// Zero the control block, classify and queue the 64-sample groups of D on the
+// device, then run the tile and pixel kernels with args tile / pix (their plan
+// pointers are filled in here).
+hipError_t launch_static(ConvArgs tile, ConvArgs pix, const DetDesc &D, bool tile_path, bool f64, int waves,
+                         int groups, void *base, hipStream_t s);
+
 }  // namespace pisco
 
 // Context accessors for the sidelobe-network and map-making runtimes (runtime.cpp).

@@ -669,6 +669,11 @@ pisco_status pisco_create(int device, pisco_ctx **out) {
     pisco_ctx *c = new pisco_ctx();
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    // the device address of the allocation-free entry point's plan array
+    if (pisco::static_scratch_init(device) != hipSuccess) {
+        delete c;
+        return PISCO_EDEVICE;
+    }
     if (!dmalloc(c, reinterpret_cast<void **>(&c->d_flag), sizeof(int32_t))) {
         delete c;
         return PISCO_ENOMEM;
@@ -1561,6 +1566,69 @@ int32_t pisco_sidelobe_history(const pisco_ctx *c, int32_t det, double *loss, in
     if (loss)
         for (int32_t i = 0; i < std::min(n, cap); ++i) loss[i] = d.sl->hist[i];
     return n;
+}
+
+pisco_status pisco_convolve_static(pisco_ctx *c, int32_t det, int out_mode, void *out, void *stream) {
+    if (!c) return PISCO_EINVAL;
+    c->err.clear();
+    if (!c->sky) return fail(c, PISCO_ESTATE, "no sky set");
+    if (out_mode != PISCO_OUT_TOD && out_mode != PISCO_OUT_STOKES && out_mode != PISCO_OUT_COUNT)
+        return fail(c, PISCO_EINVAL, "bad out_mode %d", out_mode);
+    if (det < 0 || (size_t)det >= c->dets.size() || !det_ready(c->dets[det]))
+        return fail(c, PISCO_ESTATE, "detector %d lacks a beam, parameters or pointing", det);
+    const DetState &d = c->dets[det];
+    if (d.beam_dtype != c->sky_dtype) return fail(c, PISCO_EINVAL, "detector %d beam dtype differs from the sky dtype", det);
+    if (!d.host_pointing.empty() || !d.host_hwp.empty())
+        return fail(c, PISCO_EINVAL, "detector %d keeps its pointing or plate angles on the host (memory budget)", det);
+    if (d.hwp && d.hwp_n != d.nsamp)
+        return fail(c, PISCO_EINVAL, "detector %d has %lld plate angles for %lld samples", det, (long long)d.hwp_n,
+                    (long long)d.nsamp);
+    if (d.beam_v && c->algo != PISCO_ALGO_PIXEL && out_mode == PISCO_OUT_TOD &&
+        (size_t)c->wpg * (4352 + std::max<size_t>(3840, 48 * (size_t)c->chunk) + 4 * (size_t)c->chunk) > 160 * 1024)
+        return fail(c, PISCO_EINVAL, "detector %d: a V-column beam needs more LDS than chunk %d with %d waves per "
+                    "group leaves", det, c->chunk, c->wpg);
+    const bool sub = out_mode == PISCO_OUT_TOD && d.sl_on && d.sl;
+    if (sub && c->sky_dtype != PISCO_F32)
+        return fail(c, PISCO_EINVAL, "detector %d: the sidelobe network runs on the FP32 path only", det);
+    if (d.nsamp == 0) return PISCO_OK;
+    if (!out) return fail(c, PISCO_EINVAL, "null output");
+    if (d.nsamp > pisco::STATIC_MAX_GROUPS * 64)
+        return fail(c, PISCO_EINVAL, "detector %d has %lld samples; the allocation-free path takes at most %lld",
+                    det, (long long)d.nsamp, (long long)(pisco::STATIC_MAX_GROUPS * 64));
+    void *base = pisco::static_scratch(c->device);
+    if (!base) return fail(c, PISCO_EDEVICE, "the plan array's device address is unknown");
+    HIP_TRY(c, hipSetDevice(c->device));
+    DetDesc x = make_desc(d, sub);
+    x.theta = d.th;
+    x.phi = d.ph;
+    x.psi = d.ps;
+    x.out_offset = 0;
+    ConvArgs a{};
+    a.sky = c->sky;
+    a.out = out;
+    a.nside = c->nside;
+    a.out_mode = out_mode;
+    a.beam_kind = d.beam_kind;
+    a.chunk = c->chunk;
+    a.coherence = c->coherence;
+    a.per_sample = d.norm_mode == PISCO_NORM_PER_SAMPLE ? 1 : 0;
+    a.hwp = d.hwp ? 1 : 0;
+    a.vbeam = d.beam_v ? 1 : 0;
+    const bool extended = d.beam_v || d.wv != 0.0 || d.hwp;
+    ConvArgs tile = a, pix = a;
+    tile.algo = (c->algo == PISCO_ALGO_TILE_MX && !extended) ? pisco::ALGO_TILE_MX : pisco::ALGO_TILE;
+    pix.algo = pisco::ALGO_PIXEL;
+    const bool tile_path = (c->algo == PISCO_ALGO_TILE || c->algo == PISCO_ALGO_TILE_MX) && c->sky_dtype == PISCO_F32;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = pisco::launch_static(tile, pix, x, tile_path, c->sky_dtype == PISCO_F64, c->wpg,
+                                        c->gpc * c->num_cu, base, s);
+    if (e == hipSuccess && sub) {
+        const SlApply ap = sl_apply_of(d, d.th, d.ph, d.ps, d.nsamp, 0);
+        e = pisco::mlp_apply_pointing(ap.net, ap.th, ap.ph, ap.ps, ap.n, ap.mean, ap.stdv, ap.coef,
+                                      static_cast<float *>(out), s);
+    }
+    if (e != hipSuccess) return fail(c, PISCO_EDEVICE, "allocation-free convolution launch failed: %s", hipGetErrorString(e));
+    return PISCO_OK;
 }
 
 }  // extern "C"
