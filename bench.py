@@ -78,18 +78,24 @@ def log(msg):
 
 def measured_traffic(launch):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter runs, or None once the kernel source or the launch shape differs
-    from the one the counters were taken with."""
+    counter runs, or None once a source they depend on (the kernel, the plan
+    builder that orders its tiles) or the launch shape differs from the one the
+    counters were taken with."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic_conv_c3.json")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()
-    except (OSError, KeyError, ValueError):
+        same = all(hashlib.sha256(open(os.path.join(ROOT, f), "rb").read()).hexdigest() == h
+                   for f, h in rec["sources_sha256"].items())
+        if not same:
+            return None
+        for r in rec["records"]:
+            if all(launch.get(k) == v for k, v in r["launch"].items()):
+                return r["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError, AttributeError, TypeError):
         return None
-    same = sha == rec["source_sha256"] and all(launch.get(k) == v for k, v in rec.get("launch", {}).items())
-    return rec["traffic_bytes_per_launch"] if same else None
+    return None
 
 
 def load(conv, w, torch):
@@ -863,8 +869,8 @@ def main():
     ap.add_argument("--no-parity", action="store_true", help="skip the per-recipe parity leg")
     ap.add_argument("--no-full-scale", action="store_true",
                     help="skip the nside-2048, 1e8-sample surrogate-vs-exact leg")
-    ap.add_argument("--full-scale-train", type=int, default=2_000_000)
-    ap.add_argument("--full-scale-epochs", type=int, default=60)
+    ap.add_argument("--full-scale-train", type=int, default=6_000_000)
+    ap.add_argument("--full-scale-epochs", type=int, default=120)
     ap.add_argument("--full-scale-net", type=str, default="512x10",
                     help="network width x hidden layers for the full-scale leg")
     ap.add_argument("--full-scale-lr", type=float, default=7e-4)

@@ -256,15 +256,22 @@ int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
  *                    (1 - n.p, the antenna-frame coordinates, the co-polar
  *                    projections) formed by FP32 matrix-core products.
  *                    Launches with a half-wave plate or V terms run the
- *                    PISCO_ALGO_TILE kernels instead.
+ *                    PISCO_ALGO_TILE kernels instead.  Kept for comparison:
+ *                    on gfx950 it runs about twice as long as PISCO_ALGO_TILE
+ *                    (it saves few vector instructions and its vector work
+ *                    waits on the matrix results).
  *   samples_per_tile consecutive samples a wavefront takes per queue pop (1..65536)
  *   waves_per_group  wavefronts per workgroup (1, 2, 4 or 8)
  *   groups_per_cu    workgroups launched per compute unit (1..16)
  *   xcd_queues       1: one shared work queue; 8: one queue per accelerator
- *                    die, each holding a contiguous block of tiles
+ *                    die, each holding a contiguous block of tiles (a
+ *                    workgroup starts on its die's queue and takes from the
+ *                    others once it is empty).  Each detector's tiles are
+ *                    queued in the Hilbert order of their first samples, so
+ *                    that tiles running together on a die share sky in L2.
  *   chunk            tile paths: union pixels staged in LDS per pass (64, 128, 256)
  *   coherence        tile paths: see algorithm, in (0, 4]
- * A new context starts at {PISCO_ALGO_TILE, 64, 4, 4, 1, 64, 0.5}.
+ * A new context starts at {PISCO_ALGO_TILE, 64, 4, 4, 8, 64, 0.5}.
  * Results are bitwise reproducible for a given launch shape.  They do not
  * depend on the shape except through the algorithm (the two paths round
  * differently) and, on the tile path, through samples_per_tile when it is not

@@ -215,12 +215,19 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline int wave_inclusive_scan(int v, int lane) {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const int o = __shfl_up(v, d, WAVE);
-        if (lane >= d) v += o;
-    }
+// Inclusive prefix sum over the 64 lanes by DPP moves (no lane-index
+// arithmetic, so nothing lane-dependent stays live between calls): shifts by
+// 1, 2, 4, 8 inside each row of 16 lanes (lanes shifted in from outside the row
+// add 0), then the total of row 0 (lane 15) is added into row 1 and that of
+// row 2 (lane 47) into row 3, and the total of rows 0-1 (lane 31) into rows 2
+// and 3.
+__device__ inline int wave_inclusive_scan(int v, int) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
     return v;
 }
 
@@ -512,7 +519,8 @@ __device__ inline BeamRsrc make_beam_rsrc(const void *p, uint32_t nrec) {
     const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
     const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
     void *u = (void *)(((unsigned long long)hi << 32) | lo);
-    return BeamRsrc{__builtin_amdgcn_make_buffer_rsrc(u, (short)0, (int)(nrec * 16u), 0x00020000)};
+    const int bytes = (int)__builtin_amdgcn_readfirstlane(nrec * 16u);   // uniform: the descriptor stays in SGPRs
+    return BeamRsrc{__builtin_amdgcn_make_buffer_rsrc(u, (short)0, bytes, 0x00020000)};
 }
 __device__ inline float4 beam_ld(const BeamRsrc &b, uint32_t off, int32_t soff) {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)off, soff, 0);
@@ -568,13 +576,16 @@ static_assert(sizeof(UnionRing) == 64 && sizeof(LaneFrame) == 60 && sizeof(PixRe
 
 struct TileFrame {
     double thc, phc, zc, sc, Ru;
+    double cosRu;           // cos of the union radius
+    int32_t r_lo, r_hi;     // rings that can meet the union cap
 };
 
 // FP64 set-up of a tile: the centre c (normalised mean boresight), the union
 // radius, and each lane's sample expressed in the frame (e1, e2, c) with
 // e1 = theta_hat(c), e2 = phi_hat(c).  Not inlined: its transcendental
 // constants stay out of the pixel loops.
-__device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int64_t t, bool valid, LaneFrame *out) {
+__device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int32_t N, int64_t t, bool valid,
+                                                          LaneFrame *out) {
     const double th0 = D.theta[t], ph0 = D.phi[t], ps0 = D.psi[t];
     double st, ct, sf, cf, sp, cp, sg, cg;
     sincos(th0, &st, &ct);
@@ -640,6 +651,11 @@ __device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int6
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) dist = fmax(dist, __shfl_xor(dist, m, WAVE));
     T.Ru = D.rho_max + dist + 1e-9;
+    // wave-uniform from here (the reductions above leave every lane equal)
+    T.cosRu = cos(T.Ru);
+    const int32_t nring = 4 * N - 1;
+    T.r_lo = (T.thc - T.Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, T.thc - T.Ru)) - 1);
+    T.r_hi = (T.thc + T.Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, T.thc + T.Ru)) + 1);
     return T;
 }
 
@@ -1009,12 +1025,11 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const bool valid = lane < cnt;
     const int64_t t = sample_at(D, begin + (valid ? lane : 0));
 
-    const TileFrame T = tile_setup(D, t, valid, &L.lane[lane]);
+    const TileFrame T = tile_setup(D, N, t, valid, &L.lane[lane]);
     const LaneFrame F = L.lane[lane];
     wave_sync();   // every lane holds its frame before records overwrite the slice
-    const double thc = uniform(T.thc), phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
-    const double Ru = uniform(T.Ru);
-    const double cosRu = cos(Ru);
+    const double phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
+    const double cosRu = uniform(T.cosRu);
     const float zcf = (float)zc, scf = (float)sc;
 
     const int32_t n = D.n;
@@ -1054,9 +1069,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     AccWide acc0, acc1, acc2, accn;
     int32_t npairs = 0;
 
-    const int32_t nring = 4 * N - 1;
-    const int32_t r_lo = (thc - Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, thc - Ru)) - 1);
-    const int32_t r_hi = (thc + Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, thc + Ru)) + 1);
+    const int32_t r_lo = __builtin_amdgcn_readfirstlane(T.r_lo), r_hi = __builtin_amdgcn_readfirstlane(T.r_hi);
 
     const LaneHull H = lane_hull(D, t, valid, phc, zc, sc);
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
@@ -1244,10 +1257,9 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const bool valid = lane < cnt;
     const int64_t t = sample_at(D, begin + (valid ? lane : 0));
 
-    const TileFrame T = tile_setup(D, t, valid, &L.lane[lane]);
-    const double thc = uniform(T.thc), phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
-    const double Ru = uniform(T.Ru);
-    const double cosRu = cos(Ru);
+    const TileFrame T = tile_setup(D, N, t, valid, &L.lane[lane]);
+    const double phc = uniform(T.phc), zc = uniform(T.zc), sc = uniform(T.sc);
+    const double cosRu = uniform(T.cosRu);
     const float zcf = (float)zc, scf = (float)sc;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -1271,9 +1283,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const int32_t row_bytes = (int32_t)(16 * n);
     const int k4 = lane >> 4, c16 = lane & 15;
 
-    const int32_t nring = 4 * N - 1;
-    const int32_t r_lo = (thc - Ru <= 0.0) ? 1 : max(1, (int32_t)floor(ring_of_theta(N, thc - Ru)) - 1);
-    const int32_t r_hi = (thc + Ru >= PI) ? nring : min(nring, (int32_t)ceil(ring_of_theta(N, thc + Ru)) + 1);
+    const int32_t r_lo = __builtin_amdgcn_readfirstlane(T.r_lo), r_hi = __builtin_amdgcn_readfirstlane(T.r_hi);
 
     const LaneHull H = lane_hull(D, t, valid, phc, zc, sc);
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {

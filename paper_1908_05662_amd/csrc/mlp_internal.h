@@ -42,6 +42,7 @@ struct MlpReduceSeg {
     float *out;
     int64_t count;
     int32_t slices;
+    int32_t groups;   // slices summed in parallel groups (divides 256), combined in order
 };
 struct MlpReduceList {
     MlpReduceSeg seg[MLP_MAX_SEGS];
@@ -49,12 +50,14 @@ struct MlpReduceList {
 };
 hipError_t mlp_reduce_many(const MlpReduceList &l, hipStream_t s);
 hipError_t mlp_out(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n, int32_t H,
-                   float *y, const float *tgt, float inv_count, __bf16 *dz, float *part_w, float *part_b,
-                   float *part_loss, int32_t waves, int32_t rows_per_wave, hipStream_t s);
-hipError_t mlp_colsum(const __bf16 *m, int32_t n, int32_t H, int32_t rows, int32_t blocks, float *part, hipStream_t s);
-hipError_t mlp_in_grad(const __bf16 *dz, const float *x, int32_t n, int32_t H, int32_t rows, int32_t blocks,
-                       float *part, hipStream_t s);
-hipError_t mlp_reduce(const float *part, int32_t slices, int64_t count, float *out, hipStream_t s);
+                   float *y, const float *tgt, float inv_count, float *dy, __bf16 *dz, float *part_loss,
+                   int32_t waves, int32_t rows_per_wave, hipStream_t s);
+// part[b * stride + u * su + k * sk] = sum over the rows r of block b (MLP_WCOL_ROWS
+// rows each) of w(r, k) m[r][u], w(r, k) = wt[r K + k] or 1 (wt null, K = 1);
+// ones[b K + k] = sum_r w(r, k) when given.  K in {1, 3, 5}.
+#define MLP_WCOL_ROWS 32
+hipError_t mlp_wcolsum(const __bf16 *m, const float *wt, int32_t K, int32_t n, int32_t H, float *part, int64_t stride,
+                       int32_t su, int32_t sk, float *ones, hipStream_t s);
 hipError_t mlp_adam(float *w, float *m, float *v, const float *g, __bf16 *wb, int64_t count, float lr_t, float b1,
                     float b2, float eps, float inv_bc2_sqrt, hipStream_t s);
 hipError_t mlp_to_bf16(const float *w, __bf16 *wb, int64_t count, hipStream_t s);

@@ -11,11 +11,10 @@
 //                 FWD   Z = A W^T + b -> Z (fp32), SiLU(Z) (bf16)
 //                 BWD_D dZ_prev = (dZ W) * SiLU'(Z_prev)   (bf16)
 //                 BWD_W partial dW = dZ^T A over one batch slice (fp32, split-K)
-//   out_fwd_bwd output layer (N = 3): Y, MSE loss, dY, dZ_L = (dY W_out) * SiLU'(Z_L),
-//               per-block partial sums of dW_out and db_out
-//   colsum      per-block partial column sums (bias gradients)
-//   in_grad     per-block partials of dW0 = dZ1^T X
-//   reduce      fixed-order sums of partials (deterministic gradients)
+//   out_rows    output layer (N = 3): Y, MSE loss, dY, dZ_L = (dY W_out) * SiLU'(Z_L)
+//   wcolsum     per-block partial weighted column sums: the bias gradients,
+//               dW0 = dZ1^T X and dW_out = dY^T A_L (with db_out)
+//   reduce_many fixed-order sums of the partials (deterministic gradients)
 //   adam        Adam on FP32 master weights, refreshing the BF16 copy
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -45,13 +44,15 @@ __device__ inline float silu_grad(float z) {
 // layers' backward passes read transposed copies the forward epilogues,
 // the output layer and Adam keep).  M, N multiples of the tile (64 or 128),
 // K of 32.  Workgroup: four waves as 2 x 2, each (BM/2) x (BN/2) of
-// v_mfma_f32_16x16x32_bf16 tiles; 32-wide k steps staged in LDS, double
+// v_mfma_f32_16x16x32_bf16 tiles; 64-wide k steps staged in LDS, double
 // buffered (the next step's tiles are fetched into registers while the
-// current step's MFMAs run).  Every output element is one MFMA chain over
-// k0 = 0, 32, 64, ... with lane l holding k0 + 8 (l / 16) .. + 7 of row
-// l % 16: the fragments and order of the fused inference kernel.
+// current step's MFMAs run; k past the end of the slice reads as zero and its
+// MFMAs are skipped).  Every output element is one MFMA chain over k0 = 0, 32,
+// 64, ... with lane l holding k0 + 8 (l / 16) .. + 7 of row l % 16: the
+// fragments and order of the fused inference kernel.
 // ----------------------------------------------------------------------
-constexpr int TK = 32, LDK = TK + 8;  // LDS rows padded by 16 bytes
+constexpr int TK = 32;                 // k per MFMA
+constexpr int KS = 64, LDK = KS + 8;   // k per staged step; LDS rows padded by 16 bytes
 
 enum { EPI_FWD = MLP_EPI_FWD, EPI_BWD_D = MLP_EPI_BWD_D, EPI_BWD_W = MLP_EPI_BWD_W };
 
@@ -70,23 +71,25 @@ struct GemmArgs {
     float *partial;        // BWD_W: [slice][M][N]
 };
 
-// Rows [r0, r0 + R) x k [k0, k0 + 32) of a k-contiguous operand: R * 4 chunks of
-// 16 bytes, CH per thread of 256.
+// Rows [r0, r0 + R) x k [k0, k0 + KS) of a k-contiguous operand: R * KS / 8
+// chunks of 16 bytes, CH per thread of 256; chunks at k >= ke read as zero.
 template <int R>
 struct TileRegs {
-    static constexpr int CH = R * 4 / 256;
+    static constexpr int CPR = KS / 8;            // chunks per row
+    static constexpr int CH = R * CPR / 256;
     bf16x8 v[CH];
-    __device__ inline void load(const __bf16 *__restrict__ p, int64_t ld, int r0, int k0, int tid) {
+    __device__ inline void load(const __bf16 *__restrict__ p, int64_t ld, int r0, int k0, int ke, int tid) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
-            const int idx = tid + 256 * c, r = idx >> 2, kk = (idx & 3) * 8;
-            v[c] = *reinterpret_cast<const bf16x8 *>(p + (int64_t)(r0 + r) * ld + (k0 + kk));
+            const int idx = tid + 256 * c, r = idx / CPR, kk = (idx % CPR) * 8;
+            if (k0 + kk < ke) v[c] = *reinterpret_cast<const bf16x8 *>(p + (int64_t)(r0 + r) * ld + (k0 + kk));
+            else v[c] = bf16x8{};
         }
     }
     __device__ inline void store(__bf16 (*dst)[LDK], int tid) const {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
-            const int idx = tid + 256 * c, r = idx >> 2, kk = (idx & 3) * 8;
+            const int idx = tid + 256 * c, r = idx / CPR, kk = (idx % CPR) * 8;
             *reinterpret_cast<bf16x8 *>(&dst[r][kk]) = v[c];
         }
     }
@@ -111,29 +114,35 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     TileRegs<BM> ra;
     TileRegs<BN> rb;
     if (kb < ke) {
-        ra.load(g.a, g.lda, m0, kb, tid);
-        rb.load(g.b, g.ldb, n0, kb, tid);
+        ra.load(g.a, g.lda, m0, kb, ke, tid);
+        rb.load(g.b, g.ldb, n0, kb, ke, tid);
         ra.store(As[0], tid);
         rb.store(Bs[0], tid);
     }
     __syncthreads();
     int cur = 0;
-    for (int k0 = kb; k0 < ke; k0 += TK) {
-        const bool more = k0 + TK < ke;
+    for (int k0 = kb; k0 < ke; k0 += KS) {
+        const bool more = k0 + KS < ke;
         if (more) {
-            ra.load(g.a, g.lda, m0, k0 + TK, tid);
-            rb.load(g.b, g.ldb, n0, k0 + TK, tid);
+            ra.load(g.a, g.lda, m0, k0 + KS, ke, tid);
+            rb.load(g.b, g.ldb, n0, k0 + KS, ke, tid);
         }
-        bf16x8 af[FI], bfr[FJ];
 #pragma unroll
-        for (int i = 0; i < FI; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][wm + 16 * i + r][kq]);
+        for (int ks = 0; ks < KS; ks += TK) {
+            if (k0 + ks >= ke) break;
+            bf16x8 af[FI], bfr[FJ];
 #pragma unroll
-        for (int j = 0; j < FJ; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][wn + 16 * j + r][kq]);
-#pragma unroll
-        for (int i = 0; i < FI; ++i)
+            for (int i = 0; i < FI; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As[cur][wm + 16 * i + r][ks + kq]);
 #pragma unroll
             for (int j = 0; j < FJ; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[cur][wn + 16 * j + r][ks + kq]);
+#pragma unroll
+            for (int i = 0; i < FI; ++i)
+#pragma unroll
+                for (int j = 0; j < FJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
         if (more) {
             ra.store(As[cur ^ 1], tid);
             rb.store(Bs[cur ^ 1], tid);
@@ -208,24 +217,21 @@ __global__ void in_fwd_kernel(const float *x, const __bf16 *w0, const float *b0,
     a[i] = (__bf16)silu(s);
 }
 
-// Output layer with loss: one wave per row, lanes over the H units (H % 64 == 0).
-// Writes y; if targets are given also the loss partial, dY, dZ_L and per-wave
-// partials of dW_out [3][H] and db_out [3].
-__global__ void out_kernel(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n,
-                           int32_t H, float *y, const float *tgt, float inv_count, __bf16 *dz, float *part_w,
-                           float *part_b, float *part_loss, int32_t waves, int32_t rows_per_wave) {
+// Output layer: `rows` consecutive rows per wave, lanes over the H units
+// (H % 64 == 0, H <= 512).  Per row, y_c = sum_u a_u W_out[c][u] + b_c as a
+// per-lane FMA chain over u = lane + 64 k followed by an xor butterfly (the
+// order the fused inference kernel repeats).  With targets it also writes
+// dY = 2 (y - t) / count (fp32, for the weight-gradient sums), dZ_L =
+// (dY W_out) * SiLU'(Z_L) (bf16) and the wave's sum of squared errors.
+__global__ void out_rows_kernel(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n,
+                                int32_t H, float *y, const float *tgt, float inv_count, float *dy_out, __bf16 *dz,
+                                float *part_loss, int32_t waves, int32_t rows) {
     const int lane = threadIdx.x & 63;
     const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (wv >= waves) return;
     const int per = H / 64;
-    float gw[MLP_OUT][8];
-    float gb[MLP_OUT] = {0.0f, 0.0f, 0.0f};
     float gl = 0.0f;
-#pragma unroll
-    for (int c = 0; c < MLP_OUT; ++c)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) gw[c][k] = 0.0f;
-    for (int64_t r = wv * rows_per_wave; r < min((int64_t)n, (wv + 1) * rows_per_wave); ++r) {
+    for (int64_t r = wv * rows; r < min((int64_t)n, (wv + 1) * rows); ++r) {
         float av[8], s[MLP_OUT] = {0.0f, 0.0f, 0.0f};
         for (int k = 0; k < per; ++k) {
             const int u = lane + 64 * k;
@@ -248,70 +254,94 @@ __global__ void out_kernel(const __bf16 *a, const float *zL, const __bf16 *wout,
             const float e = s[c] - tgt[r * MLP_OUT + c];
             gl += e * e;
             dy[c] = 2.0f * e * inv_count;
-            gb[c] += dy[c];
         }
+        if (lane == 0)
+            for (int c = 0; c < MLP_OUT; ++c) dy_out[r * MLP_OUT + c] = dy[c];
         for (int k = 0; k < per; ++k) {
             const int u = lane + 64 * k;
             float da = 0.0f;
 #pragma unroll
-            for (int c = 0; c < MLP_OUT; ++c) {
-                da = fmaf(dy[c], (float)wout[c * H + u], da);
-                gw[c][k] = fmaf(dy[c], av[k], gw[c][k]);
-            }
+            for (int c = 0; c < MLP_OUT; ++c) da = fmaf(dy[c], (float)wout[c * H + u], da);
             dz[r * H + u] = (__bf16)(da * silu_grad(zL[r * H + u]));
         }
     }
-    if (!tgt) return;
-    for (int k = 0; k < per; ++k)
+    if (tgt && lane == 0) part_loss[wv] = gl;  // lane 0 saw every row's error (the sums were reduced)
+}
+
+// Weighted column sums over blocks of MLP_WCOL_ROWS rows.  Block (b, slab)
+// writes, for the columns u of its 512-column slab (thread t: u = 512 slab +
+// 2t, 2t + 1),
+//   part[b * stride + u * su + k * sk] = sum_r w(r, k) m[r][u]   (rows in order)
+// with w(r, k) = wt[r K + k], or 1 when wt is null (K = 1); with `ones` set,
+// block b also writes ones[b K + k] = sum_r w(r, k).  The block's rows are
+// loaded before any is added, so their loads are in flight together.
+template <int K>
+__global__ void __launch_bounds__(256) wcolsum_kernel(const __bf16 *m, const float *wt, int32_t n, int32_t H,
+                                                      float *part, int64_t stride, int32_t su, int32_t sk,
+                                                      float *ones) {
+    constexpr int R = MLP_WCOL_ROWS;
+    const int u0 = blockIdx.y * 512 + 2 * threadIdx.x;
+    const bool act = u0 < H;   // H is even
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    uint32_t mv[R];   // two bf16 per row, low half first
 #pragma unroll
-        for (int c = 0; c < MLP_OUT; ++c) part_w[(wv * MLP_OUT + c) * H + lane + 64 * k] = gw[c][k];
-    if (lane == 0) {
-        for (int c = 0; c < MLP_OUT; ++c) part_b[wv * MLP_OUT + c] = gb[c];
-        part_loss[wv] = gl;  // lane 0 saw every row's error (the sums were reduced)
+    for (int q = 0; q < R; ++q)
+        mv[q] = (act && r0 + q < n) ? *reinterpret_cast<const uint32_t *>(m + (r0 + q) * H + u0) : 0u;
+    float s0[K], s1[K], so[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s0[k] = s1[k] = so[k] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        if (r0 + q >= n) break;
+        float w[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) w[k] = wt ? wt[(r0 + q) * K + k] : 1.0f;
+        const float m0 = __uint_as_float(mv[q] << 16), m1 = __uint_as_float(mv[q] & 0xffff0000u);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            s0[k] = fmaf(w[k], m0, s0[k]);
+            s1[k] = fmaf(w[k], m1, s1[k]);
+            so[k] += w[k];
+        }
+    }
+    float *pb = part + (int64_t)blockIdx.x * stride;
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            pb[(int64_t)u0 * su + (int64_t)k * sk] = s0[k];
+            pb[(int64_t)(u0 + 1) * su + (int64_t)k * sk] = s1[k];
+        }
+    }
+    if (ones && blockIdx.y == 0 && threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) ones[(int64_t)blockIdx.x * K + k] = so[k];
     }
 }
 
-// Per-block partial column sums of a [n][H] bf16 matrix: block b covers rows
-// [b*rows, (b+1)*rows), thread u sums column u (blockDim = H).
-__global__ void colsum_kernel(const __bf16 *m, int32_t n, int32_t H, int32_t rows, float *part) {
-    const int u = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min((int64_t)n, r0 + rows);
-    float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += (float)m[r * H + u];
-    part[(int64_t)blockIdx.x * H + u] = s;
-}
-
-// Per-block partials of dW0 = dZ1^T X: thread u of block b sums over its rows.
-__global__ void in_grad_kernel(const __bf16 *dz, const float *x, int32_t n, int32_t H, int32_t rows, float *part) {
-    const int u = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min((int64_t)n, r0 + rows);
-    float s[MLP_IN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t r = r0; r < r1; ++r) {
-        const float d = (float)dz[r * H + u];
-#pragma unroll
-        for (int k = 0; k < MLP_IN; ++k) s[k] = fmaf(d, x[r * MLP_IN + k], s[k]);
-    }
-#pragma unroll
-    for (int k = 0; k < MLP_IN; ++k) part[((int64_t)blockIdx.x * H + u) * MLP_IN + k] = s[k];
-}
-
-// out[i] = sum_s part[s * count + i] in order s = 0, 1, ...
-__global__ void reduce_kernel(const float *part, int32_t slices, int64_t count, float *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    float s = 0.0f;
-    for (int k = 0; k < slices; ++k) s += part[(int64_t)k * count + i];
-    out[i] = s;
-}
-
-// The same sums for a list of (partials, slices, count, out) segments in one
-// launch; blockIdx.y picks the segment.
-__global__ void reduce_many_kernel(MlpReduceList L) {
-    const MlpReduceSeg &g = L.seg[blockIdx.y];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.count; i += (int64_t)gridDim.x * blockDim.x) {
+// Fixed-order sums of several partial arrays in one launch: out[i] = sum over
+// slices j = 0, 1, ... of part[j * count + i], for the segment blockIdx.y.  A
+// segment with G slice groups (G divides 256) gives each block 256 / G outputs;
+// thread (o, g) adds slices g, g + G, ... in order, then group 0 adds the G
+// group sums in order g = 0, 1, ...: the same result on every run.
+__global__ void __launch_bounds__(256) reduce_many_kernel(MlpReduceList L) {
+    __shared__ float red[256];
+    const MlpReduceSeg &sg = L.seg[blockIdx.y];
+    const int G = sg.groups, OB = 256 / G;
+    const int o = threadIdx.x % OB, g = threadIdx.x / OB;
+    const int64_t chunks = (sg.count + OB - 1) / OB;
+    for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+        const int64_t i = c * OB + o;
         float s = 0.0f;
-        for (int k = 0; k < g.slices; ++k) s += g.part[(int64_t)k * g.count + i];
-        g.out[i] = s;
+        if (i < sg.count)
+            for (int j = g; j < sg.slices; j += G) s += sg.part[(int64_t)j * sg.count + i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        if (g == 0 && i < sg.count) {
+            float t = red[o];
+            for (int q = 1; q < G; ++q) t += red[q * OB + o];
+            sg.out[i] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -335,14 +365,20 @@ __global__ void to_bf16_kernel(const float *w, __bf16 *wb, int64_t count) {
     if (i < count) wb[i] = (__bf16)w[i];
 }
 
-__global__ void loss_sum_kernel(const float *part, int32_t count, float inv_count, float *loss) {
-    // one wave; fixed order
-    const int lane = threadIdx.x;
+// Sum of the per-wave squared errors in a fixed order: thread t adds entries
+// t, t + 256, ... in order, then a tree over the 256 partial sums.
+__global__ void __launch_bounds__(256) loss_sum_kernel(const float *part, int32_t count, float inv_count, float *loss) {
+    __shared__ float red[256];
+    const int t = threadIdx.x;
     float s = 0.0f;
-    for (int i = lane; i < count; i += 64) s += part[i];
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m, 64);
-    if (lane == 0) *loss = s * inv_count;
+    for (int i = t; i < count; i += 256) s += part[i];
+    red[t] = s;
+    __syncthreads();
+    for (int h = 128; h >= 1; h >>= 1) {
+        if (t < h) red[t] += red[t + h];
+        __syncthreads();
+    }
+    if (t == 0) *loss = red[0] * inv_count;
 }
 
 // Features of a pointing stream: (sin th cos ph, sin th sin ph, cos th, sin psi, cos psi).
@@ -378,7 +414,7 @@ __global__ void apply_kernel(const float *y, int64_t n, float m0, float m1, floa
 // (two buffers), weights read from L2.  The H x H layers use the operand
 // fragments and K order of gemm_kernel, layer 0 the FMA chain of
 // in_fwd_kernel, the output layer the per-lane order and butterfly of
-// out_kernel and the epilogue apply_kernel's arithmetic, so the result equals
+// out_rows_kernel and the epilogue apply_kernel's arithmetic, so the result equals
 // the layer-by-layer forward pass followed by apply, bit for bit.
 // ----------------------------------------------------------------------
 constexpr int IR = 64;        // rows per workgroup
@@ -526,20 +562,23 @@ hipError_t mlp_in_fwd(const float *x, const __bf16 *w0, const float *b0, int32_t
     return hipGetLastError();
 }
 
+// 128 x 128 tiles only when they still give two workgroups per CU (512);
+// otherwise 64 x 64 tiles, four times as many workgroups to hide the load
+// latency of these short-K products.
 template <int EPI>
 static void gemm_launch(const GemmArgs &g, hipStream_t s) {
-    const int bm = g.M % 128 == 0 ? 128 : 64, bn = g.N % 128 == 0 ? 128 : 64;
-    const dim3 grid(g.N / bn, g.M / bm, (g.K + g.k_slice - 1) / g.k_slice);
-    if (bm == 128 && bn == 128) hipLaunchKernelGGL((gemm_kernel<EPI, 128, 128>), grid, dim3(256), 0, s, g);
-    else if (bm == 128) hipLaunchKernelGGL((gemm_kernel<EPI, 128, 64>), grid, dim3(256), 0, s, g);
-    else if (bn == 128) hipLaunchKernelGGL((gemm_kernel<EPI, 64, 128>), grid, dim3(256), 0, s, g);
+    const int64_t z = (g.K + g.k_slice - 1) / g.k_slice;
+    const bool big = g.M % 128 == 0 && g.N % 128 == 0 && (int64_t)(g.M / 128) * (g.N / 128) * z >= 512;
+    const int t = big ? 128 : 64;
+    const dim3 grid(g.N / t, g.M / t, (unsigned)z);
+    if (big) hipLaunchKernelGGL((gemm_kernel<EPI, 128, 128>), grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL((gemm_kernel<EPI, 64, 64>), grid, dim3(256), 0, s, g);
 }
 
 hipError_t mlp_gemm(int epi, const __bf16 *a, int64_t lda, const __bf16 *b, int64_t ldb, int32_t M, int32_t N,
                     int32_t K, int32_t k_slice, const float *bias, float *z_out, __bf16 *a_out, __bf16 *t_out,
                     int64_t ldt, const float *z_prev, float *partial, hipStream_t s) {
-    if (M % 64 || N % 64 || K % TK || k_slice % TK || k_slice <= 0) return hipErrorInvalidValue;
+    if (M % 64 || N % 64 || K % TK || k_slice % KS || k_slice <= 0) return hipErrorInvalidValue;
     GemmArgs g;
     g.a = a;
     g.b = b;
@@ -574,36 +613,42 @@ hipError_t mlp_transpose(const __bf16 *src, int64_t lds, __bf16 *dst, int64_t ld
 hipError_t mlp_reduce_many(const MlpReduceList &l, hipStream_t s) {
     if (l.n <= 0) return hipSuccess;
     int64_t mx = 0;
-    for (int i = 0; i < l.n; ++i) mx = std::max<int64_t>(mx, l.seg[i].count);
-    const unsigned bx = (unsigned)std::min<int64_t>(1024, (mx + 255) / 256);
+    for (int i = 0; i < l.n; ++i) {
+        const int G = l.seg[i].groups;
+        if (G < 1 || G > 256 || 256 % G || l.seg[i].slices < 0) return hipErrorInvalidValue;
+        mx = std::max<int64_t>(mx, (l.seg[i].count + 256 / G - 1) / (256 / G));
+    }
+    if (mx == 0) return hipSuccess;
+    const unsigned bx = (unsigned)std::min<int64_t>(4096, mx);
     hipLaunchKernelGGL(reduce_many_kernel, dim3(bx, l.n), dim3(256), 0, s, l);
     return hipGetLastError();
 }
 
 hipError_t mlp_out(const __bf16 *a, const float *zL, const __bf16 *wout, const float *bout, int32_t n, int32_t H,
-                   float *y, const float *tgt, float inv_count, __bf16 *dz, float *part_w, float *part_b,
-                   float *part_loss, int32_t waves, int32_t rows_per_wave, hipStream_t s) {
+                   float *y, const float *tgt, float inv_count, float *dy, __bf16 *dz, float *part_loss,
+                   int32_t waves, int32_t rows_per_wave, hipStream_t s) {
     if (n == 0) return hipSuccess;
+    if (H % 64 || H > 512) return hipErrorInvalidValue;
     const int wpb = 4;
-    hipLaunchKernelGGL(out_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, a, zL, wout, bout,
-                       n, H, y, tgt, inv_count, dz, part_w, part_b, part_loss, waves, rows_per_wave);
+    hipLaunchKernelGGL(out_rows_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(64 * wpb), 0, s, a, zL, wout,
+                       bout, n, H, y, tgt, inv_count, dy, dz, part_loss, waves, rows_per_wave);
     return hipGetLastError();
 }
 
-hipError_t mlp_colsum(const __bf16 *m, int32_t n, int32_t H, int32_t rows, int32_t blocks, float *part, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3(blocks), dim3(H), 0, s, m, n, H, rows, part);
-    return hipGetLastError();
-}
-
-hipError_t mlp_in_grad(const __bf16 *dz, const float *x, int32_t n, int32_t H, int32_t rows, int32_t blocks,
-                       float *part, hipStream_t s) {
-    hipLaunchKernelGGL(in_grad_kernel, dim3(blocks), dim3(H), 0, s, dz, x, n, H, rows, part);
-    return hipGetLastError();
-}
-
-hipError_t mlp_reduce(const float *part, int32_t slices, int64_t count, float *out, hipStream_t s) {
-    if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(count, 256)), dim3(256), 0, s, part, slices, count, out);
+hipError_t mlp_wcolsum(const __bf16 *m, const float *wt, int32_t K, int32_t n, int32_t H, float *part, int64_t stride,
+                       int32_t su, int32_t sk, float *ones, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (H % 2 || (!wt && K != 1)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + MLP_WCOL_ROWS - 1) / MLP_WCOL_ROWS), (unsigned)((H + 511) / 512));
+    switch (K) {
+    case 1: hipLaunchKernelGGL(wcolsum_kernel<1>, grid, dim3(256), 0, s, m, wt, n, H, part, stride, su, sk, ones);
+        break;
+    case 3: hipLaunchKernelGGL(wcolsum_kernel<3>, grid, dim3(256), 0, s, m, wt, n, H, part, stride, su, sk, ones);
+        break;
+    case 5: hipLaunchKernelGGL(wcolsum_kernel<5>, grid, dim3(256), 0, s, m, wt, n, H, part, stride, su, sk, ones);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -620,7 +665,7 @@ hipError_t mlp_to_bf16(const float *w, __bf16 *wb, int64_t count, hipStream_t s)
 }
 
 hipError_t mlp_loss_sum(const float *part, int32_t count, float inv_count, float *loss, hipStream_t s) {
-    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(64), 0, s, part, count, inv_count, loss);
+    hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, s, part, count, inv_count, loss);
     return hipGetLastError();
 }
 

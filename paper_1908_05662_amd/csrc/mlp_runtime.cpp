@@ -31,6 +31,7 @@ struct pisco_mlp {
     __bf16 *dzT[2] = {nullptr, nullptr};     // their transposes [H][mbp]
     __bf16 *wbT = nullptr;           // transposes of the hidden maps' BF16 weights, [L-1][H][H]
     float *y = nullptr, *xbuf = nullptr, *ybuf = nullptr;
+    float *dy = nullptr;             // output-layer dL/dy [max_batch][3] (fp32)
     float *part_w = nullptr, *part_b = nullptr, *part_loss = nullptr;
     std::vector<float *> part_map;   // split-K partials of each hidden map's weight gradient
     std::vector<float *> part_bias;  // per-block partial column sums of each hidden layer's dL/dz
@@ -40,8 +41,8 @@ struct pisco_mlp {
 
 namespace {
 
-constexpr int ROWS_PER_WAVE = 16;   // output layer
-constexpr int ROWS_PER_BLOCK = 64;  // column sums / input-layer gradient
+constexpr int ROWS_PER_WAVE = 2;    // output layer
+constexpr int ROWS_PER_BLOCK = MLP_WCOL_ROWS;  // weighted column sums (bias, input- and output-layer gradients)
 
 pisco_status mfail(pisco_mlp *m, pisco_status st, const char *msg) {
     if (m && m->ctx) pisco::set_error(m->ctx, msg);
@@ -71,18 +72,25 @@ uint64_t splitmix(uint64_t &s) {
 }
 
 // Split of the batch for a weight gradient of H x H: enough slices that the
-// output tiles times the slices make about 256 workgroups, each slice a
-// multiple of 32 rows.
+// 64 x 64 output tiles times the slices make about 512 workgroups (two per
+// CU), each slice a multiple of 64 rows (the GEMM's k step).
 int32_t slices_for(int32_t H) {
-    const int32_t t = H % 128 == 0 ? 128 : 64;
-    const int32_t tiles = (H / t) * (H / t);
-    return std::max(1, std::min(256, (256 + tiles - 1) / tiles));
+    const int32_t tiles = (H / 64) * (H / 64);
+    return std::max(1, std::min(256, (512 + tiles - 1) / tiles));
+}
+
+// Slice groups the reduction adds in parallel: the largest power of two up to
+// a quarter of the slices (at most 64).
+int32_t groups_for(int32_t slices) {
+    int32_t g = 1;
+    while (g < 64 && 2 * g * 4 <= slices) g *= 2;
+    return g;
 }
 
 int32_t k_slice_for(int32_t n, int32_t H) {
     const int32_t want = slices_for(H);
-    int32_t ks = ((n + want - 1) / want + 31) / 32 * 32;
-    return std::max(32, ks);
+    int32_t ks = ((n + want - 1) / want + 63) / 64 * 64;
+    return std::max(64, ks);
 }
 
 int32_t round_up(int32_t n, int32_t q) { return (n + q - 1) / q * q; }
@@ -112,8 +120,7 @@ pisco_status run(pisco_mlp *m, const float *x, const float *tgt, int32_t n, floa
     const int32_t waves = (n + ROWS_PER_WAVE - 1) / ROWS_PER_WAVE;
     int cur = 0;
     MLP_TRY(m, pisco::mlp_out(m->a[L - 1], m->z[L - 1], m->wb + m->off_w[L], m->w + m->off_b[L], n, H, y, tgt,
-                              1.0f / (float)(n * MLP_OUT), m->dz[cur], m->part_w, m->part_b, m->part_loss, waves,
-                              ROWS_PER_WAVE, s));
+                              1.0f / (float)(n * MLP_OUT), m->dy, m->dz[cur], m->part_loss, waves, ROWS_PER_WAVE, s));
     if (!train) return PISCO_OK;
     MLP_TRY(m, pisco::mlp_loss_sum(m->part_loss, waves, 1.0f / (float)(n * MLP_OUT), loss, s));
     pisco::MlpReduceList R{};
@@ -123,10 +130,14 @@ pisco_status run(pisco_mlp *m, const float *x, const float *tgt, int32_t n, floa
         g.slices = slices;
         g.count = count;
         g.out = out;
+        g.groups = groups_for(slices);
     };
-    seg(m->part_w, waves, (int64_t)MLP_OUT * H, grad + m->off_w[L]);
-    seg(m->part_b, waves, MLP_OUT, grad + m->off_b[L]);
     const int32_t cblocks = (n + ROWS_PER_BLOCK - 1) / ROWS_PER_BLOCK;
+    // output map: dW_out[c][u] = sum_r dY[r][c] A_L[r][u], db_out[c] = sum_r dY[r][c]
+    MLP_TRY(m, pisco::mlp_wcolsum(m->a[L - 1], m->dy, MLP_OUT, n, H, m->part_w,
+                                  (int64_t)MLP_OUT * H, 1, H, m->part_b, s));
+    seg(m->part_w, cblocks, (int64_t)MLP_OUT * H, grad + m->off_w[L]);
+    seg(m->part_b, cblocks, MLP_OUT, grad + m->off_b[L]);
     if (L > 1) MLP_TRY(m, pisco::mlp_transpose(m->dz[cur], H, m->dzT[cur], ldt, np, H, 1, 0, 0, s));
     for (int l = L - 1; l >= 1; --l) {
         // weight gradient of map l: dZ_l^T A_{l-1} over the batch, split into slices
@@ -135,7 +146,8 @@ pisco_status run(pisco_mlp *m, const float *x, const float *tgt, int32_t n, floa
         MLP_TRY(m, pisco::mlp_gemm(pisco::MLP_EPI_BWD_W, m->dzT[cur], ldt, m->aT[l - 1], ldt, H, H, n, ks, nullptr,
                                    nullptr, nullptr, nullptr, 0, nullptr, m->part_map[l], s));
         seg(m->part_map[l], slices, (int64_t)H * H, grad + m->off_w[l]);
-        MLP_TRY(m, pisco::mlp_colsum(m->dz[cur], n, H, ROWS_PER_BLOCK, cblocks, m->part_bias[l], s));
+        MLP_TRY(m, pisco::mlp_wcolsum(m->dz[cur], nullptr, 1, n, H, m->part_bias[l], H, 1, 0,
+                                      nullptr, s));
         seg(m->part_bias[l], cblocks, H, grad + m->off_b[l]);
         // gradient into the previous layer's pre-activation (and its transpose unless it is layer 0)
         const int nxt = cur ^ 1;
@@ -144,9 +156,12 @@ pisco_status run(pisco_mlp *m, const float *x, const float *tgt, int32_t n, floa
                                    m->z[l - 1], nullptr, s));
         cur = nxt;
     }
-    MLP_TRY(m, pisco::mlp_in_grad(m->dz[cur], x, n, H, ROWS_PER_BLOCK, cblocks, m->part_in, s));
+    // input map: dW0[u][k] = sum_r dZ_1[r][u] X[r][k], and the first bias
+    MLP_TRY(m, pisco::mlp_wcolsum(m->dz[cur], x, MLP_IN, n, H, m->part_in, (int64_t)H * MLP_IN,
+                                  MLP_IN, 1, nullptr, s));
     seg(m->part_in, cblocks, (int64_t)H * MLP_IN, grad + m->off_w[0]);
-    MLP_TRY(m, pisco::mlp_colsum(m->dz[cur], n, H, ROWS_PER_BLOCK, cblocks, m->part_bias[0], s));
+    MLP_TRY(m, pisco::mlp_wcolsum(m->dz[cur], nullptr, 1, n, H, m->part_bias[0], H, 1, 0, nullptr,
+                                  s));
     seg(m->part_bias[0], cblocks, H, grad + m->off_b[0]);
     MLP_TRY(m, pisco::mlp_reduce_many(R, s));
     return PISCO_OK;
@@ -230,8 +245,9 @@ pisco_status pisco_mlp_create(pisco_ctx *ctx, int32_t width, int32_t hidden_laye
               alloc(m, &m->wbT, (size_t)std::max(1, hidden_layers - 1) * width * width) &&
               alloc(m, &m->y, (size_t)max_batch * MLP_OUT) && alloc(m, &m->xbuf, (size_t)max_batch * MLP_IN) &&
               alloc(m, &m->ybuf, (size_t)max_batch * MLP_OUT) &&
-              alloc(m, &m->part_w, (size_t)waves * MLP_OUT * width) &&
-              alloc(m, &m->part_b, (size_t)waves * MLP_OUT) && alloc(m, &m->part_loss, waves) &&
+              alloc(m, &m->dy, (size_t)max_batch * MLP_OUT) &&
+              alloc(m, &m->part_w, (size_t)cblocks * MLP_OUT * width) &&
+              alloc(m, &m->part_b, (size_t)cblocks * MLP_OUT) && alloc(m, &m->part_loss, waves) &&
               alloc(m, &m->part_in, (size_t)cblocks * width * MLP_IN);
     m->part_map.assign(hidden_layers, nullptr);
     m->part_bias.assign(hidden_layers, nullptr);

@@ -36,23 +36,45 @@ __device__ inline uint32_t hilbert_rank(uint32_t x, uint32_t y) {
     return d;
 }
 
-__global__ void order_keys_kernel(const double *__restrict__ th, const double *__restrict__ ph, int64_t n,
-                                  uint32_t *__restrict__ keys, int32_t *__restrict__ idx) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Hilbert rank of the (phi, z) cell of one direction.
+__device__ inline uint32_t cell_key(double th, double ph) {
     const double two_pi = 6.283185307179586477;
-    double u = fmod(ph[i], two_pi) / two_pi;
+    double u = fmod(ph, two_pi) / two_pi;
     if (u < 0.0) u += 1.0;
-    const double v = 0.5 * (cos(th[i]) + 1.0);
+    const double v = 0.5 * (cos(th) + 1.0);
     const double fx = floor(u * GRID), fy = floor(v * GRID);
     // non-finite pointing sorts anywhere (the convolution reports it)
     const uint32_t x = (fx >= 0.0 && fx < GRID) ? (uint32_t)fx : (fx >= GRID ? GRID - 1 : 0);
     const uint32_t y = (fy >= 0.0 && fy < GRID) ? (uint32_t)fy : (fy >= GRID ? GRID - 1 : 0);
-    keys[i] = hilbert_rank(x, y);
+    return hilbert_rank(x, y);
+}
+
+__global__ void order_keys_kernel(const double *__restrict__ th, const double *__restrict__ ph, int64_t n,
+                                  uint32_t *__restrict__ keys, int32_t *__restrict__ idx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = cell_key(th[i], ph[i]);
     idx[i] = (int32_t)i;
 }
 
+// Key of each tile: the cell of its first sample (in processing order).
+__global__ void tile_keys_kernel(const DetDesc *__restrict__ dets, const Tile *__restrict__ tiles, int32_t n,
+                                 uint32_t *__restrict__ keys) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    const Tile t = tiles[i];
+    const DetDesc &D = dets[t.det];
+    const int64_t s = D.order ? (int64_t)D.order[t.begin] : t.begin;
+    keys[i] = cell_key(D.theta[s], D.phi[s]);
+}
+
 }  // namespace
+
+hipError_t launch_tile_keys(const DetDesc *dets, const Tile *tiles, int32_t n, uint32_t *keys, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tile_keys_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dets, tiles, n, keys);
+    return hipGetLastError();
+}
 
 hipError_t spatial_order(const double *theta, const double *phi, int64_t n, int32_t *order, hipStream_t s) {
     if (n <= 0) return hipSuccess;

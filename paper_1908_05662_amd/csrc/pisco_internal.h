@@ -83,6 +83,8 @@ hipError_t launch_healpix_grid(const HpxGridArgs &a, bool f64, hipStream_t s);
 // Spatial processing order (order_kernel.hip): order[t] = the sample at position t when the n samples
 // are sorted along a Hilbert curve over (phi, cos theta); synchronises on `s`.
 hipError_t spatial_order(const double *theta, const double *phi, int64_t n, int32_t *order, hipStream_t s);
+// keys[i] = Hilbert rank (as in spatial_order) of the first sample of tiles[i].
+hipError_t launch_tile_keys(const DetDesc *dets, const Tile *tiles, int32_t n, uint32_t *keys, hipStream_t s);
 hipError_t launch_classify(const DetDesc *dets, const Tile *groups, int32_t n_groups, double frac, int32_t *flag,
                            hipStream_t s);
 hipError_t launch_check_pointing(const double *theta, const double *phi, const double *psi, int64_t n,

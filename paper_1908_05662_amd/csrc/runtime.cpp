@@ -135,7 +135,7 @@ struct pisco_ctx {
     uint64_t generation = 1;  // bumped whenever anything a launch reads changes
 
     // launch shape
-    int32_t spt = 64, wpg = 4, gpc = 4, xq = 1;
+    int32_t spt = 64, wpg = 4, gpc = 4, xq = 8;
     int32_t algo = PISCO_ALGO_TILE, chunk = 64;
     double coherence = 0.5;
     int32_t ordering = PISCO_ORDER_AUTO;   // processing order of the samples
@@ -514,6 +514,25 @@ pisco_status build_plan(pisco_ctx *c, Plan &p, std::vector<DetDesc> &descs, cons
         } else {
             ptiles.push_back(x);
         }
+    }
+    // each detector's coherent tiles in the Hilbert order of their first samples:
+    // tiles that run at the same time then share more of their union caps in
+    // L2 (the order of tiles does not change any output)
+    if (ttiles.size() > 1) {
+        Tile *dg = reinterpret_cast<Tile *>(p.d_scratch);
+        uint32_t *dk = reinterpret_cast<uint32_t *>(dg + ttiles.size());
+        std::vector<uint32_t> key(ttiles.size());
+        HIP_TRY(c, hipMemcpy(dg, ttiles.data(), ttiles.size() * sizeof(Tile), hipMemcpyHostToDevice));
+        HIP_TRY(c, pisco::launch_tile_keys(p.d_dets, dg, (int32_t)ttiles.size(), dk, nullptr));
+        HIP_TRY(c, hipMemcpy(key.data(), dk, key.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        std::vector<size_t> idx(ttiles.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) {
+            return ttiles[a].det != ttiles[b].det ? ttiles[a].det < ttiles[b].det : key[a] < key[b];
+        });
+        std::vector<Tile> sorted(ttiles.size());
+        for (size_t i = 0; i < idx.size(); ++i) sorted[i] = ttiles[idx[i]];
+        ttiles.swap(sorted);
     }
     const int nq = std::max<int32_t>(1, std::min<int32_t>(c->xq, 8));
     int32_t lens[32] = {0};
