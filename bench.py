@@ -335,6 +335,51 @@ def full_beam_leg(conv, w, stream, out, steps, warmup, torch, pairs):
             "parity_max_rel_err": max(errs), "parity_samples": 5 * len(errs)}
 
 
+def network_leg(torch):
+    """Training-step and fused-inference rates of the sidelobe network for both
+    sizes the bench uses (4 x 256 on the nside-256 workload, 10 x 512 at full
+    scale): one Adam step on a batch of 8192 (forward, loss, backward, fixed-order
+    gradient sums, Adam; three times the forward flops), and the fused TOD
+    epilogue over 1e6 pointings (features, every layer, the TOD sum), HIP
+    events.  Against the dense BF16 matrix-core peak."""
+    from paper_1908_05662_amd import surrogate as SG
+    from paper_1908_05662_amd.api import Convolver, Mlp
+    from synth import workloads as W
+
+    conv = Convolver(0)
+    w = W.c4(1_000_000, stream=2)
+    d = w.detectors[0]
+    T, g = W.sidelobe_beam(401, 20.0, 1.0)
+    conv.set_sky(w.nside, *(torch.from_numpy(m.astype(np.float32)).cuda() for m in w.sky), dtype=torch.float32)
+    conv.set_beam_scalar(0, 401, T, torch.from_numpy(g.astype(np.float32)).cuda(), 0.5, 0.5, 0.0, 1.0,
+                         dtype=torch.float32)
+    conv.set_detector(0, 0.0, 0.0, np.deg2rad(5.0), W.NORM_FIXED, d.norm_scale)
+    conv.set_pointing(0, *(torch.from_numpy(v).cuda() for v in (d.theta, d.phi, d.psi)))
+    res = {}
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    for (H, L) in ((256, 4), (512, 10)):
+        batch = 8192
+        m = Mlp(conv, H, L, max_batch=batch, seed=1)
+        x = torch.randn(batch, 5, device="cuda", generator=gen)
+        t = torch.randn(batch, 3, device="cuda", generator=gen)
+        t_step = SG.time_call(lambda: m.train_step(x, t, lr=1e-4), reps=50)
+        m.close()
+        fwd = SG.network_flops_per_sample(H, L)
+        inf = SG.network_rate(conv, 0, H, L)
+        res[f"{L}x{H}"] = {
+            "train_step_ms": t_step * 1e3, "train_batch": batch,
+            "train_tflops": 3 * fwd * batch / t_step / 1e12,
+            "train_frac": 3 * fwd * batch / t_step / 1e12 / SG.BF16_PEAK_TFLOPS,
+            "infer_ms_per_1e6": inf["ms"] * 1e6 / d.n, "infer_tflops": inf["achieved_tflops"],
+            "infer_frac": inf["frac"], "flops_per_sample": fwd}
+        log(f"network {L}x{H}: train step {t_step * 1e3:.3f} ms ({res[f'{L}x{H}']['train_tflops']:.1f} TFLOP/s), "
+            f"inference {inf['ms']:.3f} ms per {d.n} ({inf['achieved_tflops']:.1f} TFLOP/s, frac {inf['frac']:.3f})")
+    conv.close()
+    res["peak_tflops"] = SG.BF16_PEAK_TFLOPS
+    res["note"] = "training counts 3x the forward flops per sample; inference is the fused TOD epilogue"
+    return res
+
+
 def surrogate_leg(epochs):
     """Exact main beam + the library-trained far-sidelobe network against the
     exact 20 deg disc on the nside-256 far-sidelobe workload: the library draws
@@ -863,6 +908,7 @@ def main():
     ap.add_argument("--no-paper-shape", action="store_true", help="skip the paper's benchmark-pattern leg")
     ap.add_argument("--no-plate", action="store_true", help="skip the half-wave-plate leg")
     ap.add_argument("--no-full-beam", action="store_true", help="skip the four-channel-beam leg")
+    ap.add_argument("--no-network", action="store_true", help="skip the sidelobe-network rate leg")
     ap.add_argument("--no-maps", action="store_true", help="skip the map-making leg (and the spectra leg)")
     ap.add_argument("--no-spectra", action="store_true", help="skip the power-spectrum leg")
     ap.add_argument("--no-ideal-cmb", action="store_true", help="skip the paper's whole-sky ideal CMB run")
@@ -1041,6 +1087,9 @@ def main():
         parity.update(parity_leg())
     if not args.no_surrogate:
         rec["surrogate"] = surrogate_leg(args.surrogate_epochs)
+    if not args.no_network:
+        torch.cuda.empty_cache()
+        rec["network"] = network_leg(torch)
     if not args.no_paper_shape:
         torch.cuda.empty_cache()
         rec["paper_shape"] = paper_shape_leg()

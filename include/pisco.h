@@ -271,7 +271,7 @@ int64_t pisco_output_samples(const pisco_ctx *ctx, int32_t det);
  *                    that tiles running together on a die share sky in L2.
  *   chunk            tile paths: union pixels staged in LDS per pass (64, 128, 256)
  *   coherence        tile paths: see algorithm, in (0, 4]
- * A new context starts at {PISCO_ALGO_TILE, 64, 4, 4, 8, 64, 0.5}.
+ * A new context starts at {PISCO_ALGO_TILE, 64, 4, 4, 1, 64, 0.5}.
  * Results are bitwise reproducible for a given launch shape.  They do not
  * depend on the shape except through the algorithm (the two paths round
  * differently) and, on the tile path, through samples_per_tile when it is not

@@ -160,9 +160,30 @@ def tune(conv, det: int = -1, subsample: float = 0.25, reps: int = 3, cache: str
             if best_ms > pass_start * (1.0 - min_gain):
                 break
 
+    # The queue split is settled on the whole streams, where the per-die
+    # queues cost less than on a prefix (on the nside-1024 benchmark 6% slower
+    # on a 25% prefix, under 1% in full; on small or gather-bound streams they
+    # stay much slower).  Within `accept` of the shared queue they are taken,
+    # as they read a fraction of the bytes from memory.
+    queues = None
+    if best["algorithm"] != L.ALGO_PIXEL and subsample < 1.0:
+        n_full = conv.output_samples(det)
+        out_full = torch.empty(n_full, dtype=conv.dtype, device=conv.torch_device)
+        per_die = dict(best, xcd_queues=8)
+        shared = dict(best, xcd_queues=1)
+        ms8 = _time_shape(conv, det, per_die, out_full, stream, reps)
+        ms1 = _time_shape(conv, det, shared, out_full, stream, reps)
+        trials.append({"launch": per_die, "ms": ms8, "full": True})
+        trials.append({"launch": shared, "ms": ms1, "full": True})
+        say(f"autotune: whole streams, eight queues {ms8} ms, one queue {ms1} ms")
+        if ms8 is not None and ms1 is not None:
+            best = shared if ms1 < ms8 * (1.0 - accept) else per_die
+            queues = {"eight_ms": ms8, "one_ms": ms1}
+        del out_full
+
     conv.set_launch(**best)
     rec = {"launch": best, "ms": best_ms, "default_ms": default_ms, "speedup": default_ms / best_ms,
-           "trials": trials, "subsample": subsample, "pairs_per_sample": pps}
+           "trials": trials, "subsample": subsample, "pairs_per_sample": pps, "queues_full": queues}
     if cache:
         table[key] = rec
         tmp = cache + ".tmp"

@@ -1058,7 +1058,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     // the end return zero
     const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n + 1) * (n + 1) : n * n);
     const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
-    const int32_t row_bytes = (int32_t)(16 * n);
+    const int32_t row_bytes = __builtin_amdgcn_readfirstlane(16 * n);   // buffer-load soffset: must stay in an SGPR
     // full beams with a V column: bV cell polynomials, and the V of each staged pixel
     const bool has_v = (BEAM == BEAM_FULL) && (MODE == MODE_TOD) && D.beam_v != nullptr && vrec != nullptr;
     const BeamRsrc vbeam = make_beam_rsrc(has_v ? D.beam_v : D.beam, (uint32_t)((n - 1) * (n - 1)));
@@ -1280,7 +1280,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
     const float kbase = BEAM == BEAM_SCALAR ? row + 1.0f : 0.0f;   // cell (0, 0) past the extrapolated ring
     const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n + 1) * (n + 1) : n * n);
     const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
-    const int32_t row_bytes = (int32_t)(16 * n);
+    const int32_t row_bytes = __builtin_amdgcn_readfirstlane(16 * n);   // buffer-load soffset: must stay in an SGPR
     const int k4 = lane >> 4, c16 = lane & 15;
 
     const int32_t r_lo = __builtin_amdgcn_readfirstlane(T.r_lo), r_hi = __builtin_amdgcn_readfirstlane(T.r_hi);

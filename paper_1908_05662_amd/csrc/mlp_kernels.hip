@@ -432,6 +432,63 @@ __device__ inline void features_of(const double *th, const double *ph, const dou
     f[4] = (float)cp;
 }
 
+// One 64-unit group of an H x H layer for the IR rows in LDS, as Z^T = W A^T:
+// the weights are the MFMA's first operand (lane l: unit u0 + 16 i + l % 16,
+// k0 + 8 (l / 16) .. + 7, from L2), the activations its second (row 16 j +
+// l % 16, the same k, from LDS), so each output element is the training
+// GEMM's product chain over k0 = 0, 32, ... with the operands exchanged.  The
+// weight fragments of D k steps are in flight (a ring of D register slots,
+// refilled as each is used).  A lane's results are four consecutive units of
+// one row: bias, SiLU, and one 8-byte LDS store.
+template <int D>
+__device__ inline void hxh_layer_group(const __bf16 *__restrict__ W, const float *__restrict__ bias,
+                                       const __bf16 *cur, __bf16 *nxt, int H, int LD, int u0, int lane) {
+    const int r16 = lane & 15, kq = (lane >> 4) * 8;
+    f32x4 acc[4][4];   // [unit tile i][row tile j]
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const __bf16 *wrow = W + (int64_t)(u0 + r16) * H + kq;
+    bf16x8 wf[D][4];
+#pragma unroll
+    for (int sl = 0; sl < D; ++sl)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wf[sl][i] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * i * H + 32 * sl);
+    for (int k0 = 0; k0 < H; k0 += D * 32) {
+#pragma unroll
+        for (int sl = 0; sl < D; ++sl) {
+            const int kc = k0 + 32 * sl;
+            bf16x8 af[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) af[j] = *reinterpret_cast<const bf16x8 *>(cur + (16 * j + r16) * LD + kc + kq);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[sl][i], af[j], acc[i][j], 0, 0, 0);
+            const int kn = kc + D * 32;
+            if (kn < H) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) wf[sl][i] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * i * H + kn);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int ub = u0 + 16 * i + 4 * (lane >> 4);   // this lane's four units
+        const float4 bq = *reinterpret_cast<const float4 *>(bias + ub);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int row = 16 * j + r16;
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            const bf16x4 o = bf16x4{(__bf16)silu(acc[i][j][0] + bq.x), (__bf16)silu(acc[i][j][1] + bq.y),
+                                    (__bf16)silu(acc[i][j][2] + bq.z), (__bf16)silu(acc[i][j][3] + bq.w)};
+            *reinterpret_cast<bf16x4 *>(nxt + row * LD + ub) = o;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(256) infer_kernel(MlpInferArgs g) {
     extern __shared__ __align__(16) unsigned char lds[];
     const int H = g.H, LD = H + 8;
@@ -464,53 +521,16 @@ __global__ void __launch_bounds__(256) infer_kernel(MlpInferArgs g) {
     }
     __syncthreads();
 
-    // H x H layers: wave w computes column groups w, w + 4, ... of 64 units for
-    // all IR rows (4 x 4 MFMA tiles); B fragments of the next K step are
-    // fetched while the current step's MFMAs run
+    // H x H layers as Z^T = W A^T (hxh_layer_group): weights first operand
+    // from L2, activations second from LDS; D k steps of weight fragments in
+    // flight (four when H is a multiple of 128, else two).
     __bf16 *cur = buf0, *nxt = buf1;
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;
     for (int l = 1; l < g.L; ++l) {
         const __bf16 *__restrict__ W = g.wb + g.off_w[l];
         const float *__restrict__ bias = g.w + g.off_b[l];
         for (int cg = wave; cg < H / 64; cg += 4) {
-            const int n0 = cg * 64;
-            f32x4 acc[4][4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            bf16x8 bfr[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bfr[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(n0 + 16 * j + r16) * H + kq);
-            for (int k0 = 0; k0 < H; k0 += 32) {
-                bf16x8 bnx[4];
-                const int k1 = (k0 + 32 < H) ? k0 + 32 : k0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    bnx[j] = *reinterpret_cast<const bf16x8 *>(W + (int64_t)(n0 + 16 * j + r16) * H + k1 + kq);
-                bf16x8 af[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const bf16x8 *>(cur + (16 * i + r16) * LD + k0 + kq);
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bfr[j] = bnx[j];
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int col = n0 + 16 * j + r16;
-                const float bc = bias[col];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int row = 16 * i + 4 * (lane >> 4) + q;
-                        nxt[row * LD + col] = (__bf16)silu(acc[i][j][q] + bc);
-                    }
-            }
+            if (H % 128 == 0) hxh_layer_group<4>(W, bias, cur, nxt, H, LD, cg * 64, lane);
+            else hxh_layer_group<2>(W, bias, cur, nxt, H, LD, cg * 64, lane);
         }
         __syncthreads();
         __bf16 *t = cur;

@@ -135,7 +135,7 @@ struct pisco_ctx {
     uint64_t generation = 1;  // bumped whenever anything a launch reads changes
 
     // launch shape
-    int32_t spt = 64, wpg = 4, gpc = 4, xq = 8;
+    int32_t spt = 64, wpg = 4, gpc = 4, xq = 1;
     int32_t algo = PISCO_ALGO_TILE, chunk = 64;
     double coherence = 0.5;
     int32_t ordering = PISCO_ORDER_AUTO;   // processing order of the samples
