@@ -29,23 +29,25 @@ sys.path.insert(0, ROOT)
 #  membership 1 - n.p 6; n.theta'_0 and n.phi'_0 12; 1/z' and 1/(1+z') as
 #  second-order series in omega 7 (third order: 11; one reciprocal of
 #  z'(1+z') and the two products: 6); grid coordinates 4; cell fractions 2;
-#  g.n 6 and q 1; carried co-polar vector 6; its projections on the pixel's
-#  theta/phi 10; cos 2chi and sin 2chi 4; one-grid bilinear cell polynomial 6;
-#  contraction with the staged sky terms 5 and the per-step sum 1; the sum of
-#  eight terms added in FP64 0.25 per sum -> 70.25, plus the normaliser of a
-#  per-sample-normalised launch (its masked add 1 + 0.25) -> 71.5.
+#  q = (n.theta'_0) / (1 + z') 1; theta'_0 carried to the pixel 6; its
+#  projections on the pixel's theta/phi 10; one-grid bilinear cell polynomial 6;
+#  one-grid TOD: the angle terms in their cos^2 form contracted with the staged
+#  sky terms 5, times the beam value 1, the per-step sum 1; the sum of eight
+#  terms added in FP64 0.25 per sum -> 61.25, plus the normaliser of a
+#  per-sample-normalised launch (its masked add 1 + 0.25) -> 62.5.
 #  Four-channel beams: floors and fractions 4 instead of 2, four bilinear
-#  channels 36 instead of 6, the contraction with the Stokes rotation 12
-#  instead of 5 -> 110.5 with the normaliser.
+#  channels 36 instead of 6, cos 2gamma and sin 2gamma 4 and the contraction with
+#  the Stokes rotation 12 instead of the 7 of the cos^2 form -> 104.5 with the
+#  normaliser.
 #  Matrix-core variant (algorithm 2): eight 16x16x4 FP32 MFMAs per 16 pixels x
 #  16 samples give the pixel-linear quantities (64 matrix flops per pair);
 #  vector ALU 44 (one-grid) / 81 (four-channel).
 #  Pixel path (FP32 incoherent groups), four-channel beam: 155; one-grid: 125.
-FLOPS_PER_PAIR = {(1, "scalar", 2, True): (71.5, 0), (1, "scalar", 2, False): (70.25, 0),
-                  (1, "scalar", 1, True): (75.5, 0), (1, "scalar", 1, False): (74.25, 0),
-                  (1, "scalar", 0, True): (70.5, 0), (1, "scalar", 0, False): (69.25, 0),
-                  (1, "full", 2, True): (110.5, 0), (1, "full", 2, False): (109.25, 0),
-                  (1, "full", 1, True): (114.5, 0), (1, "full", 0, True): (109.5, 0),
+FLOPS_PER_PAIR = {(1, "scalar", 2, True): (62.5, 0), (1, "scalar", 2, False): (61.25, 0),
+                  (1, "scalar", 1, True): (66.5, 0), (1, "scalar", 1, False): (65.25, 0),
+                  (1, "scalar", 0, True): (61.5, 0), (1, "scalar", 0, False): (60.25, 0),
+                  (1, "full", 2, True): (104.5, 0), (1, "full", 2, False): (103.25, 0),
+                  (1, "full", 1, True): (108.5, 0), (1, "full", 0, True): (103.5, 0),
                   (2, "scalar"): (44, 64), (2, "full"): (81, 64), (0, "scalar"): (125, 0), (0, "full"): (155, 0)}
 
 

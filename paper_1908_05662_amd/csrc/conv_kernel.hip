@@ -548,8 +548,8 @@ struct LaneFrame {
     float om, p1, p2, p3;   // 1 - p.c and p
     float a1, a2, a3;       // theta'_0
     float b1, b2, b3;       // phi'_0
-    float g1, g2, g3;       // co-polar direction at the boresight
-    float c4, s4;           // cos, sin of 4 phi_t (half-wave plate; 1, 0 without one)
+    float g1, g2, g3;       // co-polar direction at the boresight (matrix-core variant)
+    float c2p, s2p;         // cos, sin of 2 phi_t (half-wave plate; 1, 0 without one)
 };
 
 // The set-up helpers below are not inlined (their FP64 constants must not be
@@ -638,13 +638,13 @@ __device__ __attribute__((noinline)) TileFrame tile_setup(const DetDesc &D, int3
     F.g1 = (float)(tg[0] * e1[0] + tg[1] * e1[1] + tg[2] * e1[2]);
     F.g2 = (float)(tg[0] * e2[0] + tg[1] * e2[1]);
     F.g3 = (float)(tg[0] * c[0] + tg[1] * c[1] + tg[2] * c[2]);
-    F.c4 = 1.0f;
-    F.s4 = 0.0f;
+    F.c2p = 1.0f;
+    F.s2p = 0.0f;
     if (D.hwp) {
-        double sh4, ch4;
-        sincos(4.0 * D.hwp[t], &sh4, &ch4);
-        F.c4 = (float)ch4;
-        F.s4 = (float)sh4;
+        double sh2, ch2;
+        sincos(2.0 * D.hwp[t], &sh2, &ch2);
+        F.c2p = (float)ch2;
+        F.s2p = (float)sh2;
     }
     *out = F;
     double dist = valid ? 2.0 * asin(fmin(1.0, 0.5 * sqrt(2.0 * om))) : 0.0;  // angle from the centre
@@ -910,22 +910,27 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
     PairOut o{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        // co-polar vector carried from the boresight to the pixel along the great
-        // circle, e = g - q (p + n) with q = g.n / (1 + n.p); the pixel's
-        // theta_hat and phi_hat are normal to n, so their projections take g - q p
-        const float gn = fmaf(-R[k].W, F.g3, fmaf(F.g2, R[k].Y, fmaf(F.g1, R[k].X, F.g3)));
-        const float q = gn * rq[k];
-        const float ex = fmaf(-q, F.p1, F.g1);
-        const float ey = fmaf(-q, F.p2, F.g2);
-        const float ez = fmaf(-q, F.p3, F.g3);
-        const float cc = fmaf(ex, R[k].t1, fmaf(ey, R[k].t2, ez * R[k].t3));
-        const float ss = fmaf(ex, R[k].f1, fmaf(ey, R[k].f2, ez * R[k].f3));
-        float c2 = fmaf(cc, cc, -ss * ss);   // cos 2chi, then cos(2chi + 4phi) with a plate
-        float sh = cc * ss;                  // sin 2chi / 2, then sin(2chi + 4phi) / 2
+        // position angle.  The co-polar direction at the boresight is
+        // cos(zeta) theta'_0 + sin(zeta) phi'_0, and carrying vectors along the
+        // great circle is linear and keeps angles, so chi = gamma + zeta with
+        // gamma the angle of theta'_0 carried to the pixel; the turn by 2 zeta
+        // is in the staged Q, U coefficients.  theta'_0 carried from the
+        // boresight to the pixel is e = a - q (p + n), q = a.n / (1 + n.p), and
+        // the pixel's theta_hat and phi_hat are normal to n, so their
+        // projections take a - q p.  a.n is xp, in grid units like the lane's
+        // a rows, so e, its projections and the angle terms below carry the
+        // grid scale (1/h, 1/h^2); the records carry h^2.
+        const float q = xp[k] * rq[k];
+        const float ex = fmaf(-q, F.p1, F.a1);
+        const float ey = fmaf(-q, F.p2, F.a2);
+        const float ez = fmaf(-q, F.p3, F.a3);
+        float cc = fmaf(ex, R[k].t1, fmaf(ey, R[k].t2, ez * R[k].t3));   // cos gamma / h
+        float ss = fmaf(ex, R[k].f1, fmaf(ey, R[k].f2, ez * R[k].f3));   // sin gamma / h
         if (HWP) {
-            const float c2p = c2;
-            c2 = fmaf(-2.0f * F.s4, sh, F.c4 * c2p);
-            sh = fmaf(F.c4, sh, 0.5f * F.s4 * c2p);
+            // the plate advances 2 chi by 4 phi_t: gamma turned by 2 phi_t
+            const float c0 = cc;
+            cc = fmaf(F.c2p, c0, -F.s2p * ss);
+            ss = fmaf(F.s2p, c0, F.c2p * ss);
         }
         const float sgn = HWP ? C.sg4 : 1.0f;
         float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
@@ -940,17 +945,20 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
             bT = lerp(lerp(q00.w, q10.w, fu[k]), lerp(q01.w, q11.w, fu[k]), fv[k]);
         }
         if (PS) o.vn += in[k] ? bT : 0.0f;
+        if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
+            // a + cos 2gamma B + sin 2gamma C = (a - B) + 2 cos gamma (cos gamma B
+            // + sin gamma C), as cc^2 + ss^2 = 1/h^2: the records hold a - B,
+            // 2 h^2 B and 2 h^2 C (the plate's signs included); the mask goes on
+            // the beam value (every factor is finite)
+            const float bTm = in[k] ? bT : 0.0f;
+            o.v0 += bTm * fmaf(cc, fmaf(R[k].b, cc, R[k].c * ss), R[k].a);
+            continue;
+        }
+        const float c2 = fmaf(cc, cc, -ss * ss);   // cos(2gamma (+ 4phi)) / h^2
+        const float sh = cc * ss;                  // sin(2gamma (+ 4phi)) / (2 h^2)
         if (MODE == MODE_TOD) {
             float term;
-            if (BEAM == BEAM_SCALAR) {
-                // R.c holds twice the U-like coefficient (sin / 2 = sh); the
-                // plate's signs are in the records; the mask goes on the beam
-                // value (every factor is finite)
-                const float bTm = in[k] ? bT : 0.0f;
-                term = bTm * fmaf(c2, R[k].b, fmaf(sh, R[k].c, R[k].a));
-                o.v0 += term;
-                continue;
-            } else {
+            {
                 const float s2 = 2.0f * sh;
                 const float sbU = sgn * bU;
                 const float bq = fmaf(bQ, R[k].b, sbU * R[k].c);
@@ -1065,6 +1073,8 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     // half-wave plate: U-row and V terms change sign (records of one-grid beams carry it)
     const float sg4 = D.hwp ? -1.0f : 1.0f;
     const float wV = (float)D.wv;
+    const float rz0 = (float)D.rot2z[0], rz1 = (float)D.rot2z[1];   // (cos 2 zeta, sin 2 zeta) h^2
+    const float ih2 = (float)(D.inv_h * D.inv_h);
 
     AccWide acc0, acc1, acc2, accn;
     int32_t npairs = 0;
@@ -1119,15 +1129,21 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                 R.f2 = 1.0f - h;
                 R.f3 = -scf * S;
                 const float4 sv = sky[u.first + j];
+                // Q, U coefficients turned by 2 zeta and scaled by h^2 (the pair
+                // loop's angle terms are those of 2 gamma = 2 chi - 2 zeta, x 1/h^2)
                 if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
+                    // B = wQ Q + wU U, C = wQ U - wU Q turned by 2 zeta (x h^2); the
+                    // pair loop takes a - B, 2 B and 2 C (its cos^2 gamma form)
                     const float swU = sg4 * wU;
-                    R.a = fmaf(sg4 * wV, sv.w, wI * sv.x);
-                    R.b = fmaf(wQ, sv.y, swU * sv.z);
-                    R.c = 2.0f * fmaf(wQ, sv.z, -swU * sv.y);
+                    const float cq = fmaf(wQ, sv.y, swU * sv.z), cu = fmaf(wQ, sv.z, -swU * sv.y);
+                    const float bh = fmaf(rz1, cu, rz0 * cq);
+                    R.a = fmaf(-bh, ih2, fmaf(sg4 * wV, sv.w, wI * sv.x));
+                    R.b = 2.0f * bh;
+                    R.c = 2.0f * fmaf(rz0, cu, -rz1 * cq);
                 } else {
                     R.a = sv.x;
-                    R.b = sv.y;
-                    R.c = sv.z;
+                    R.b = fmaf(rz1, sv.z, rz0 * sv.y);
+                    R.c = fmaf(rz0, sv.z, -rz1 * sv.y);
                 }
                 L.rec[m] = R;
                 if (has_v) vrec[m] = sv.w;

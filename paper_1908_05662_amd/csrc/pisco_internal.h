@@ -33,6 +33,7 @@ struct DetDesc {
     const double *hwp;     // per-sample half-wave-plate angle, or null (no plate)
     const int32_t *order;  // processing order: position t holds the caller's sample order[t]; null = given order
     double wv;             // scalar beam V weight
+    double rot2z[2];       // (cos 2 zeta, sin 2 zeta) / inv_h^2: the tile path's turn of the staged Q, U
     int32_t n;             // grid nodes per side
     int32_t norm_mode;     // 0 fixed, 1 per sample
     int32_t has_inner;     // rho_min > 0

@@ -379,6 +379,8 @@ DetDesc make_desc(const DetState &d, bool sub) {
     x.norm_scale = d.norm_scale;
     x.half_span_tan = d.T;
     x.inv_h = (double)(d.n - 1) / (2.0 * d.T);
+    x.rot2z[0] = std::cos(2.0 * d.zeta) / (x.inv_h * x.inv_h);
+    x.rot2z[1] = std::sin(2.0 * d.zeta) / (x.inv_h * x.inv_h);
     x.omega_max = 2.0 * std::sin(0.5 * rho_max) * std::sin(0.5 * rho_max);
     x.omega_min = 2.0 * std::sin(0.5 * d.rho_min) * std::sin(0.5 * d.rho_min);
     for (int i = 0; i < 4; ++i) x.w[i] = d.w[i];
