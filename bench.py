@@ -29,23 +29,26 @@ sys.path.insert(0, ROOT)
 #  membership 1 - n.p 6; n.theta'_0 and n.phi'_0 12; 1/z' and 1/(1+z') as
 #  second-order series in omega 7 (third order: 11; one reciprocal of
 #  z'(1+z') and the two products: 6); grid coordinates 4; cell fractions 2;
-#  q = (n.theta'_0) / (1 + z') 1; theta'_0 carried to the pixel 6; its
-#  projections on the pixel's theta/phi 10; one-grid bilinear cell polynomial 6;
-#  one-grid TOD: the angle terms in their cos^2 form contracted with the staged
-#  sky terms 5, times the beam value 1, the per-step sum 1; the sum of eight
-#  terms added in FP64 0.25 per sum -> 61.25, plus the normaliser of a
-#  per-sample-normalised launch (its masked add 1 + 0.25) -> 62.5.
-#  Four-channel beams: floors and fractions 4 instead of 2, four bilinear
-#  channels 36 instead of 6, cos 2gamma and sin 2gamma 4 and the contraction with
-#  the Stokes rotation 12 instead of the 7 of the cos^2 form -> 104.5 with the
-#  normaliser.
+#  q = (n.theta'_0) / (1 + z') 1; one-grid bilinear cell polynomial 6; times
+#  the beam value 1 and the per-step sum 1; the sum of eight terms added in
+#  FP64 0.25 per sum; the normaliser of a per-sample-normalised launch (its
+#  masked add 1 + 0.25).  The position-angle part:
+#  one-grid TOD without a plate (the quadratic-form records): the first two
+#  tile-frame components of theta'_0 carried to the pixel 6, the quadratic form
+#  8 -> 54.25, 55.5 with the normaliser;
+#  otherwise theta'_0 carried to the pixel 6, its projections on the pixel's
+#  theta/phi 10, and for one-grid TOD with a plate the turn by 2 phi_t 6 and the
+#  cos^2 form 5 (-> 68.5 with the normaliser); four-channel beams: floors and
+#  fractions 4 instead of 2, four bilinear channels 36 instead of 6, cos 2gamma
+#  and sin 2gamma 4 and the contraction with the Stokes rotation 12 -> 104.5
+#  with the normaliser.
 #  Matrix-core variant (algorithm 2): eight 16x16x4 FP32 MFMAs per 16 pixels x
 #  16 samples give the pixel-linear quantities (64 matrix flops per pair);
 #  vector ALU 44 (one-grid) / 81 (four-channel).
 #  Pixel path (FP32 incoherent groups), four-channel beam: 155; one-grid: 125.
-FLOPS_PER_PAIR = {(1, "scalar", 2, True): (62.5, 0), (1, "scalar", 2, False): (61.25, 0),
-                  (1, "scalar", 1, True): (66.5, 0), (1, "scalar", 1, False): (65.25, 0),
-                  (1, "scalar", 0, True): (61.5, 0), (1, "scalar", 0, False): (60.25, 0),
+FLOPS_PER_PAIR = {(1, "scalar", 2, True): (55.5, 0), (1, "scalar", 2, False): (54.25, 0),
+                  (1, "scalar", 1, True): (59.5, 0), (1, "scalar", 1, False): (58.25, 0),
+                  (1, "scalar", 0, True): (54.5, 0), (1, "scalar", 0, False): (53.25, 0),
                   (1, "full", 2, True): (104.5, 0), (1, "full", 2, False): (103.25, 0),
                   (1, "full", 1, True): (108.5, 0), (1, "full", 0, True): (103.5, 0),
                   (2, "scalar"): (44, 64), (2, "full"): (81, 64), (0, "scalar"): (125, 0), (0, "full"): (155, 0)}

@@ -534,6 +534,19 @@ struct PixRec {
     float a, b, c;      // scalar beam, TOD: wI I, wQ Q + wU U, wQ U - wU Q; otherwise I, Q, U
 };
 
+// Pixel record of the one-grid TOD loop without a plate (the quadratic-form
+// path): n as above, and the pixel's angle terms as a quadratic form in the
+// first two tile-frame components of the carried theta'_0 (see tile_pairs).
+struct PixRecQ {
+    float X, Y, W;
+    float A;              // wI I + wV V - B, B the turned Q, U term
+    float P11, P12, P22;  // e^T P e = 2 cos gamma (B cos gamma + C sin gamma) / h^2 ... x h^2
+    float pad;
+};
+
+template <bool B, class T, class F> struct Cond { using type = T; };
+template <class T, class F> struct Cond<false, T, F> { using type = F; };
+
 // One ring of the union cap, with the ring's coefficients relative to the
 // tile centre (the same difference formulas as the pixel path, with the
 // centre in place of the boresight).
@@ -566,7 +579,7 @@ struct TileLds {
         PixRec rec[CH];
     };
 };
-static_assert(sizeof(UnionRing) == 64 && sizeof(LaneFrame) == 60 && sizeof(PixRec) == 48 &&
+static_assert(sizeof(UnionRing) == 64 && sizeof(LaneFrame) == 60 && sizeof(PixRec) == 48 && sizeof(PixRecQ) == 32 &&
                   sizeof(TileLds<64>) == 4352 + 3840 && sizeof(TileLds<128>) == 4352 + 128 * 48 &&
                   sizeof(TileLds<256>) == 4352 + 256 * 48,
               "the runtime's LDS budget assumes 4352 bytes + max(3840, 48 per staged record) per wave");
@@ -822,11 +835,12 @@ constexpr int tile_min_waves() {
 constexpr double SC_OMEGA = 4e-3;
 constexpr double SC2_OMEGA = 1e-3;
 
-template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER, int SC = 0>
-__device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp, const PairCtx &C,
-                                              const BeamRsrc &beam, const BeamRsrc &vbeam) {
+template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER, int SC = 0, bool QF = false>
+__device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, PixRec>::type *Rp, const float *Vp,
+                                              const PairCtx &C, const BeamRsrc &beam, const BeamRsrc &vbeam) {
+    static_assert(!QF || (MODE == MODE_TOD && BEAM == BEAM_SCALAR && !HWP), "quadratic form: one-grid TOD, no plate");
     const LaneFrame &F = C.F;
-    PixRec R[NP];
+    typename Cond<QF, PixRecQ, PixRec>::type R[NP];
     float omg[NP], xp[NP], yp[NP], rzh[NP], rq[NP], fu[NP], fv[NP];
     bool in[NP];
     uint32_t off[NP];
@@ -921,6 +935,22 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
         // a rows, so e, its projections and the angle terms below carry the
         // grid scale (1/h, 1/h^2); the records carry h^2.
         const float q = xp[k] * rq[k];
+        if constexpr (QF) {
+            // e is normal to n, so its first two tile-frame components fix it:
+            // for vectors v, w normal to n, v.w = v_xy . (w_xy - (w_z / n_z) n_xy),
+            // and the records hold 2 cos gamma (B cos gamma + C sin gamma), the
+            // product of the projections on theta_hat and on B theta_hat + C phi_hat,
+            // as the quadratic form e_xy^T P e_xy (x h^2)
+            const float ex = fmaf(-q, F.p1 + R[k].X, F.a1);
+            const float ey = fmaf(-q, F.p2 + R[k].Y, F.a2);
+            const float4 c = cl[k][0];
+            const float bT = fmaf(fv[k], fmaf(fu[k], c.w, c.z), fmaf(fu[k], c.y, c.x));
+            const float bTm = in[k] ? bT : 0.0f;
+            if (PS) o.vn += bTm;
+            const float quad = fmaf(ex, fmaf(R[k].P11, ex, R[k].P12 * ey), fmaf(R[k].P22 * ey, ey, R[k].A));
+            o.v0 += bTm * quad;
+            continue;
+        } else {
         const float ex = fmaf(-q, F.p1, F.a1);
         const float ey = fmaf(-q, F.p2, F.a2);
         const float ez = fmaf(-q, F.p3, F.a3);
@@ -973,6 +1003,7 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
             o.v1 += in[k] ? bT * fmaf(c2, R[k].b, s2 * R[k].c) : 0.0f;
             o.v2 += in[k] ? bT * (sgn * fmaf(-s2, R[k].b, c2 * R[k].c)) : 0.0f;
         }
+        }
     }
     return o;
 }
@@ -981,8 +1012,9 @@ __device__ __forceinline__ PairOut tile_pairs(const PixRec *Rp, const float *Vp,
 // per step, then the remainder one by one.  CLIP (the disc-versus-grid test)
 // and INNER (the inner-disc test of an annulus) are uniform per detector and
 // template switches, so the common case runs a loop without either.
-template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER, int SC = 0>
-__device__ __forceinline__ void consume_records(const PixRec *rec, const float *vrec, int32_t m_end, const PairCtx &C,
+template <int MODE, int BEAM, bool PS, bool HWP, bool CLIP, bool INNER, int SC = 0, bool QF = false>
+__device__ __forceinline__ void consume_records(const typename Cond<QF, PixRecQ, PixRec>::type *rec,
+                                                const float *vrec, int32_t m_end, const PairCtx &C,
                                                 const BeamRsrc &beam, const BeamRsrc &vbeam, AccWide &acc0,
                                                 AccWide &acc1, AccWide &acc2, AccWide &accn) {
     // pairs whose beam loads are in flight together: four for one-grid beams (one
@@ -992,9 +1024,9 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
     int32_t m = 0;
     // two groups per compensated add: 2 NP masked terms summed in FP32
     for (; m + 2 * NP - 1 < m_end; m += 2 * NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC>(
+        const PairOut a = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC, QF>(
             &rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
-        const PairOut b = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC>(
+        const PairOut b = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC, QF>(
             &rec[m + NP], vrec ? &vrec[m + NP] : nullptr, C, beam, vbeam);
         acc0.add(a.v0 + b.v0);
         if (MODE == MODE_STOKES) {
@@ -1004,7 +1036,7 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
         if (PS) accn.add(a.vn + b.vn);
     }
     for (; m + NP - 1 < m_end; m += NP) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC>(
+        const PairOut a = tile_pairs<MODE, BEAM, PS, NP, HWP, CLIP, INNER, SC, QF>(
             &rec[m], vrec ? &vrec[m] : nullptr, C, beam, vbeam);
         acc0.add(a.v0);
         if (MODE == MODE_STOKES) {
@@ -1014,7 +1046,7 @@ __device__ __forceinline__ void consume_records(const PixRec *rec, const float *
         if (PS) accn.add(a.vn);
     }
     for (; m < m_end; ++m) {
-        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP, CLIP, INNER, SC>(&rec[m], vrec ? &vrec[m] : nullptr, C,
+        const PairOut a = tile_pairs<MODE, BEAM, PS, 1, HWP, CLIP, INNER, SC, QF>(&rec[m], vrec ? &vrec[m] : nullptr, C,
                                                                               beam, vbeam);
         acc0.add(a.v0);
         if (MODE == MODE_STOKES) {
@@ -1042,6 +1074,11 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
 
     const int32_t n = D.n;
     const float inv_h = (float)D.inv_h;
+    // one-grid TOD without a plate: the angle terms as a quadratic form in the
+    // tangent-plane components of the carried theta'_0 (caps up to 60 deg, so
+    // that the third component n_z >= 1/2 of every staged pixel stays large)
+    const bool qf = MODE == MODE_TOD && BEAM == BEAM_SCALAR && !HWP && D.needs_clip == 0 && D.has_inner == 0 &&
+                    cosRu >= 0.5;
     const float c0 = (float)(0.5 * (n - 1));
     const float tmax = (float)(n - 1);
     // the lane's theta'_0 and phi'_0 rows scaled to grid units for the pair loop
@@ -1145,7 +1182,28 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     R.b = fmaf(rz1, sv.z, rz0 * sv.y);
                     R.c = fmaf(rz0, sv.z, -rz1 * sv.y);
                 }
-                L.rec[m] = R;
+                if (qf) {
+                    // theta_hat and phi_hat reduced to the first two components
+                    // (w_xy - (w_z / n_z) n_xy, the pair loop's tangent-plane dot
+                    // product), then P = sym(theta~ (b theta~ + c phi~)^T)
+                    const float rnz = __builtin_amdgcn_rcpf(1.0f - R.W);   // n_z >= 1/2
+                    const float tz = R.t3 * rnz, fz = R.f3 * rnz;
+                    const float t1 = fmaf(-tz, R.X, R.t1), t2 = fmaf(-tz, R.Y, R.t2);
+                    const float f1 = fmaf(-fz, R.X, R.f1), f2 = fmaf(-fz, R.Y, R.f2);
+                    const float w1 = fmaf(R.b, t1, R.c * f1), w2 = fmaf(R.b, t2, R.c * f2);
+                    PixRecQ Q;
+                    Q.X = R.X;
+                    Q.Y = R.Y;
+                    Q.W = R.W;
+                    Q.A = R.a;
+                    Q.P11 = t1 * w1;
+                    Q.P12 = fmaf(t1, w2, t2 * w1);
+                    Q.P22 = t2 * w2;
+                    Q.pad = 0.0f;
+                    reinterpret_cast<PixRecQ *>(L.rec)[m] = Q;
+                } else {
+                    L.rec[m] = R;
+                }
                 if (has_v) vrec[m] = sv.w;
             }
             wave_sync();
@@ -1165,6 +1223,21 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     const PairCtx C{Fg, omax, omin, clip, inv_h, c0 + ringoff, tmax + ringoff, cmax, row, row_bytes,
                                     sg4, (float)(n - 1), ringoff, (uint32_t)row};
                     const float *vr = has_v ? vrec : nullptr;
+                    if constexpr (MODE == MODE_TOD && BEAM == BEAM_SCALAR && !HWP) {
+                        if (qf) {
+                            const PixRecQ *rq = reinterpret_cast<const PixRecQ *>(L.rec);
+                            if (tiny_cap)
+                                consume_records<MODE, BEAM, PS, HWP, false, false, 2, true>(rq, vr, m_end, C, beam, vbeam,
+                                                                                            acc0, acc1, acc2, accn);
+                            else if (small_cap)
+                                consume_records<MODE, BEAM, PS, HWP, false, false, 1, true>(rq, vr, m_end, C, beam, vbeam,
+                                                                                            acc0, acc1, acc2, accn);
+                            else
+                                consume_records<MODE, BEAM, PS, HWP, false, false, 0, true>(rq, vr, m_end, C, beam, vbeam,
+                                                                                            acc0, acc1, acc2, accn);
+                            goto consumed;
+                        }
+                    }
                     if (clip) {
                         if (inner)
                             consume_records<MODE, BEAM, PS, HWP, true, true>(L.rec, vr, m_end, C, beam, vbeam, acc0,
@@ -1188,6 +1261,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     }
                 }
             }
+        consumed:
             wave_sync();
         }
     }
