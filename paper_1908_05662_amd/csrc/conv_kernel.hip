@@ -794,6 +794,65 @@ __device__ void narrow_rings(UnionRing *ring, int32_t &rc, int32_t nb, const Lan
     }
 }
 
+// The same narrowing with the roles exchanged: lane i owns ring i of the batch
+// and walks the tile's ns samples, whose (colatitude offset, 1 / sine of the
+// colatitude, longitude offset) are staged in LDS (`hull`, broadcast reads; a
+// sample outside the tile has an offset of 16 rad, so it meets no ring).  Each
+// (ring, sample) interval is computed exactly as in narrow_rings (same
+// expressions, so the narrowed intervals are the same) and the lane keeps
+// their running minimum and maximum: no cross-lane reductions.
+__device__ void narrow_rings_lanes(UnionRing *ring, int32_t &rc, int32_t nb, const float4 *hull, int32_t ns, float R,
+                                   int lane) {
+    const int32_t cnt = rc;
+    const int32_t rn = ring[lane].n;
+    const float sr = ring[lane].s;
+    const bool act = lane < nb && cnt > 0 && cnt < rn && sr >= 0.25f;
+    if (__ballot(act) == 0) return;
+    const int32_t lo = ring[lane].lo, hi = lo + cnt - 1;
+    const float rdth = ring[lane].dth, rsr = __builtin_amdgcn_rcpf(sr), inv = __builtin_amdgcn_rcpf(ring[lane].dphi);
+    const float dphic = ring[lane].dphic;
+    int32_t klo = 0x7fffffff, khi = -0x7fffffff;
+    for (int32_t l = 0; l < ns; ++l) {
+        const float4 h = hull[l];
+        const float dth = fabsf(rdth - h.x);
+        const float ha = fmaf(0.5f, R - dth, 1.5e-7f);
+        const float hac = fmaxf(ha, 0.0f);   // a disc that misses the ring: hav = 0 (discarded below)
+        float sa, ca, sb, cb;
+        half_sincos(hac, sa, ca);
+        half_sincos(hac + dth, sb, cb);
+        const float hav = sa * sb * (h.y * rsr) * (1.0f + 1e-6f);
+        const float y = __builtin_amdgcn_sqrtf(hav), y2 = y * y;
+        float ps = fmaf(y2, 63.0f / 2816.0f, 35.0f / 1152.0f);
+        ps = fmaf(y2, ps, 5.0f / 112.0f);
+        ps = fmaf(y2, ps, 3.0f / 40.0f);
+        ps = fmaf(y2, ps, 1.0f / 6.0f);
+        const float as = (y < 0.3f) ? y * fmaf(y2, ps, 1.0f) : asinf(fminf(y, 1.0f));
+        const float dm = 2.0f * as;
+        const float base = h.z - dphic;
+        int32_t a = max(lo, (int32_t)ceilf(fmaf(base - dm, inv, -0.02f)));
+        int32_t b = min(hi, (int32_t)floorf(fmaf(base + dm, inv, 0.02f)));
+        if (hav >= 1.0f) {
+            a = lo;
+            b = hi;
+        }
+        if (!(ha > 0.0f)) {
+            a = 0x7fffffff;
+            b = -0x7fffffff;
+        }
+        klo = min(klo, a);
+        khi = max(khi, b);
+    }
+    if (act) {
+        int32_t nlo = lo, ncnt = 0;
+        if (klo <= khi) {
+            nlo = max(lo, klo);
+            ncnt = max(0, min(hi, khi) - nlo + 1);
+        }
+        rc = ncnt;
+        ring[lane].lo = nlo;
+    }
+}
+
 // Per-sample constants of the tile consume loop.
 struct PairCtx {
     LaneFrame F;
@@ -1119,13 +1178,17 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const int32_t r_lo = __builtin_amdgcn_readfirstlane(T.r_lo), r_hi = __builtin_amdgcn_readfirstlane(T.r_hi);
 
     const LaneHull H = lane_hull(D, t, valid, phc, zc, sc);
+    const float4 hull_mine = make_float4(valid ? H.dth : 16.0f, H.rsl, H.dphl, 0.0f);
     for (int32_t rb = r_lo; rb <= r_hi; rb += WAVE) {
         const int32_t r = rb + lane;
         int32_t rc = 0;
         if (r <= r_hi) rc = union_ring_setup(N, r, phc, zc, sc, cosRu, &L.ring[lane]);
         if (H.ok) {
+            // the lanes' discs, staged where the records go (free between batches)
+            float4 *hull = reinterpret_cast<float4 *>(L.rec);
+            hull[lane] = hull_mine;
             wave_sync();
-            narrow_rings(L.ring, rc, min(WAVE, r_hi - rb + 1), H, valid, lane);
+            narrow_rings_lanes(L.ring, rc, min(WAVE, r_hi - rb + 1), hull, cnt, H.R, lane);
             wave_sync();
         }
         const int32_t incl = wave_inclusive_scan(rc, lane);
