@@ -408,17 +408,22 @@ __global__ void apply_kernel(const float *y, int64_t n, float m0, float m1, floa
 }
 
 // ----------------------------------------------------------------------
-// Fused inference with the TOD epilogue: IR pointings per workgroup of four
-// waves.  Features, layer 0, the H x H layers, the output layer and
-// tod += sum_c coef_c (mean_c + std_c y_c) stay on chip: activations in LDS
-// (two buffers), weights read from L2.  The H x H layers use the operand
-// fragments and K order of gemm_kernel, layer 0 the FMA chain of
-// in_fwd_kernel, the output layer the per-lane order and butterfly of
-// out_rows_kernel and the epilogue apply_kernel's arithmetic, so the result equals
-// the layer-by-layer forward pass followed by apply, bit for bit.
+// Fused inference with the TOD epilogue: IR pointings per workgroup of H/64
+// waves, wave w owning units 64 w .. 64 w + 63 of every hidden layer.
+// Features, layer 0, the H x H layers, the output layer and
+// tod += sum_c coef_c (mean_c + std_c y_c) stay on chip: one activation
+// buffer in LDS, updated in place (each layer's products are formed in
+// registers, then, after a barrier, its activations overwrite its input),
+// weights read from L2.  At most 128 registers per lane, so that four waves
+// share a SIMD.  The H x H layers use the operand fragments and K order of
+// gemm_kernel, layer 0 the FMA chain of in_fwd_kernel, the output layer the
+// per-lane order and butterfly of out_rows_kernel and the epilogue
+// apply_kernel's arithmetic, so the result equals the layer-by-layer forward
+// pass followed by apply, bit for bit.
 // ----------------------------------------------------------------------
 constexpr int IR = 64;        // rows per workgroup
 constexpr int XLD = 8;        // feature row stride in LDS (floats)
+constexpr int WD = 2;         // k steps of weight fragments in flight
 
 __device__ inline void features_of(const double *th, const double *ph, const double *ps, int64_t i, float *f) {
     double st, ct, sf, cf, sp, cp;
@@ -432,48 +437,52 @@ __device__ inline void features_of(const double *th, const double *ph, const dou
     f[4] = (float)cp;
 }
 
-// One 64-unit group of an H x H layer for the IR rows in LDS, as Z^T = W A^T:
+// The wave's 64 units of an H x H layer for the IR rows in LDS, as Z^T = W A^T:
 // the weights are the MFMA's first operand (lane l: unit u0 + 16 i + l % 16,
 // k0 + 8 (l / 16) .. + 7, from L2), the activations its second (row 16 j +
 // l % 16, the same k, from LDS), so each output element is the training
 // GEMM's product chain over k0 = 0, 32, ... with the operands exchanged.  The
-// weight fragments of D k steps are in flight (a ring of D register slots,
-// refilled as each is used).  A lane's results are four consecutive units of
-// one row: bias, SiLU, and one 8-byte LDS store.
-template <int D>
-__device__ inline void hxh_layer_group(const __bf16 *__restrict__ W, const float *__restrict__ bias,
-                                       const __bf16 *cur, __bf16 *nxt, int H, int LD, int u0, int lane) {
+// weight fragments of WD k steps are in flight (a ring of register slots,
+// refilled as each is used).  acc[i][j]: lane l holds units
+// u0 + 16 i + 4 (l / 16) .. + 3 of row 16 j + l % 16.
+__device__ inline void hxh_products(const __bf16 *__restrict__ W, const __bf16 *act, int H, int LD, int u0, int lane,
+                                    f32x4 (&acc)[4][4]) {
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    f32x4 acc[4][4];   // [unit tile i][row tile j]
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const __bf16 *wrow = W + (int64_t)(u0 + r16) * H + kq;
-    bf16x8 wf[D][4];
+    bf16x8 wf[WD][4];
 #pragma unroll
-    for (int sl = 0; sl < D; ++sl)
+    for (int sl = 0; sl < WD; ++sl)
 #pragma unroll
         for (int i = 0; i < 4; ++i) wf[sl][i] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * i * H + 32 * sl);
-    for (int k0 = 0; k0 < H; k0 += D * 32) {
+    for (int k0 = 0; k0 < H; k0 += WD * 32) {
 #pragma unroll
-        for (int sl = 0; sl < D; ++sl) {
+        for (int sl = 0; sl < WD; ++sl) {
             const int kc = k0 + 32 * sl;
-            bf16x8 af[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) af[j] = *reinterpret_cast<const bf16x8 *>(cur + (16 * j + r16) * LD + kc + kq);
+            for (int j = 0; j < 4; ++j) {
+                const bf16x8 af = *reinterpret_cast<const bf16x8 *>(act + (16 * j + r16) * LD + kc + kq);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[sl][i], af[j], acc[i][j], 0, 0, 0);
-            const int kn = kc + D * 32;
+                for (int i = 0; i < 4; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[sl][i], af, acc[i][j], 0, 0, 0);
+            }
+            const int kn = kc + WD * 32;
             if (kn < H) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) wf[sl][i] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * i * H + kn);
             }
         }
     }
+}
+
+// bias, SiLU and the wave's activations into the buffer (one 8-byte store
+// per four consecutive units of a row)
+__device__ inline void hxh_store(const float *__restrict__ bias, __bf16 *act, int LD, int u0, int lane,
+                                 const f32x4 (&acc)[4][4]) {
+    const int r16 = lane & 15;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int ub = u0 + 16 * i + 4 * (lane >> 4);   // this lane's four units
@@ -484,17 +493,16 @@ __device__ inline void hxh_layer_group(const __bf16 *__restrict__ W, const float
             typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
             const bf16x4 o = bf16x4{(__bf16)silu(acc[i][j][0] + bq.x), (__bf16)silu(acc[i][j][1] + bq.y),
                                     (__bf16)silu(acc[i][j][2] + bq.z), (__bf16)silu(acc[i][j][3] + bq.w)};
-            *reinterpret_cast<bf16x4 *>(nxt + row * LD + ub) = o;
+            *reinterpret_cast<bf16x4 *>(act + row * LD + ub) = o;
         }
     }
 }
 
-__global__ void __launch_bounds__(256) infer_kernel(MlpInferArgs g) {
+__global__ void __launch_bounds__(512, 4) infer_kernel(MlpInferArgs g) {
     extern __shared__ __align__(16) unsigned char lds[];
-    const int H = g.H, LD = H + 8;
+    const int H = g.H, LD = H + 8, NT = blockDim.x, NW = NT / 64;
     float *X = reinterpret_cast<float *>(lds);
-    __bf16 *buf0 = reinterpret_cast<__bf16 *>(lds + IR * XLD * sizeof(float));
-    __bf16 *buf1 = buf0 + IR * LD;
+    __bf16 *act = reinterpret_cast<__bf16 *>(lds + IR * XLD * sizeof(float));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t r0 = (int64_t)blockIdx.x * IR;
 
@@ -507,7 +515,7 @@ __global__ void __launch_bounds__(256) infer_kernel(MlpInferArgs g) {
     __syncthreads();
 
     // layer 0 (K = 5) on the vector ALU: thread u owns unit u for every row
-    for (int u = tid; u < H; u += 256) {
+    for (int u = tid; u < H; u += NT) {
         float w0[MLP_IN];
 #pragma unroll
         for (int k = 0; k < MLP_IN; ++k) w0[k] = (float)g.wb[g.off_w[0] + u * MLP_IN + k];
@@ -516,38 +524,31 @@ __global__ void __launch_bounds__(256) infer_kernel(MlpInferArgs g) {
             float s = b0;
 #pragma unroll
             for (int k = 0; k < MLP_IN; ++k) s = fmaf(X[r * XLD + k], w0[k], s);
-            buf0[r * LD + u] = (__bf16)silu(s);
+            act[r * LD + u] = (__bf16)silu(s);
         }
     }
     __syncthreads();
 
-    // H x H layers as Z^T = W A^T (hxh_layer_group): weights first operand
-    // from L2, activations second from LDS; D k steps of weight fragments in
-    // flight (four when H is a multiple of 128, else two).
-    __bf16 *cur = buf0, *nxt = buf1;
+    // H x H layers, in place: every wave's products from the whole input,
+    // then (after the barrier) its units' activations over that input
+    const int u0 = 64 * wave;
     for (int l = 1; l < g.L; ++l) {
-        const __bf16 *__restrict__ W = g.wb + g.off_w[l];
-        const float *__restrict__ bias = g.w + g.off_b[l];
-        for (int cg = wave; cg < H / 64; cg += 4) {
-            if (H % 128 == 0) hxh_layer_group<4>(W, bias, cur, nxt, H, LD, cg * 64, lane);
-            else hxh_layer_group<2>(W, bias, cur, nxt, H, LD, cg * 64, lane);
-        }
+        f32x4 acc[4][4];
+        hxh_products(g.wb + g.off_w[l], act, H, LD, u0, lane, acc);
         __syncthreads();
-        __bf16 *t = cur;
-        cur = nxt;
-        nxt = t;
+        hxh_store(g.w + g.off_b[l], act, LD, u0, lane, acc);
+        __syncthreads();
     }
 
-    // output layer (N = 3): wave w takes rows w * IR/4 ...; lanes over units
+    // output layer (N = 3): wave w takes rows w, w + NW, ...; lanes over units
     const __bf16 *__restrict__ Wo = g.wb + g.off_w[g.L];
     const float *__restrict__ bo = g.w + g.off_b[g.L];
     const int per = H / 64;
-    for (int rr = 0; rr < IR / 4; ++rr) {
-        const int r = wave * (IR / 4) + rr;
+    for (int r = wave; r < IR; r += NW) {
         float sc[MLP_OUT] = {0.0f, 0.0f, 0.0f};
         for (int k = 0; k < per; ++k) {
             const int u = lane + 64 * k;
-            const float av = (float)cur[r * LD + u];
+            const float av = (float)act[r * LD + u];
 #pragma unroll
             for (int c = 0; c < MLP_OUT; ++c) sc[c] = fmaf(av, (float)Wo[c * H + u], sc[c]);
         }
@@ -697,13 +698,14 @@ hipError_t mlp_features(const double *th, const double *ph, const double *ps, in
 
 hipError_t mlp_infer_apply(const MlpInferArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
-    const size_t lds = (size_t)IR * XLD * sizeof(float) + 2 * (size_t)IR * (a.H + 8) * sizeof(__bf16);
+    if (a.H % 64 || a.H < 64 || a.H > 512) return hipErrorInvalidValue;
+    const size_t lds = (size_t)IR * XLD * sizeof(float) + (size_t)IR * (a.H + 8) * sizeof(__bf16);
     if (lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&infer_kernel),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(infer_kernel, dim3(blocks_for(a.n, IR)), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(infer_kernel, dim3(blocks_for(a.n, IR)), dim3(a.H), lds, s, a);
     return hipGetLastError();
 }
 
