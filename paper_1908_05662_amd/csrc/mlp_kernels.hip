@@ -498,12 +498,16 @@ __device__ inline void hxh_store(const float *__restrict__ bias, __bf16 *act, in
     }
 }
 
-__global__ void __launch_bounds__(512, 4) infer_kernel(MlpInferArgs g) {
+// NW = H / 64 waves (and 64-unit groups) per workgroup.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW, 4) infer_kernel(MlpInferArgs g) {
+    constexpr int H = 64 * NW, LD = H + 8;
     extern __shared__ __align__(16) unsigned char lds[];
-    const int H = g.H, LD = H + 8, NT = blockDim.x, NW = NT / 64;
     float *X = reinterpret_cast<float *>(lds);
     __bf16 *act = reinterpret_cast<__bf16 *>(lds + IR * XLD * sizeof(float));
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int u0 = 64 * wave;
     const int64_t r0 = (int64_t)blockIdx.x * IR;
 
     if (tid < IR) {
@@ -514,24 +518,39 @@ __global__ void __launch_bounds__(512, 4) infer_kernel(MlpInferArgs g) {
     }
     __syncthreads();
 
-    // layer 0 (K = 5) on the vector ALU: thread u owns unit u for every row
-    for (int u = tid; u < H; u += NT) {
-        float w0[MLP_IN];
+    // layer 0 (K = 5) on the vector ALU: lane r of wave w forms row r of units
+    // 64 w .. 64 w + 63 (wave-uniform weights), eight units per 16-byte store
+    {
+        float xr[MLP_IN];
 #pragma unroll
-        for (int k = 0; k < MLP_IN; ++k) w0[k] = (float)g.wb[g.off_w[0] + u * MLP_IN + k];
-        const float b0 = g.w[g.off_b[0] + u];
-        for (int r = 0; r < IR; ++r) {
-            float s = b0;
+        for (int k = 0; k < MLP_IN; ++k) xr[k] = X[lane * XLD + k];
+        // the wave's 320 BF16 weights as 32-bit words (wave-uniform, so scalar
+        // loads; the offset of layer 0 and 5 u0 are even): BF16 k of unit u is
+        // the high or low half of word (5 u + k) / 2
+        const uint32_t *__restrict__ w0 =
+            reinterpret_cast<const uint32_t *>(g.wb + g.off_w[0] + (int64_t)u0 * MLP_IN);
+        const float *__restrict__ b0 = g.w + g.off_b[0] + u0;
+        for (int q = 0; q < 8; ++q) {
+            bf16x8 o;
 #pragma unroll
-            for (int k = 0; k < MLP_IN; ++k) s = fmaf(X[r * XLD + k], w0[k], s);
-            act[r * LD + u] = (__bf16)silu(s);
+            for (int e = 0; e < 8; ++e) {
+                const int u = 8 * q + e;
+                float sv = b0[u];
+#pragma unroll
+                for (int k = 0; k < MLP_IN; ++k) {
+                    const int i = u * MLP_IN + k;
+                    const uint32_t wd = w0[i >> 1];
+                    sv = fmaf(xr[k], __uint_as_float((i & 1) ? (wd & 0xffff0000u) : (wd << 16)), sv);
+                }
+                o[e] = (__bf16)silu(sv);
+            }
+            *reinterpret_cast<bf16x8 *>(act + lane * LD + u0 + 8 * q) = o;
         }
     }
     __syncthreads();
 
     // H x H layers, in place: every wave's products from the whole input,
     // then (after the barrier) its units' activations over that input
-    const int u0 = 64 * wave;
     for (int l = 1; l < g.L; ++l) {
         f32x4 acc[4][4];
         hxh_products(g.wb + g.off_w[l], act, H, LD, u0, lane, acc);
@@ -540,30 +559,46 @@ __global__ void __launch_bounds__(512, 4) infer_kernel(MlpInferArgs g) {
         __syncthreads();
     }
 
-    // output layer (N = 3): wave w takes rows w, w + NW, ...; lanes over units
+    // output layer (N = 3): wave w takes rows 4 w .. 4 w + 3, 4 (w + NW) ..,
+    // four at a time; lanes over units, the weights held in registers
     const __bf16 *__restrict__ Wo = g.wb + g.off_w[g.L];
     const float *__restrict__ bo = g.w + g.off_b[g.L];
-    const int per = H / 64;
-    for (int r = wave; r < IR; r += NW) {
-        float sc[MLP_OUT] = {0.0f, 0.0f, 0.0f};
-        for (int k = 0; k < per; ++k) {
-            const int u = lane + 64 * k;
-            const float av = (float)act[r * LD + u];
+    float wo[NW][MLP_OUT];
 #pragma unroll
-            for (int c = 0; c < MLP_OUT; ++c) sc[c] = fmaf(av, (float)Wo[c * H + u], sc[c]);
-        }
+    for (int k = 0; k < NW; ++k)
 #pragma unroll
-        for (int c = 0; c < MLP_OUT; ++c) {
+        for (int c = 0; c < MLP_OUT; ++c) wo[k][c] = (float)Wo[c * H + lane + 64 * k];
+    for (int rb = 4 * wave; rb < IR; rb += 4 * NW) {
+        float sc[4][MLP_OUT];
 #pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) sc[c] += __shfl_xor(sc[c], m, 64);
-            sc[c] += bo[c];
-        }
-        const int64_t i = r0 + r;
-        if (lane == 0 && i < g.n) {
-            const double p0 = g.mean[0] + (double)g.stdv[0] * sc[0];
-            const double p1 = g.mean[1] + (double)g.stdv[1] * sc[1];
-            const double p2 = g.mean[2] + (double)g.stdv[2] * sc[2];
-            g.tod[i] = (float)((double)g.tod[i] + g.coef[0] * p0 + g.coef[1] * p1 + g.coef[2] * p2);
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < MLP_OUT; ++c) sc[q][c] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float av = (float)act[(rb + q) * LD + lane + 64 * k];
+#pragma unroll
+                for (int c = 0; c < MLP_OUT; ++c) sc[q][c] = fmaf(av, wo[k][c], sc[q][c]);
+            }
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int c = 0; c < MLP_OUT; ++c) sc[q][c] += __shfl_xor(sc[q][c], m, 64);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t i = r0 + rb + q;
+                if (i < g.n) {
+                    const double p0 = g.mean[0] + (double)g.stdv[0] * (sc[q][0] + bo[0]);
+                    const double p1 = g.mean[1] + (double)g.stdv[1] * (sc[q][1] + bo[1]);
+                    const double p2 = g.mean[2] + (double)g.stdv[2] * (sc[q][2] + bo[2]);
+                    g.tod[i] = (float)((double)g.tod[i] + g.coef[0] * p0 + g.coef[1] * p1 + g.coef[2] * p2);
+                }
+            }
         }
     }
 }
@@ -696,17 +731,32 @@ hipError_t mlp_features(const double *th, const double *ph, const double *ps, in
     return hipGetLastError();
 }
 
-hipError_t mlp_infer_apply(const MlpInferArgs &a, hipStream_t s) {
-    if (a.n == 0) return hipSuccess;
-    if (a.H % 64 || a.H < 64 || a.H > 512) return hipErrorInvalidValue;
-    const size_t lds = (size_t)IR * XLD * sizeof(float) + (size_t)IR * (a.H + 8) * sizeof(__bf16);
+template <int NW>
+static hipError_t infer_launch(const MlpInferArgs &a, hipStream_t s) {
+    const size_t lds = (size_t)IR * XLD * sizeof(float) + (size_t)IR * (64 * NW + 8) * sizeof(__bf16);
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&infer_kernel),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&infer_kernel<NW>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(infer_kernel, dim3(blocks_for(a.n, IR)), dim3(a.H), lds, s, a);
+    hipLaunchKernelGGL(infer_kernel<NW>, dim3(blocks_for(a.n, IR)), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
+}
+
+hipError_t mlp_infer_apply(const MlpInferArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    if (a.off_w[0] % 2) return hipErrorInvalidValue;   // layer 0 is read as 32-bit words
+    switch (a.H) {
+    case 64: return infer_launch<1>(a, s);
+    case 128: return infer_launch<2>(a, s);
+    case 192: return infer_launch<3>(a, s);
+    case 256: return infer_launch<4>(a, s);
+    case 320: return infer_launch<5>(a, s);
+    case 384: return infer_launch<6>(a, s);
+    case 448: return infer_launch<7>(a, s);
+    case 512: return infer_launch<8>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t mlp_apply(const float *y, int64_t n, const float *mean, const float *stdv, const double *coef, float *tod,
