@@ -493,28 +493,42 @@ pisco_status build_plan(pisco_ctx *c, Plan &p, std::vector<DetDesc> &descs, cons
             if (cs != PISCO_OK) return cs;
         }
     }
+    // pixel path: runs of incoherent groups of one detector merged, then cut into
+    // tiles of at most spt samples, and of fewer when the pixel path has fewer
+    // samples than twice the launch's waves hold at spt each (a wave takes one
+    // sample at a time, so small tiles spread a few incoherent groups -- scan
+    // discontinuities -- over the whole chip instead of a few waves)
+    int64_t pix_samples = 0;
+    for (size_t g = 0; g < groups.size(); ++g)
+        if (!flag[g]) pix_samples += groups[g].count;
+    // (under a memory budget at least 16 samples a tile: the block sizing allows
+    // about 2 bytes of queues per sample)
+    const int64_t waves = std::max<int64_t>(1, (int64_t)c->gpc * c->num_cu * c->wpg);
+    const int64_t min_pspt = c->budget > 0 ? 16 : 1;
+    const int32_t pspt = (int32_t)std::min<int64_t>(
+        c->spt, std::max<int64_t>(min_pspt, (pix_samples + 2 * waves - 1) / (2 * waves)));
     std::vector<Tile> ttiles, ptiles;
     for (size_t g = 0; g < groups.size(); ++g) {
         if (flag[g]) {
             ttiles.push_back(groups[g]);
             continue;
         }
-        // pixel path: merge runs of incoherent groups of one detector, then cut into spt-sample tiles
-        const Tile &x = groups[g];
-        if (!ptiles.empty() && ptiles.back().det == x.det && ptiles.back().begin + ptiles.back().count == x.begin &&
-            ptiles.back().count < c->spt) {
-            Tile &b = ptiles.back();
-            const int32_t room = c->spt - b.count, take = std::min(room, x.count);
-            b.count += take;
-            if (take < x.count) {
-                Tile t;
-                t.det = x.det;
-                t.begin = x.begin + take;
-                t.count = x.count - take;
+        Tile x = groups[g];
+        while (x.count > 0) {
+            if (!ptiles.empty() && ptiles.back().det == x.det && ptiles.back().begin + ptiles.back().count == x.begin &&
+                ptiles.back().count < pspt) {
+                Tile &b = ptiles.back();
+                const int32_t take = std::min(pspt - b.count, x.count);
+                b.count += take;
+                x.begin += take;
+                x.count -= take;
+            } else {
+                Tile t = x;
+                t.count = std::min(pspt, x.count);
                 ptiles.push_back(t);
+                x.begin += t.count;
+                x.count -= t.count;
             }
-        } else {
-            ptiles.push_back(x);
         }
     }
     // each detector's coherent tiles in the Hilbert order of their first samples:
