@@ -1699,6 +1699,15 @@ __device__ inline bool tile_is_coherent(const DetDesc &D, int64_t begin, int32_t
 // ----------------------------------------------------------------------
 // Kernels
 // ----------------------------------------------------------------------
+// Next tile of queue q for the calling wave (lane 0): a plain load first, so
+// waves that find a queue drained add nothing to the atomics its counter
+// serialises (thousands of waves checking every queue at the end of a launch).
+// The counter only grows, so a stale load at worst leads to the atomic.
+__device__ inline int32_t pop_tile(int32_t *counter, int32_t len) {
+    if (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= len) return len;
+    return atomicAdd(counter, 1);
+}
+
 template <typename T, int MODE, int BEAM>
 __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -1709,7 +1718,7 @@ __global__ void __launch_bounds__(512) conv_kernel(ConvArgs A) {
     int32_t exhausted = 0;
     while (exhausted < A.n_queues) {
         int32_t ti = 0;
-        if (lane == 0) ti = atomicAdd(&A.counters[q], 1);
+        if (lane == 0) ti = pop_tile(&A.counters[q], A.queue_len[q]);
         ti = __shfl(ti, 0, WAVE);
         if (ti >= A.queue_len[q]) {
             q = (q + 1 == A.n_queues) ? 0 : q + 1;
@@ -1735,7 +1744,7 @@ __global__ void __launch_bounds__(512, (tile_min_waves<MODE, BEAM>())) tile_kern
     int32_t exhausted = 0;
     while (exhausted < A.n_queues) {
         int32_t ti = 0;
-        if (lane == 0) ti = atomicAdd(&A.counters[q], 1);
+        if (lane == 0) ti = pop_tile(&A.counters[q], A.queue_len[q]);
         ti = __builtin_amdgcn_readfirstlane(__shfl(ti, 0, WAVE));
         if (ti >= A.queue_len[q]) {
             q = (q + 1 == A.n_queues) ? 0 : q + 1;
@@ -1758,7 +1767,7 @@ __global__ void __launch_bounds__(512, 2) tile_mx_kernel(ConvArgs A) {
     int32_t exhausted = 0;
     while (exhausted < A.n_queues) {
         int32_t ti = 0;
-        if (lane == 0) ti = atomicAdd(&A.counters[q], 1);
+        if (lane == 0) ti = pop_tile(&A.counters[q], A.queue_len[q]);
         ti = __builtin_amdgcn_readfirstlane(__shfl(ti, 0, WAVE));
         if (ti >= A.queue_len[q]) {
             q = (q + 1 == A.n_queues) ? 0 : q + 1;

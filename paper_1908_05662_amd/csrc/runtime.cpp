@@ -655,7 +655,9 @@ hipError_t enqueue(pisco_ctx *c, const Plan &p, void *out, int out_mode, hipStre
         if (e != hipSuccess) return e;
     }
     if (p.pq.ntiles > 0) {
-        e = pisco::launch_conv(make_args(c, p, out, out_mode, false), f64, c->wpg, c->gpc * c->num_cu, s);
+        // no more workgroups than the pixel path has tiles for (a wave takes a tile)
+        const int64_t g = std::min<int64_t>((int64_t)c->gpc * c->num_cu, (p.pq.ntiles + c->wpg - 1) / c->wpg);
+        e = pisco::launch_conv(make_args(c, p, out, out_mode, false), f64, c->wpg, (int)std::max<int64_t>(1, g), s);
         if (e != hipSuccess) return e;
     }
     // far-sidelobe network of surrogate-enabled detectors, added to their TOD
