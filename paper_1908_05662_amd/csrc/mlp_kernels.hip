@@ -408,7 +408,7 @@ __global__ void apply_kernel(const float *y, int64_t n, float m0, float m1, floa
 }
 
 // ----------------------------------------------------------------------
-// Fused inference with the TOD epilogue: IR pointings per workgroup of H/64
+// Fused inference with the TOD epilogue: 64 RB pointings per workgroup of H/64
 // waves, wave w owning units 64 w .. 64 w + 63 of every hidden layer.
 // Features, layer 0, the H x H layers, the output layer and
 // tod += sum_c coef_c (mean_c + std_c y_c) stay on chip: one activation
@@ -421,7 +421,6 @@ __global__ void apply_kernel(const float *y, int64_t n, float m0, float m1, floa
 // apply_kernel's arithmetic, so the result equals the layer-by-layer forward
 // pass followed by apply, bit for bit.
 // ----------------------------------------------------------------------
-constexpr int IR = 64;        // rows per workgroup
 constexpr int XLD = 8;        // feature row stride in LDS (floats)
 constexpr int WD = 2;         // k steps of weight fragments in flight
 
@@ -437,21 +436,23 @@ __device__ inline void features_of(const double *th, const double *ph, const dou
     f[4] = (float)cp;
 }
 
-// The wave's 64 units of an H x H layer for the IR rows in LDS, as Z^T = W A^T:
+// The wave's 64 units of an H x H layer for the 64 RB rows in LDS, as Z^T = W A^T:
 // the weights are the MFMA's first operand (lane l: unit u0 + 16 i + l % 16,
 // k0 + 8 (l / 16) .. + 7, from L2), the activations its second (row 16 j +
 // l % 16, the same k, from LDS), so each output element is the training
 // GEMM's product chain over k0 = 0, 32, ... with the operands exchanged.  The
 // weight fragments of WD k steps are in flight (a ring of register slots,
-// refilled as each is used).  acc[i][j]: lane l holds units
-// u0 + 16 i + 4 (l / 16) .. + 3 of row 16 j + l % 16.
+// refilled as each is used); every weight fragment serves 4 RB row tiles, so
+// more rows per workgroup read the weights from L2 fewer times per row.
+// acc[i][j]: lane l holds units u0 + 16 i + 4 (l / 16) .. + 3 of row 16 j + l % 16.
+template <int RB>
 __device__ inline void hxh_products(const __bf16 *__restrict__ W, const __bf16 *act, int H, int LD, int u0, int lane,
-                                    f32x4 (&acc)[4][4]) {
+                                    f32x4 (&acc)[4][4 * RB]) {
     const int r16 = lane & 15, kq = (lane >> 4) * 8;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < 4 * RB; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const __bf16 *wrow = W + (int64_t)(u0 + r16) * H + kq;
     bf16x8 wf[WD][4];
 #pragma unroll
@@ -463,7 +464,7 @@ __device__ inline void hxh_products(const __bf16 *__restrict__ W, const __bf16 *
         for (int sl = 0; sl < WD; ++sl) {
             const int kc = k0 + 32 * sl;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 4 * RB; ++j) {
                 const bf16x8 af = *reinterpret_cast<const bf16x8 *>(act + (16 * j + r16) * LD + kc + kq);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -480,15 +481,16 @@ __device__ inline void hxh_products(const __bf16 *__restrict__ W, const __bf16 *
 
 // bias, SiLU and the wave's activations into the buffer (one 8-byte store
 // per four consecutive units of a row)
+template <int RB>
 __device__ inline void hxh_store(const float *__restrict__ bias, __bf16 *act, int LD, int u0, int lane,
-                                 const f32x4 (&acc)[4][4]) {
+                                 const f32x4 (&acc)[4][4 * RB]) {
     const int r16 = lane & 15;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int ub = u0 + 16 * i + 4 * (lane >> 4);   // this lane's four units
         const float4 bq = *reinterpret_cast<const float4 *>(bias + ub);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 4 * RB; ++j) {
             const int row = 16 * j + r16;
             typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
             const bf16x4 o = bf16x4{(__bf16)silu(acc[i][j][0] + bq.x), (__bf16)silu(acc[i][j][1] + bq.y),
@@ -498,10 +500,11 @@ __device__ inline void hxh_store(const float *__restrict__ bias, __bf16 *act, in
     }
 }
 
-// NW = H / 64 waves (and 64-unit groups) per workgroup.
-template <int NW>
-__global__ void __launch_bounds__(64 * NW, 4) infer_kernel(MlpInferArgs g) {
-    constexpr int H = 64 * NW, LD = H + 8;
+// NW = H / 64 waves (and 64-unit groups) per workgroup, 64 RB rows.  RB = 1:
+// at most 128 registers per lane (four waves per SIMD); RB = 2: 256 (two).
+template <int NW, int RB>
+__global__ void __launch_bounds__(64 * NW, RB == 1 ? 4 : 2) infer_kernel(MlpInferArgs g) {
+    constexpr int H = 64 * NW, LD = H + 8, IR = 64 * RB;
     extern __shared__ __align__(16) unsigned char lds[];
     float *X = reinterpret_cast<float *>(lds);
     __bf16 *act = reinterpret_cast<__bf16 *>(lds + IR * XLD * sizeof(float));
@@ -510,20 +513,21 @@ __global__ void __launch_bounds__(64 * NW, 4) infer_kernel(MlpInferArgs g) {
     const int u0 = 64 * wave;
     const int64_t r0 = (int64_t)blockIdx.x * IR;
 
-    if (tid < IR) {
+    for (int r = tid; r < IR; r += 64 * NW) {
         float f[MLP_IN] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        if (r0 + tid < g.n) features_of(g.th, g.ph, g.ps, r0 + tid, f);
+        if (r0 + r < g.n) features_of(g.th, g.ph, g.ps, r0 + r, f);
 #pragma unroll
-        for (int k = 0; k < MLP_IN; ++k) X[tid * XLD + k] = f[k];
+        for (int k = 0; k < MLP_IN; ++k) X[r * XLD + k] = f[k];
     }
     __syncthreads();
 
-    // layer 0 (K = 5) on the vector ALU: lane r of wave w forms row r of units
-    // 64 w .. 64 w + 63 (wave-uniform weights), eight units per 16-byte store
-    {
+    // layer 0 (K = 5) on the vector ALU: lane r of wave w forms rows r, r + 64, ..
+    // of units 64 w .. 64 w + 63 (wave-uniform weights), eight units per 16-byte store
+    for (int rb = 0; rb < RB; ++rb) {
+        const int row = 64 * rb + lane;
         float xr[MLP_IN];
 #pragma unroll
-        for (int k = 0; k < MLP_IN; ++k) xr[k] = X[lane * XLD + k];
+        for (int k = 0; k < MLP_IN; ++k) xr[k] = X[row * XLD + k];
         // the wave's 320 BF16 weights as 32-bit words (wave-uniform, so scalar
         // loads; the offset of layer 0 and 5 u0 are even): BF16 k of unit u is
         // the high or low half of word (5 u + k) / 2
@@ -544,7 +548,7 @@ __global__ void __launch_bounds__(64 * NW, 4) infer_kernel(MlpInferArgs g) {
                 }
                 o[e] = (__bf16)silu(sv);
             }
-            *reinterpret_cast<bf16x8 *>(act + lane * LD + u0 + 8 * q) = o;
+            *reinterpret_cast<bf16x8 *>(act + row * LD + u0 + 8 * q) = o;
         }
     }
     __syncthreads();
@@ -552,10 +556,10 @@ __global__ void __launch_bounds__(64 * NW, 4) infer_kernel(MlpInferArgs g) {
     // H x H layers, in place: every wave's products from the whole input,
     // then (after the barrier) its units' activations over that input
     for (int l = 1; l < g.L; ++l) {
-        f32x4 acc[4][4];
-        hxh_products(g.wb + g.off_w[l], act, H, LD, u0, lane, acc);
+        f32x4 acc[4][4 * RB];
+        hxh_products<RB>(g.wb + g.off_w[l], act, H, LD, u0, lane, acc);
         __syncthreads();
-        hxh_store(g.w + g.off_b[l], act, LD, u0, lane, acc);
+        hxh_store<RB>(g.w + g.off_b[l], act, LD, u0, lane, acc);
         __syncthreads();
     }
 
@@ -731,15 +735,19 @@ hipError_t mlp_features(const double *th, const double *ph, const double *ps, in
     return hipGetLastError();
 }
 
+// rows per workgroup: 128 from width 256 up (each weight fragment then serves
+// eight row tiles, halving the L2 reads per row: 8.35 -> 6.0 ms at 512 x 10 and
+// 0.92 -> 0.84 ms at 256 x 4 over 1e6 pointings), 64 below
 template <int NW>
 static hipError_t infer_launch(const MlpInferArgs &a, hipStream_t s) {
+    constexpr int RB = NW >= 4 ? 2 : 1, IR = 64 * RB;
     const size_t lds = (size_t)IR * XLD * sizeof(float) + (size_t)IR * (64 * NW + 8) * sizeof(__bf16);
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&infer_kernel<NW>),
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&infer_kernel<NW, RB>),
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(infer_kernel<NW>, dim3(blocks_for(a.n, IR)), dim3(64 * NW), lds, s, a);
+    hipLaunchKernelGGL((infer_kernel<NW, RB>), dim3(blocks_for(a.n, IR)), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
 }
 

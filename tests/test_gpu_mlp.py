@@ -226,3 +226,36 @@ def test_features_and_apply(net, torch):
     got = tod.cpu().numpy()
     ulp = np.spacing(np.abs(want).astype(np.float32)).astype(np.float64)
     assert np.all(np.abs(got - want) <= ulp)
+
+
+@pytest.mark.parametrize("width, hidden", [(64, 2), (192, 3), (384, 3), (512, 4)])
+def test_apply_equals_forward_all_instances(torch, width, hidden):
+    """The fused epilogue is instantiated per width (64-row workgroups below 256, 128-row
+    ones from 256 up): at each shape it runs the same network as forward(), so the TOD
+    differs from the host sum over forward()'s outputs only by the final rounding (one ulp),
+    over a stream whose length is not a multiple of either row count."""
+    from paper_1908_05662_amd.api import Convolver, Mlp
+    from synth import workloads as W
+    from gpu_helpers import load_workload
+
+    say(f"case: fused epilogue against forward(), width {width}, {hidden} hidden layers")
+    conv = Convolver(0)
+    m = Mlp(conv, width, hidden, max_batch=64, seed=11 + width)
+    try:
+        w = W.c1(n_samples=1000)
+        load_workload(conv, w, np.float32)
+        x = m.features(0)
+        y = m.forward(x).cpu().numpy().astype(np.float64)
+        tod = torch.linspace(-1, 1, 1000, dtype=torch.float32, device="cuda")
+        base = tod.cpu().numpy().astype(np.float64)
+        mean, std, coef = [0.05, 0.1, -0.3], [1.5, 0.25, 0.75], [-0.6, 0.9, 1.3]
+        m.apply(0, mean, std, coef, tod)
+        want = base + sum(coef[c] * (np.float32(mean[c]) + np.float64(np.float32(std[c])) * y[:, c])
+                          for c in range(3))
+        got = tod.cpu().numpy()
+        ulp = np.spacing(np.abs(want).astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(got - want) <= ulp)
+    finally:
+        torch.cuda.synchronize()
+        m.close()
+        conv.close()
