@@ -27,37 +27,42 @@ sys.path.insert(0, ROOT)
 # counted from its source (FMA = 2; add, multiply, fract, floor and reciprocal 1;
 # compares, selects, conversions to integers and address arithmetic 0):
 #  membership 1 - n.p 6; n.theta'_0 and n.phi'_0 12; 1/z' and 1/(1+z') as
-#  second-order series in omega 7 (third order: 11; one reciprocal of
-#  z'(1+z') and the two products: 6); grid coordinates 4; cell fractions 2;
+#  series in omega, to the second and first power 5 (third and second: 9; one
+#  reciprocal of z'(1+z') and the two products: 6); grid coordinates 4; cell
+#  fractions 2;
 #  q = (n.theta'_0) / (1 + z') 1; one-grid bilinear cell polynomial 6; times
 #  the beam value 1 and the per-step sum 1; the sum of eight terms added in
 #  FP64 0.25 per sum; the normaliser of a per-sample-normalised launch (its
 #  masked add 1 + 0.25).  The position-angle part:
-#  one-grid TOD without a plate (the quadratic-form records): the first two
-#  tile-frame components of theta'_0 carried to the pixel 6, the quadratic form
-#  8 -> 54.25, 55.5 with the normaliser;
+#  one-grid TOD without a plate (the quadratic-form records, in gnomonic
+#  coordinates about the tile centre): n.theta'_0 and n.phi'_0 over n_z 8
+#  instead of 12 (the scale 1/(1 - t) has the same series and reciprocal counts),
+#  the first two tile-frame components of theta'_0 carried to the pixel 8, the
+#  quadratic form 8 -> 50.25, 51.5 with the normaliser;
 #  otherwise theta'_0 carried to the pixel 6, its projections on the pixel's
 #  theta/phi 10, and for one-grid TOD with a plate the turn by 2 phi_t 6 and the
-#  cos^2 form 5 (-> 68.5 with the normaliser); four-channel beams: floors and
+#  cos^2 form 5 (-> 66.5 with the normaliser); four-channel beams: floors and
 #  fractions 4 instead of 2, four bilinear channels 36 instead of 6, cos 2gamma
-#  and sin 2gamma 4 and the contraction with the Stokes rotation 12 -> 104.5
+#  and sin 2gamma 4 and the contraction with the Stokes rotation 12 -> 102.5
 #  with the normaliser.
 #  Matrix-core variant (algorithm 2): eight 16x16x4 FP32 MFMAs per 16 pixels x
 #  16 samples give the pixel-linear quantities (64 matrix flops per pair);
 #  vector ALU 44 (one-grid) / 81 (four-channel).
 #  Pixel path (FP32 incoherent groups), four-channel beam: 155; one-grid: 125.
-FLOPS_PER_PAIR = {(1, "scalar", 2, True): (55.5, 0), (1, "scalar", 2, False): (54.25, 0),
-                  (1, "scalar", 1, True): (59.5, 0), (1, "scalar", 1, False): (58.25, 0),
-                  (1, "scalar", 0, True): (54.5, 0), (1, "scalar", 0, False): (53.25, 0),
-                  (1, "full", 2, True): (104.5, 0), (1, "full", 2, False): (103.25, 0),
-                  (1, "full", 1, True): (108.5, 0), (1, "full", 0, True): (103.5, 0),
+FLOPS_PER_PAIR = {(1, "scalar", 2, True): (51.5, 0), (1, "scalar", 2, False): (50.25, 0),
+                  (1, "scalar", 1, True): (55.5, 0), (1, "scalar", 1, False): (54.25, 0),
+                  (1, "scalar", 0, True): (52.5, 0), (1, "scalar", 0, False): (51.25, 0),
+                  (1, "full", 2, True): (102.5, 0), (1, "full", 2, False): (101.25, 0),
+                  (1, "full", 1, True): (106.5, 0), (1, "full", 0, True): (103.5, 0),
                   (2, "scalar"): (44, 64), (2, "full"): (81, 64), (0, "scalar"): (125, 0), (0, "full"): (155, 0)}
 
 
 def flops_per_pair(algorithm, kind, rho_max, per_sample):
     """(vector, matrix) flops per pair of the loop a launch runs: the series
     order follows the disc (omega = 1 - cos rho_max <= 1e-3: second order, <= 4e-3:
-    third, else the reciprocal)."""
+    third, else the reciprocal; quadratic-form tiles also need their union radius
+    within 3.6 deg for the second order, which every tile of coherence 0.5 on a
+    2 deg disc meets)."""
     if algorithm != 1:
         return FLOPS_PER_PAIR[(algorithm, kind)]
     om = 2.0 * np.sin(0.5 * rho_max) ** 2

@@ -538,10 +538,12 @@ struct PixRec {
 // path): n as above, and the pixel's angle terms as a quadratic form in the
 // first two tile-frame components of the carried theta'_0 (see tile_pairs).
 struct PixRecQ {
-    float X, Y, W;
+    float G1, G2;         // gnomonic coordinates about the tile centre: n_xy / n_z
+    float W, Z;           // 1 - n_z and n_z
+    float ZX, ZY;         // n_z n_xy
     float A;              // wI I + wV V - B, B the turned Q, U term
     float P11, P12, P22;  // e^T P e = 2 cos gamma (B cos gamma + C sin gamma) / h^2 ... x h^2
-    float pad;
+    float pad0, pad1;
 };
 
 template <bool B, class T, class F> struct Cond { using type = T; };
@@ -579,7 +581,7 @@ struct TileLds {
         PixRec rec[CH];
     };
 };
-static_assert(sizeof(UnionRing) == 64 && sizeof(LaneFrame) == 60 && sizeof(PixRec) == 48 && sizeof(PixRecQ) == 32 &&
+static_assert(sizeof(UnionRing) == 64 && sizeof(LaneFrame) == 60 && sizeof(PixRec) == 48 && sizeof(PixRecQ) == 48 &&
                   sizeof(TileLds<64>) == 4352 + 3840 && sizeof(TileLds<128>) == 4352 + 128 * 48 &&
                   sizeof(TileLds<256>) == 4352 + 256 * 48,
               "the runtime's LDS budget assumes 4352 bytes + max(3840, 48 per staged record) per wave");
@@ -888,11 +890,23 @@ constexpr int tile_min_waves() {
 // SC (small cap): every pair inside the disc has omega = 1 - n.p <= SC_OMEGA, so
 // 1 / z' = 1 / (1 - omega) and 1 / (1 + z') = (1/2) / (1 - omega / 2) are their
 // geometric series instead of a quarter-rate reciprocal; pairs outside the disc
-// are masked.  SC = 1: to the third power (truncation below omega^4 = 2.6e-10,
-// inside FP32's rounding); SC = 2, for omega <= SC2_OMEGA: to the second power
-// (truncation below omega^3 = 1e-9), two instructions fewer.
+// are masked.  SC = 1: 1 / z' to the third power (truncation below
+// omega^4 = 2.6e-10, inside FP32's rounding); SC = 2, for omega <= SC2_OMEGA: to
+// the second power (truncation below omega^3 = 1e-9).  1 / (1 + z') only scales
+// q = (a.n) / (1 + z') in e = a - q (p + n), with a.n at most sin(rho) ~
+// sqrt(2 omega) and |p + n| <= 2, so one power fewer suffices there: the
+// truncation moves e by less than sqrt(2 omega) omega^3 / 8 of |a| (SC = 1,
+// 7e-10) and sqrt(2 omega) omega^2 / 4 (SC = 2, 1.1e-8), both under FP32's half
+// ulp.
 constexpr double SC_OMEGA = 4e-3;
 constexpr double SC2_OMEGA = 1e-3;
+// The quadratic-form records take the gnomonic scale 1 / (1 - t) instead of
+// 1 / z' (see tile_pairs), with |t| <= max(omega_max, (1 - cos R_u) / cos R_u)
+// for every pair inside the disc (R_u the tile's union radius); its series
+// to the second power for |t| <= SCT2 (truncation below 8e-9) and the third
+// for |t| <= SCT1 (below 4.1e-9), both an order under FP32's rounding.
+constexpr double SCT2 = 2e-3;
+constexpr double SCT1 = 8e-3;
 
 template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER, int SC = 0, bool QF = false>
 __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, PixRec>::type *Rp, const float *Vp,
@@ -906,6 +920,31 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         R[k] = Rp[k];
+        if constexpr (QF) {
+            // gnomonic form about the tile centre: with G = n_xy / n_z and
+            // t = om - p1 G1 - p2 G2, n.p / n_z = p3 + p.G = 1 - t, so
+            // 1 - n.p = W + n_z t, and n.theta'_0 / n_z = a3 + a1 G1 + a2 G2
+            // (phi'_0 likewise): the grid coordinates are these over 1 - t,
+            // two products each instead of three
+            const float tt = fmaf(-R[k].G2, F.p2, fmaf(-R[k].G1, F.p1, F.om));
+            omg[k] = fmaf(R[k].Z, tt, R[k].W);
+            in[k] = omg[k] <= C.omax;
+            xp[k] = fmaf(R[k].G2, F.a2, fmaf(R[k].G1, F.a1, F.a3));   // n.theta'_0 / n_z, grid units
+            yp[k] = fmaf(R[k].G2, F.b2, fmaf(R[k].G1, F.b1, F.b3));
+            const float w = omg[k];
+            if (SC == 2) {
+                rzh[k] = fmaf(tt, tt + 1.0f, 1.0f);                              // 1 / (1 - t)
+                rq[k] = fmaf(w, 0.25f, 0.5f);                                    // 1 / (1 + z')
+            } else if (SC == 1) {
+                rzh[k] = fmaf(tt, fmaf(tt, tt + 1.0f, 1.0f), 1.0f);
+                rq[k] = fmaf(w, fmaf(w, 0.125f, 0.25f), 0.5f);
+            } else {
+                const float dn = 1.0f - tt, zq = 2.0f - w;
+                const float rr = rcp(dn * zq);
+                rzh[k] = rr * zq;
+                rq[k] = rr * dn;
+            }
+        } else {
         // n = X e1 + Y e2 + (1 - W) c in the tile frame
         omg[k] = fmaf(-R[k].Y, F.p2, fmaf(-R[k].X, F.p1, fmaf(R[k].W, F.p3, F.om)));  // 1 - n.p
         in[k] = INNER ? ((omg[k] <= C.omax) & (omg[k] > C.omin)) : (omg[k] <= C.omax);
@@ -915,17 +954,18 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
         if (SC == 2) {
             const float w = omg[k];
             rzh[k] = fmaf(w, w + 1.0f, 1.0f);                                  // 1 / z'
-            rq[k] = fmaf(w, fmaf(w, 0.125f, 0.25f), 0.5f);                      // 1 / (1 + z')
+            rq[k] = fmaf(w, 0.25f, 0.5f);                                      // 1 / (1 + z')
         } else if (SC == 1) {
             const float w = omg[k];
             rzh[k] = fmaf(w, fmaf(w, w + 1.0f, 1.0f), 1.0f);                   // 1 / z'
-            rq[k] = fmaf(w, fmaf(w, fmaf(w, 0.0625f, 0.125f), 0.25f), 0.5f);    // 1 / (1 + z')
+            rq[k] = fmaf(w, fmaf(w, 0.125f, 0.25f), 0.5f);                      // 1 / (1 + z')
         } else {
             // one reciprocal for both divisions of the pair: 1 / (z' (1 + z')), z' = n.p
             const float zp = 1.0f - omg[k], zq = 2.0f - omg[k];
             const float rr = rcp(zp * zq);
             rzh[k] = rr * zq;            // gnomonic scale 1 / z'
             rq[k] = rr * zp;             // 1 / (1 + z')
+        }
         }
         const float tu = fmaf(xp[k], rzh[k], C.c0);
         const float tv = fmaf(yp[k], rzh[k], C.c0);
@@ -999,9 +1039,10 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
             // for vectors v, w normal to n, v.w = v_xy . (w_xy - (w_z / n_z) n_xy),
             // and the records hold 2 cos gamma (B cos gamma + C sin gamma), the
             // product of the projections on theta_hat and on B theta_hat + C phi_hat,
-            // as the quadratic form e_xy^T P e_xy (x h^2)
-            const float ex = fmaf(-q, F.p1 + R[k].X, F.a1);
-            const float ey = fmaf(-q, F.p2 + R[k].Y, F.a2);
+            // as the quadratic form e_xy^T P e_xy (x h^2).  Here xp is
+            // a.n / n_z, so q (p + n) = (xp rq) n_z (p + n).
+            const float ex = fmaf(-q, fmaf(R[k].Z, F.p1, R[k].ZX), F.a1);
+            const float ey = fmaf(-q, fmaf(R[k].Z, F.p2, R[k].ZY), F.a2);
             const float4 c = cl[k][0];
             const float bT = fmaf(fv[k], fmaf(fu[k], c.w, c.z), fmaf(fu[k], c.y, c.x));
             const float bTm = in[k] ? bT : 0.0f;
@@ -1119,6 +1160,7 @@ __device__ __forceinline__ void consume_records(const typename Cond<QF, PixRecQ,
 template <int MODE, int BEAM, int CH, bool PS, bool HWP>
 __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt, TileLds<CH> &L,
                               float *vrec, int lane) {
+    static_assert(CH % WAVE == 0, "chunks are whole waves of records");
     const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
     const int32_t N = (int32_t)A.nside;
     const bool valid = lane < cnt;
@@ -1154,6 +1196,9 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     const bool clip = D.needs_clip != 0;
     const bool small_cap = D.omega_max <= SC_OMEGA;    // reciprocal-free pair geometry (see tile_pairs)
     const bool tiny_cap = D.omega_max <= SC2_OMEGA;
+    // the quadratic-form records' series orders (the bound on |t| uses the union radius)
+    const double tb = fmax(D.omega_max, (1.0 - cosRu) / cosRu);
+    const bool tiny_q = tiny_cap && tb <= SCT2, small_q = small_cap && tb <= SCT1;
     const float wI = (float)D.w[0], wQ = (float)D.w[1], wU = (float)D.w[2];
     const float cmax = (float)(n - 2);          // largest cell index
     const float row = (float)(BEAM == BEAM_SCALAR ? n + 1 : n);
@@ -1196,10 +1241,13 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
         const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
         wave_sync();
 
+        // ring of the chunk's first record, or an earlier one: each lane's search
+        // starts there instead of at the batch's first ring
+        int32_t seg0 = 0;
         for (int32_t pb = 0; pb < total; pb += CH) {
             const int32_t m_end = min(CH, total - pb);
             // fill: one pixel record per lane, FP32 differences from the centre
-            int32_t seg = 0;
+            int32_t seg = seg0;
             for (int32_t m = lane; m < m_end; m += WAVE) {
                 const int32_t f = pb + m;
                 while (f >= L.seg_end[seg]) ++seg;
@@ -1249,26 +1297,34 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     // theta_hat and phi_hat reduced to the first two components
                     // (w_xy - (w_z / n_z) n_xy, the pair loop's tangent-plane dot
                     // product), then P = sym(theta~ (b theta~ + c phi~)^T)
-                    const float rnz = __builtin_amdgcn_rcpf(1.0f - R.W);   // n_z >= 1/2
+                    const float nz = 1.0f - R.W;                             // n_z >= 1/2
+                    const float rnz = __builtin_amdgcn_rcpf(nz);
                     const float tz = R.t3 * rnz, fz = R.f3 * rnz;
                     const float t1 = fmaf(-tz, R.X, R.t1), t2 = fmaf(-tz, R.Y, R.t2);
                     const float f1 = fmaf(-fz, R.X, R.f1), f2 = fmaf(-fz, R.Y, R.f2);
                     const float w1 = fmaf(R.b, t1, R.c * f1), w2 = fmaf(R.b, t2, R.c * f2);
                     PixRecQ Q;
-                    Q.X = R.X;
-                    Q.Y = R.Y;
+                    Q.G1 = R.X / nz;   // correctly rounded: the grid coordinates scale these
+                    Q.G2 = R.Y / nz;
                     Q.W = R.W;
+                    Q.Z = nz;
+                    Q.ZX = nz * R.X;
+                    Q.ZY = nz * R.Y;
                     Q.A = R.a;
                     Q.P11 = t1 * w1;
                     Q.P12 = fmaf(t1, w2, t2 * w1);
                     Q.P22 = t2 * w2;
-                    Q.pad = 0.0f;
+                    Q.pad0 = 0.0f;
+                    Q.pad1 = 0.0f;
                     reinterpret_cast<PixRecQ *>(L.rec)[m] = Q;
                 } else {
                     L.rec[m] = R;
                 }
                 if (has_v) vrec[m] = sv.w;
             }
+            // the last lane filled the chunk's last record (CH is a multiple of
+            // the wave; only the batch's last chunk is partial)
+            seg0 = __builtin_amdgcn_readlane(seg, WAVE - 1);
             wave_sync();
 
             // consume: every lane (sample) against every staged pixel
@@ -1289,10 +1345,10 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     if constexpr (MODE == MODE_TOD && BEAM == BEAM_SCALAR && !HWP) {
                         if (qf) {
                             const PixRecQ *rq = reinterpret_cast<const PixRecQ *>(L.rec);
-                            if (tiny_cap)
+                            if (tiny_q)
                                 consume_records<MODE, BEAM, PS, HWP, false, false, 2, true>(rq, vr, m_end, C, beam, vbeam,
                                                                                             acc0, acc1, acc2, accn);
-                            else if (small_cap)
+                            else if (small_q)
                                 consume_records<MODE, BEAM, PS, HWP, false, false, 1, true>(rq, vr, m_end, C, beam, vbeam,
                                                                                             acc0, acc1, acc2, accn);
                             else
@@ -1405,6 +1461,7 @@ template <int MODE, int BEAM, int CH, bool PS>
 __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t begin, int32_t cnt,
                                  TileLdsMx<CH, mx_nacc<MODE>()> &L, int lane) {
     constexpr int NACC = mx_nacc<MODE>();
+    static_assert(CH % WAVE == 0, "chunks are whole waves of records");
     const float4 *__restrict__ sky = reinterpret_cast<const float4 *>(A.sky);
     const int32_t N = (int32_t)A.nside;
     const bool valid = lane < cnt;
@@ -1453,11 +1510,12 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
         const int32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, WAVE - 1, WAVE));
         wave_sync();
 
+        int32_t seg0 = 0;   // as in the vector tile kernel
         for (int32_t pb = 0; pb < total; pb += CH) {
             const int32_t m_end = min(CH, total - pb);
             const int32_t m_pad = (m_end + 15) & ~15;
             // fill: one pixel record per lane; padding records lie outside every disc
-            int32_t seg = 0;
+            int32_t seg = seg0;
             for (int32_t m = lane; m < m_pad; m += WAVE) {
                 if (m < m_end) {
                     const int32_t f = pb + m;
@@ -1516,6 +1574,7 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
                     L.sky[m] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 }
             }
+            seg0 = __builtin_amdgcn_readlane(seg, WAVE - 1);
             wave_sync();
 
             // one pass per 16-sample block: its coefficients and running sums
