@@ -898,6 +898,9 @@ constexpr int tile_min_waves() {
 // truncation moves e by less than sqrt(2 omega) omega^3 / 8 of |a| (SC = 1,
 // 7e-10) and sqrt(2 omega) omega^2 / 4 (SC = 2, 1.1e-8), both under FP32's half
 // ulp.
+// A byte offset past every beam-record array (grids have at most 4096^2 cell
+// records, 256 MiB), with room for the 16-byte load before 2^32.
+constexpr uint32_t OOB_OFFSET = 0x80000000u;
 constexpr double SC_OMEGA = 4e-3;
 constexpr double SC2_OMEGA = 1e-3;
 // The quadratic-form records take the gnomonic scale 1 / (1 - t) instead of
@@ -912,6 +915,7 @@ template <int MODE, int BEAM, bool PS, int NP, bool HWP, bool CLIP, bool INNER, 
 __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, PixRec>::type *Rp, const float *Vp,
                                               const PairCtx &C, const BeamRsrc &beam, const BeamRsrc &vbeam) {
     static_assert(!QF || (MODE == MODE_TOD && BEAM == BEAM_SCALAR && !HWP), "quadratic form: one-grid TOD, no plate");
+    constexpr bool ZMASK = BEAM == BEAM_SCALAR && SC != 0 && MODE == MODE_TOD;
     const LaneFrame &F = C.F;
     typename Cond<QF, PixRecQ, PixRec>::type R[NP];
     float omg[NP], xp[NP], yp[NP], rzh[NP], rq[NP], fu[NP], fv[NP];
@@ -998,6 +1002,10 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
         // wide discs: a masked pair's unclamped cell can be anywhere in a large
         // record array, so its load is sent to record 0 (kept in cache)
         if (BEAM == BEAM_SCALAR && SC == 0) off[k] = in[k] ? off[k] : 0u;
+        // series geometry (every factor of a pair finite): a masked pair's load is
+        // sent past the records, so it reads zero without a cache access, and that
+        // zero is its mask
+        if (ZMASK) off[k] = in[k] ? off[k] : OOB_OFFSET;
     }
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
 #pragma unroll
@@ -1045,7 +1053,7 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
             const float ey = fmaf(-q, fmaf(R[k].Z, F.p2, R[k].ZY), F.a2);
             const float4 c = cl[k][0];
             const float bT = fmaf(fv[k], fmaf(fu[k], c.w, c.z), fmaf(fu[k], c.y, c.x));
-            const float bTm = in[k] ? bT : 0.0f;
+            const float bTm = ZMASK ? bT : (in[k] ? bT : 0.0f);
             if (PS) o.vn += bTm;
             const float quad = fmaf(ex, fmaf(R[k].P11, ex, R[k].P12 * ey), fmaf(R[k].P22 * ey, ey, R[k].A));
             o.v0 += bTm * quad;
@@ -1074,13 +1082,13 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
             bU = lerp(lerp(q00.z, q10.z, fu[k]), lerp(q01.z, q11.z, fu[k]), fv[k]);
             bT = lerp(lerp(q00.w, q10.w, fu[k]), lerp(q01.w, q11.w, fu[k]), fv[k]);
         }
-        if (PS) o.vn += in[k] ? bT : 0.0f;
+        if (PS) o.vn += (ZMASK || in[k]) ? bT : 0.0f;
         if (MODE == MODE_TOD && BEAM == BEAM_SCALAR) {
             // a + cos 2gamma B + sin 2gamma C = (a - B) + 2 cos gamma (cos gamma B
             // + sin gamma C), as cc^2 + ss^2 = 1/h^2: the records hold a - B,
             // 2 h^2 B and 2 h^2 C (the plate's signs included); the mask goes on
             // the beam value (every factor is finite)
-            const float bTm = in[k] ? bT : 0.0f;
+            const float bTm = ZMASK ? bT : (in[k] ? bT : 0.0f);
             o.v0 += bTm * fmaf(cc, fmaf(R[k].b, cc, R[k].c * ss), R[k].a);
             continue;
         }
