@@ -899,7 +899,8 @@ constexpr int tile_min_waves() {
 // 7e-10) and sqrt(2 omega) omega^2 / 4 (SC = 2, 1.1e-8), both under FP32's half
 // ulp.
 // A byte offset past every beam-record array (grids have at most 4096^2 cell
-// records, 256 MiB), with room for the 16-byte load before 2^32.
+// records, 256 MiB), with room before 2^32 for a load at it plus a row
+// (at most 16 x 4095 bytes) plus 16.
 constexpr uint32_t OOB_OFFSET = 0x80000000u;
 constexpr double SC_OMEGA = 4e-3;
 constexpr double SC2_OMEGA = 1e-3;
@@ -1006,6 +1007,9 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
         // sent past the records, so it reads zero without a cache access, and that
         // zero is its mask
         if (ZMASK) off[k] = in[k] ? off[k] : OOB_OFFSET;
+        // four-channel beams: the four node loads of a masked pair likewise
+        // (the term keeps its select: a V column is read from another array)
+        if (BEAM == BEAM_FULL && MODE == MODE_TOD && SC != 0) off[k] = in[k] ? off[k] : OOB_OFFSET;
     }
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
 #pragma unroll
