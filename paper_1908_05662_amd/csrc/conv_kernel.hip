@@ -244,6 +244,15 @@ __device__ inline double rcp(double x) { return 1.0 / x; }
 //            the cell's four corner values (b00, b10, b01, b11), (n-1)^2 records,
 //            so a bilinear lookup is a single 16/32-byte load
 // ----------------------------------------------------------------------
+// One-grid cell records: the (n + 1)^2 padded array (n odd, so the side is
+// even) stores its rows in interleaved pairs, record (U, V) at
+// 2 ((V >> 1) side + U) + (V & 1), so a 128-byte line holds a 4 x 2 block of
+// cells.  The 64 lanes of a tile gather cells along a short segment whose
+// direction follows the scan and the position angle; row-major lines of 8
+// cells meet one line per row the segment crosses.
+__host__ __device__ inline int64_t cell_index(int64_t U, int64_t V, int64_t side) {
+    return 2 * ((V >> 1) * side + U) + (V & 1);
+}
 template <typename T>
 struct BeamVals {
     T bI, bQ, bU, bT;
@@ -263,9 +272,9 @@ __device__ inline BeamVals<T> beam_lookup(const void *beam, int32_t n, int32_t i
         o.bT = lerp(lerp(q00.w, q10.w, fu), lerp(q01.w, q11.w, fu), fv);
     } else {
         // cell record (b00, b10 - b00, b01 - b00, b11 - b10 - b01 + b00); the
-        // records carry a ring of extrapolated cells, so cell (iv, iu) is record
-        // (iv + 1, iu + 1) of rows of n + 1
-        const R4 c = g[(iv + 1) * (n + 1) + iu + 1];
+        // records carry a ring of extrapolated cells, so cell (iu, iv) is padded
+        // cell (iu + 1, iv + 1) of side n + 1 (rows stored in pairs)
+        const R4 c = g[cell_index(iu + 1, iv + 1, n + 1)];
         o.bT = fma(fv, fma(fu, c.w, c.z), fma(fu, c.y, c.x));
         o.bI = o.bQ = o.bU = o.bT;
     }
@@ -525,6 +534,24 @@ __device__ inline BeamRsrc make_beam_rsrc(const void *p, uint32_t nrec) {
 __device__ inline float4 beam_ld(const BeamRsrc &b, uint32_t off, int32_t soff) {
     const auto v = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)off, soff, 0);
     return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+
+// Structured access to the cell records (stride 16): the range test is on the
+// record index, so an index at or past the count reads zero.
+__device__ inline BeamRsrc make_cell_rsrc(const void *p, uint32_t nrec) {
+    const unsigned long long a = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+    void *u = (void *)(((unsigned long long)hi << 32) | lo);
+    const int cnt = (int)__builtin_amdgcn_readfirstlane(nrec);
+    return BeamRsrc{__builtin_amdgcn_make_buffer_rsrc(u, (short)16, cnt, 0x00020000)};
+}
+typedef int32_t cell_v4i __attribute__((ext_vector_type(4)));
+__device__ cell_v4i cell_struct_load(__amdgpu_buffer_rsrc_t r, int32_t vindex, int32_t voffset, int32_t soffset,
+                                     int32_t aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+__device__ inline float4 cell_ld(const BeamRsrc &b, uint32_t idx) {
+    const cell_v4i v = cell_struct_load(b.r, (int32_t)idx, 0, 0, 0);
+    return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
 }
 
 struct PixRec {
@@ -900,7 +927,7 @@ constexpr int tile_min_waves() {
 // ulp.
 // A byte offset past every beam-record array (grids have at most 4096^2 cell
 // records, 256 MiB), with room before 2^32 for a load at it plus a row
-// (at most 16 x 4095 bytes) plus 16.
+// (at most 16 x 4095 bytes) plus 16; as a record index, past every record count.
 constexpr uint32_t OOB_OFFSET = 0x80000000u;
 constexpr double SC_OMEGA = 4e-3;
 constexpr double SC2_OMEGA = 1e-3;
@@ -987,12 +1014,13 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
             // truncation is the floor there (t >= 0 up to rounding; a masked pair's
             // index only picks some record or a zero read, and wide discs send it
             // to record 0 below), fract gives t - floor(t) exactly, and the record
-            // offset takes one 24-bit multiply-add (row < 4097)
+            // index takes a shift and two 24-bit multiply-adds (row < 4097)
             const uint32_t iu = (uint32_t)(int32_t)tu, iv = (uint32_t)(int32_t)tv;
             fu[k] = __builtin_amdgcn_fractf(tu);
             fv[k] = __builtin_amdgcn_fractf(tv);
-            off[k] = (uint32_t)__umul24(iv, C.irow) + iu;
-            off[k] <<= 4;
+            // the record index in row pairs: 2 ((iv >> 1) (side - 1) + iu) + iv
+            const uint32_t m = (uint32_t)__umul24(iv >> 1, C.irow - 1u) + iu;
+            off[k] = (m << 1) + iv;
         } else {
             const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, C.cmax));
             const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, C.cmax));
@@ -1014,7 +1042,7 @@ __device__ __forceinline__ PairOut tile_pairs(const typename Cond<QF, PixRecQ, P
     float4 cl[NP][BEAM == BEAM_SCALAR ? 1 : 4];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        cl[k][0] = beam_ld(beam, off[k], 0);
+        cl[k][0] = BEAM == BEAM_SCALAR ? cell_ld(beam, off[k]) : beam_ld(beam, off[k], 0);
         if (BEAM != BEAM_SCALAR) {
             cl[k][1] = beam_ld(beam, off[k] + 16, 0);
             cl[k][2] = beam_ld(beam, off[k], C.row_bytes);
@@ -1218,7 +1246,7 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
     // beam records through a buffer resource: 32-bit byte offsets, reads past
     // the end return zero
     const uint32_t nrec = (uint32_t)(BEAM == BEAM_SCALAR ? (n + 1) * (n + 1) : n * n);
-    const BeamRsrc beam = make_beam_rsrc(D.beam, nrec);
+    const BeamRsrc beam = BEAM == BEAM_SCALAR ? make_cell_rsrc(D.beam, nrec) : make_beam_rsrc(D.beam, nrec);
     const int32_t row_bytes = __builtin_amdgcn_readfirstlane(16 * n);   // buffer-load soffset: must stay in an SGPR
     // full beams with a V column: bV cell polynomials, and the V of each staged pixel
     const bool has_v = (BEAM == BEAM_FULL) && (MODE == MODE_TOD) && D.beam_v != nullptr && vrec != nullptr;
@@ -1640,7 +1668,11 @@ __device__ void convolve_tile_mx(const ConvArgs &A, const DetDesc &D, int64_t be
                         const float ku = floorf(__builtin_amdgcn_fmed3f(tu, 0.0f, cmax));
                         const float kv = floorf(__builtin_amdgcn_fmed3f(tv, 0.0f, cmax));
                         const float fu = fmaf(su, inv_h, c0 - ku), fv = fmaf(sv, inv_h, c0 - kv);
-                        const uint32_t off = (uint32_t)fmaf(kv, row, ku + kbase) << 4;
+                        // one-grid records: padded cell (ku + 1, kv + 1) in row pairs
+                        const uint32_t off =
+                            BEAM == BEAM_SCALAR
+                                ? (uint32_t)cell_index((int64_t)ku + 1, (int64_t)kv + 1, (int64_t)row) << 4
+                                : (uint32_t)fmaf(kv, row, ku + kbase) << 4;
                         float bT, bI = 0.0f, bQ = 0.0f, bU = 0.0f;
                         if (BEAM == BEAM_SCALAR) {
                             const float4 cl = beam_ld(beam, off, 0);
@@ -1960,9 +1992,10 @@ __global__ void __launch_bounds__(256) healpix_grid_kernel(HpxGridArgs a) {
 }
 
 // Cell polynomials (b00, b10 - b00, b01 - b00, b11 - b10 - b01 + b00) of the
-// (n - 1)^2 grid cells; with `padded`, (n + 1)^2 records: a ring of cells one
-// step outside the grid whose polynomials continue those of the nearest edge
-// cell (P(x + du, y + dv) with du, dv in {-1, 0, 1}), the interior unchanged.
+// (n - 1)^2 grid cells, row-major; with `padded`, (n + 1)^2 records: a ring of
+// cells one step outside the grid whose polynomials continue those of the
+// nearest edge cell (P(x + du, y + dv) with du, dv in {-1, 0, 1}), the interior
+// unchanged, stored in the row-pair order of cell_index.
 template <typename T>
 __global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::type *out, bool padded) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1987,7 +2020,10 @@ __global__ void repack_cells_kernel(const T *b, int32_t n, typename Rec4<T>::typ
         r.z = (T)(c01 + c11 * du);
         r.w = (T)c11;
     }
-    out[i] = r;
+    if (padded)
+        out[cell_index(iu + 1, iv + 1, side)] = r;   // rows in interleaved pairs (side = n + 1 is even)
+    else
+        out[i] = r;
 }
 
 __global__ void check_pointing_kernel(const double *th, const double *ph, const double *ps, int64_t n,
