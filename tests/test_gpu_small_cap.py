@@ -77,3 +77,51 @@ def test_small_cap_boundaries(conv, torch, algo, beam):
         e = rel_err(got, want)
         say(f"  omega_max {1 - np.cos(d.rho_max):.6e}: max rel err {e:.3e}")
         assert e <= F32_TOL
+
+
+# The one-grid loop without a plate (the quadratic-form records) divides by
+# 1 - t instead of n.p, |t| <= max(omega_max, (1 - cos R_u) / cos R_u) with R_u
+# the union radius of the tile, and picks the series order per tile from that
+# bound: second power up to 2e-3, third up to 8e-3, else the reciprocal.
+SCT2, SCT1 = 2e-3, 8e-3
+
+
+def _wide_tile_workload():
+    from synth.sky import make_sky
+
+    d2r = np.pi / 180
+    T, u, v, rho, sig = B.tangent_grid(161, 5.5 * d2r)
+    bs = B.ideal_beamsor(B.elliptical_gaussian(rho, sig, 1.5 * d2r, 0.05, 0.3), T)
+    n = 512
+    t = np.linspace(0.0, 1.0, n)
+    dets = []
+    # arc per 64-sample group ~1, 4.5 and 13 deg: union radii ~2.5, 4.3, 8.5 deg on a 2 deg disc
+    for span in (1.0, 4.5, 13.0):
+        phi_range = span * d2r * (n / 64) / np.sin(1.2)
+        th, ph, ps = 1.2 + 0.05 * t, 2.0 + phi_range * t, 2.5 * t
+        dets.append(Detector(bs, B.DetectorParams(0.2, 0.01, 1.0), 0.0, 2.0 * d2r, W.NORM_PER_SAMPLE, 1.0,
+                             th, ph, ps))
+    return Workload("wide-tiles", 128, tuple(make_sky(128, 383, 2.0, seed=12)), dets)
+
+
+def test_series_order_follows_union_radius(conv, torch):
+    say("case: quadratic-form series order per tile (2 deg disc, tiles of 1 to 13 deg)")
+    coherence = 4.0
+    conv.set_launch(algorithm=1, coherence=coherence)
+    w = _wide_tile_workload()
+    bounds = []
+    for d in w.detectors:
+        chord, lim = coherence_chords(d, coherence)
+        assert chord.max() < 0.9 * lim, "a group would leave the tile path"
+        ru = d.rho_max + 2.0 * np.arcsin(chord / 2.0)
+        bounds.append(np.maximum(1.0 - np.cos(d.rho_max), (1.0 - np.cos(ru)) / np.cos(ru)))
+    tb = np.concatenate(bounds)
+    assert (tb <= 0.9 * SCT2).any() and ((tb > 1.1 * SCT2) & (tb <= 0.9 * SCT1)).any() and (tb > 1.1 * SCT1).any(), \
+        "the tiles must cover all three series orders"
+    load_workload(conv, w, np.float32, beam="auto")
+    for k, d in enumerate(w.detectors):
+        got = conv.convolve(k).cpu().numpy()
+        want = oracle_detector(w, k, slice(None), np.float32)
+        e = rel_err(got, want)
+        say(f"  detector {k}: |t| bound {bounds[k].min():.2e} .. {bounds[k].max():.2e}, max rel err {e:.3e}")
+        assert e <= F32_TOL
