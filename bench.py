@@ -86,11 +86,12 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(launch):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter runs, or None once a source they depend on (the kernel, the plan
-    builder that orders its tiles) or the launch shape differs from the one the
-    counters were taken with."""
+def measured_counters(launch):
+    """The committed rocprofv3 counter record of the dominant kernel for this
+    launch shape (HBM bytes per launch, and for the default shape the texture
+    path and L1 counters), or None once a source they depend on (the kernel, the
+    plan builder that orders its tiles) or the launch shape differs from the one
+    the counters were taken with."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic_conv_c3.json")
@@ -102,10 +103,31 @@ def measured_traffic(launch):
             return None
         for r in rec["records"]:
             if all(launch.get(k) == v for k, v in r["launch"].items()):
-                return r["traffic_bytes_per_launch"]
+                return r
     except (OSError, KeyError, ValueError, AttributeError, TypeError):
         return None
     return None
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of the dominant kernel (see measured_counters)."""
+    r = measured_counters(launch)
+    return None if r is None else r.get("traffic_bytes_per_launch")
+
+
+def gather_roofline(launch, pairs, k_ms):
+    """The beam gathers of the one-grid tile loop (one 16-byte cell record per
+    pair, from L1/L2): their rate, and from the committed counter runs how busy
+    the texture path that serves them was and how many L1 lines a 64-lane gather
+    touched.  None without a matching counter record."""
+    r = measured_counters(launch)
+    p = None if r is None else r.get("pipeline")
+    if p is None:
+        return None
+    return {"unit": "GB/s", "bytes_per_pair": 16, "achieved": pairs * 16 / (k_ms / 1e3) / 1e9,
+            "binding": "texture-data path of the L1 (beam-record gathers)",
+            "td_busy": p["td_busy"], "ta_busy": p["ta_busy"], "l1_lines_per_gather": p["l1_lines_per_gather"],
+            "l1_miss_frac": p["l1_miss_frac"]}
 
 
 def load(conv, w, torch):
@@ -1078,6 +1100,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / ALU_PEAK_TFLOPS, "traffic": measured_traffic(launch),
                      "flops_per_pair": fpp,
+                     "gather": gather_roofline(launch, pairs, k_ms) if kind == "scalar" else None,
                      "matrix_tflops": mfma_per_pair * pairs / (k_ms / 1e3) / 1e12,
                      "valu_issue_probe": probe},
         "cpu_baseline": cpu,
