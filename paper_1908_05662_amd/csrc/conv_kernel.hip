@@ -32,6 +32,13 @@
 #include <algorithm>
 #include <mutex>
 
+// The structured buffer load (index mode, stride from the descriptor) of the
+// LLVM AMDGPU back end, declared by its intrinsic name.
+typedef int32_t pisco_cell_v4i __attribute__((ext_vector_type(4)));
+__device__ pisco_cell_v4i pisco_cell_struct_load(__amdgpu_buffer_rsrc_t r, int32_t vindex, int32_t voffset,
+                                                 int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
+
 namespace pisco {
 namespace {
 
@@ -546,11 +553,8 @@ __device__ inline BeamRsrc make_cell_rsrc(const void *p, uint32_t nrec) {
     const int cnt = (int)__builtin_amdgcn_readfirstlane(nrec);
     return BeamRsrc{__builtin_amdgcn_make_buffer_rsrc(u, (short)16, cnt, 0x00020000)};
 }
-typedef int32_t cell_v4i __attribute__((ext_vector_type(4)));
-__device__ cell_v4i cell_struct_load(__amdgpu_buffer_rsrc_t r, int32_t vindex, int32_t voffset, int32_t soffset,
-                                     int32_t aux) __asm("llvm.amdgcn.struct.ptr.buffer.load.v4i32");
 __device__ inline float4 cell_ld(const BeamRsrc &b, uint32_t idx) {
-    const cell_v4i v = cell_struct_load(b.r, (int32_t)idx, 0, 0, 0);
+    const pisco_cell_v4i v = pisco_cell_struct_load(b.r, (int32_t)idx, 0, 0, 0);
     return make_float4(__int_as_float(v[0]), __int_as_float(v[1]), __int_as_float(v[2]), __int_as_float(v[3]));
 }
 
