@@ -290,7 +290,7 @@ def parity_leg():
     r_main = w.meta["r_main"]
     conv = Convolver(0)
     keep = load_any(conv, w, np.float32, torch)
-    idx = np.unique(np.concatenate([np.linspace(0, d.n - 1, 40).astype(np.int64), [63, 64]]))
+    idx = np.unique(np.concatenate([np.linspace(0, d.n - 1, 400).astype(np.int64), [63, 64]]))
     full = conv.convolve(0).cpu().numpy()[idx]
     conv.set_detector(0, d.det.zeta, 0.0, r_main, d.norm_mode, d.norm_scale)
     main = conv.convolve(0).cpu().numpy()[idx]
@@ -874,11 +874,13 @@ def full_scale_leg(epochs, n_train, width, hidden, lr):
     # sampled parity of this recipe against the oracle: main beams and annulus pickups
     main_np = d_main_all.cpu().numpy()
     e_main = 0.0
-    for k in range(0, R, 32):
+    n_main = 0
+    for k in range(0, R, 8):
         d = w.detectors[k]
-        j = np.array([0, 63, 64, d.n - 1])
+        j = np.unique(np.array([0, 1, 63, 64, 127, 128, d.n // 2, d.n - 1]))
         e_main = max(e_main, rel_inf(main_np[offs[k] + j], oracle_samples(w, k, j, np.float32)))
-    jj = np.arange(0, idx.size, idx.size // 8)[:8]
+        n_main += j.size
+    jj = np.arange(0, idx.size, idx.size // 32)[:32]
     ring = B_ideal(g, T)
     import oracle
 
@@ -887,7 +889,7 @@ def full_scale_leg(epochs, n_train, width, hidden, lr):
                       all_th[idx[jj]], all_ph[idx[jj]], all_ps[idx[jj]], OUT_STOKES)
     e_ann = rel_inf(p_held.cpu().numpy()[jj], want)
     parity = {"max_rel_err": max(e_main, e_ann), "main_beams": e_main, "annulus_stokes": e_ann,
-              "samples": int(4 * ((R + 31) // 32) + jj.size), "of": int(n), "tolerance": 1e-6,
+              "samples": int(n_main + jj.size), "of": int(n), "tolerance": 1e-6,
               "path": "FP32 tile path"}
 
     t_exact = t_main + per_sample_ann * n
