@@ -918,6 +918,11 @@ constexpr int tile_min_waves() {
     return (MODE == MODE_STOKES || (MODE == MODE_TOD && BEAM == BEAM_FULL)) ? 2 : 4;
 }
 
+// A byte offset past every beam-record array (grids have at most 4096^2 cell
+// records, 256 MiB), with room before 2^32 for a load at it plus a row
+// (at most 16 x 4095 bytes) plus 16; as a record index, past every record count.
+constexpr uint32_t OOB_OFFSET = 0x80000000u;
+
 // SC (small cap): every pair inside the disc has omega = 1 - n.p <= SC_OMEGA, so
 // 1 / z' = 1 / (1 - omega) and 1 / (1 + z') = (1/2) / (1 - omega / 2) are their
 // geometric series instead of a quarter-rate reciprocal; pairs outside the disc
@@ -929,10 +934,6 @@ constexpr int tile_min_waves() {
 // truncation moves e by less than sqrt(2 omega) omega^3 / 8 of |a| (SC = 1,
 // 7e-10) and sqrt(2 omega) omega^2 / 4 (SC = 2, 1.1e-8), both under FP32's half
 // ulp.
-// A byte offset past every beam-record array (grids have at most 4096^2 cell
-// records, 256 MiB), with room before 2^32 for a load at it plus a row
-// (at most 16 x 4095 bytes) plus 16; as a record index, past every record count.
-constexpr uint32_t OOB_OFFSET = 0x80000000u;
 constexpr double SC_OMEGA = 4e-3;
 constexpr double SC2_OMEGA = 1e-3;
 // The quadratic-form records take the gnomonic scale 1 / (1 - t) instead of
@@ -1348,8 +1349,8 @@ __device__ void convolve_tile(const ConvArgs &A, const DetDesc &D, int64_t begin
                     const float f1 = fmaf(-fz, R.X, R.f1), f2 = fmaf(-fz, R.Y, R.f2);
                     const float w1 = fmaf(R.b, t1, R.c * f1), w2 = fmaf(R.b, t2, R.c * f2);
                     PixRecQ Q;
-                    Q.G1 = R.X / nz;   // correctly rounded: the grid coordinates scale these
-                    Q.G2 = R.Y / nz;
+                    Q.G1 = R.X * rnz;
+                    Q.G2 = R.Y * rnz;
                     Q.W = R.W;
                     Q.Z = nz;
                     Q.ZX = nz * R.X;
