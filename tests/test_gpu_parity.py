@@ -322,25 +322,30 @@ def test_tile_counts_on_coherent_scans(conv, torch, nside, rmax_deg, step_deg):
     assert e <= F32_TOL
 
 
-@pytest.mark.parametrize("n,algo", [(3, 0), (3, 1), (3, 2), (4095, 0), (4095, 1), (4095, 2)])
-def test_grid_size_limits(conv, torch, n, algo):
-    """One-grid beams at the smallest and the largest grid the ABI accepts (n = 3
-    and 4095; the padded record array of the largest holds 4096^2 records in row
-    pairs, so record indices reach 2^24) on every FP32 path, against the oracle."""
-    say(f"case: grid size {n} x {n}, algo {algo}")
+@pytest.mark.parametrize("n,algo,beam", [(3, 0, "auto"), (3, 1, "auto"), (3, 2, "auto"), (4095, 0, "auto"),
+                                         (4095, 1, "auto"), (4095, 2, "auto"), (3, 1, "full"), (4095, 0, "full"),
+                                         (4095, 1, "full")])
+def test_grid_size_limits(conv, torch, n, algo, beam):
+    """Beams at the smallest and the largest grid the ABI accepts (n = 3 and 4095).
+    One-grid: the padded record array of the largest holds 4096^2 records in row
+    pairs, so record indices reach 2^24; four-channel: node byte offsets reach
+    268 MB.  Every FP32 path, against the oracle."""
+    say(f"case: grid size {n} x {n}, algo {algo}, beam {beam}")
     from synth.sky import make_sky
 
     span = 3.0 if n == 3 else 2.5
     T, u, v, rho, sig = B.tangent_grid(n, span * D2R)
     g = B.elliptical_gaussian(rho, sig, 1.5 * D2R, 0.05, 0.4)
     bs = B.ideal_beamsor(g, T)
+    if beam == "full":
+        bs = B.with_qu_leakage(bs, g, 0.01)
     m = 256
     t = np.linspace(0.0, 1.0, m)
     th, ph, ps = 1.0 + 0.05 * t, 2.0 + 0.1 * t, 0.7 + 0.3 * t
     det = Detector(bs, B.DetectorParams(0.2, 0.01, 1.0), 0.0, 2.0 * D2R, W.NORM_PER_SAMPLE, 1.0, th, ph, ps)
     w = Workload("grid-limits", 128, tuple(make_sky(128, 383, 2.0, seed=13)), [det])
     conv.set_launch(algorithm=algo, coherence=0.5)
-    load_workload(conv, w, np.float32)
+    load_workload(conv, w, np.float32, beam=beam)
     got = conv.convolve(0).cpu().numpy()
     want = oracle_detector(w, 0, slice(None), np.float32)
     e = rel_err(got, want)
