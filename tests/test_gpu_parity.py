@@ -351,3 +351,48 @@ def test_grid_size_limits(conv, torch, n, algo, beam):
     e = rel_err(got, want)
     say(f"  max rel err {e:.3e}")
     assert e <= F32_TOL
+
+
+@pytest.mark.parametrize("algo", [0, 1])
+def test_max_nside_sky(conv, torch, algo):
+    """The largest sky the ABI accepts (nside 8192, 805M pixels, 12.9 GB on the
+    device): zero maps with a smooth I, Q, U on the rings within 4 deg of a
+    128-sample scan (2 deg disc, ~2.4e5 pixels per sample), against the oracle
+    on the same (FP32-rounded) maps."""
+    import gc
+
+    from synth.rings import ring_table
+
+    say(f"case: nside 8192 sky, algo {algo}")
+    N = 8192
+    npix = 12 * N * N
+    th0 = 1.0
+    z, st, nring, first, phi0 = ring_table(N)
+    rth = np.arctan2(st, z)
+    maps = [np.zeros(npix, dtype=np.float32) for _ in range(3)]
+    for r in np.nonzero(np.abs(rth - th0) < 4.0 * D2R)[0]:
+        n = int(nring[r])
+        ph = phi0[r] + 2.0 * np.pi * np.arange(n) / n
+        sl = slice(int(first[r]), int(first[r]) + n)
+        t = rth[r]
+        maps[0][sl] = 1.0 + np.sin(40.0 * t) * np.cos(30.0 * ph) + 0.3 * np.cos(70.0 * ph + 5.0 * t)
+        maps[1][sl] = 0.1 * np.cos(50.0 * t + 20.0 * ph)
+        maps[2][sl] = 0.1 * np.sin(35.0 * t - 45.0 * ph)
+    T, u, v, rho, sig = B.tangent_grid(201, 2.2 * D2R)
+    bs = B.ideal_beamsor(B.elliptical_gaussian(rho, sig, 1.0 * D2R, 0.05, 0.3), T)
+    m = 128
+    s = np.linspace(0.0, 1.0, m)
+    th, ph, ps = th0 + 0.002 * s, 2.0 + 0.02 * s, 0.4 + 0.5 * s
+    det = Detector(bs, B.DetectorParams(0.2, 0.01, 1.0), 0.0, 2.0 * D2R, W.NORM_PER_SAMPLE, 1.0, th, ph, ps)
+    w = Workload("max-nside", N, tuple(maps), [det])
+    try:
+        conv.set_launch(algorithm=algo, coherence=0.5)
+        load_workload(conv, w, np.float32)
+        got = conv.convolve(0).cpu().numpy()
+        want = oracle_detector(w, 0, slice(None), np.float32)
+        e = rel_err(got, want)
+        say(f"  max rel err {e:.3e}")
+        assert e <= F32_TOL
+    finally:
+        del w, maps
+        gc.collect()
