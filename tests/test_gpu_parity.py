@@ -396,3 +396,36 @@ def test_max_nside_sky(conv, torch, algo):
     finally:
         del w, maps
         gc.collect()
+
+
+@pytest.mark.parametrize("algo", [0, 1, 2])
+def test_discs_with_zero_or_one_pixel(conv, torch, algo):
+    """Degenerate discs: radius 0.2 deg on an nside-64 sky (pixels ~0.9 deg apart)
+    along a slow scan, so most samples see no pixel centre (per-sample
+    normalisation by an empty sum: the TOD is 0) or exactly one (the TOD is that
+    pixel's term, normalised); the GPU must give 0 exactly where the oracle does
+    and match it elsewhere."""
+    say(f"case: discs of zero or one pixel, algo {algo}")
+    from synth.sky import make_sky
+
+    T, u, v, rho, sig = B.tangent_grid(41, 0.5 * D2R)
+    bs = B.ideal_beamsor(B.elliptical_gaussian(rho, sig, 0.3 * D2R, 0.05, 0.3), T)
+    m = 512
+    s = np.linspace(0.0, 1.0, m)
+    th, ph, ps = 1.0 + 0.3 * s, 2.0 + 0.05 * s, 0.4 + 2.0 * s
+    det = Detector(bs, B.DetectorParams(0.2, 0.01, 1.0), 0.0, 0.2 * D2R, W.NORM_PER_SAMPLE, 1.0, th, ph, ps)
+    w = Workload("tiny-discs", 64, tuple(make_sky(64, 191, 2.0, seed=17)), [det])
+    conv.set_launch(algorithm=algo, coherence=0.5)
+    load_workload(conv, w, np.float32)
+    got = conv.convolve(0).cpu().numpy()
+    from paper_1908_05662_amd import OUT_COUNT
+
+    cnt = conv.convolve(0, out_mode=OUT_COUNT).cpu().numpy()
+    want = oracle_detector(w, 0, slice(None), np.float32)
+    empty = want == 0.0
+    say(f"  {int(empty.sum())} empty discs, {int((cnt == 1).sum())} with one pixel, of {m}")
+    assert empty.sum() >= m // 4 and (cnt == 1).sum() >= m // 8, "the scan must produce both degenerate cases"
+    assert np.all(got[empty] == 0.0)
+    e = rel_err(got[~empty], want[~empty])
+    say(f"  max rel err {e:.3e}")
+    assert e <= F32_TOL
