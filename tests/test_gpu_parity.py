@@ -429,3 +429,32 @@ def test_discs_with_zero_or_one_pixel(conv, torch, algo):
     e = rel_err(got[~empty], want[~empty])
     say(f"  max rel err {e:.3e}")
     assert e <= F32_TOL
+
+
+@pytest.mark.parametrize("eps", [1.0, -1.0])
+@pytest.mark.parametrize("algo,beam", [(0, "auto"), (1, "auto"), (0, "full"), (1, "full")])
+def test_polarisation_efficiency_extremes(conv, torch, eps, algo, beam):
+    """Detector polarisation efficiency at its extremes: eps = 1 cancels the
+    polarised response (the TOD sees I only), eps = -1 the total-intensity one
+    (Q and U only); the folded channels then have zero weights, in the one-grid
+    and the four-channel forms alike."""
+    say(f"case: eps {eps}, algo {algo}, beam {beam}")
+    from synth.sky import make_sky
+
+    T, u, v, rho, sig = B.tangent_grid(101, 2.5 * D2R)
+    g = B.elliptical_gaussian(rho, sig, 1.0 * D2R, 0.05, 0.3)
+    bs = B.ideal_beamsor(g, T)
+    if beam == "full":
+        bs = B.with_qu_leakage(bs, g, 0.01)
+    m = 256
+    s = np.linspace(0.0, 1.0, m)
+    th, ph, ps = 0.8 + 0.01 * s, 1.0 + 0.05 * s, 0.3 + 2.0 * s
+    det = Detector(bs, B.DetectorParams(0.35, eps, 1.0), 0.0, 2.0 * D2R, W.NORM_PER_SAMPLE, 1.0, th, ph, ps)
+    w = Workload("eps-extremes", 128, tuple(make_sky(128, 383, 2.0, seed=19)), [det])
+    conv.set_launch(algorithm=algo, coherence=0.5)
+    load_workload(conv, w, np.float32, beam=beam)
+    got = conv.convolve(0).cpu().numpy()
+    want = oracle_detector(w, 0, slice(None), np.float32)
+    e = rel_err(got, want)
+    say(f"  max rel err {e:.3e}")
+    assert e <= F32_TOL
